@@ -1,0 +1,247 @@
+"""Scan form of the recursions -- TEST INFRASTRUCTURE ONLY.
+
+Dense scan operands exactly as Sec. III writes them, built from the serial
+oracle's intermediates, and prefix products under several bracketings. A
+correct operand reproduces the serial recursion for every bracketing because
+matrix multiplication is associative; that is the "scan equals serial" check.
+
+Operand order: the recursion x_i = A_i x_{i-1} needs P_i = A_i A_{i-1} ... A_0,
+so a combine puts the LATER element on the left. Eq. (11) writes
+x_i = x_{i-1} (+) a_i while (13) composes g g' with the earlier element on the
+left; only the reading "later on the left" satisfies the recursion (12).
+
+Operands (1-based links, n links):
+  (12) forward velocity/acceleration, 13x13, on (dV, V, 1):
+       A_0 = [[I, 0, dV0], [0, I, V0], [0, 0, 1]]
+       A_i = [[X_i, -ad(S_i qd_i) X_i, S_i qdd_i], [0, X_i, S_i qd_i], [0, 0, 1]],
+       X_i = Ad_{f_{i-1,i}^-1}
+  (13)/(14) the same operands in compact form (g, xi1, xi2) in SE(3) x se(3)^2.
+  (16) backward wrench/torque, 8x8, on (F_{i+1}, tau_{i+2}, 1) -> (F_i, tau_{i+1}, 1):
+       A_i = [[X_{i+1}^T, 0, Fhat_i], [S_{i+1}^T, 0, 0], [0, 0, 1]], i = n..0,
+       with X_{n+1} = I, S_{n+1} = 0 (padding tau_{n+1} = 0), Fhat_0 = 0.
+  (18) ABIA backward, 8x8, on (zhat_{i+1}, chat_{i+2}, 1) -> (zhat_i, chat_{i+1}, 1):
+       A_i = [[Y_{i,i+1}, 0, Pi_{i,i+1} tauhat_{i+1}],
+              [-Omega_{i+1}^-1 S_{i+1}^T, 0, Omega_{i+1}^-1 tauhat_{i+1}], [0, 0, 1]],
+       i = n-1..0, started from (zhat_n, chat_{n+1}) = 0. (The paper prints
+       Omega_{i+1} in the last column; (8) defines chat = Omega^-1 c, so it is read
+       as the inverse.)
+  (19) ABIA forward, 8x8, on (lambda_{i-1}, qdd_{i-1}, 1) -> (lambda_i, qdd_i, 1):
+       A_i = [[Y_{i-1,i}^T, 0, S_i chat_i], [-Pi_{i-1,i}^T, 0, chat_i], [0, 0, 1]], i = 1..n.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def skew(a):
+    return np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+
+
+def Ad(R, p):
+    """Ad_g = [[R, [p] R], [0, R]] on twists (v, w)."""
+    A = np.zeros((6, 6))
+    A[:3, :3] = R
+    A[3:, 3:] = R
+    A[:3, 3:] = skew(p) @ R
+    return A
+
+
+def ad(V):
+    """ad_V = [[[w], [v]], [0, [w]]] for V = (v, w)."""
+    A = np.zeros((6, 6))
+    A[:3, :3] = skew(V[3:])
+    A[3:, 3:] = skew(V[3:])
+    A[:3, 3:] = skew(V[:3])
+    return A
+
+
+def inv_pose(R, p):
+    return R.T, -R.T @ p
+
+
+# ---- bracketings of the prefix products P_k = A_k ... A_0 ----------------------
+
+def prefix_serial(ops):
+    out = [ops[0]]
+    for A in ops[1:]:
+        out.append(A @ out[-1])
+    return out
+
+
+def prefix_hillis_steele(ops):
+    x = list(ops)
+    d = 1
+    while d < len(x):
+        x = [x[i] @ x[i - d] if i >= d else x[i] for i in range(len(x))]
+        d *= 2
+    return x
+
+
+def prefix_blelloch(ops):
+    """Work-efficient up-sweep / down-sweep (exclusive), then one combine per element."""
+    m = 1
+    while m < len(ops):
+        m *= 2
+    eye = np.eye(ops[0].shape[0])
+    t = list(ops) + [eye] * (m - len(ops))
+    d = 1
+    while d < m:
+        for i in range(2 * d - 1, m, 2 * d):
+            t[i] = t[i] @ t[i - d]
+        d *= 2
+    t[m - 1] = eye
+    d = m // 2
+    while d >= 1:
+        for i in range(2 * d - 1, m, 2 * d):
+            left = t[i - d]
+            t[i - d] = t[i]
+            t[i] = left @ t[i]
+        d //= 2
+    return [ops[k] @ t[k] for k in range(len(ops))]
+
+
+def prefix_random_tree(ops, rng):
+    """Each prefix product evaluated under its own random binary bracketing."""
+    def prod(lo, hi):  # A_hi ... A_lo
+        if lo == hi:
+            return ops[lo]
+        mid = int(rng.integers(lo, hi))
+        return prod(mid + 1, hi) @ prod(lo, mid)
+    return [prod(0, k) for k in range(len(ops))]
+
+
+BRACKETINGS = ("serial", "hillis_steele", "blelloch", "random")
+
+
+def prefix(ops, how, rng=None):
+    if how == "serial":
+        return prefix_serial(ops)
+    if how == "hillis_steele":
+        return prefix_hillis_steele(ops)
+    if how == "blelloch":
+        return prefix_blelloch(ops)
+    if how == "random":
+        return prefix_random_tree(ops, rng if rng is not None else np.random.default_rng(0))
+    raise ValueError(how)
+
+
+# ---- dense operands from the serial intermediates ------------------------------
+
+def fwd_operands(ch, rt, qd, qdd, V0, dV0):
+    """Eq. (12) operands A_0..A_n from an RNEA trace (R, p of f_{i-1,i})."""
+    n = len(qd)
+    ops = []
+    A0 = np.eye(13)
+    A0[:6, 12] = dV0
+    A0[6:12, 12] = V0
+    ops.append(A0)
+    for i in range(1, n + 1):
+        X = Ad(*inv_pose(rt["R"][i], rt["p"][i]))
+        S = ch.twist[i - 1]
+        A = np.eye(13)
+        A[:6, :6] = X
+        A[:6, 6:12] = -ad(S * qd[i - 1]) @ X
+        A[:6, 12] = S * qdd[i - 1]
+        A[6:12, 6:12] = X
+        A[6:12, 12] = S * qd[i - 1]
+        ops.append(A)
+    return ops
+
+
+def force_operands(ch, rt):
+    """Eq. (16) operands in scan order A_n, A_{n-1}, ..., A_0."""
+    n = len(rt["tau"]) - 1
+    ops = []
+    for i in range(n, -1, -1):
+        A = np.zeros((8, 8))
+        A[7, 7] = 1.0
+        if i == n:
+            XT = np.eye(6)
+            Snext = np.zeros(6)
+        else:
+            XT = Ad(*inv_pose(rt["R"][i + 1], rt["p"][i + 1])).T
+            Snext = ch.twist[i]
+        A[:6, :6] = XT
+        A[6, :6] = Snext
+        A[:6, 7] = rt["Fhat"][i] if i >= 1 else 0.0
+        ops.append(A)
+    return ops
+
+
+def zhat_operands(ch, at):
+    """Eq. (18) operands in scan order A_{n-1}, ..., A_0 (Omega read as Omega^-1)."""
+    n = len(at["qdd"]) - 1
+    ops = []
+    for i in range(n - 1, -1, -1):
+        A = np.zeros((8, 8))
+        A[7, 7] = 1.0
+        Om = at["Omega"][i + 1]
+        A[:6, :6] = at["Y"][i + 1]
+        A[:6, 7] = at["Pi"][i + 1] * at["tauhat"][i + 1]
+        A[6, :6] = -ch.twist[i] / Om
+        A[6, 7] = at["tauhat"][i + 1] / Om
+        ops.append(A)
+    return ops
+
+
+def lambda_operands(ch, at):
+    """Eq. (19) operands in scan order A_1, ..., A_n."""
+    n = len(at["qdd"]) - 1
+    ops = []
+    for i in range(1, n + 1):
+        A = np.zeros((8, 8))
+        A[7, 7] = 1.0
+        A[:6, :6] = at["Y"][i].T
+        A[:6, 7] = ch.twist[i - 1] * at["chat"][i]
+        A[6, :6] = -at["Pi"][i]
+        A[6, 7] = at["chat"][i]
+        ops.append(A)
+    return ops
+
+
+# ---- compact operands of eqs. (13)-(14) ------------------------------------------
+
+def compact_fwd_operands(ch, rt, qd, qdd, V0, dV0):
+    """(g, xi1, xi2): a_0 = (I, dV0, V0), a_i = (f_{i-1,i}^-1, S_i qdd_i, S_i qd_i)."""
+    n = len(qd)
+    ops = [(np.eye(3), np.zeros(3), np.array(dV0, float), np.array(V0, float))]
+    for i in range(1, n + 1):
+        R, p = inv_pose(rt["R"][i], rt["p"][i])
+        S = ch.twist[i - 1]
+        ops.append((R, p, S * qdd[i - 1], S * qd[i - 1]))
+    return ops
+
+
+def compact_combine(a, b):
+    """Eq. (13): (g, x1, x2) (+) (g', x1', x2') = (g g', Ad_g x1' + x1 - ad_x2 Ad_g x2', Ad_g x2' + x2)."""
+    Ra, pa, x1a, x2a = a
+    Rb, pb, x1b, x2b = b
+    A = Ad(Ra, pa)
+    Ax2 = A @ x2b
+    return (Ra @ Rb, Ra @ pb + pa, A @ x1b + x1a - ad(x2a) @ Ax2, Ax2 + x2a)
+
+
+def compact_inverse(a):
+    """Eq. (14): (g, x1, x2)^-1 = (g^-1, -Ad_{g^-1} x1, -Ad_{g^-1} x2)."""
+    R, p, x1, x2 = a
+    Ri, pi = inv_pose(R, p)
+    Ai = Ad(Ri, pi)
+    return (Ri, pi, -Ai @ x1, -Ai @ x2)
+
+
+def compact_identity():
+    return (np.eye(3), np.zeros(3), np.zeros(6), np.zeros(6))
+
+
+def compact_to_dense(a):
+    """The isomorphism onto the 13x13 operands of eq. (12)."""
+    R, p, x1, x2 = a
+    A = np.eye(13)
+    X = Ad(R, p)
+    A[:6, :6] = X
+    A[:6, 6:12] = -ad(x2) @ X
+    A[:6, 12] = x1
+    A[6:12, 6:12] = X
+    A[6:12, 12] = x2
+    return A

@@ -1,0 +1,147 @@
+"""The scan operands of Sec. III reproduce the serial recursions under every bracketing (CPU only)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scan_form as sf
+from paper_1609_04493_amd import synth
+
+
+def _setup(n, seed):
+    ch = synth.make_chains([n], seed)
+    rng = np.random.default_rng(seed)
+    q, qd, qdd, tau = rng.uniform(-np.pi, np.pi, n), rng.standard_normal(n), rng.standard_normal(n), 10 * rng.standard_normal(n)
+    V0, dV0, Ft = rng.standard_normal(6), oracle.GRAVITY_ACC + rng.standard_normal(6), rng.standard_normal(6)
+    return ch, q, qd, qdd, tau, V0, dV0, Ft
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_velocity_acceleration_scan(n, how):
+    """Eq. (12): the last column of A_i ... A_0 is (dV_i, V_i, 1)."""
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 100 + n)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    P = sf.prefix(sf.fwd_operands(ch, rt, qd, qdd, V0, dV0), how, np.random.default_rng(n))
+    for i in range(n + 1):
+        scale = 1 + np.abs(rt["dV"][i]).max()
+        assert np.abs(P[i][:6, 12] - rt["dV"][i]).max() <= 1e-12 * scale
+        assert np.abs(P[i][6:12, 12] - rt["V"][i]).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 3, 8])
+def test_force_torque_scan(n, how):
+    """Eq. (16): A_i ... A_n (F_{n+1}, 0, 1) = (F_i, tau_{i+1}, 1) for i = n..0."""
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 200 + n)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    P = sf.prefix(sf.force_operands(ch, rt), how, np.random.default_rng(n))
+    x = np.concatenate([Ft, [0.0, 1.0]])
+    for k, i in enumerate(range(n, -1, -1)):
+        y = P[k] @ x
+        scale = 1 + np.abs(rt["F"]).max()
+        if i >= 1:
+            assert np.abs(y[:6] - rt["F"][i]).max() <= 1e-12 * scale
+        tau_next = rt["tau"][i + 1] if i + 1 <= n else 0.0
+        assert abs(y[6] - tau_next) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [2, 5, 8])
+def test_abia_backward_scan(n, how):
+    """Eq. (18) with Omega^-1: A_i ... A_{n-1} (0, 0, 1) = (zhat_i, chat_{i+1}, 1)."""
+    ch, q, qd, _, tau, V0, dV0, Ft = _setup(n, 300 + n)
+    at = oracle.aba_trace(ch, q, qd, tau, V0, dV0, Ft)
+    P = sf.prefix(sf.zhat_operands(ch, at), how, np.random.default_rng(n))
+    x = np.zeros(8); x[7] = 1.0
+    for k, i in enumerate(range(n - 1, -1, -1)):
+        y = P[k] @ x
+        scale = 1 + np.abs(at["zhat"]).max() + np.abs(at["chat"]).max()
+        if i >= 1:
+            assert np.abs(y[:6] - at["zhat"][i]).max() <= 1e-11 * scale
+        assert abs(y[6] - at["chat"][i + 1]) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 4, 8])
+def test_abia_forward_scan(n, how):
+    """Eq. (19): A_i ... A_1 (0, 0, 1) = (lambda_i, qdd_i, 1)."""
+    ch, q, qd, _, tau, V0, dV0, Ft = _setup(n, 400 + n)
+    at = oracle.aba_trace(ch, q, qd, tau, V0, dV0, Ft)
+    P = sf.prefix(sf.lambda_operands(ch, at), how, np.random.default_rng(n))
+    x = np.zeros(8); x[7] = 1.0
+    for k, i in enumerate(range(1, n + 1)):
+        y = P[k] @ x
+        scale = 1 + np.abs(at["lam"]).max() + np.abs(at["qdd"]).max()
+        assert np.abs(y[:6] - at["lam"][i]).max() <= 1e-11 * scale
+        assert abs(y[6] - at["qdd"][i]) <= 1e-11 * scale
+
+
+def test_omega_not_inverted_breaks_the_backward_scan():
+    """The printed Omega_{i+1} (not its inverse) in (18) does not reproduce (8): the reading matters."""
+    n = 5
+    ch, q, qd, _, tau, V0, dV0, Ft = _setup(n, 500)
+    at = oracle.aba_trace(ch, q, qd, tau, V0, dV0, Ft)
+    ops = sf.zhat_operands(ch, at)
+    for k, i in enumerate(range(n - 1, -1, -1)):
+        Om = at["Omega"][i + 1]
+        ops[k][6, 7] *= Om * Om  # Omega^-1 tauhat -> Omega tauhat, as printed
+    P = sf.prefix_serial(ops)
+    y = P[-1] @ np.array([0, 0, 0, 0, 0, 0, 0, 1.0])
+    assert abs(y[6] - at["chat"][1]) > 1e-3 * (1 + abs(at["chat"][1]))
+
+
+def test_later_operand_must_be_on_the_left():
+    """Combining with the earlier element on the left (x_{i-1} (+) a_i read as a matrix product) is wrong."""
+    n = 5
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 600)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    ops = sf.fwd_operands(ch, rt, qd, qdd, V0, dV0)
+    P = ops[0]
+    for A in ops[1:]:
+        P = P @ A
+    assert np.abs(P[6:12, 12] - rt["V"][n]).max() > 1e-3
+
+
+# ---- the compact group of eqs. (13)-(14) ---------------------------------------
+
+def _rand_elem(rng):
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_quat(rng.standard_normal(4) / 2).as_matrix()
+    return (R, rng.standard_normal(3), rng.standard_normal(6), rng.standard_normal(6))
+
+
+def _close(a, b, tol=1e-12):
+    return all(np.abs(x - y).max() <= tol * (1 + np.abs(y).max()) for x, y in zip(a, b))
+
+
+def test_compact_combine_is_the_dense_product():
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        a, b = _rand_elem(rng), _rand_elem(rng)
+        D = sf.compact_to_dense(sf.compact_combine(a, b))
+        assert np.abs(D - sf.compact_to_dense(a) @ sf.compact_to_dense(b)).max() <= 1e-12 * np.abs(D).max()
+
+
+def test_compact_group_axioms():
+    rng = np.random.default_rng(8)
+    e = sf.compact_identity()
+    for _ in range(20):
+        a, b, c = _rand_elem(rng), _rand_elem(rng), _rand_elem(rng)
+        assert _close(sf.compact_combine(a, e), a) and _close(sf.compact_combine(e, a), a)
+        assert _close(sf.compact_combine(a, sf.compact_inverse(a)), e)
+        assert _close(sf.compact_combine(sf.compact_inverse(a), a), e)
+        assert _close(sf.compact_combine(sf.compact_combine(a, b), c), sf.compact_combine(a, sf.compact_combine(b, c)))
+
+
+@pytest.mark.parametrize("n", [1, 6, 8])
+def test_compact_scan_reads_off_velocity_and_acceleration(n):
+    """Scanning (f^-1, S qdd, S qd) with (13) and reading (xi1, xi2) gives (dV_i, V_i)."""
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 700 + n)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    ops = sf.compact_fwd_operands(ch, rt, qd, qdd, V0, dV0)
+    P = ops[0]
+    for i in range(1, n + 1):
+        P = sf.compact_combine(ops[i], P)
+        assert np.abs(P[2] - rt["dV"][i]).max() <= 1e-12 * (1 + np.abs(rt["dV"][i]).max())
+        assert np.abs(P[3] - rt["V"][i]).max() <= 1e-12 * (1 + np.abs(rt["V"][i]).max())
