@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of batched scan-form dynamics on one MI355X.
+
+Workload: one 32-link serial chain shared by 16384 states, FP32 (the 32-link,
+16384-state configuration). One step = inverse dynamics and forward dynamics of
+every state (the fused pdyn_id_fd kernel): tau = ID(q, qd, qdd) and
+qdd' = FD(q, qd, tau'). Inputs are resident in HBM before timing starts; the
+derived link tables of the (fixed) model are prepared once before timing.
+
+Prints ONE JSON line. ``value`` is ID+FD evaluations per second (one eval =
+one ID and one FD of one state). Extra keys: the separate-call ("plain") form,
+per-output errors against the FP64 oracle on a sample, the roofline of the
+dominant kernel (HIP-event timing, algorithmic flops per link stated in
+the design doc), and the oracle timed on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dynamics evals/s (ID+FD, ±grad) at 32 links FP32 vs plain, at stated error"
+N_LINKS, N_STATES = 32, 16384
+# Algorithmic flops per link (structured spatial algebra, counted once per link;
+# derivation in the design doc): ID 433, FD 1045, ID+FD sharing transforms and velocities 1212.
+FLOPS_PER_LINK = {"id": 433, "fd": 1045, "id_fd": 1212}
+BYTES_PER_LINK = {"id": 16, "fd": 16, "id_fd": 24}  # joint inputs + outputs, FP32
+PEAK_VALU_FLOPS = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, unpacked FP32 = FP64 vector
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile-only", action="store_true", help="launch the timed steps only (for rocprofv3)")
+    return p.parse_args()
+
+
+def time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step
+
+
+def rel_rows(x, ref):
+    return np.linalg.norm(np.asarray(x, np.float64) - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+
+
+def err_stats(e):
+    return {"p50": float(np.median(e)), "p99": float(np.quantile(e, 0.99)), "max": float(e.max())}
+
+
+def cpu_baseline(ch, st):
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    cr, sr = ch.rounded(), st.rounded()
+    oracle.rnea(cr, sr.q[:64], sr.qd[:64], sr.qdd[:64])  # load + warm up
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.rnea(cr, sr.q, sr.qd, sr.qdd, threads=threads)
+        oracle.aba(cr, sr.q, sr.qd, sr.tau, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= 10.0 or reps >= 20:
+            break
+    return {"value": reps * len(sr.q) / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full {len(sr.q)}-state, {N_LINKS}-link batch (ID + FD per state), {reps} pass(es), "
+                      f"{el:.1f} s wall, {threads} Python threads each running the C oracle on a contiguous slice of states"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
+        return 2
+    import torch
+    from paper_1609_04493_amd import api, synth
+    api.lib()  # fails loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    ch, st = synth.workload_32link(N_STATES)
+    model = api.Model(ch, dev, torch.float32)
+    q, qd, qdd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.qdd, st.tau))
+    tau_out, qdd_out = torch.empty_like(q), torch.empty_like(q)
+    ws = api.Workspace()
+    stream = torch.cuda.current_stream(dev)
+
+    fused = lambda: api.id_fd(model, q, qd, qdd, tau, out=(tau_out, qdd_out), workspace=ws)
+    if args.profile_only:
+        for _ in range(args.warmup + args.steps):
+            fused()
+        torch.cuda.synchronize()
+        print("profile-only run done", flush=True)
+        return 0
+
+    def plain():
+        api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws)
+        api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws)
+
+    torch.cuda.synchronize()
+    ms_fused = time_steps(fused, args.steps, args.warmup, stream)
+    print(f"fused ID+FD: {ms_fused * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    ms_plain = time_steps(plain, args.steps, args.warmup, stream)
+    print(f"separate ID, FD calls: {ms_plain * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    ms_id = time_steps(lambda: api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws), args.steps, args.warmup, stream)
+    ms_fd = time_steps(lambda: api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws), args.steps, args.warmup, stream)
+
+    # stated error: the fused outputs against the FP64 oracle on a sample of states
+    import oracle
+    fused()
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(1).choice(N_STATES, 1024, replace=False)
+    cr, sr = ch.rounded(), st.rounded()
+    thr = len(os.sched_getaffinity(0))
+    et = rel_rows(tau_out.cpu().numpy()[idx], oracle.rnea(cr, sr.q[idx], sr.qd[idx], sr.qdd[idx], threads=thr))
+    eq = rel_rows(qdd_out.cpu().numpy()[idx], oracle.aba(cr, sr.q[idx], sr.qd[idx], sr.tau[idx], threads=thr))
+
+    links = N_LINKS * N_STATES
+    achieved = FLOPS_PER_LINK["id_fd"] * links / (ms_fused * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": N_STATES / (ms_fused * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_fused,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{N_LINKS}-link serial chain shared by {N_STATES} states, fused ID+FD per state",
+                   "n_links": N_LINKS, "n_states": N_STATES,
+                   "precision": "f32 bulk; f64 wrench and articulated-bias accumulations"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_FLOPS / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_FLOPS, "traffic": None,
+                     "kernel": "k_dynamics<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
+                     "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
+        "plain": {"form": "separate pdyn_rnea_id + pdyn_aba_fd calls", "value": N_STATES / (ms_plain * 1e-3),
+                  "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
+        "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3)},
+        "error_vs_fp64_oracle": {"sample_states": len(idx), "tau": err_stats(et), "qdd": err_stats(eq),
+                                 "metric": "per-state ||x - x*|| / ||x*||"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ch, st)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

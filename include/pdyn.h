@@ -1,0 +1,170 @@
+/*
+ * pdyn -- batched rigid-body dynamics of serial chains on AMD Instinct MI355X
+ * (gfx950), after Yang, Wu & Pan, "Parallel Dynamics Computation using Prefix
+ * Sum Operations" (arXiv:1609.04493).
+ *
+ * C ABI. Every array argument is a DEVICE pointer unless marked "host". The
+ * caller owns every buffer; the library allocates no user-visible memory and
+ * keeps no pointer after a call returns. Outputs are overwritten, never
+ * accumulated. Calls are asynchronous on the given HIP stream (a hipStream_t
+ * passed as void*, NULL = the null stream), perform no host synchronisation and
+ * no allocation, and are re-entrant.
+ *
+ * Conventions (paper, Table I and Sec. II):
+ *   twist V = (v, w), wrench F = (f, n), power V^T F.
+ *   f_{i-1,i} = M_i exp(S_i q_i) maps link frame i to frame i-1 (eq. (1)).
+ *   S_i (joint twist) and the link inertia are expressed in frame i.
+ *   Links are numbered base (1) to tip (n); arrays are 0-based.
+ *
+ * Errors: 0 on success; a negative PDYN_E* code otherwise. Arguments are
+ * checked on the host BEFORE any device work is queued, so a failing call
+ * leaves outputs and device state untouched. Non-finite inputs or a
+ * non-positive articulated pivot S^T Jhat S are not trapped: they propagate
+ * as NaN/Inf in the outputs.
+ */
+#ifndef PDYN_H
+#define PDYN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PDYN_OK = 0,
+  PDYN_EINVAL = -1,        /* null required pointer, non-positive size, inconsistent sizes */
+  PDYN_EALIGN = -2,        /* a pointer not aligned to its element size (workspace: 256 B) */
+  PDYN_EWORKSPACE = -3,    /* workspace smaller than pdyn_workspace_bytes() */
+  PDYN_ELAUNCH = -4,       /* the HIP runtime reported an error when queueing a kernel */
+  PDYN_EUNSUPPORTED = -5   /* a size beyond the library's limits (see pdyn_max_links) */
+};
+
+/*
+ * A set of serial chains (the robot model), CSR over links.
+ *
+ * n_chains == 1: one chain of n_links_max links, shared by every state.
+ * n_chains  > 1: one chain per state (n_chains must equal the batch's
+ *                n_states); chain c owns links link_ptr[c] .. link_ptr[c+1]-1.
+ *
+ * Per-link arrays, scalar = float for the plain entry points and double for
+ * the _f64 ones, row-major, L = total link count:
+ *   placement [L][7]  M_i: unit quaternion (w, x, y, z) of the rotation
+ *                     (normalised by the library), then the translation.
+ *   twist     [L][6]  S_i = (v, w) in frame i, w != 0 (revolute or helical
+ *                     joint; the exponential is exact for any |w| > 0).
+ *   inertia   [L][10] m, c_x, c_y, c_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz:
+ *                     mass, centre of mass in frame i, and the rotational
+ *                     inertia about the centre of mass in frame-i axes.
+ */
+typedef struct pdyn_model {
+  int32_t n_chains;
+  int32_t n_links_max;      /* host: links of the longest chain (the only chain if n_chains == 1) */
+  int64_t n_links_total;    /* host: L */
+  const int32_t* link_ptr;  /* [n_chains + 1], link_ptr[0] = 0; may be NULL when n_chains == 1 */
+  const void* placement;
+  const void* twist;
+  const void* inertia;
+  /* Derived per-link tables filled by pdyn_model_prepare for this model and
+   * scalar type, or NULL: then every call derives them again inside its
+   * workspace (one extra small kernel per call). */
+  const void* prepared;
+} pdyn_model;
+
+/*
+ * A batch of states. n_states == 0 is a valid empty batch (the call returns
+ * PDYN_OK and queues nothing) when the chain is shared.
+ *
+ * Joint arrays (q, qd, qdd, tau and their adjoints): with a shared chain,
+ * [n_states][n] row-major; with one chain per state, ragged: state s owns
+ * entries link_ptr[s] .. link_ptr[s+1]-1.
+ *
+ * base_vel, base_acc (host): V_0 and dV_0 of eqs. (3)-(4), uniform over the
+ * batch. A uniform gravity field g enters as dV_0 = (-g, 0), e.g.
+ * (0, 0, 9.81, 0, 0, 0) for gravity -9.81 z.
+ * tip_wrench: F_{n+1} of eqs. (2)-(4) per state, [n_states][6], expressed in
+ * the frame of the last link (the wrench the last link exerts on its
+ * environment), or NULL for zero.
+ */
+typedef struct pdyn_batch {
+  int32_t n_states;
+  double base_vel[6];
+  double base_acc[6];
+  const void* tip_wrench;
+} pdyn_batch;
+
+/* Operation selector for pdyn_workspace_bytes. */
+enum {
+  PDYN_OP_RNEA_ID = 0,
+  PDYN_OP_ABA_FD = 1,
+  PDYN_OP_ID_FD = 2,
+  PDYN_OP_RNEA_ID_VJP = 3,
+  PDYN_OP_ABA_FD_VJP = 4
+};
+
+/* Bytes of device workspace that operation op needs for this model and batch
+ * with the given scalar size (4 or 8); 0 on invalid arguments. It includes
+ * room for the derived tables unless model->prepared is set. The workspace
+ * must be 256-byte aligned; its contents on entry are ignored. */
+size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes);
+
+/* Bytes of the derived per-link tables of a model (scalar_bytes 4 or 8); 0 on
+ * invalid arguments. */
+size_t pdyn_model_prepared_bytes(const pdyn_model* model, int scalar_bytes);
+
+/* Derive the per-link tables (rotation of each placement, twist norms, first
+ * moments and inertias about the joint frame) into `prepared` (device, 256-byte
+ * aligned, pdyn_model_prepared_bytes long), asynchronously on `stream`. The
+ * model's own `prepared` field is ignored. Valid until the model's arrays
+ * change. */
+int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared, size_t prepared_bytes,
+                       void* stream);
+
+/* Longest chain the kernels accept. */
+int pdyn_max_links(void);
+
+/* Human-readable text for a status code (static storage). */
+const char* pdyn_strerror(int status);
+
+/*
+ * Inverse dynamics, eq. (3): tau = ID(q, qd, qdd, V_0, dV_0, F_{n+1}) by the
+ * recursive Newton-Euler recursions (1)-(2): link transforms, the forward
+ * velocity/acceleration scan (12)-(13), the bias wrench, the backward wrench
+ * scan (16) and tau_i = S_i^T F_i.
+ */
+int pdyn_rnea_id(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                 const float* qdd, float* tau, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_rnea_id_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                     const double* qdd, double* tau, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Forward dynamics, eq. (4): qdd = FD(q, qd, tau, V_0, dV_0, F_{n+1}) by the
+ * articulated-body recursions (Sec. II-B and III-E): the bias torques
+ * tau_bias = ID(q, qd, 0, ...) of eq. (5), the articulated-body inertia
+ * recursion (7) (run serially: it is not a linear recursion), then the
+ * backward z-hat / c-hat recursion and the forward lambda / qdd recursion of
+ * eq. (8) (the scans (18)-(19)).
+ */
+int pdyn_aba_fd(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                const float* tau, float* qdd, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_aba_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                    const double* tau, double* qdd, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Inverse and forward dynamics of the same states in one pass:
+ *   tau_out = ID(q, qd, qdd_in, ...)  and  qdd_out = FD(q, qd, tau_in, ...).
+ * The link transforms and velocities are shared between the two.
+ */
+int pdyn_id_fd(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+               const float* qdd_in, const float* tau_in, float* tau_out, float* qdd_out,
+               void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_id_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                   const double* qdd_in, const double* tau_in, double* tau_out, double* qdd_out,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDYN_H */

@@ -1,0 +1,11 @@
+"""pdyn: batched rigid-body dynamics of serial chains on MI355X (gfx950).
+
+Scan-form recursive Newton-Euler inverse dynamics and articulated-body
+forward dynamics after Yang, Wu & Pan (arXiv:1609.04493), as hand-written HIP
+kernels behind the C ABI of include/pdyn.h. This package is the thin Python
+binding; ``synth`` is the seeded input generator.
+"""
+
+from .api import (GRAVITY_ACC, Model, PdynError, Workspace, aba_fd, id_fd, lib, rnea_id)
+
+__all__ = ["GRAVITY_ACC", "Model", "PdynError", "Workspace", "aba_fd", "id_fd", "lib", "rnea_id"]

@@ -1,0 +1,238 @@
+"""Python binding of libpdyn (ctypes): argument marshalling only.
+
+Every step of the dynamics runs in the HIP kernels of libpdyn.so; PyTorch
+supplies device memory and the current stream. There is no CPU fallback: if
+the library is not built, or a call fails, an exception is raised.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdyn.so")
+
+OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP = 0, 1, 2, 3, 4
+GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
+ZERO6 = (0.0,) * 6
+
+
+class PdynError(RuntimeError):
+    pass
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int32), ("n_links_max", ctypes.c_int32), ("n_links_total", ctypes.c_int64),
+                ("link_ptr", ctypes.c_void_p), ("placement", ctypes.c_void_p), ("twist", ctypes.c_void_p),
+                ("inertia", ctypes.c_void_p), ("prepared", ctypes.c_void_p)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("base_vel", ctypes.c_double * 6), ("base_acc", ctypes.c_double * 6),
+                ("tip_wrench", ctypes.c_void_p)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+# name -> number of pointer arguments between (model, batch) and (workspace, bytes, stream)
+_ENTRY_ARITY = {
+    "pdyn_rnea_id": 4, "pdyn_aba_fd": 4, "pdyn_id_fd": 6,
+    "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 9,
+}
+
+
+def lib():
+    """Load libpdyn.so (built by paper_1609_04493_amd.build); raise if it is missing."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise PdynError(f"{LIB_PATH} is not built; run paper_1609_04493_amd.build.build() first")
+            L = ctypes.CDLL(LIB_PATH)
+            vp = ctypes.c_void_p
+            for base, k in _ENTRY_ARITY.items():
+                for name in (base, base + "_f64"):
+                    if hasattr(L, name):
+                        fn = getattr(L, name)
+                        fn.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Batch)] + [vp] * k + [vp, ctypes.c_size_t, vp]
+                        fn.restype = ctypes.c_int
+            L.pdyn_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ctypes.c_int]
+            L.pdyn_workspace_bytes.restype = ctypes.c_size_t
+            L.pdyn_strerror.argtypes = [ctypes.c_int]
+            L.pdyn_strerror.restype = ctypes.c_char_p
+            L.pdyn_max_links.restype = ctypes.c_int
+            L.pdyn_model_prepared_bytes.argtypes = [ctypes.POINTER(_Model), ctypes.c_int]
+            L.pdyn_model_prepared_bytes.restype = ctypes.c_size_t
+            L.pdyn_model_prepare.argtypes = [ctypes.POINTER(_Model), ctypes.c_int, vp, ctypes.c_size_t, vp]
+            L.pdyn_model_prepare.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise PdynError(f"{what}: {lib().pdyn_strerror(status).decode()} ({status})")
+
+
+class Model:
+    """A chain set resident on one device.
+
+    ``chains`` holds ``placement`` [L,7], ``twist`` [L,6], ``inertia`` [L,10]
+    and ``link_ptr`` [n_chains+1] (numpy or torch). With one chain it is
+    shared by every state; with several, state s uses chain s.
+    """
+
+    def __init__(self, chains, device="cuda", dtype=torch.float32, prepare=True):
+        self.device = torch.device(device)
+        self.dtype = dtype
+        t = lambda a: torch.as_tensor(np.asarray(a), dtype=dtype).contiguous().to(self.device)
+        self.placement = t(chains.placement)
+        self.twist = t(chains.twist)
+        self.inertia = t(chains.inertia)
+        lp = np.asarray(chains.link_ptr, dtype=np.int32)
+        self.n_chains = len(lp) - 1
+        self.lengths = np.diff(lp)
+        self.n_links_max = int(self.lengths.max())
+        self.n_links_total = int(lp[-1])
+        self.link_ptr_host = lp
+        self.link_ptr = torch.as_tensor(lp).to(self.device) if self.n_chains > 1 else None
+        self.prepared = None
+        if prepare:
+            self.prepare()
+
+    def c_struct(self, with_prepared=True) -> _Model:
+        prep = self.prepared if with_prepared else None
+        return _Model(self.n_chains, self.n_links_max, self.n_links_total,
+                      0 if self.link_ptr is None else self.link_ptr.data_ptr(),
+                      self.placement.data_ptr(), self.twist.data_ptr(), self.inertia.data_ptr(),
+                      0 if prep is None else prep.data_ptr())
+
+    @property
+    def scalar_bytes(self) -> int:
+        return 8 if self.dtype == torch.float64 else 4
+
+    def prepare(self):
+        """Derive the per-link tables once (pdyn_model_prepare) so calls skip that kernel."""
+        L = lib()
+        m = self.c_struct(with_prepared=False)
+        nbytes = L.pdyn_model_prepared_bytes(ctypes.byref(m), self.scalar_bytes)
+        if nbytes == 0:
+            raise PdynError("pdyn_model_prepared_bytes: invalid model")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        tab = buf[off:off + nbytes]
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(L.pdyn_model_prepare(ctypes.byref(m), self.scalar_bytes, tab.data_ptr(), nbytes, stream),
+               "pdyn_model_prepare")
+        self._prepared_buf = buf
+        self.prepared = tab
+        return self
+
+    def invalidate(self):
+        """Drop the derived tables (call after changing placement, twist or inertia in place)."""
+        self.prepared = None
+
+    def state_shape(self, n_states: int):
+        return (n_states, self.n_links_max) if self.n_chains == 1 else (self.n_links_total,)
+
+
+def _batch_struct(n_states, base_vel, base_acc, tip):
+    b = _Batch()
+    b.n_states = n_states
+    for k in range(6):
+        b.base_vel[k] = float(base_vel[k])
+        b.base_acc[k] = float(base_acc[k])
+    b.tip_wrench = 0 if tip is None else tip.data_ptr()
+    return b
+
+
+class Workspace:
+    """Reusable device scratch: grows on demand, 256-byte aligned."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        return self.buf[off:]
+
+
+_default_ws = {}
+
+
+def _workspace(device):
+    key = (str(device), threading.get_ident())
+    if key not in _default_ws:
+        _default_ws[key] = Workspace()
+    return _default_ws[key]
+
+
+def _n_states(model: Model, q: torch.Tensor) -> int:
+    if model.n_chains == 1:
+        if q.dim() != 2 or q.shape[1] != model.n_links_max:
+            raise PdynError(f"expected joint arrays [B, {model.n_links_max}], got {tuple(q.shape)}")
+        return q.shape[0]
+    if q.dim() != 1 or q.shape[0] != model.n_links_total:
+        raise PdynError(f"expected ragged joint arrays [{model.n_links_total}], got {tuple(q.shape)}")
+    return model.n_chains
+
+
+def _prep(model, arrays):
+    for a in arrays:
+        if a is None:
+            continue
+        if a.device != model.device or a.dtype != model.dtype or not a.is_contiguous():
+            raise PdynError("joint arrays must be contiguous, on the model's device, of the model's dtype")
+
+
+def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace):
+    L = lib()
+    fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
+    m = model.c_struct()
+    b = _batch_struct(n_states, base_vel, base_acc, tip)
+    scalar = model.scalar_bytes
+    nbytes = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), scalar)
+    if nbytes == 0:
+        raise PdynError(f"{name}: invalid model/batch for workspace query")
+    ws = (workspace or _workspace(model.device)).get(nbytes, model.device)
+    stream = torch.cuda.current_stream(model.device).cuda_stream
+    st = fn(ctypes.byref(m), ctypes.byref(b), *[0 if p is None else p.data_ptr() for p in ptrs],
+            ws.data_ptr(), ws.numel(), stream)
+    _check(st, name)
+
+
+def rnea_id(model: Model, q, qd, qdd, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None, workspace=None):
+    """tau = ID(q, qd, qdd, V0, dV0, F_tip) for every state (eq. (3))."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd, tip))
+    tau = torch.empty_like(q) if out is None else out
+    _call("pdyn_rnea_id", OP_RNEA_ID, model, n_states, (q, qd, qdd, tau), base_vel, base_acc, tip, workspace)
+    return tau
+
+
+def aba_fd(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None, workspace=None):
+    """qdd = FD(q, qd, tau, V0, dV0, F_tip) for every state (eq. (4))."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, tau, tip))
+    qdd = torch.empty_like(q) if out is None else out
+    _call("pdyn_aba_fd", OP_ABA_FD, model, n_states, (q, qd, tau, qdd), base_vel, base_acc, tip, workspace)
+    return qdd
+
+
+def id_fd(model: Model, q, qd, qdd_in, tau_in, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None,
+          workspace=None):
+    """(ID(q, qd, qdd_in), FD(q, qd, tau_in)) of the same states in one pass."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd_in, tau_in, tip))
+    tau_out, qdd_out = (torch.empty_like(q), torch.empty_like(q)) if out is None else out
+    _call("pdyn_id_fd", OP_ID_FD, model, n_states, (q, qd, qdd_in, tau_in, tau_out, qdd_out),
+          base_vel, base_acc, tip, workspace)
+    return tau_out, qdd_out

@@ -1,0 +1,273 @@
+// libpdyn: C-ABI entry points and HIP kernels for gfx950.
+//
+// Kernel map (one lane = one state; consecutive lanes = consecutive states):
+//   k_link_table   per link: the derived 32-word record (rotation of M_i from
+//                  its quaternion, twist norms, h = m c, I_O) -- a parallel map.
+//   k_dynamics     per state: the sweeps of sweeps.hpp (ID, FD or both).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/pdyn.h"
+#include "sweeps.hpp"
+
+namespace pdyn {
+namespace {
+
+constexpr int kMaxLinks = 1 << 16;
+constexpr int kBlock = 64;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Link records in T and in double (the double table serves the transforms of
+// the wrench recursion).
+template <class T>
+__global__ void __launch_bounds__(256) k_link_table(int64_t n_links, const T* __restrict__ placement,
+                                                    const T* __restrict__ twist, const T* __restrict__ inertia,
+                                                    T* __restrict__ table, double* __restrict__ wtable) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_links) return;
+  double rec[kLinkWords];
+  make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, rec);
+#pragma unroll
+  for (int k = 0; k < kLinkWords; ++k) {
+    table[i * kLinkWords + k] = (T)rec[k];
+    wtable[i * kLinkWords + k] = rec[k];
+  }
+}
+
+template <class T> struct BoundaryArgs {
+  T V0[6], dV0[6];
+};
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_dynamics(int n_states, int n_chains, int n_max,
+                                                     const int32_t* __restrict__ link_ptr,
+                                                     const T* __restrict__ table,
+                                                     const double* __restrict__ wtable, const T* q, const T* qd,
+                                                     const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
+                                                     const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_states) return;
+  int n;
+  int64_t link0, dof0;
+  if (n_chains == 1) {
+    n = n_max;
+    link0 = 0;
+    dof0 = (int64_t)s * n_max;
+  } else {
+    link0 = link_ptr[s];
+    n = link_ptr[s + 1] - (int)link0;
+    dof0 = link0;
+  }
+  JointIO<T> io;
+  io.q = q + dof0;
+  io.qd = qd + dof0;
+  io.qdd_in = qdd_in ? qdd_in + dof0 : nullptr;
+  io.tau_in = tau_in ? tau_in + dof0 : nullptr;
+  io.tau_out = tau_out ? tau_out + dof0 : nullptr;
+  io.qdd_out = qdd_out ? qdd_out + dof0 : nullptr;
+  Boundary<T> bd;
+  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  if (tip) {
+    const T* t = tip + 6 * (int64_t)s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  } else {
+    bd.Ftip = sp_zero<T>();
+  }
+  Scratch<T> scr{scratch + s, (long)n_states, ScratchWords<MODE>::value};
+  dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
+}
+
+// ---- host side ------------------------------------------------------------------
+
+struct Layout {
+  size_t table_off, wtable_off, scratch_off, scratch_bytes, total;
+};
+
+int scratch_words(int op) {
+  switch (op) {
+    case PDYN_OP_RNEA_ID: return ScratchWords<kModeID>::value;
+    case PDYN_OP_ABA_FD: return ScratchWords<kModeFD>::value;
+    case PDYN_OP_ID_FD: return ScratchWords<kModeIDFD>::value;
+    default: return -1;
+  }
+}
+
+int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
+  if (!m || !b) return PDYN_EINVAL;
+  if (m->n_chains < 1 || m->n_links_max < 1 || m->n_links_total < 1 || b->n_states < 0) return PDYN_EINVAL;
+  if (!m->placement || !m->twist || !m->inertia) return PDYN_EINVAL;
+  if (m->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
+  if (m->n_chains == 1) {
+    if (m->n_links_total != m->n_links_max) return PDYN_EINVAL;
+  } else {
+    if (m->n_chains != b->n_states || !m->link_ptr) return PDYN_EINVAL;
+    if (m->n_links_total > INT32_MAX) return PDYN_EUNSUPPORTED;
+  }
+  return PDYN_OK;
+}
+
+// The derived tables: [L][32] in the scalar type, then [L][32] in double.
+size_t tables_bytes(const pdyn_model* m, size_t scalar, size_t* wtable_off) {
+  size_t t = align_up((size_t)m->n_links_total * kLinkWords * scalar);
+  if (wtable_off) *wtable_off = t;
+  return t + align_up((size_t)m->n_links_total * kLinkWords * sizeof(double));
+}
+
+int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, Layout* L) {
+  int words = scratch_words(op);
+  if (words < 0) return PDYN_EINVAL;
+  size_t woff;
+  size_t tb = tables_bytes(m, scalar, &woff);
+  L->table_off = 0;
+  L->wtable_off = woff;
+  L->scratch_off = m->prepared ? 0 : tb;
+  L->scratch_bytes = align_up((size_t)m->n_links_max * (size_t)words * (size_t)b->n_states * scalar);
+  L->total = L->scratch_off + L->scratch_bytes;
+  if (L->total < kAlign) L->total = kAlign;
+  return PDYN_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+template <class T>
+int check_ptrs(std::initializer_list<const void*> ptrs) {
+  for (const void* p : ptrs)
+    if (!p) return PDYN_EINVAL;
+  for (const void* p : ptrs)
+    if (!aligned(p, sizeof(T))) return PDYN_EALIGN;
+  return PDYN_OK;
+}
+
+template <class T>
+int launch_link_table(const pdyn_model* m, char* dst, hipStream_t s) {
+  size_t woff;
+  tables_bytes(m, sizeof(T), &woff);
+  int64_t nl = m->n_links_total;
+  unsigned grid = (unsigned)((nl + 255) / 256);
+  hipLaunchKernelGGL(k_link_table<T>, dim3(grid), dim3(256), 0, s, nl, static_cast<const T*>(m->placement),
+                     static_cast<const T*>(m->twist), static_cast<const T*>(m->inertia),
+                     reinterpret_cast<T*>(dst), reinterpret_cast<double*>(dst + woff));
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+template <class T, int MODE>
+int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* qdd_in,
+                 const T* tau_in, T* tau_out, T* qdd_out, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (b->n_states == 0) return PDYN_OK;  // empty batch: nothing to do
+  if (MODE & kModeID) {
+    if ((st = check_ptrs<T>({q, qd, qdd_in, tau_out}))) return st;
+  }
+  if (MODE & kModeFD) {
+    if ((st = check_ptrs<T>({q, qd, tau_in, qdd_out}))) return st;
+  }
+  if ((st = check_ptrs<T>({m->placement, m->twist, m->inertia}))) return st;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  Layout L;
+  if ((st = layout_for(op, m, b, sizeof(T), &L))) return st;
+  if (ws_bytes < L.total) return PDYN_EWORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
+  const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
+  if (!m->prepared) {
+    if ((st = launch_link_table<T>(m, base, s))) return st;
+  }
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,
+                     m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                     static_cast<const T*>(b->tip_wrench), ba, scratch);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+}  // namespace
+}  // namespace pdyn
+
+using namespace pdyn;
+
+extern "C" {
+
+size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
+  if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
+  if (check_model_batch(model, batch)) return 0;
+  Layout L;
+  if (layout_for(op, model, batch, (size_t)scalar_bytes, &L)) return 0;
+  return L.total;
+}
+
+size_t pdyn_model_prepared_bytes(const pdyn_model* model, int scalar_bytes) {
+  if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
+  if (!model || model->n_chains < 1 || model->n_links_total < 1) return 0;
+  return tables_bytes(model, (size_t)scalar_bytes, nullptr);
+}
+
+int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared, size_t prepared_bytes,
+                       void* stream) {
+  if (scalar_bytes != 4 && scalar_bytes != 8) return PDYN_EINVAL;
+  if (!model || model->n_chains < 1 || model->n_links_total < 1 || !prepared) return PDYN_EINVAL;
+  if (!model->placement || !model->twist || !model->inertia) return PDYN_EINVAL;
+  if (!aligned(prepared, kAlign)) return PDYN_EALIGN;
+  size_t a = (size_t)scalar_bytes;
+  if (!aligned(model->placement, a) || !aligned(model->twist, a) || !aligned(model->inertia, a)) return PDYN_EALIGN;
+  if (prepared_bytes < tables_bytes(model, a, nullptr)) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (scalar_bytes == 4) return launch_link_table<float>(model, static_cast<char*>(prepared), s);
+  return launch_link_table<double>(model, static_cast<char*>(prepared), s);
+}
+
+int pdyn_max_links(void) { return kMaxLinks; }
+
+const char* pdyn_strerror(int status) {
+  switch (status) {
+    case PDYN_OK: return "success";
+    case PDYN_EINVAL: return "invalid argument";
+    case PDYN_EALIGN: return "misaligned pointer";
+    case PDYN_EWORKSPACE: return "workspace too small";
+    case PDYN_ELAUNCH: return "kernel launch failed";
+    case PDYN_EUNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+int pdyn_rnea_id(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* qdd,
+                 float* tau, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<float, kModeID>(PDYN_OP_RNEA_ID, m, b, q, qd, qdd, nullptr, tau, nullptr, ws, ws_bytes, stream);
+}
+int pdyn_rnea_id_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd,
+                     double* tau, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<double, kModeID>(PDYN_OP_RNEA_ID, m, b, q, qd, qdd, nullptr, tau, nullptr, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* tau,
+                float* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<float, kModeFD>(PDYN_OP_ABA_FD, m, b, q, qd, nullptr, tau, nullptr, qdd, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* tau,
+                    double* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<double, kModeFD>(PDYN_OP_ABA_FD, m, b, q, qd, nullptr, tau, nullptr, qdd, ws, ws_bytes, stream);
+}
+int pdyn_id_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* qdd_in,
+               const float* tau_in, float* tau_out, float* qdd_out, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<float, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd_in,
+                   const double* tau_in, double* tau_out, double* qdd_out, void* ws, size_t ws_bytes, void* stream) {
+  return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Per-state recursions of the inverse and forward dynamics, as three sweeps
+// over the links of one chain. One GPU lane runs them for one state; the CPU
+// test build runs the very same functions on the host.
+//
+// Sweep 1 (base to tip): link transforms f_{i-1,i} = M_i exp(S_i q_i),
+//   velocities and accelerations (eq. (1); the scan (12)-(13) evaluated as a
+//   left fold) and the bias wrenches Fhat_i = J_i dV_i - ad^T_{V_i}(J_i V_i).
+// Sweep 2 (tip to base): the wrench recursion F_i = X_{i+1}^T F_{i+1} + Fhat_i
+//   and tau_i = S_i^T F_i (eq. (2), the scan (16)); for forward dynamics also
+//   the articulated-body inertia (7), which is not a linear recursion and is
+//   run serially, and the z-hat / c-hat recursion of (8) (the scan (18)), all
+//   in the same pass because all three run from the tip.
+// Sweep 3 (base to tip): lambda and qdd of (8) (the scan (19)).
+//
+// Per-link intermediates that a later sweep needs go to a scratch array laid
+// out [link][component][state], so that consecutive lanes (states) touch
+// consecutive words.
+//
+// Precision: the bulk arithmetic (transforms of sweeps 1 and 3, velocities,
+// accelerations, bias wrenches, articulated-body inertias, lambda) runs in the
+// scalar type T. The two force-like accumulations of sweep 2 that carry loads
+// through every link transform -- the wrench F_i = X^T F_{i+1} + Fhat_i and the
+// articulated bias force z-hat -- always run in double, with that sweep's
+// transforms built in double: forward dynamics multiplies their errors by M^-1
+// (condition number ~1e4-1e5 at 32 links), and in single precision they alone
+// push the relative qdd error past 1e-4. The sine and cosine stay in T and are
+// renormalised in double, so the double transform is an exact rigid motion.
+#pragma once
+
+#include "spatial.hpp"
+
+namespace pdyn {
+
+// Words per record of the derived link table (see make_link_record).
+constexpr int kLinkWords = 32;
+
+PD_HD void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+PD_HD void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+
+// Derived per-link constants, computed once per call in precision T from the
+// user's (quaternion, translation), twist and inertia parameters:
+//   [0..8] R of M_i, [9..11] p of M_i, [12..14] v, [15..17] w of S_i,
+//   [18] k = |w|, [19] 1/k, [20] 1/k^2, [21] (w.v)/k^3,
+//   [22] m, [23..25] h = m c, [26..31] I_O = I_c - m [c][c] as (xx, yy, zz, xy, xz, yz).
+template <class T, class In>
+PD_HD void make_link_record(const In* pl_in, const In* tw_in, const In* in_in, T* rec) {
+  T pl[7], tw[6], in[10];
+  for (int k = 0; k < 7; ++k) pl[k] = (T)pl_in[k];
+  for (int k = 0; k < 6; ++k) tw[k] = (T)tw_in[k];
+  for (int k = 0; k < 10; ++k) in[k] = (T)in_in[k];
+  T qw = pl[0], qx = pl[1], qy = pl[2], qz = pl[3];
+  T inv = T(1) / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+  rec[0] = T(1) - T(2) * (qy * qy + qz * qz); rec[1] = T(2) * (qx * qy - qw * qz); rec[2] = T(2) * (qx * qz + qw * qy);
+  rec[3] = T(2) * (qx * qy + qw * qz); rec[4] = T(1) - T(2) * (qx * qx + qz * qz); rec[5] = T(2) * (qy * qz - qw * qx);
+  rec[6] = T(2) * (qx * qz - qw * qy); rec[7] = T(2) * (qy * qz + qw * qx); rec[8] = T(1) - T(2) * (qx * qx + qy * qy);
+  rec[9] = pl[4]; rec[10] = pl[5]; rec[11] = pl[6];
+  for (int k = 0; k < 6; ++k) rec[12 + k] = tw[k];
+  T k2 = tw[3] * tw[3] + tw[4] * tw[4] + tw[5] * tw[5];
+  T k = sqrt(k2);
+  rec[18] = k;
+  rec[19] = T(1) / k;
+  rec[20] = T(1) / k2;
+  rec[21] = (tw[0] * tw[3] + tw[1] * tw[4] + tw[2] * tw[5]) / (k2 * k);
+  T m = in[0], cx = in[1], cy = in[2], cz = in[3];
+  rec[22] = m;
+  rec[23] = m * cx; rec[24] = m * cy; rec[25] = m * cz;
+  // I_O = I_c - m [c][c] = I_c + m (|c|^2 I - c c^T)
+  T c2 = cx * cx + cy * cy + cz * cz;
+  rec[26] = in[4] + m * (c2 - cx * cx);
+  rec[27] = in[5] + m * (c2 - cy * cy);
+  rec[28] = in[6] + m * (c2 - cz * cz);
+  rec[29] = in[7] - m * cx * cy;
+  rec[30] = in[8] - m * cx * cz;
+  rec[31] = in[9] - m * cy * cz;
+}
+
+template <class T> struct Link {
+  M3<T> RM;
+  V3<T> pM;
+  Sp<T> S;
+  T k, ik, ik2, pc;
+  Inertia<T> J;
+};
+
+template <class T, class U> PD_HD Sp<T> cast_sp(const Sp<U>& x) {
+  return {v3((T)x.a.x, (T)x.a.y, (T)x.a.z), v3((T)x.b.x, (T)x.b.y, (T)x.b.z)};
+}
+template <class T, class U> PD_HD Pose<T> cast_pose(const Pose<U>& g) {
+  Pose<T> r;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.R.m[k] = (T)g.R.m[k];
+  r.p = v3((T)g.p.x, (T)g.p.y, (T)g.p.z);
+  return r;
+}
+
+template <class T> PD_HD Link<T> load_link(const T* rec) {
+  Link<T> L;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) L.RM.m[k] = rec[k];
+  L.pM = v3(rec[9], rec[10], rec[11]);
+  L.S = {v3(rec[12], rec[13], rec[14]), v3(rec[15], rec[16], rec[17])};
+  L.k = rec[18]; L.ik = rec[19]; L.ik2 = rec[20]; L.pc = rec[21];
+  L.J.m = rec[22];
+  L.J.h = v3(rec[23], rec[24], rec[25]);
+  L.J.Io = {rec[26], rec[27], rec[28], rec[29], rec[30], rec[31]};
+  return L;
+}
+
+// f_{i-1,i} = M_i exp(S_i q_i). With theta = k q, a = sin(theta)/k,
+// b = (1 - cos theta)/k^2 and e = (theta - sin theta)(w.v)/k^3, the matrix
+// exponential of the twist is R_e = cos(theta) I + a [w] + b w w^T,
+// p_e = a v + b (w x v) + e w.
+template <class T> PD_HD Pose<T> joint_transform(const Link<T>& L, T q) {
+  T th = L.k * q;
+  T s, c;
+  sin_cos(th, &s, &c);
+  T a = s * L.ik;
+  T b = (T(1) - c) * L.ik2;
+  T e = (th - s) * L.pc;
+  const V3<T> w = L.S.b, v = L.S.a;
+  M3<T> Re = {{c + b * w.x * w.x, -a * w.z + b * w.x * w.y, a * w.y + b * w.x * w.z,
+               a * w.z + b * w.x * w.y, c + b * w.y * w.y, -a * w.x + b * w.y * w.z,
+               -a * w.y + b * w.x * w.z, a * w.x + b * w.y * w.z, c + b * w.z * w.z}};
+  V3<T> pe = a * v + b * cross(w, v) + e * w;
+  Pose<T> g;
+  g.R = mul(L.RM, Re);
+  g.p = mul(L.RM, pe) + L.pM;
+  return g;
+}
+
+// f_{i-1,i} in double from a double-precision link record, with sin and cos
+// of k q taken in T and renormalised (s^2 + c^2 = 1 - d with |d| ~ 1e-7, so one
+// first-order step r = 1.5 - 0.5 (s^2 + c^2) is exact to ~1e-14).
+template <class T> PD_HD Pose<double> joint_transform_wide(const Link<double>& L, T q) {
+  const double th = L.k * (double)q;
+  T sT, cT;
+  sin_cos((T)th, &sT, &cT);
+  double s = sT, c = cT;
+  const double r = 1.5 - 0.5 * (s * s + c * c);
+  s *= r;
+  c *= r;
+  const double a = s * L.ik;
+  const double b = (1.0 - c) * L.ik2;
+  const double e = (th - s) * L.pc;
+  const V3<double> w = L.S.b, v = L.S.a;
+  M3<double> Re = {{c + b * w.x * w.x, -a * w.z + b * w.x * w.y, a * w.y + b * w.x * w.z,
+                    a * w.z + b * w.x * w.y, c + b * w.y * w.y, -a * w.x + b * w.y * w.z,
+                    -a * w.y + b * w.x * w.z, a * w.x + b * w.y * w.z, c + b * w.z * w.z}};
+  V3<double> pe = a * v + b * cross(w, v) + e * w;
+  Pose<double> g;
+  g.R = mul(L.RM, Re);
+  g.p = mul(L.RM, pe) + L.pM;
+  return g;
+}
+
+// Which outputs a pass produces.
+enum : int { kModeID = 1, kModeFD = 2, kModeIDFD = 3 };
+
+template <int MODE> struct ScratchWords {
+  // sweep 1 writes Fhat (ID) and/or Fhat_bias (FD); sweep 2 overwrites link i's
+  // slot with U_i (6), 1/D_i and c-hat_i for sweep 3.
+  static constexpr int value = (MODE == kModeIDFD) ? 12 : (MODE == kModeFD ? 8 : 6);
+};
+
+// Strided view of the per-link scratch of one state.
+template <class T> struct Scratch {
+  T* base;        // &scratch[0][0][state]
+  long stride;    // number of states
+  int words;      // components per link
+  PD_HD T& at(int link, int comp) const { return base[((long)link * words + comp) * stride]; }
+  PD_HD void put(int link, int comp, const Sp<T>& x) const {
+    at(link, comp + 0) = x.a.x; at(link, comp + 1) = x.a.y; at(link, comp + 2) = x.a.z;
+    at(link, comp + 3) = x.b.x; at(link, comp + 4) = x.b.y; at(link, comp + 5) = x.b.z;
+  }
+  PD_HD Sp<T> get(int link, int comp) const {
+    return {v3(at(link, comp + 0), at(link, comp + 1), at(link, comp + 2)),
+            v3(at(link, comp + 3), at(link, comp + 4), at(link, comp + 5))};
+  }
+};
+
+// Joint arrays of one state (element i of the chain at ptr[i]).
+template <class T> struct JointIO {
+  const T* q;
+  const T* qd;
+  const T* qdd_in;   // ID input accelerations (kModeID)
+  const T* tau_in;   // FD input torques (kModeFD)
+  T* tau_out;        // ID output
+  T* qdd_out;        // FD output
+};
+
+template <class T> struct Boundary {
+  Sp<T> V0, dV0, Ftip;
+};
+
+// The three sweeps for one state of an n-link chain whose link records start at
+// `table` (scalar T) and `wtable` (the same records in double). MODE selects ID
+// (tau_out), FD (qdd_out) or both.
+template <class T, int MODE>
+PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
+                              const Boundary<T>& bd, const Scratch<T>& scr) {
+  constexpr bool kID = (MODE & kModeID) != 0;
+  constexpr bool kFD = (MODE & kModeFD) != 0;
+  constexpr int kOffB = kID ? 6 : 0;  // scratch offset of the bias wrench
+
+  // ---- sweep 1: base to tip
+  {
+    Sp<T> V = bd.V0, dV = bd.dV0, dVb = bd.dV0;
+    for (int i = 0; i < n; ++i) {
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Pose<T> g = joint_transform(L, io.q[i]);
+      const Sp<T> XV = X_twist(g, V);
+      const Sp<T> Sqd = io.qd[i] * L.S;
+      V = XV + Sqd;
+      const Sp<T> cor = ad_twist(Sqd, XV);            // ad_{S qd} X V_{i-1}
+      const Sp<T> gyro = adT_wrench(V, mul(L.J, V));  // ad^T_V (J V)
+      if (kID) {
+        dV = X_twist(g, dV) + io.qdd_in[i] * L.S - cor;
+        scr.put(i, 0, mul(L.J, dV) - gyro);
+      }
+      if (kFD) {
+        dVb = X_twist(g, dVb) - cor;
+        scr.put(i, kOffB, mul(L.J, dVb) - gyro);
+      }
+    }
+  }
+
+  // ---- sweep 2: tip to base
+  {
+    Sp<double> F = cast_sp<double>(bd.Ftip), Fb = F;
+    Sp<double> zA = sp_zero<double>();  // z-hat_{i+1} + U_{i+1} c-hat_{i+1}
+    Sym6<T> JA;
+    Pose<double> gcw;  // f_{i,i+1} of the child link, double
+    Pose<T> gc;        // the same, rounded to T
+    for (int i = n - 1; i >= 0; --i) {
+      const bool has_child = (i < n - 1);
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+      if (kID) {
+        Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
+        F = Fc + cast_sp<double>(scr.get(i, 0));
+        io.tau_out[i] = (T)dot(Lw.S, F);
+      }
+      if (kFD) {
+        Sp<double> Fc = has_child ? XT_wrench(gcw, Fb) : Fb;
+        Fb = Fc + cast_sp<double>(scr.get(i, kOffB));
+        const double tauhat = (double)io.tau_in[i] - dot(Lw.S, Fb);
+        // articulated-body inertia, eq. (7): Jhat_i = J_i + X^T (Jhat_{i+1} - U U^T / D) X
+        Sym6<T> Jh = sym6_from_inertia(L.J);
+        Sp<double> z = sp_zero<double>();
+        if (has_child) {
+          const Sym6<T> P = congruence_to_parent(gc, JA);
+          Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+          Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+          Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+          Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+          // z-hat_i = X^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}), eq. (8) with Y, Pi expanded
+          z = XT_wrench(gcw, zA);
+        }
+        const Sp<T> U = mul(Jh, L.S);
+        const T invD = T(1) / dot(L.S, U);
+        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
+        const T chat = (T)chat_w;
+        JA = sym6_minus_outer(Jh, U, invD);
+        zA = z + chat_w * cast_sp<double>(U);
+        scr.put(i, 0, U);
+        scr.at(i, 6) = invD;
+        scr.at(i, 7) = chat;
+      }
+      gcw = joint_transform_wide(Lw, io.q[i]);
+      gc = cast_pose<T>(gcw);
+    }
+  }
+
+  // ---- sweep 3: base to tip
+  if (kFD) {
+    Sp<T> lam = sp_zero<T>();
+    for (int i = 0; i < n; ++i) {
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Pose<T> g = joint_transform(L, io.q[i]);
+      const Sp<T> U = scr.get(i, 0);
+      const T invD = scr.at(i, 6), chat = scr.at(i, 7);
+      const Sp<T> a = X_twist(g, lam);
+      const T qdd = chat - dot(U, a) * invD;
+      lam = a + qdd * L.S;
+      io.qdd_out[i] = qdd;
+    }
+  }
+}
+
+}  // namespace pdyn

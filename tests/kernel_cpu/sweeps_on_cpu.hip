@@ -1,0 +1,56 @@
+// Host-only build of the GPU path's per-state sweeps (paper_1609_04493_amd/csrc/sweeps.hpp),
+// used by CPU tests to check the kernels' arithmetic against the oracle without a GPU.
+// Same layouts and scratch indexing as the kernel k_dynamics, one state at a time.
+#include <cstdint>
+#include <vector>
+
+#include "../../paper_1609_04493_amd/csrc/sweeps.hpp"
+
+using namespace pdyn;
+
+template <class T>
+static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
+               const T* twist, const T* inertia, const T* q, const T* qd, const T* qdd_in, const T* tau_in,
+               T* tau_out, T* qdd_out, const T* tip, const T* V0, const T* dV0) {
+  int64_t L = (n_chains == 1) ? n_max : link_ptr[n_chains];
+  std::vector<T> table((size_t)L * kLinkWords);
+  std::vector<double> wtable((size_t)L * kLinkWords);
+  for (int64_t i = 0; i < L; ++i) {
+    make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, &wtable[i * kLinkWords]);
+    for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
+  }
+  int words = mode == kModeIDFD ? ScratchWords<kModeIDFD>::value : (mode == kModeFD ? ScratchWords<kModeFD>::value : ScratchWords<kModeID>::value);
+  std::vector<T> scratch((size_t)n_max * words * n_states, T(-7777));  // poisoned
+  Boundary<T> bd;
+  bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
+  bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
+  for (int s = 0; s < n_states; ++s) {
+    int n;
+    int64_t link0, dof0;
+    if (n_chains == 1) { n = n_max; link0 = 0; dof0 = (int64_t)s * n_max; }
+    else { link0 = link_ptr[s]; n = link_ptr[s + 1] - (int)link0; dof0 = link0; }
+    JointIO<T> io{q + dof0, qd + dof0, qdd_in ? qdd_in + dof0 : nullptr, tau_in ? tau_in + dof0 : nullptr,
+                  tau_out ? tau_out + dof0 : nullptr, qdd_out ? qdd_out + dof0 : nullptr};
+    bd.Ftip = tip ? Sp<T>{v3(tip[6 * s], tip[6 * s + 1], tip[6 * s + 2]), v3(tip[6 * s + 3], tip[6 * s + 4], tip[6 * s + 5])} : sp_zero<T>();
+    Scratch<T> scr{scratch.data() + s, (long)n_states, words};
+    if (mode == kModeID) dynamics_one_state<T, kModeID>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);
+    else if (mode == kModeFD) dynamics_one_state<T, kModeFD>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);
+    else dynamics_one_state<T, kModeIDFD>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);
+  }
+  return 0;
+}
+
+extern "C" {
+int cpu_dynamics_f32(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const float* pl,
+                     const float* tw, const float* in, const float* q, const float* qd, const float* qdd_in,
+                     const float* tau_in, float* tau_out, float* qdd_out, const float* tip, const float* V0,
+                     const float* dV0) {
+  return run<float>(mode, n_states, n_chains, n_max, link_ptr, pl, tw, in, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, V0, dV0);
+}
+int cpu_dynamics_f64(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const double* pl,
+                     const double* tw, const double* in, const double* q, const double* qd, const double* qdd_in,
+                     const double* tau_in, double* tau_out, double* qdd_out, const double* tip, const double* V0,
+                     const double* dV0) {
+  return run<double>(mode, n_states, n_chains, n_max, link_ptr, pl, tw, in, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, V0, dV0);
+}
+}
