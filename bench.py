@@ -124,6 +124,26 @@ def main():
     ms_id = time_steps(lambda: api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws), args.steps, args.warmup, stream)
     ms_fd = time_steps(lambda: api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws), args.steps, args.warmup, stream)
 
+    # with gradients: ID + FD forward, then the ID adjoint (cotangent tau_bar) and the FD
+    # adjoint of L = ||qdd||^2 (cotangent 2 qdd), inertia-parameter gradients included
+    tau_bar = torch.as_tensor(np.random.default_rng(2).standard_normal((N_STATES, N_LINKS)), dtype=torch.float32).to(dev)
+    qdd_bar = torch.empty_like(q)
+    gid = tuple(torch.empty_like(q) for _ in range(3)) + (torch.empty((N_LINKS, 10), device=dev),)
+    gfd = tuple(torch.empty_like(q) for _ in range(3)) + (torch.empty((N_LINKS, 10), device=dev),)
+
+    def with_grad():
+        api.id_fd(model, q, qd, qdd, tau, out=(tau_out, qdd_out), workspace=ws)
+        api.rnea_id_vjp(model, q, qd, qdd, tau_bar, out=gid, workspace=ws)
+        torch.mul(qdd_out, 2.0, out=qdd_bar)
+        api.aba_fd_vjp(model, q, qd, qdd_out, qdd_bar, out=gfd, workspace=ws)
+
+    ms_grad = time_steps(with_grad, args.steps, args.warmup, stream)
+    print(f"ID+FD with both adjoints: {ms_grad * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    ms_idv = time_steps(lambda: api.rnea_id_vjp(model, q, qd, qdd, tau_bar, out=gid, workspace=ws), args.steps,
+                        args.warmup, stream)
+    ms_fdv = time_steps(lambda: api.aba_fd_vjp(model, q, qd, qdd_out, qdd_bar, out=gfd, workspace=ws), args.steps,
+                        args.warmup, stream)
+
     # stated error: the fused outputs against the FP64 oracle on a sample of states
     import oracle
     fused()
@@ -133,6 +153,22 @@ def main():
     thr = len(os.sched_getaffinity(0))
     et = rel_rows(tau_out.cpu().numpy()[idx], oracle.rnea(cr, sr.q[idx], sr.qd[idx], sr.qdd[idx], threads=thr))
     eq = rel_rows(qdd_out.cpu().numpy()[idx], oracle.aba(cr, sr.q[idx], sr.qd[idx], sr.tau[idx], threads=thr))
+
+    # gradient errors on a few sampled states (oracle complex-step vector-Jacobian products)
+    from oracle import grad as ograd
+    with_grad()
+    torch.cuda.synchronize()
+    gidx = idx[:4]
+    tb_np = tau_bar.cpu().numpy().astype(np.float64)
+    qb_np = qdd_bar.cpu().numpy().astype(np.float64)
+    gerr = {k: 0.0 for k in ("id_q", "id_qd", "id_qdd", "fd_q", "fd_qd", "fd_tau")}
+    for s in gidx:
+        r = ograd.rnea_vjp(cr, sr.q[s], sr.qd[s], sr.qdd[s], tb_np[s])
+        for k, x, y in zip(("id_q", "id_qd", "id_qdd"), gid[:3], r[:3]):
+            gerr[k] = max(gerr[k], float(np.linalg.norm(x[s].cpu().numpy() - y) / np.linalg.norm(y)))
+        r = ograd.aba_vjp(cr, sr.q[s], sr.qd[s], sr.tau[s], qb_np[s])
+        for k, x, y in zip(("fd_q", "fd_qd", "fd_tau"), gfd[:3], r[:3]):
+            gerr[k] = max(gerr[k], float(np.linalg.norm(x[s].cpu().numpy() - y) / np.linalg.norm(y)))
 
     links = N_LINKS * N_STATES
     achieved = FLOPS_PER_LINK["id_fd"] * links / (ms_fused * 1e-3)
@@ -158,7 +194,11 @@ def main():
                      "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
         "plain": {"form": "separate pdyn_rnea_id + pdyn_aba_fd calls", "value": N_STATES / (ms_plain * 1e-3),
                   "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
-        "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3)},
+        "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),
+                               "id_vjp": N_STATES / (ms_idv * 1e-3), "fd_vjp": N_STATES / (ms_fdv * 1e-3)},
+        "grad": {"form": "fused ID+FD, then pdyn_rnea_id_vjp and pdyn_aba_fd_vjp (L = ||qdd||^2), inertia gradients on",
+                 "value": N_STATES / (ms_grad * 1e-3), "unit": "evals/s", "ms_per_step": ms_grad,
+                 "max_rel_err_vs_oracle_4_states": gerr},
         "error_vs_fp64_oracle": {"sample_states": len(idx), "tau": err_stats(et), "qdd": err_stats(eq),
                                  "metric": "per-state ||x - x*|| / ||x*||"},
     }

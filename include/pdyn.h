@@ -163,6 +163,40 @@ int pdyn_id_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const doubl
                    const double* qdd_in, const double* tau_in, double* tau_out, double* qdd_out,
                    void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Adjoint of the inverse dynamics (vector-Jacobian product). Gradients of the
+ * dynamics are the paper's stated future work (Sec. VI); this is reverse-mode
+ * differentiation of the recursions (1)-(2):
+ *   (q_bar, qd_bar, qdd_bar, inertia_bar) = (d tau / d(q, qd, qdd, pi))^T tau_bar
+ * at tau = ID(q, qd, qdd, V_0, dV_0, F_{n+1}). V_0, dV_0, F_{n+1} and the
+ * joint geometry are held constant. inertia_bar is [n][10] summed over the
+ * states for a shared chain, [L][10] (one row per link) with one chain per
+ * state, in the order of the model's inertia parameters; pass NULL to skip it.
+ * The sum over states is deterministic (fixed reduction order).
+ */
+int pdyn_rnea_id_vjp(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                     const float* qdd, const float* tau_bar, float* q_bar, float* qd_bar, float* qdd_bar,
+                     float* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_rnea_id_vjp_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                         const double* qdd, const double* tau_bar, double* q_bar, double* qd_bar, double* qdd_bar,
+                         double* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Adjoint of the forward dynamics at the solution qdd = FD(q, qd, tau, ...)
+ * (pass the forward output as `qdd`). Since ID(q, qd, FD(q, qd, tau)) = tau
+ * (eq. (5)), with u = M(q)^-1 qdd_bar:
+ *   tau_bar = u,   (q_bar, qd_bar, inertia_bar) = -(d tau/d(q, qd, pi))^T u,
+ * the derivative of ID taken at (q, qd, qdd). u is computed by the
+ * articulated-body recursions of eq. (8) with tau-hat := qdd_bar; inertia_bar
+ * as for pdyn_rnea_id_vjp (NULL to skip).
+ */
+int pdyn_aba_fd_vjp(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                    const float* qdd, const float* qdd_bar, float* q_bar, float* qd_bar, float* tau_bar,
+                    float* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_aba_fd_vjp_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                        const double* qdd, const double* qdd_bar, double* q_bar, double* qd_bar, double* tau_bar,
+                        double* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

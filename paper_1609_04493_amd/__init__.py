@@ -6,6 +6,9 @@ kernels behind the C ABI of include/pdyn.h. This package is the thin Python
 binding; ``synth`` is the seeded input generator.
 """
 
-from .api import (GRAVITY_ACC, Model, PdynError, Workspace, aba_fd, id_fd, lib, rnea_id)
+from .api import (GRAVITY_ACC, Model, PdynError, Workspace, aba_fd, aba_fd_vjp, id_fd, lib, rnea_id,
+                  rnea_id_vjp)
+from .autograd import forward_dynamics, inverse_dynamics
 
-__all__ = ["GRAVITY_ACC", "Model", "PdynError", "Workspace", "aba_fd", "id_fd", "lib", "rnea_id"]
+__all__ = ["GRAVITY_ACC", "Model", "PdynError", "Workspace", "aba_fd", "aba_fd_vjp", "forward_dynamics", "id_fd",
+           "inverse_dynamics", "lib", "rnea_id", "rnea_id_vjp"]

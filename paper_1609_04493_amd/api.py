@@ -43,7 +43,7 @@ _lib_lock = threading.Lock()
 # name -> number of pointer arguments between (model, batch) and (workspace, bytes, stream)
 _ENTRY_ARITY = {
     "pdyn_rnea_id": 4, "pdyn_aba_fd": 4, "pdyn_id_fd": 6,
-    "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 9,
+    "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 8,
 }
 
 
@@ -236,3 +236,36 @@ def id_fd(model: Model, q, qd, qdd_in, tau_in, base_vel=ZERO6, base_acc=GRAVITY_
     _call("pdyn_id_fd", OP_ID_FD, model, n_states, (q, qd, qdd_in, tau_in, tau_out, qdd_out),
           base_vel, base_acc, tip, workspace)
     return tau_out, qdd_out
+
+
+def _inertia_bar_like(model):
+    n = model.n_links_max if model.n_chains == 1 else model.n_links_total
+    return torch.empty((n, 10), dtype=model.dtype, device=model.device)
+
+
+def rnea_id_vjp(model: Model, q, qd, qdd, tau_bar, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None,
+                want_inertia=True, out=None, workspace=None):
+    """(q_bar, qd_bar, qdd_bar, inertia_bar) = (d tau/d(q, qd, qdd, pi))^T tau_bar."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd, tau_bar, tip))
+    if out is None:
+        out = (torch.empty_like(q), torch.empty_like(q), torch.empty_like(q),
+               _inertia_bar_like(model) if want_inertia else None)
+    qb, qdb, qddb, pib = out
+    _call("pdyn_rnea_id_vjp", OP_RNEA_ID_VJP, model, n_states, (q, qd, qdd, tau_bar, qb, qdb, qddb, pib),
+          base_vel, base_acc, tip, workspace)
+    return qb, qdb, qddb, pib
+
+
+def aba_fd_vjp(model: Model, q, qd, qdd, qdd_bar, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None,
+               want_inertia=True, out=None, workspace=None):
+    """(q_bar, qd_bar, tau_bar, inertia_bar) of qdd = FD(q, qd, tau) at its output qdd."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd, qdd_bar, tip))
+    if out is None:
+        out = (torch.empty_like(q), torch.empty_like(q), torch.empty_like(q),
+               _inertia_bar_like(model) if want_inertia else None)
+    qb, qdb, tb, pib = out
+    _call("pdyn_aba_fd_vjp", OP_ABA_FD_VJP, model, n_states, (q, qd, qdd, qdd_bar, qb, qdb, tb, pib),
+          base_vel, base_acc, tip, workspace)
+    return qb, qdb, tb, pib

@@ -1,9 +1,12 @@
 // libpdyn: C-ABI entry points and HIP kernels for gfx950.
 //
 // Kernel map (one lane = one state; consecutive lanes = consecutive states):
-//   k_link_table   per link: the derived 32-word record (rotation of M_i from
-//                  its quaternion, twist norms, h = m c, I_O) -- a parallel map.
-//   k_dynamics     per state: the sweeps of sweeps.hpp (ID, FD or both).
+//   k_link_table       per link: the derived 32-word record (rotation of M_i
+//                      from its quaternion, twist norms, h = m c, I_O) -- a map.
+//   k_dynamics         per state: the sweeps of sweeps.hpp (ID, FD or both).
+//   k_vjp              per state: the adjoint sweeps (ID or FD vector-Jacobian
+//                      product), inertia cotangents summed per wave.
+//   k_reduce_partials  per (link, parameter): sum of the per-wave partials.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -82,10 +85,127 @@ __global__ void __launch_bounds__(kBlock) k_dynamics(int n_states, int n_chains,
   dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
 }
 
+// ---- adjoints ------------------------------------------------------------------
+//
+// One lane per state as above. With a shared chain the inertia-parameter
+// cotangents of the 64 states of a wave are summed in registers by a fixed
+// xor-butterfly (every lane ends with the same, order-independent sum) and
+// lane 0 writes one partial per wave; k_reduce_partials then sums the waves in
+// a fixed order, so the result is deterministic. Lanes past the last state run
+// a copy of the last state with zero weight so that every lane takes part in
+// the butterflies. With one chain per state each lane writes its own links.
+
+enum : int { kVjpID = 0, kVjpFD = 1 };
+enum : int { kPiNone = 0, kPiWave = 1, kPiDirect = 2 };
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <class T, int PI> struct PiSink {
+  T* out;        // kPiWave: partials [link][10][n_waves] at (.., wave); kPiDirect: [links of this chain][10]
+  long stride;   // kPiWave: n_waves
+  T weight;      // 0 for lanes past the last state
+  bool leader;   // lane 0 of the wave
+  __device__ void put(int i, const T g[10]) {
+    if (PI == kPiWave) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        const T v = wave_sum(weight * g[k]);
+        if (leader) out[((long)i * 10 + k) * stride] = v;
+      }
+    } else if (PI == kPiDirect) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) out[(long)i * 10 + k] = g[k];
+    }
+  }
+};
+
+// Scratch of the adjoints: [n_max][kVjpWords][stride] with stride = states
+// rounded up to a whole wave, then [4][64][n_max] outputs of idle lanes.
+template <class T, int OP, int PI>
+__global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
+                                                const T* __restrict__ table, const double* __restrict__ wtable,
+                                                const T* q, const T* qd, const T* qdd, const T* bar_in, T* q_bar,
+                                                T* qd_bar, T* qdd_bar, T* tau_bar, T* pi_out, long n_waves,
+                                                const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
+                                                long stride) {
+  const int lane_state = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = lane_state < n_states;
+  if (PI != kPiWave && !active) return;
+  const int s = active ? lane_state : n_states - 1;  // idle lanes of a shared chain redo the last state
+  int n;
+  int64_t link0, dof0;
+  if (n_chains == 1) {
+    n = n_max;
+    link0 = 0;
+    dof0 = (int64_t)s * n_max;
+  } else {
+    link0 = link_ptr[s];
+    n = link_ptr[s + 1] - (int)link0;
+    dof0 = link0;
+  }
+  VjpIO<T> io;
+  io.q = q + dof0;
+  io.qd = qd + dof0;
+  io.qdd = qdd + dof0;
+  io.bar_in = bar_in + dof0;
+  if (active) {
+    io.q_bar = q_bar + dof0;
+    io.qd_bar = qd_bar + dof0;
+    io.qdd_bar = (OP == kVjpID) ? qdd_bar + dof0 : nullptr;
+    io.tau_bar = (OP == kVjpFD) ? tau_bar + dof0 : nullptr;
+  } else {
+    T* idle = scratch + (long)n_max * kVjpWords * stride + (long)(lane_state - n_states) * n_max;
+    const long part = 64L * n_max;
+    io.q_bar = idle;
+    io.qd_bar = idle + part;
+    io.qdd_bar = (OP == kVjpID) ? idle + 2 * part : nullptr;
+    io.tau_bar = (OP == kVjpFD) ? idle + 3 * part : nullptr;
+  }
+  Boundary<T> bd;
+  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  if (tip) {
+    const T* t = tip + 6 * (int64_t)s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  } else {
+    bd.Ftip = sp_zero<T>();
+  }
+  Scratch<T> scr{scratch + lane_state, stride, kVjpWords};
+  PiSink<T, PI> sink;
+  sink.out = nullptr;
+  sink.stride = 0;
+  sink.weight = active ? T(1) : T(0);
+  sink.leader = (threadIdx.x % 64) == 0;
+  if (PI == kPiWave) {
+    sink.out = pi_out + lane_state / 64;
+    sink.stride = n_waves;
+  } else if (PI == kPiDirect) {
+    sink.out = pi_out + link0 * 10;
+  }
+  if (OP == kVjpID) id_vjp_one_state(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr, sink);
+  else fd_vjp_one_state(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr, sink);
+}
+
+// out[i] = sum over w of partials[i][w], w in increasing order.
+template <class T>
+__global__ void __launch_bounds__(256) k_reduce_partials(int n_out, int n_waves, const T* __restrict__ partials,
+                                                        T* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_out) return;
+  T acc = T(0);
+  for (int w = 0; w < n_waves; ++w) acc += partials[(long)i * n_waves + w];
+  out[i] = acc;
+}
+
 // ---- host side ------------------------------------------------------------------
 
 struct Layout {
-  size_t table_off, wtable_off, scratch_off, scratch_bytes, total;
+  size_t table_off, wtable_off, scratch_off, scratch_bytes, partial_off, total;
+  long stride, n_waves;
 };
 
 int scratch_words(int op) {
@@ -93,9 +213,13 @@ int scratch_words(int op) {
     case PDYN_OP_RNEA_ID: return ScratchWords<kModeID>::value;
     case PDYN_OP_ABA_FD: return ScratchWords<kModeFD>::value;
     case PDYN_OP_ID_FD: return ScratchWords<kModeIDFD>::value;
+    case PDYN_OP_RNEA_ID_VJP:
+    case PDYN_OP_ABA_FD_VJP: return kVjpWords;
     default: return -1;
   }
 }
+
+bool is_vjp(int op) { return op == PDYN_OP_RNEA_ID_VJP || op == PDYN_OP_ABA_FD_VJP; }
 
 int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (!m || !b) return PDYN_EINVAL;
@@ -126,8 +250,22 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
   L->table_off = 0;
   L->wtable_off = woff;
   L->scratch_off = m->prepared ? 0 : tb;
-  L->scratch_bytes = align_up((size_t)m->n_links_max * (size_t)words * (size_t)b->n_states * scalar);
-  L->total = L->scratch_off + L->scratch_bytes;
+  const size_t nm = (size_t)m->n_links_max;
+  if (is_vjp(op)) {
+    // [n_max][words][stride] + idle-lane outputs [4][64][n_max], then the
+    // per-wave inertia partials [n_max][10][n_waves].
+    L->n_waves = (b->n_states + 63) / 64;
+    L->stride = L->n_waves * 64;
+    L->scratch_bytes = align_up((nm * (size_t)words * (size_t)L->stride + 4 * 64 * nm) * scalar);
+    L->partial_off = L->scratch_off + L->scratch_bytes;
+    L->total = L->partial_off + align_up(nm * 10 * (size_t)L->n_waves * scalar);
+  } else {
+    L->n_waves = 0;
+    L->stride = b->n_states;
+    L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
+    L->partial_off = 0;
+    L->total = L->scratch_off + L->scratch_bytes;
+  }
   if (L->total < kAlign) L->total = kAlign;
   return PDYN_OK;
 }
@@ -192,6 +330,59 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,
                      m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                      static_cast<const T*>(b->tip_wrench), ba, scratch);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+template <class T, int OP>
+int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* qdd, const T* bar_in,
+            T* q_bar, T* qd_bar, T* out3, T* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
+  const int op = (OP == kVjpID) ? PDYN_OP_RNEA_ID_VJP : PDYN_OP_ABA_FD_VJP;
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, qd, qdd, bar_in, q_bar, qd_bar, out3}))) return st;
+  if ((st = check_ptrs<T>({m->placement, m->twist, m->inertia}))) return st;
+  if (inertia_bar && !aligned(inertia_bar, sizeof(T))) return PDYN_EALIGN;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  Layout L;
+  if ((st = layout_for(op, m, b, sizeof(T), &L))) return st;
+  if (ws_bytes < L.total) return PDYN_EWORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
+  T* partials = reinterpret_cast<T*>(base + L.partial_off);
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
+  const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
+  if (!m->prepared) {
+    if ((st = launch_link_table<T>(m, base, s))) return st;
+  }
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
+  T* qdd_bar = (OP == kVjpID) ? out3 : nullptr;
+  T* tau_bar = (OP == kVjpFD) ? out3 : nullptr;
+  const T* tip = static_cast<const T*>(b->tip_wrench);
+#define PDYN_LAUNCH_VJP(PI, PIOUT)                                                                            \
+  hipLaunchKernelGGL((k_vjp<T, OP, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
+                     m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar,   \
+                     tau_bar, PIOUT, L.n_waves, tip, ba, scratch, L.stride)
+  if (!inertia_bar) {
+    PDYN_LAUNCH_VJP(kPiNone, static_cast<T*>(nullptr));
+  } else if (m->n_chains == 1) {
+    PDYN_LAUNCH_VJP(kPiWave, partials);
+    const int n_out = m->n_links_max * 10;
+    hipLaunchKernelGGL(k_reduce_partials<T>, dim3((n_out + 255) / 256), dim3(256), 0, s, n_out, (int)L.n_waves,
+                       partials, inertia_bar);
+  } else {
+    PDYN_LAUNCH_VJP(kPiDirect, inertia_bar);
+  }
+#undef PDYN_LAUNCH_VJP
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -268,6 +459,27 @@ int pdyn_id_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const f
 int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd_in,
                    const double* tau_in, double* tau_out, double* qdd_out, void* ws, size_t ws_bytes, void* stream) {
   return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+
+int pdyn_rnea_id_vjp(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* qdd,
+                     const float* tau_bar, float* q_bar, float* qd_bar, float* qdd_bar, float* inertia_bar, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return run_vjp<float, kVjpID>(m, b, q, qd, qdd, tau_bar, q_bar, qd_bar, qdd_bar, inertia_bar, ws, ws_bytes, stream);
+}
+int pdyn_rnea_id_vjp_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                         const double* qdd, const double* tau_bar, double* q_bar, double* qd_bar, double* qdd_bar,
+                         double* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
+  return run_vjp<double, kVjpID>(m, b, q, qd, qdd, tau_bar, q_bar, qd_bar, qdd_bar, inertia_bar, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_vjp(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* qdd,
+                    const float* qdd_bar, float* q_bar, float* qd_bar, float* tau_bar, float* inertia_bar, void* ws,
+                    size_t ws_bytes, void* stream) {
+  return run_vjp<float, kVjpFD>(m, b, q, qd, qdd, qdd_bar, q_bar, qd_bar, tau_bar, inertia_bar, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_vjp_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                        const double* qdd, const double* qdd_bar, double* q_bar, double* qd_bar, double* tau_bar,
+                        double* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
+  return run_vjp<double, kVjpFD>(m, b, q, qd, qdd, qdd_bar, q_bar, qd_bar, tau_bar, inertia_bar, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -290,4 +290,203 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   }
 }
 
+// ============================================================================
+// Adjoints (vector-Jacobian products). Not in the paper (its future work asks
+// for gradients of the dynamics); they are the reverse-mode derivatives of the
+// recursions above. With X_i = Ad_{f_{i-1,i}^-1}, dX_i/dq_i = -ad_{S_i} X_i.
+//
+// ID:  tau = ID(q, qd, qdd; pi). Given tau_bar:
+//   Fbar_i = X_i Fbar_{i-1} + S_i tau_bar_i          (forward; adjoint of the wrench scan)
+//   local adjoints of Fhat_i = J A_i - ad^T_{V_i}(J V_i) with w = Fbar_i:
+//     Abar_i += J w,   Vbar_i += ad^T_w (J V_i) - J ad_{V_i} w,
+//     pi_bar_i += d/dpi [ w^T J A_i - (ad_{V_i} w)^T J V_i ]
+//   backward through V_i = y_i + S_i qd_i, A_i = X_i A_{i-1} + S_i qdd_i - ad_{S_i qd_i} y_i,
+//   y_i = X_i V_{i-1}:
+//     qdd_bar_i = S_i . Abar_i
+//     ybar_i    = Vbar_i - ad^T_{S_i qd_i} Abar_i
+//     qd_bar_i  = S_i . Vbar_i + (ad_{y_i} S_i) . Abar_i
+//     q_bar_i   = -(ad_{S_i} Fbar_i) . F_i - (ad_{S_i} X_i A_{i-1}) . Abar_i - (ad_{S_i} y_i) . ybar_i
+//     Abar_{i-1} += X_i^T Abar_i,  Vbar_{i-1} += X_i^T ybar_i
+// FD:  qdd = FD(q, qd, tau; pi) solves ID(q, qd, qdd) = tau, so with u = M^-1 qdd_bar:
+//   tau_bar = u,  (q_bar, qd_bar, pi_bar) = -VJP_ID(q, qd, qdd; u).
+//   u is the articulated-body solve of Sec. II-B with tau-hat := qdd_bar (no bias).
+// ============================================================================
+
+// d/dpi of x^T J(pi) y for pi = (m, c, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz),
+// J (v, w) = (m v - h x w, h x v + I_O w), h = m c, I_O = I_c + m (|c|^2 I - c c^T):
+//   x^T J y = m x_v.y_v + h.(y_v x x_w - y_w x x_v) + x_w^T I_c y_w + m (|c|^2 x_w.y_w - (c.x_w)(c.y_w)).
+template <class T>
+PD_HD void add_inertia_grad(T m, const V3<T>& c, const Sp<T>& x, const Sp<T>& y, T sgn, T g[10]) {
+  const V3<T> k = cross(y.a, x.b) - cross(y.b, x.a);
+  const T xwyw = dot(x.b, y.b), cx = dot(c, x.b), cy = dot(c, y.b);
+  g[0] += sgn * (dot(x.a, y.a) + dot(c, k) + dot(c, c) * xwyw - cx * cy);
+  const V3<T> gc = m * (k + (T(2) * xwyw) * c - cy * x.b - cx * y.b);
+  g[1] += sgn * gc.x; g[2] += sgn * gc.y; g[3] += sgn * gc.z;
+  g[4] += sgn * x.b.x * y.b.x;
+  g[5] += sgn * x.b.y * y.b.y;
+  g[6] += sgn * x.b.z * y.b.z;
+  g[7] += sgn * (x.b.x * y.b.y + x.b.y * y.b.x);
+  g[8] += sgn * (x.b.x * y.b.z + x.b.z * y.b.x);
+  g[9] += sgn * (x.b.y * y.b.z + x.b.z * y.b.y);
+}
+
+template <class T> struct VjpIO {
+  const T* q;
+  const T* qd;
+  const T* qdd;      // ID: input accelerations; FD: the forward output qdd = FD(q, qd, tau)
+  const T* bar_in;   // ID: tau_bar; FD: qdd_bar
+  T* q_bar;
+  T* qd_bar;
+  T* qdd_bar;        // ID only
+  T* tau_bar;        // FD only (receives u = M^-1 qdd_bar)
+};
+
+// Scratch words per link of the adjoint passes: Fbar, V, A (6 each), the
+// wrench part of q_bar (1), padding (1).
+constexpr int kVjpWords = 20;
+
+// Sweep 1 of the inverse dynamics: V, A and Fhat_i into scratch slot 0.
+template <class T>
+PD_HD void vjp_forward_fhat(int i, const Link<T>& L, const Pose<T>& g, T qd, T qdd, Sp<T>& V, Sp<T>& A,
+                            const Scratch<T>& scr) {
+  const Sp<T> XV = X_twist(g, V);
+  const Sp<T> Sqd = qd * L.S;
+  V = XV + Sqd;
+  A = X_twist(g, A) + qdd * L.S - ad_twist(Sqd, XV);
+  scr.put(i, 0, mul(L.J, A) - adT_wrench(V, mul(L.J, V)));
+}
+
+// Sweeps 2-4 of an ID adjoint with cotangent sgn * tb (Fhat already in scratch
+// slot 0). pi_bar contributions go to sink.put(i, g[10]).
+template <class T, class Sink>
+PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, const T* q, const T* qd, const T* qdd,
+                       const T* tb, T sgn, T* q_bar, T* qd_bar, T* qdd_bar, const Boundary<T>& bd,
+                       const Scratch<T>& scr, Sink& sink) {
+  // sweep 2 (tip to base): wrenches F_i in double, stored rounded in slot 0
+  {
+    Sp<double> F = cast_sp<double>(bd.Ftip);
+    Pose<double> gcw;
+    for (int i = n - 1; i >= 0; --i) {
+      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+      if (i < n - 1) F = XT_wrench(gcw, F);
+      F = F + cast_sp<double>(scr.get(i, 0));
+      scr.put(i, 0, cast_sp<T>(F));
+      gcw = joint_transform_wide(Lw, q[i]);
+    }
+  }
+  // sweep 3 (base to tip): Fbar, V, A again; the wrench part of q_bar; pi_bar
+  {
+    Sp<T> V = bd.V0, A = bd.dV0, Fb = sp_zero<T>();
+    for (int i = 0; i < n; ++i) {
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Pose<T> g = joint_transform(L, q[i]);
+      const Sp<T> XV = X_twist(g, V);
+      const Sp<T> Sqd = qd[i] * L.S;
+      V = XV + Sqd;
+      A = X_twist(g, A) + qdd[i] * L.S - ad_twist(Sqd, XV);
+      Fb = X_twist(g, Fb) + (sgn * tb[i]) * L.S;
+      const Sp<T> F = scr.get(i, 0);
+      const T qbp = -dot(ad_twist(L.S, Fb), F);
+      T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+      const V3<T> c = (T(1) / L.J.m) * L.J.h;
+      add_inertia_grad(L.J.m, c, Fb, A, T(1), gpi);
+      add_inertia_grad(L.J.m, c, ad_twist(V, Fb), V, T(-1), gpi);
+      sink.put(i, gpi);
+      scr.put(i, 0, Fb);
+      scr.put(i, 6, V);
+      scr.put(i, 12, A);
+      scr.at(i, 18) = qbp;
+    }
+  }
+  // sweep 4 (tip to base): adjoints of the velocity / acceleration recursion
+  {
+    Sp<T> Ac = sp_zero<T>(), yc = sp_zero<T>();
+    for (int i = n - 1; i >= 0; --i) {
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Sp<T> Fb = scr.get(i, 0), V = scr.get(i, 6), A = scr.get(i, 12);
+      const T qbp = scr.at(i, 18);
+      const Sp<T> Ab = mul(L.J, Fb) + Ac;
+      const Sp<T> Vb = adT_wrench(Fb, mul(L.J, V)) - mul(L.J, ad_twist(V, Fb)) + yc;
+      const Sp<T> Sqd = qd[i] * L.S;
+      const Sp<T> y = V - Sqd;
+      const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
+      const Sp<T> XA = A - qdd[i] * L.S + ad_twist(Sqd, y);
+      if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
+      qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
+      q_bar[i] = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+      const Pose<T> g = joint_transform(L, q[i]);
+      Ac = XT_wrench(g, Ab);
+      yc = XT_wrench(g, yb);
+    }
+  }
+}
+
+template <class T, class Sink>
+PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const VjpIO<T>& io,
+                            const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
+  Sp<T> V = bd.V0, A = bd.dV0;
+  for (int i = 0; i < n; ++i) {
+    const Link<T> L = load_link(table + (long)i * kLinkWords);
+    vjp_forward_fhat(i, L, joint_transform(L, io.q[i]), io.qd[i], io.qdd[i], V, A, scr);
+  }
+  id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.bar_in, T(1), io.q_bar, io.qd_bar, io.qdd_bar, bd, scr,
+              sink);
+}
+
+template <class T, class Sink>
+PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const VjpIO<T>& io,
+                            const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
+  // u = M^-1 qdd_bar: articulated-body inertia and z-hat (tip to base) with tau-hat = qdd_bar
+  {
+    Sp<double> zA = sp_zero<double>();
+    Sym6<T> JA;
+    Pose<double> gcw;
+    Pose<T> gc;
+    for (int i = n - 1; i >= 0; --i) {
+      const bool has_child = (i < n - 1);
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+      Sym6<T> Jh = sym6_from_inertia(L.J);
+      Sp<double> z = sp_zero<double>();
+      if (has_child) {
+        const Sym6<T> P = congruence_to_parent(gc, JA);
+        Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+        Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+        Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+        Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+        z = XT_wrench(gcw, zA);
+      }
+      const Sp<T> U = mul(Jh, L.S);
+      const T invD = T(1) / dot(L.S, U);
+      const double chat_w = ((double)io.bar_in[i] - dot(Lw.S, z)) * (double)invD;
+      JA = sym6_minus_outer(Jh, U, invD);
+      zA = z + chat_w * cast_sp<double>(U);
+      scr.put(i, 0, U);
+      scr.at(i, 6) = invD;
+      scr.at(i, 7) = (T)chat_w;
+      gcw = joint_transform_wide(Lw, io.q[i]);
+      gc = cast_pose<T>(gcw);
+    }
+  }
+  // lambda (base to tip) gives u; in the same pass, sweep 1 of ID at (q, qd, qdd)
+  {
+    Sp<T> lam = sp_zero<T>(), V = bd.V0, A = bd.dV0;
+    for (int i = 0; i < n; ++i) {
+      const Link<T> L = load_link(table + (long)i * kLinkWords);
+      const Pose<T> g = joint_transform(L, io.q[i]);
+      const Sp<T> U = scr.get(i, 0);
+      const T invD = scr.at(i, 6), chat = scr.at(i, 7);
+      const Sp<T> a = X_twist(g, lam);
+      const T u = chat - dot(U, a) * invD;
+      lam = a + u * L.S;
+      io.tau_bar[i] = u;
+      vjp_forward_fhat(i, L, g, io.qd[i], io.qdd[i], V, A, scr);
+    }
+  }
+  id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.tau_bar, T(-1), io.q_bar, io.qd_bar,
+              static_cast<T*>(nullptr), bd, scr, sink);
+}
+
 }  // namespace pdyn

@@ -54,3 +54,60 @@ int cpu_dynamics_f64(int mode, int n_states, int n_chains, int n_max, const int3
   return run<double>(mode, n_states, n_chains, n_max, link_ptr, pl, tw, in, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, V0, dV0);
 }
 }
+
+// ---- adjoints -------------------------------------------------------------------
+template <class T> struct SumSink {
+  double* acc;  // [links][10] of this state's chain
+  void put(int i, const T g[10]) {
+    for (int k = 0; k < 10; ++k) acc[10 * i + k] += (double)g[k];
+  }
+};
+
+template <class T>
+static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
+                   const T* twist, const T* inertia, const T* q, const T* qd, const T* qdd, const T* bar_in,
+                   T* q_bar, T* qd_bar, T* qdd_bar, T* tau_bar, double* pi_bar, const T* tip, const T* V0,
+                   const T* dV0) {
+  int64_t L = (n_chains == 1) ? n_max : link_ptr[n_chains];
+  std::vector<T> table((size_t)L * kLinkWords);
+  std::vector<double> wtable((size_t)L * kLinkWords);
+  for (int64_t i = 0; i < L; ++i) {
+    make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, &wtable[i * kLinkWords]);
+    for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
+  }
+  std::vector<T> scratch((size_t)n_max * kVjpWords * n_states, T(-7777));
+  Boundary<T> bd;
+  bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
+  bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
+  for (int s = 0; s < n_states; ++s) {
+    int n;
+    int64_t link0, dof0;
+    if (n_chains == 1) { n = n_max; link0 = 0; dof0 = (int64_t)s * n_max; }
+    else { link0 = link_ptr[s]; n = link_ptr[s + 1] - (int)link0; dof0 = link0; }
+    VjpIO<T> io{q + dof0, qd + dof0, qdd + dof0, bar_in + dof0, q_bar + dof0, qd_bar + dof0,
+                qdd_bar ? qdd_bar + dof0 : nullptr, tau_bar ? tau_bar + dof0 : nullptr};
+    bd.Ftip = tip ? Sp<T>{v3(tip[6 * s], tip[6 * s + 1], tip[6 * s + 2]), v3(tip[6 * s + 3], tip[6 * s + 4], tip[6 * s + 5])} : sp_zero<T>();
+    Scratch<T> scr{scratch.data() + s, (long)n_states, kVjpWords};
+    SumSink<T> sink{pi_bar + 10 * link0};
+    if (op == 0) id_vjp_one_state(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr, sink);
+    else fd_vjp_one_state(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr, sink);
+  }
+  return 0;
+}
+
+extern "C" {
+int cpu_vjp_f32(int op, int n_states, int n_chains, int n_max, const int32_t* lp, const float* pl, const float* tw,
+                const float* in, const float* q, const float* qd, const float* qdd, const float* bar_in, float* q_bar,
+                float* qd_bar, float* qdd_bar, float* tau_bar, double* pi_bar, const float* tip, const float* V0,
+                const float* dV0) {
+  return run_vjp<float>(op, n_states, n_chains, n_max, lp, pl, tw, in, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar,
+                        tau_bar, pi_bar, tip, V0, dV0);
+}
+int cpu_vjp_f64(int op, int n_states, int n_chains, int n_max, const int32_t* lp, const double* pl, const double* tw,
+                const double* in, const double* q, const double* qd, const double* qdd, const double* bar_in,
+                double* q_bar, double* qd_bar, double* qdd_bar, double* tau_bar, double* pi_bar, const double* tip,
+                const double* V0, const double* dV0) {
+  return run_vjp<double>(op, n_states, n_chains, n_max, lp, pl, tw, in, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar,
+                         tau_bar, pi_bar, tip, V0, dV0);
+}
+}

@@ -1,0 +1,189 @@
+"""GPU parity of the adjoint kernels against the oracle's complex-step derivatives (needs an MI355X).
+
+FP64 kernels must match to rounding. FP32 tolerances are per output, relative
+per state (||x - x*|| / ||x*||). For the forward-dynamics adjoint, q_bar is a
+strongly cancelling sum -(dtau/dq)^T M^-1 qdd_bar whose FP32 error grows with
+cond(M) (~1e4-1e5 here): it is held to 1e-3, the other outputs to 1e-4.
+
+Full-size launches use a cotangent that is zero except on sampled states, so
+the batch-summed inertia gradient equals the oracle's sum over those states.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grad
+from paper_1609_04493_amd import api, autograd, synth
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, len(os.sched_getaffinity(0)))
+
+
+def dev_t(a, device, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
+
+
+def rel(x, ref, floor=1e-13):
+    """Relative error; quantities that vanish analytically (a one-link chain's qd_bar) get an absolute floor."""
+    return np.linalg.norm(np.asarray(x, np.float64) - ref) / max(np.linalg.norm(ref), floor)
+
+
+def id_refs(ch, st, bar, idx):
+    out = [np.zeros((len(idx), st.q.shape[1])) for _ in range(3)]
+    pib = np.zeros((st.q.shape[1], 10))
+    for k, s in enumerate(idx):
+        r = grad.rnea_vjp(ch, st.q[s], st.qd[s], st.qdd[s], bar[s])
+        for j in range(3):
+            out[j][k] = r[j]
+        pib += r[3]
+    return out, pib
+
+
+def fd_refs(ch, st, bar, idx):
+    out = [np.zeros((len(idx), st.q.shape[1])) for _ in range(3)]
+    pib = np.zeros((st.q.shape[1], 10))
+    for k, s in enumerate(idx):
+        r = grad.aba_vjp(ch, st.q[s], st.qd[s], st.tau[s], bar[s])
+        for j in range(3):
+            out[j][k] = r[j]
+        pib += r[3]
+    return out, pib
+
+
+@pytest.mark.parametrize("B", [64, 67])
+def test_fp64_id_and_fd_vjp_7_links(device, B):
+    print(f"case: fp64 vjp 7 links B={B}", flush=True)
+    ch, st = synth.workload_fp64_7link(B)
+    bar = np.random.default_rng(B).standard_normal((B, 7))
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    qb, qdb, qddb, pib = (x.cpu().numpy() for x in api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), d(bar)))
+    idx = np.arange(B)
+    (rq, rqd, rqdd), rpi = id_refs(ch, st, bar, idx)
+    for x, r in ((qb, rq), (qdb, rqd), (qddb, rqdd)):
+        assert max(rel(x[s], r[s]) for s in idx) <= 1e-11
+    assert rel(pib, rpi) <= 1e-11
+    qdd = oracle.aba(ch, st.q, st.qd, st.tau)
+    qb, qdb, tb, pib = (x.cpu().numpy() for x in api.aba_fd_vjp(model, d(st.q), d(st.qd), d(qdd), d(bar)))
+    (rq, rqd, rt), rpi = fd_refs(ch, st, bar, idx)
+    for x, r in ((qb, rq), (qdb, rqd), (tb, rt)):
+        assert max(rel(x[s], r[s]) for s in idx) <= 1e-10
+    assert rel(pib, rpi) <= 1e-10
+
+
+def test_fp32_id_vjp_32_links_full_batch_sparse_cotangent(device):
+    print("case: fp32 id vjp 32 links x 16384", flush=True)
+    ch, st = synth.workload_32link(16384)
+    idx = np.random.default_rng(5).choice(16384, 24, replace=False)
+    bar = np.zeros((16384, 32))
+    bar[idx] = np.random.default_rng(6).standard_normal((24, 32))
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: dev_t(a, device, torch.float32)
+    qb, qdb, qddb, pib = (x.cpu().numpy() for x in api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), d(bar)))
+    cr, sr = ch.rounded(), st.rounded()
+    (rq, rqd, rqdd), rpi = id_refs(cr, sr, bar, idx)
+    errs = {k: max(rel(x[s], r[k2]) for k2, s in enumerate(idx)) for k, x, r in
+            (("q", qb, rq), ("qd", qdb, rqd), ("qdd", qddb, rqdd))}
+    errs["pi"] = rel(pib, rpi)
+    print("fp32 ID vjp errors", errs, flush=True)
+    assert max(errs.values()) <= 1e-4
+    zero = np.setdiff1d(np.arange(16384), idx)
+    assert np.abs(qb[zero]).max() == 0 and np.abs(qddb[zero]).max() == 0
+
+
+def test_fp32_fd_vjp_50_links_8192_states(device):
+    """The 50-link, 8192-state workload: FD + adjoint of L = ||qdd||^2 (cotangent 2 qdd) on sampled states."""
+    print("case: fp32 fd vjp 50 links x 8192", flush=True)
+    ch, st = synth.workload_50link(8192)
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: dev_t(a, device, torch.float32)
+    q, qd, tau = d(st.q), d(st.qd), d(st.tau)
+    qdd = api.aba_fd(model, q, qd, tau)
+    idx = np.random.default_rng(7).choice(8192, 12, replace=False)
+    mask = torch.zeros(8192, 1, device=device)
+    mask[torch.as_tensor(idx)] = 1.0
+    bar = (2.0 * qdd * mask).contiguous()
+    qb, qdb, tb, pib = (x.cpu().numpy() for x in api.aba_fd_vjp(model, q, qd, qdd, bar))
+    cr, sr = ch.rounded(), st.rounded()
+    bar_np = bar.cpu().numpy().astype(np.float64)
+    (rq, rqd, rt), rpi = fd_refs(cr, sr, bar_np, idx)
+    errs = {k: max(rel(x[s], r[k2]) for k2, s in enumerate(idx)) for k, x, r in
+            (("q", qb, rq), ("qd", qdb, rqd), ("tau", tb, rt))}
+    errs["pi"] = rel(pib, rpi)
+    print("fp32 FD vjp errors (50 links)", errs, flush=True)
+    assert errs["q"] <= 1e-3
+    assert max(errs["qd"], errs["tau"], errs["pi"]) <= 1e-4
+
+
+def test_fp64_fd_vjp_vs_central_differences(device):
+    """d/de L(q + e dq, qd + e dqd, tau + e dtau), L = ||FD||^2, by FP64 central differences (h = 1e-6) on the GPU."""
+    print("case: fp64 fd vjp vs central differences", flush=True)
+    ch = synth.make_chains([50], 11)
+    st = synth.make_states((8, 50), 11)
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    q, qd, tau = d(st.q), d(st.qd), d(st.tau)
+    qdd = api.aba_fd(model, q, qd, tau)
+    qb, qdb, tb, _ = api.aba_fd_vjp(model, q, qd, qdd, (2 * qdd).contiguous(), want_inertia=False)
+    rng = np.random.default_rng(12)
+    dq, dqd, dtau = (d(rng.standard_normal((8, 50))) for _ in range(3))
+    h = 1e-6
+    Lp = (api.aba_fd(model, q + h * dq, qd + h * dqd, tau + h * dtau) ** 2).sum(1)
+    Lm = (api.aba_fd(model, q - h * dq, qd - h * dqd, tau - h * dtau) ** 2).sum(1)
+    cd = ((Lp - Lm) / (2 * h)).cpu().numpy()
+    adj = ((qb * dq).sum(1) + (qdb * dqd).sum(1) + (tb * dtau).sum(1)).cpu().numpy()
+    assert np.abs(cd - adj).max() <= 1e-5 * np.abs(adj).max()
+
+
+def test_ragged_chains_vjp_direct_inertia_rows(device):
+    print("case: ragged vjp", flush=True)
+    ch = synth.make_chains([3, 10, 1, 17, 7], 21)
+    st = synth.make_states((ch.n_links_total,), 21)
+    bar = np.random.default_rng(21).standard_normal(ch.n_links_total)
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    qb, qdb, qddb, pib = (x.cpu().numpy() for x in api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), d(bar)))
+    qdd = oracle.aba(ch, st.q, st.qd, st.tau)
+    fb, fdb, ftb, fpib = (x.cpu().numpy() for x in api.aba_fd_vjp(model, d(st.q), d(st.qd), d(qdd), d(bar)))
+    for c in range(ch.n_chains):
+        a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+        sub = ch.chain(c)
+        r = grad.rnea_vjp(sub, st.q[a:b], st.qd[a:b], st.qdd[a:b], bar[a:b])
+        for x, y in zip((qb[a:b], qdb[a:b], qddb[a:b], pib[a:b]), r):
+            assert rel(x, y) <= 1e-11
+        r = grad.aba_vjp(sub, st.q[a:b], st.qd[a:b], st.tau[a:b], bar[a:b])
+        for x, y in zip((fb[a:b], fdb[a:b], ftb[a:b], fpib[a:b]), r):
+            assert rel(x, y) <= 1e-10
+
+
+def test_autograd_functions_match_vjp_kernels(device):
+    print("case: autograd", flush=True)
+    ch, st = synth.workload_fp64_7link(32)
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64).requires_grad_(True)
+    q, qd, tau, ine = d(st.q), d(st.qd), d(st.tau), d(ch.inertia)
+    qdd = autograd.forward_dynamics(model, q, qd, tau, ine)
+    loss = (qdd ** 2).sum()
+    gq, gqd, gt, gpi = torch.autograd.grad(loss, (q, qd, tau, ine))
+    for s in range(0, 32, 8):
+        r = grad.aba_vjp(ch, st.q[s], st.qd[s], st.tau[s], 2 * qdd[s].detach().cpu().numpy())
+        for x, y in zip((gq[s], gqd[s], gt[s]), r[:3]):
+            assert rel(x.cpu().numpy(), y) <= 1e-10
+    tauo = autograd.inverse_dynamics(model, q, qd, qdd.detach(), ine)
+    g2 = torch.autograd.grad(tauo.sum(), (q, ine))
+    r = grad.rnea_vjp(ch, st.q[3], st.qd[3], qdd[3].detach().cpu().numpy(), np.ones(7))
+    assert rel(g2[0][3].cpu().numpy(), r[0]) <= 1e-10
+
+
+def test_inertia_gradient_is_deterministic(device):
+    ch, st = synth.workload_32link(4096)
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: dev_t(a, device, torch.float32)
+    bar = d(np.random.default_rng(3).standard_normal((4096, 32)))
+    a = api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), bar)[3].cpu().numpy()
+    b = api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), bar)[3].cpu().numpy()
+    assert np.array_equal(a, b)

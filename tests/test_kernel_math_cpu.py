@@ -107,3 +107,73 @@ def test_fp32_sweeps_32_links(cpu_lib):
     ref_qdd = oracle.aba(chr_, str_.q, str_.qd, str_.tau)
     assert rel_err_rows(tau, ref_tau).max() <= 1e-4
     assert rel_err_rows(qdd, ref_qdd).max() <= 1e-4
+
+
+# ---- adjoints -----------------------------------------------------------------------
+
+def run_vjp_cpu(lib, op, chains, q, qd, qdd, bar, dtype):
+    dt = np.dtype(dtype)
+    fn = lib.cpu_vjp_f64 if dt == np.float64 else lib.cpu_vjp_f32
+    fn.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 16
+    conv = lambda a: np.ascontiguousarray(a, dtype=dt)
+    n_chains = chains.n_chains
+    q = conv(q)
+    n_states = q.shape[0] if n_chains == 1 else n_chains
+    n_max = int(chains.lengths().max())
+    outs = [np.zeros_like(q) for _ in range(4)]
+    pib = np.zeros((n_max if n_chains == 1 else chains.n_links_total, 10))
+    lp = np.ascontiguousarray(chains.link_ptr, dtype=np.int32)
+    fn(op, n_states, n_chains, n_max, _p(lp), _p(conv(chains.placement)), _p(conv(chains.twist)),
+       _p(conv(chains.inertia)), _p(q), _p(conv(qd)), _p(conv(qdd)), _p(conv(bar)), *[_p(o) for o in outs],
+       _p(pib), None, _p(conv(np.zeros(6))), _p(conv(oracle.GRAVITY_ACC)))
+    return outs, pib
+
+
+def test_fp64_adjoint_sweeps_match_oracle(cpu_lib):
+    from oracle import grad
+    ch = synth.make_chains([8], 41)
+    st = synth.make_states((5, 8), 41)
+    bar = np.random.default_rng(41).standard_normal((5, 8))
+    (qb, qdb, qddb, _), pib = run_vjp_cpu(cpu_lib, 0, ch, st.q, st.qd, st.qdd, bar, np.float64)
+    ref_pi = np.zeros((8, 10))
+    for s in range(5):
+        r = grad.rnea_vjp(ch, st.q[s], st.qd[s], st.qdd[s], bar[s])
+        for x, y in zip((qb[s], qdb[s], qddb[s]), r[:3]):
+            assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y)
+        ref_pi += r[3]
+    assert np.linalg.norm(pib - ref_pi) <= 1e-12 * np.linalg.norm(ref_pi)
+    qdd = oracle.aba(ch, st.q, st.qd, st.tau)
+    (qb, qdb, _, tb), pib = run_vjp_cpu(cpu_lib, 1, ch, st.q, st.qd, qdd, bar, np.float64)
+    ref_pi = np.zeros((8, 10))
+    for s in range(5):
+        r = grad.aba_vjp(ch, st.q[s], st.qd[s], st.tau[s], bar[s])
+        for x, y in zip((qb[s], qdb[s], tb[s]), r[:3]):
+            assert np.linalg.norm(x - y) <= 1e-11 * np.linalg.norm(y)
+        ref_pi += r[3]
+    assert np.linalg.norm(pib - ref_pi) <= 1e-11 * np.linalg.norm(ref_pi)
+
+
+def test_fp64_adjoint_sweeps_ragged(cpu_lib):
+    from oracle import grad
+    ch = synth.make_chains([2, 9, 1], 43)
+    st = synth.make_states((ch.n_links_total,), 43)
+    bar = np.random.default_rng(43).standard_normal(ch.n_links_total)
+    (qb, qdb, qddb, _), pib = run_vjp_cpu(cpu_lib, 0, ch, st.q, st.qd, st.qdd, bar, np.float64)
+    for c in range(ch.n_chains):
+        a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+        r = grad.rnea_vjp(ch.chain(c), st.q[a:b], st.qd[a:b], st.qdd[a:b], bar[a:b])
+        for x, y in zip((qb[a:b], qdb[a:b], qddb[a:b], pib[a:b]), r):
+            # (a one-link chain's qd_bar is exactly zero: absolute floor for rounding noise)
+            assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y) + 1e-14
+
+
+def test_fp32_adjoint_sweeps_32_links(cpu_lib):
+    from oracle import grad
+    ch, st = synth.workload_32link(6)
+    cr, sr = ch.rounded(), st.rounded()
+    bar = np.random.default_rng(44).standard_normal((6, 32)).astype(np.float32).astype(np.float64)
+    (qb, qdb, qddb, _), pib = run_vjp_cpu(cpu_lib, 0, cr, sr.q, sr.qd, sr.qdd, bar, np.float32)
+    for s in range(6):
+        r = grad.rnea_vjp(cr, sr.q[s], sr.qd[s], sr.qdd[s], bar[s])
+        for x, y in zip((qb[s], qdb[s], qddb[s]), r[:3]):
+            assert np.linalg.norm(x - y) <= 1e-4 * np.linalg.norm(y)
