@@ -27,7 +27,7 @@ def dev_t(a, device, dtype):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
 
 
-def rel(x, ref, floor=1e-13):
+def rel(x, ref, floor=1e-3):
     """Relative error; quantities that vanish analytically (a one-link chain's qd_bar) get an absolute floor."""
     return np.linalg.norm(np.asarray(x, np.float64) - ref) / max(np.linalg.norm(ref), floor)
 
