@@ -197,6 +197,45 @@ int pdyn_aba_fd_vjp_f64(const pdyn_model* model, const pdyn_batch* batch, const 
                         const double* qdd, const double* qdd_bar, double* q_bar, double* qd_bar, double* tau_bar,
                         double* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Rollouts: `steps` steps of semi-implicit Euler driven by the forward
+ * dynamics (eq. (4) is "numerically integrated" to produce trajectories),
+ *   qdd_t = FD(q_t, qd_t, tau_t), qd_{t+1} = qd_t + dt qdd_t, q_{t+1} = q_t + dt qd_{t+1},
+ * all steps in one launch. q and qd (joint layout) hold the initial state on
+ * entry and the final state on return. tau_seq is [steps][joint layout].
+ * Checkpoints of (q_t, qd_t) at t = 0, k, 2k, ... (k = ckpt_every) are written
+ * to ckpt_q, ckpt_qd, each [ceil(steps / k)][joint layout]. No tip wrench
+ * (batch->tip_wrench must be NULL: PDYN_EUNSUPPORTED otherwise).
+ */
+int pdyn_rollout(const pdyn_model* model, const pdyn_batch* batch, int steps, double dt, int ckpt_every,
+                 const float* tau_seq, float* q, float* qd, float* ckpt_q, float* ckpt_qd, void* workspace,
+                 size_t workspace_bytes, void* stream);
+int pdyn_rollout_f64(const pdyn_model* model, const pdyn_batch* batch, int steps, double dt, int ckpt_every,
+                     const double* tau_seq, double* q, double* qd, double* ckpt_q, double* ckpt_qd, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/*
+ * Adjoint of a rollout: given the checkpoints written by pdyn_rollout (same
+ * steps, dt, ckpt_every, tau_seq) and the cotangents qT_bar, qdT_bar of the
+ * final state, returns dL/dq_0 (q0_bar), dL/dqd_0 (qd0_bar), dL/dtau_t for
+ * every step (tau_bar_seq, [steps][joint layout]) and, unless NULL, dL/dpi
+ * (inertia_bar, as for pdyn_rnea_id_vjp, summed over steps and states). Each
+ * k-step segment is recomputed from its checkpoint, then run backwards with
+ * the forward-dynamics adjoint. One launch for the whole reverse pass.
+ */
+int pdyn_rollout_vjp(const pdyn_model* model, const pdyn_batch* batch, int steps, double dt, int ckpt_every,
+                     const float* tau_seq, const float* ckpt_q, const float* ckpt_qd, const float* qT_bar,
+                     const float* qdT_bar, float* q0_bar, float* qd0_bar, float* tau_bar_seq, float* inertia_bar,
+                     void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_rollout_vjp_f64(const pdyn_model* model, const pdyn_batch* batch, int steps, double dt, int ckpt_every,
+                         const double* tau_seq, const double* ckpt_q, const double* ckpt_qd, const double* qT_bar,
+                         const double* qdT_bar, double* q0_bar, double* qd0_bar, double* tau_bar_seq,
+                         double* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of pdyn_rollout (with_grad = 0) or pdyn_rollout_vjp (1). */
+size_t pdyn_rollout_workspace_bytes(int with_grad, const pdyn_model* model, const pdyn_batch* batch, int ckpt_every,
+                                    int scalar_bytes);
+
 #ifdef __cplusplus
 }
 #endif

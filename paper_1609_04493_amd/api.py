@@ -71,6 +71,15 @@ def lib():
             L.pdyn_model_prepared_bytes.restype = ctypes.c_size_t
             L.pdyn_model_prepare.argtypes = [ctypes.POINTER(_Model), ctypes.c_int, vp, ctypes.c_size_t, vp]
             L.pdyn_model_prepare.restype = ctypes.c_int
+            ci, cd = ctypes.c_int, ctypes.c_double
+            for name in ("pdyn_rollout", "pdyn_rollout_f64"):
+                getattr(L, name).argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ci, cd, ci] + [vp] * 5 + [vp, ctypes.c_size_t, vp]
+                getattr(L, name).restype = ci
+            for name in ("pdyn_rollout_vjp", "pdyn_rollout_vjp_f64"):
+                getattr(L, name).argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ci, cd, ci] + [vp] * 9 + [vp, ctypes.c_size_t, vp]
+                getattr(L, name).restype = ci
+            L.pdyn_rollout_workspace_bytes.argtypes = [ci, ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ci, ci]
+            L.pdyn_rollout_workspace_bytes.restype = ctypes.c_size_t
             _lib = L
     return _lib
 
@@ -269,3 +278,56 @@ def aba_fd_vjp(model: Model, q, qd, qdd, qdd_bar, base_vel=ZERO6, base_acc=GRAVI
     _call("pdyn_aba_fd_vjp", OP_ABA_FD_VJP, model, n_states, (q, qd, qdd, qdd_bar, qb, qdb, tb, pib),
           base_vel, base_acc, tip, workspace)
     return qb, qdb, tb, pib
+
+
+def n_checkpoints(steps: int, every: int) -> int:
+    return (steps + every - 1) // every
+
+
+def _rollout_call(name, with_grad, model, n_states, steps, dt, every, ptrs, base_vel, base_acc, workspace):
+    L = lib()
+    fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
+    m = model.c_struct()
+    b = _batch_struct(n_states, base_vel, base_acc, None)
+    nbytes = L.pdyn_rollout_workspace_bytes(with_grad, ctypes.byref(m), ctypes.byref(b), every, model.scalar_bytes)
+    if nbytes == 0:
+        raise PdynError(f"{name}: invalid arguments for workspace query")
+    ws = (workspace or _workspace(model.device)).get(nbytes, model.device)
+    stream = torch.cuda.current_stream(model.device).cuda_stream
+    st = fn(ctypes.byref(m), ctypes.byref(b), int(steps), float(dt), int(every),
+            *[0 if p is None else p.data_ptr() for p in ptrs], ws.data_ptr(), ws.numel(), stream)
+    _check(st, name)
+
+
+def rollout(model: Model, q0, qd0, tau_seq, dt, ckpt_every=10, base_vel=ZERO6, base_acc=GRAVITY_ACC,
+            out=None, workspace=None):
+    """Fused rollout (pdyn_rollout). Returns (q_T, qd_T, ckpt_q, ckpt_qd); tau_seq is [steps, *joint layout]."""
+    n_states = _n_states(model, q0)
+    steps = tau_seq.shape[0]
+    _prep(model, (q0, qd0, tau_seq))
+    C = n_checkpoints(steps, ckpt_every)
+    if out is None:
+        out = (q0.clone(), qd0.clone(), torch.empty((C,) + tuple(q0.shape), dtype=q0.dtype, device=q0.device),
+               torch.empty((C,) + tuple(q0.shape), dtype=q0.dtype, device=q0.device))
+    else:
+        out[0].copy_(q0)
+        out[1].copy_(qd0)
+    q, qd, cq, cqd = out
+    _rollout_call("pdyn_rollout", 0, model, n_states, steps, dt, ckpt_every, (tau_seq, q, qd, cq, cqd),
+                  base_vel, base_acc, workspace)
+    return q, qd, cq, cqd
+
+
+def rollout_vjp(model: Model, tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, dt, ckpt_every=10, base_vel=ZERO6,
+                base_acc=GRAVITY_ACC, want_inertia=True, out=None, workspace=None):
+    """Fused rollout adjoint (pdyn_rollout_vjp). Returns (q0_bar, qd0_bar, tau_bar_seq, inertia_bar)."""
+    n_states = _n_states(model, qT_bar)
+    steps = tau_seq.shape[0]
+    _prep(model, (tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar))
+    if out is None:
+        out = (torch.empty_like(qT_bar), torch.empty_like(qT_bar), torch.empty_like(tau_seq),
+               _inertia_bar_like(model) if want_inertia else None)
+    q0b, qd0b, tb, pib = out
+    _rollout_call("pdyn_rollout_vjp", 1, model, n_states, steps, dt, ckpt_every,
+                  (tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0b, qd0b, tb, pib), base_vel, base_acc, workspace)
+    return q0b, qd0b, tb, pib

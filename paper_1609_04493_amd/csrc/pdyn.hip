@@ -7,6 +7,10 @@
 //   k_vjp              per state: the adjoint sweeps (ID or FD vector-Jacobian
 //                      product), inertia cotangents summed per wave.
 //   k_reduce_partials  per (link, parameter): sum of the per-wave partials.
+//   k_rollout          per state: T steps of forward dynamics + semi-implicit
+//                      Euler in one launch, (q, qd) checkpoints every k steps.
+//   k_rollout_vjp      per state: the rollout adjoint, segment by segment from
+//                      the checkpoints (recompute k steps, then k reverse steps).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -190,6 +194,126 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
   else fd_vjp_one_state(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr, sink);
 }
 
+// ---- rollouts -------------------------------------------------------------------
+
+template <class T> struct DevRows {  // row t of a [T][dofs] array, offset to this state
+  const T* base;
+  long stride;
+  __device__ const T* operator()(int t) const { return base + (long)t * stride; }
+};
+template <class T> struct DevMutRows {
+  T* base;
+  long stride;
+  __device__ T* operator()(int t) const { return base + (long)t * stride; }
+};
+template <class T> struct DevCkpt {
+  T* qb;
+  T* qdb;
+  long stride;
+  __device__ T* q(int c) const { return qb + (long)c * stride; }
+  __device__ T* qd(int c) const { return qdb + (long)c * stride; }
+};
+// pi_bar accumulated over steps: element (link i, parameter k) at acc[(10 i + k) * stride].
+template <class T> struct AccumSink {
+  T* acc;
+  long stride;
+  __device__ void put(int i, const T g[10]) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[(10L * i + k) * stride] += g[k];
+  }
+};
+struct NoSink {
+  template <class T> __device__ void put(int, const T*) {}
+};
+
+struct ChainOf {
+  int n;
+  int64_t link0, dof0;
+};
+__device__ __forceinline__ ChainOf chain_of(int s, int n_chains, int n_max, const int32_t* link_ptr) {
+  ChainOf c;
+  if (n_chains == 1) {
+    c.n = n_max;
+    c.link0 = 0;
+    c.dof0 = (int64_t)s * n_max;
+  } else {
+    c.link0 = link_ptr[s];
+    c.n = link_ptr[s + 1] - (int)c.link0;
+    c.dof0 = c.link0;
+  }
+  return c;
+}
+
+template <class T>
+__device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
+  Boundary<T> bd;
+  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  bd.Ftip = sp_zero<T>();
+  return bd;
+}
+
+// Forward rollout, one lane per state, all steps in one launch.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_rollout(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
+                                                    const T* __restrict__ table, const double* __restrict__ wtable,
+                                                    int steps, T dt, int every, const T* tau_seq, T* q, T* qd,
+                                                    T* ckpt_q, T* ckpt_qd, long dofs, BoundaryArgs<T> ba, T* scratch) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_states) return;
+  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+  Scratch<T> scr{scratch + s, (long)n_states, ScratchWords<kModeFD>::value};
+  rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every, q + c.dof0,
+                    qd + c.dof0, DevRows<T>{tau_seq + c.dof0, dofs}, DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs},
+                    boundary_of(ba), scr);
+}
+
+// Adjoint of a rollout, one lane per state. Workspace regions (all per state):
+// adjoint scratch [n_max][kVjpWords][n_states]; rows [n_states][(3 every + 6) n_max];
+// pi accumulators [n_max][10][n_states] (shared chain; zeroed here).
+template <class T, int PI>
+__global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chains, int n_max,
+                                                        const int32_t* __restrict__ link_ptr, const T* __restrict__ table,
+                                                        const double* __restrict__ wtable, int steps, T dt, int every,
+                                                        const T* tau_seq, const T* ckpt_q, const T* ckpt_qd,
+                                                        const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar,
+                                                        T* tau_bar_seq, T* pi_out, long dofs, BoundaryArgs<T> ba,
+                                                        T* scratch, T* rows_ws, T* pi_acc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_states) return;
+  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+  const long row_len = (long)(3 * every + 6) * n_max;
+  T* r = rows_ws + (long)s * row_len;
+  RolloutRows<T> rows{r, q0_bar + c.dof0, qd0_bar + c.dof0, r + 3L * every * n_max, r + (3L * every + 1) * n_max,
+                      r + (3L * every + 2) * n_max, r + (3L * every + 3) * n_max, r + (3L * every + 4) * n_max,
+                      r + (3L * every + 5) * n_max, c.n};
+  for (int i = 0; i < c.n; ++i) {
+    rows.lq[i] = qT_bar[c.dof0 + i];
+    rows.lqd[i] = qdT_bar[c.dof0 + i];
+  }
+  Scratch<T> scr{scratch + s, (long)n_states, kVjpWords};
+  DevRows<T> tau{tau_seq + c.dof0, dofs};
+  DevCkpt<T> ck{const_cast<T*>(ckpt_q) + c.dof0, const_cast<T*>(ckpt_qd) + c.dof0, dofs};
+  DevMutRows<T> tb{tau_bar_seq + c.dof0, dofs};
+  const T* tab = table + c.link0 * kLinkWords;
+  const double* wtab = wtable + c.link0 * kLinkWords;
+  if (PI == kPiNone) {
+    NoSink sink;
+    rollout_vjp_one_state(c.n, tab, wtab, steps, dt, every, tau, ck, tb, rows, boundary_of(ba), scr, sink);
+  } else {
+    AccumSink<T> sink;
+    if (PI == kPiWave) {  // shared chain: a private column per state, summed afterwards
+      sink.acc = pi_acc + s;
+      sink.stride = n_states;
+    } else {  // one chain per state: its own rows of the output
+      sink.acc = pi_out + c.link0 * 10;
+      sink.stride = 1;
+    }
+    for (int i = 0; i < 10 * c.n; ++i) sink.acc[(long)i * sink.stride] = T(0);
+    rollout_vjp_one_state(c.n, tab, wtab, steps, dt, every, tau, ck, tb, rows, boundary_of(ba), scr, sink);
+  }
+}
+
 // out[i] = sum over w of partials[i][w], w in increasing order.
 template <class T>
 __global__ void __launch_bounds__(256) k_reduce_partials(int n_out, int n_waves, const T* __restrict__ partials,
@@ -330,6 +454,111 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,
                      m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                      static_cast<const T*>(b->tip_wrench), ba, scratch);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+size_t rollout_layout(int with_grad, const pdyn_model* m, const pdyn_batch* b, int every, size_t scalar,
+                      size_t* scratch_off, size_t* rows_off, size_t* acc_off) {
+  size_t woff;
+  const size_t tb = tables_bytes(m, scalar, &woff);
+  const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
+  size_t off = m->prepared ? 0 : tb;
+  *scratch_off = off;
+  if (!with_grad) {
+    off += align_up(nm * (size_t)ScratchWords<kModeFD>::value * B * scalar);
+    *rows_off = *acc_off = off;
+    return off < kAlign ? kAlign : off;
+  }
+  off += align_up(nm * (size_t)kVjpWords * B * scalar);
+  *rows_off = off;
+  off += align_up(B * (size_t)(3 * every + 6) * nm * scalar);
+  *acc_off = off;
+  off += align_up(nm * 10 * B * scalar);
+  return off;
+}
+
+template <class T>
+int check_rollout_args(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int every) {
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (steps < 0 || every < 1 || !(dt == dt)) return PDYN_EINVAL;
+  if (b->tip_wrench) return PDYN_EUNSUPPORTED;  // rollouts run without an external tip wrench
+  if ((st = check_ptrs<T>({m->placement, m->twist, m->inertia}))) return st;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  return PDYN_OK;
+}
+
+template <class T>
+int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int every, const T* tau_seq, T* q,
+                T* qd, T* ckpt_q, T* ckpt_qd, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_rollout_args<T>(m, b, steps, dt, every);
+  if (st) return st;
+  if (b->n_states == 0 || steps == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({tau_seq, q, qd, ckpt_q, ckpt_qd}))) return st;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  size_t so, ro, ao;
+  if (ws_bytes < rollout_layout(0, m, b, every, sizeof(T), &so, &ro, &ao)) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  size_t woff;
+  tables_bytes(m, sizeof(T), &woff);
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const long dofs = (m->n_chains == 1) ? (long)b->n_states * m->n_links_max : (long)m->n_links_total;
+  const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_rollout<T>, dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains, m->n_links_max,
+                     m->link_ptr, reinterpret_cast<const T*>(tbase), reinterpret_cast<const double*>(tbase + woff),
+                     steps, (T)dt, every, tau_seq, q, qd, ckpt_q, ckpt_qd, dofs, ba,
+                     reinterpret_cast<T*>(base + so));
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+template <class T>
+int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int every, const T* tau_seq,
+                    const T* ckpt_q, const T* ckpt_qd, const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar,
+                    T* tau_bar_seq, T* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_rollout_args<T>(m, b, steps, dt, every);
+  if (st) return st;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq}))) return st;
+  if (inertia_bar && !aligned(inertia_bar, sizeof(T))) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  size_t so, ro, ao;
+  if (ws_bytes < rollout_layout(1, m, b, every, sizeof(T), &so, &ro, &ao)) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  size_t woff;
+  tables_bytes(m, sizeof(T), &woff);
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const long dofs = (m->n_chains == 1) ? (long)b->n_states * m->n_links_max : (long)m->n_links_total;
+  const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
+  T* acc = reinterpret_cast<T*>(base + ao);
+#define PDYN_LAUNCH_RVJP(PI)                                                                                     \
+  hipLaunchKernelGGL((k_rollout_vjp<T, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
+                     m->n_links_max, m->link_ptr, reinterpret_cast<const T*>(tbase),                             \
+                     reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
+                     ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
+                     reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc)
+  if (!inertia_bar) {
+    PDYN_LAUNCH_RVJP(kPiNone);
+  } else if (m->n_chains == 1) {
+    PDYN_LAUNCH_RVJP(kPiWave);
+    const int n_out = m->n_links_max * 10;
+    hipLaunchKernelGGL(k_reduce_partials<T>, dim3((n_out + 255) / 256), dim3(256), 0, s, n_out, b->n_states, acc,
+                       inertia_bar);
+  } else {
+    PDYN_LAUNCH_RVJP(kPiDirect);
+  }
+#undef PDYN_LAUNCH_RVJP
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -480,6 +709,38 @@ int pdyn_aba_fd_vjp_f64(const pdyn_model* m, const pdyn_batch* b, const double* 
                         const double* qdd, const double* qdd_bar, double* q_bar, double* qd_bar, double* tau_bar,
                         double* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
   return run_vjp<double, kVjpFD>(m, b, q, qd, qdd, qdd_bar, q_bar, qd_bar, tau_bar, inertia_bar, ws, ws_bytes, stream);
+}
+
+size_t pdyn_rollout_workspace_bytes(int with_grad, const pdyn_model* model, const pdyn_batch* batch, int ckpt_every,
+                                    int scalar_bytes) {
+  if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
+  if (check_model_batch(model, batch) || ckpt_every < 1) return 0;
+  size_t so, ro, ao;
+  return rollout_layout(with_grad ? 1 : 0, model, batch, ckpt_every, (size_t)scalar_bytes, &so, &ro, &ao);
+}
+
+int pdyn_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int ckpt_every, const float* tau_seq,
+                 float* q, float* qd, float* ckpt_q, float* ckpt_qd, void* ws, size_t ws_bytes, void* stream) {
+  return run_rollout<float>(m, b, steps, dt, ckpt_every, tau_seq, q, qd, ckpt_q, ckpt_qd, ws, ws_bytes, stream);
+}
+int pdyn_rollout_f64(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int ckpt_every,
+                     const double* tau_seq, double* q, double* qd, double* ckpt_q, double* ckpt_qd, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return run_rollout<double>(m, b, steps, dt, ckpt_every, tau_seq, q, qd, ckpt_q, ckpt_qd, ws, ws_bytes, stream);
+}
+int pdyn_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int ckpt_every,
+                     const float* tau_seq, const float* ckpt_q, const float* ckpt_qd, const float* qT_bar,
+                     const float* qdT_bar, float* q0_bar, float* qd0_bar, float* tau_bar_seq, float* inertia_bar,
+                     void* ws, size_t ws_bytes, void* stream) {
+  return run_rollout_vjp<float>(m, b, steps, dt, ckpt_every, tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0_bar,
+                                qd0_bar, tau_bar_seq, inertia_bar, ws, ws_bytes, stream);
+}
+int pdyn_rollout_vjp_f64(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, int ckpt_every,
+                         const double* tau_seq, const double* ckpt_q, const double* ckpt_qd, const double* qT_bar,
+                         const double* qdT_bar, double* q0_bar, double* qd0_bar, double* tau_bar_seq,
+                         double* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
+  return run_rollout_vjp<double>(m, b, steps, dt, ckpt_every, tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0_bar,
+                                 qd0_bar, tau_bar_seq, inertia_bar, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -193,12 +193,20 @@ template <class T> struct Boundary {
   Sp<T> V0, dV0, Ftip;
 };
 
+// Default consumer of the forward-dynamics output: qdd_out[i] = qdd_i.
+template <class T> struct StoreQdd {
+  T* out;
+  PD_HD void operator()(int i, T qdd) const { out[i] = qdd; }
+};
+
 // The three sweeps for one state of an n-link chain whose link records start at
 // `table` (scalar T) and `wtable` (the same records in double). MODE selects ID
-// (tau_out), FD (qdd_out) or both.
-template <class T, int MODE>
+// (tau_out), FD (qdd_out) or both. Each qdd_i is handed to epi(i, qdd_i) as
+// soon as the last sweep produces it (after the last read of q_i), so a caller
+// can fold an integrator update into the pass.
+template <class T, int MODE, class Epi>
 PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
-                              const Boundary<T>& bd, const Scratch<T>& scr) {
+                              const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi) {
   constexpr bool kID = (MODE & kModeID) != 0;
   constexpr bool kFD = (MODE & kModeFD) != 0;
   constexpr int kOffB = kID ? 6 : 0;  // scratch offset of the bias wrench
@@ -285,9 +293,15 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
       const Sp<T> a = X_twist(g, lam);
       const T qdd = chat - dot(U, a) * invD;
       lam = a + qdd * L.S;
-      io.qdd_out[i] = qdd;
+      epi(i, qdd);
     }
   }
+}
+
+template <class T, int MODE>
+PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
+                              const Boundary<T>& bd, const Scratch<T>& scr) {
+  dynamics_one_state<T, MODE>(n, table, wtable, io, bd, scr, StoreQdd<T>{io.qdd_out});
 }
 
 // ============================================================================
@@ -487,6 +501,117 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
   }
   id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.tau_bar, T(-1), io.q_bar, io.qd_bar,
               static_cast<T*>(nullptr), bd, scr, sink);
+}
+
+
+// ============================================================================
+// Rollouts: semi-implicit Euler driven by the forward dynamics,
+//   qdd_t = FD(q_t, qd_t, tau_t);  qd_{t+1} = qd_t + dt qdd_t;  q_{t+1} = q_t + dt qd_{t+1},
+// with (q, qd) checkpoints every k steps, and the adjoint of L(q_T, qd_T)
+// through the whole rollout by checkpoint recomputation. Reverse step t, with
+// (lq, lqd) the cotangents of (q_{t+1}, qd_{t+1}):
+//   w = lqd + dt lq                       (qd_{t+1} also feeds q_{t+1})
+//   (q_bar, qd_bar, tau_bar, pi_bar) = FD adjoint at (q_t, qd_t, qdd_t) with qdd_bar = dt w
+//   lq <- lq + q_bar,  lqd <- w + qd_bar,  tau_bar_t = tau_bar,  pi_bar summed over steps.
+// Per-state working rows (this state's n-vectors) live in RolloutRows.
+// ============================================================================
+
+template <class T> struct EulerStep {
+  T* q;
+  T* qd;
+  T dt;
+  PD_HD void operator()(int i, T qdd) const {
+    const T v = qd[i] + dt * qdd;
+    qd[i] = v;
+    q[i] = q[i] + dt * v;
+  }
+};
+
+template <class T> struct EulerStepKeep {  // also records qdd_t for the reverse pass
+  T* q;
+  T* qd;
+  T* qdd_keep;
+  T dt;
+  PD_HD void operator()(int i, T qdd) const {
+    qdd_keep[i] = qdd;
+    const T v = qd[i] + dt * qdd;
+    qd[i] = v;
+    q[i] = q[i] + dt * v;
+  }
+};
+
+// Forward rollout of one state: q, qd (length n) are advanced in place; tau(t)
+// returns the torque row of step t; ckpt(c) returns (q, qd) rows of checkpoint c.
+template <class T, class TauRow, class CkptRow>
+PD_HD void rollout_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every, T* q, T* qd,
+                             const TauRow& tau, const CkptRow& ckpt, const Boundary<T>& bd, const Scratch<T>& scr) {
+  for (int t = 0; t < steps; ++t) {
+    if (t % every == 0) {
+      T* cq = ckpt.q(t / every);
+      T* cqd = ckpt.qd(t / every);
+      for (int i = 0; i < n; ++i) { cq[i] = q[i]; cqd[i] = qd[i]; }
+    }
+    JointIO<T> io{q, qd, nullptr, tau(t), nullptr, nullptr};
+    dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr, EulerStep<T>{q, qd, dt});
+  }
+}
+
+// Per-state rows used by the reverse pass (each of length n unless stated):
+//   seg_q(j), seg_qd(j), seg_qdd(j): the k states of the current segment;
+//   lq, lqd: running cotangents; w, qddbar: temporaries; qbar, qdbar: FD
+//   adjoint outputs; cur_q, cur_qd: the state being recomputed.
+template <class T> struct RolloutRows {
+  T* seg;    // [every][3][n]
+  T* lq;
+  T* lqd;
+  T* w;
+  T* qddbar;
+  T* qbar;
+  T* qdbar;
+  T* cur_q;
+  T* cur_qd;
+  int n;
+  PD_HD T* seg_q(int j) const { return seg + (long)(3 * j) * n; }
+  PD_HD T* seg_qd(int j) const { return seg + (long)(3 * j + 1) * n; }
+  PD_HD T* seg_qdd(int j) const { return seg + (long)(3 * j + 2) * n; }
+};
+
+// Adjoint of L(q_T, qd_T) for one state. On entry rows.lq / rows.lqd hold
+// dL/dq_T, dL/dqd_T; on exit dL/dq_0, dL/dqd_0. taubar(t) receives dL/dtau_t.
+template <class T, class TauRow, class CkptRow, class TauBarRow, class Sink>
+PD_HD void rollout_vjp_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every,
+                                 const TauRow& tau, const CkptRow& ckpt, const TauBarRow& taubar,
+                                 const RolloutRows<T>& rows, const Boundary<T>& bd, const Scratch<T>& scr,
+                                 Sink& sink) {
+  const int n_ckpt = (steps + every - 1) / every;
+  for (int c = n_ckpt - 1; c >= 0; --c) {
+    const int t0 = c * every;
+    const int t1 = (t0 + every < steps) ? t0 + every : steps;
+    // recompute the segment from its checkpoint, keeping (q_t, qd_t, qdd_t)
+    const T* cq = ckpt.q(c);
+    const T* cqd = ckpt.qd(c);
+    for (int i = 0; i < n; ++i) { rows.cur_q[i] = cq[i]; rows.cur_qd[i] = cqd[i]; }
+    for (int t = t0; t < t1; ++t) {
+      const int j = t - t0;
+      for (int i = 0; i < n; ++i) { rows.seg_q(j)[i] = rows.cur_q[i]; rows.seg_qd(j)[i] = rows.cur_qd[i]; }
+      JointIO<T> io{rows.cur_q, rows.cur_qd, nullptr, tau(t), nullptr, nullptr};
+      dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr,
+                                     EulerStepKeep<T>{rows.cur_q, rows.cur_qd, rows.seg_qdd(j), dt});
+    }
+    // reverse steps
+    for (int t = t1 - 1; t >= t0; --t) {
+      const int j = t - t0;
+      for (int i = 0; i < n; ++i) rows.w[i] = rows.lqd[i] + dt * rows.lq[i];
+      for (int i = 0; i < n; ++i) rows.qddbar[i] = dt * rows.w[i];
+      VjpIO<T> io{rows.seg_q(j), rows.seg_qd(j), rows.seg_qdd(j), rows.qddbar, rows.qbar, rows.qdbar, nullptr,
+                  taubar(t)};
+      fd_vjp_one_state(n, table, wtable, io, bd, scr, sink);
+      for (int i = 0; i < n; ++i) {
+        rows.lq[i] += rows.qbar[i];
+        rows.lqd[i] = rows.w[i] + rows.qdbar[i];
+      }
+    }
+  }
 }
 
 }  // namespace pdyn

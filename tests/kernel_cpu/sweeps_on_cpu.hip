@@ -111,3 +111,79 @@ int cpu_vjp_f64(int op, int n_states, int n_chains, int n_max, const int32_t* lp
                          tau_bar, pi_bar, tip, V0, dV0);
 }
 }
+
+// ---- rollouts -------------------------------------------------------------------
+template <class T> struct RowsOf {
+  const T* base;
+  long stride;
+  const T* operator()(int t) const { return base + (long)t * stride; }
+};
+template <class T> struct MutRowsOf {
+  T* base;
+  long stride;
+  T* operator()(int t) const { return base + (long)t * stride; }
+};
+template <class T> struct CkptOf {
+  T* q_base;
+  T* qd_base;
+  long stride;
+  T* q(int c) const { return q_base + (long)c * stride; }
+  T* qd(int c) const { return qd_base + (long)c * stride; }
+};
+
+// Shared chain, states [B][n]; tau_seq [T][B][n]; checkpoints [C][B][n].
+template <class T>
+static int run_rollout(int with_grad, int n_states, int n, const T* placement, const T* twist, const T* inertia,
+                       int steps, T dt, int every, const T* tau_seq, T* q, T* qd, T* ckq, T* ckqd,
+                       const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar, T* tau_bar_seq, double* pi_bar,
+                       const T* V0, const T* dV0) {
+  std::vector<T> table((size_t)n * kLinkWords);
+  std::vector<double> wtable((size_t)n * kLinkWords);
+  for (int i = 0; i < n; ++i) {
+    make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, &wtable[i * kLinkWords]);
+    for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
+  }
+  Boundary<T> bd;
+  bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
+  bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
+  bd.Ftip = sp_zero<T>();
+  std::vector<T> scratch((size_t)n * kVjpWords, T(-7777));
+  Scratch<T> scr{scratch.data(), 1, kVjpWords};
+  const long bn = (long)n_states * n;
+  for (int s = 0; s < n_states; ++s) {
+    RowsOf<T> tau{tau_seq + (long)s * n, bn};
+    CkptOf<T> ck{ckq + (long)s * n, ckqd + (long)s * n, bn};
+    if (!with_grad) {
+      Scratch<T> scr8{scratch.data(), 1, ScratchWords<kModeFD>::value};
+      rollout_one_state(n, table.data(), wtable.data(), steps, dt, every, q + (long)s * n, qd + (long)s * n, tau, ck,
+                        bd, scr8);
+    } else {
+      std::vector<T> seg((size_t)every * 3 * n), rowbuf((size_t)8 * n);
+      RolloutRows<T> rows{seg.data(), q0_bar + (long)s * n, qd0_bar + (long)s * n, rowbuf.data(),
+                          rowbuf.data() + n, rowbuf.data() + 2 * n, rowbuf.data() + 3 * n, rowbuf.data() + 4 * n,
+                          rowbuf.data() + 5 * n, n};
+      for (int i = 0; i < n; ++i) { rows.lq[i] = qT_bar[(long)s * n + i]; rows.lqd[i] = qdT_bar[(long)s * n + i]; }
+      MutRowsOf<T> tb{tau_bar_seq + (long)s * n, bn};
+      SumSink<T> sink{pi_bar};
+      rollout_vjp_one_state(n, table.data(), wtable.data(), steps, dt, every, tau, ck, tb, rows, bd, scr, sink);
+    }
+  }
+  return 0;
+}
+
+extern "C" {
+int cpu_rollout_f64(int with_grad, int n_states, int n, const double* pl, const double* tw, const double* in,
+                    int steps, double dt, int every, const double* tau_seq, double* q, double* qd, double* ckq,
+                    double* ckqd, const double* qT_bar, const double* qdT_bar, double* q0_bar, double* qd0_bar,
+                    double* tau_bar_seq, double* pi_bar, const double* V0, const double* dV0) {
+  return run_rollout<double>(with_grad, n_states, n, pl, tw, in, steps, dt, every, tau_seq, q, qd, ckq, ckqd, qT_bar,
+                             qdT_bar, q0_bar, qd0_bar, tau_bar_seq, pi_bar, V0, dV0);
+}
+int cpu_rollout_f32(int with_grad, int n_states, int n, const float* pl, const float* tw, const float* in,
+                    int steps, float dt, int every, const float* tau_seq, float* q, float* qd, float* ckq,
+                    float* ckqd, const float* qT_bar, const float* qdT_bar, float* q0_bar, float* qd0_bar,
+                    float* tau_bar_seq, double* pi_bar, const float* V0, const float* dV0) {
+  return run_rollout<float>(with_grad, n_states, n, pl, tw, in, steps, dt, every, tau_seq, q, qd, ckq, ckqd, qT_bar,
+                            qdT_bar, q0_bar, qd0_bar, tau_bar_seq, pi_bar, V0, dV0);
+}
+}

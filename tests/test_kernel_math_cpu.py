@@ -177,3 +177,37 @@ def test_fp32_adjoint_sweeps_32_links(cpu_lib):
         r = grad.rnea_vjp(cr, sr.q[s], sr.qd[s], sr.qdd[s], bar[s])
         for x, y in zip((qb[s], qdb[s], qddb[s]), r[:3]):
             assert np.linalg.norm(x - y) <= 1e-4 * np.linalg.norm(y)
+
+
+# ---- rollouts -----------------------------------------------------------------------
+
+def test_fp64_rollout_sweeps_match_oracle(cpu_lib):
+    """Forward rollout and its checkpointed adjoint (partial last segment) against the oracle."""
+    from oracle import grad
+    f = cpu_lib.cpu_rollout_f64
+    f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_double, ctypes.c_int] + [ctypes.c_void_p] * 13
+    n, B, T, dt, k = 5, 3, 23, 1e-2, 10
+    ch = synth.make_chains([n], 3)
+    st = synth.make_states((B, n), 3)
+    tau = 10 * np.random.default_rng(1).standard_normal((T, B, n))
+    C = (T + k - 1) // k
+    q, qd = st.q.copy(), st.qd.copy()
+    ckq, ckqd = np.zeros((C, B, n)), np.zeros((C, B, n))
+    args = [_p(np.ascontiguousarray(a)) for a in (ch.placement, ch.twist, ch.inertia)]
+    z6, g6 = np.zeros(6), np.ascontiguousarray(oracle.GRAVITY_ACC)
+    f(0, B, n, *args, T, dt, k, _p(tau), _p(q), _p(qd), _p(ckq), _p(ckqd), None, None, None, None, None, None, _p(z6), _p(g6))
+    qT_bar, qdT_bar = 2 * q, np.zeros((B, n))
+    q0b, qd0b, tb, pb = np.zeros((B, n)), np.zeros((B, n)), np.zeros((T, B, n)), np.zeros((n, 10))
+    f(1, B, n, *args, T, dt, k, _p(tau), None, None, _p(ckq), _p(ckqd), _p(qT_bar), _p(qdT_bar), _p(q0b), _p(qd0b),
+      _p(tb), _p(pb), _p(z6), _p(g6))
+    pref = np.zeros((n, 10))
+    for s in range(B):
+        rq, rqd = oracle.rollout1(ch, T, dt, st.q[s], st.qd[s], tau[:, s, :])
+        assert np.linalg.norm(q[s] - rq) <= 1e-13 * np.linalg.norm(rq)
+        assert np.array_equal(ckq[0, s], st.q[s])
+        gq, gqd, gt, gpi = grad.rollout_gradient(ch, T, dt, st.q[s], st.qd[s], tau[:, s, :])
+        assert np.linalg.norm(q0b[s] - gq) <= 1e-12 * np.linalg.norm(gq)
+        assert np.linalg.norm(qd0b[s] - gqd) <= 1e-12 * np.linalg.norm(gqd)
+        assert np.linalg.norm(tb[:, s, :] - gt) <= 1e-12 * np.linalg.norm(gt)
+        pref += gpi
+    assert np.linalg.norm(pb - pref) <= 1e-12 * np.linalg.norm(pref)
