@@ -42,6 +42,7 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-other-workloads", action="store_true", help="only the 32-link headline workload")
     p.add_argument("--profile-only", action="store_true", help="launch the timed steps only (for rocprofv3)")
     return p.parse_args()
 
@@ -85,6 +86,82 @@ def cpu_baseline(ch, st):
     return {"value": reps * len(sr.q) / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"the full {len(sr.q)}-state, {N_LINKS}-link batch (ID + FD per state), {reps} pass(es), "
                       f"{el:.1f} s wall, {threads} Python threads each running the C oracle on a contiguous slice of states"}
+
+
+def bench_uneven(args, dev):
+    """4096 chains of U[10, 100] links, one state each: fused ID+FD, autotuned launch, eager and graph replay."""
+    import torch
+    from paper_1609_04493_amd import api, autotune, synth
+    ch, st = synth.workload_uneven()
+    model = api.Model(ch, dev, torch.float32)
+    q, qd, qdd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.qdd, st.tau))
+    out = (torch.empty_like(q), torch.empty_like(q))
+    ws = api.Workspace()
+    call = lambda: api.id_fd(model, q, qd, qdd, tau, out=out, workspace=ws)
+    api.set_launch(api.OP_ID_FD, 0, 0)
+    model.use_order = False
+    ms_plain_launch = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
+    best, timings = autotune.tune(api.OP_ID_FD, model, call, model.n_chains)
+    autotune.apply(best, api.OP_ID_FD, model)
+    ms_eager = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    ms_graph = time_steps(g.replay, args.steps, args.warmup, torch.cuda.current_stream(dev))
+    api.set_launch(api.OP_ID_FD, 0, 0)
+    return {"workload": "4096 chains, links uniform in [10, 100] (%d joints), one state each, fused ID+FD" % ch.n_links_total,
+            "evals_per_s_graph": model.n_chains / (ms_graph * 1e-3),
+            "joint_evals_per_s_graph": ch.n_links_total / (ms_graph * 1e-3),
+            "ms_graph": ms_graph, "ms_eager_tuned": ms_eager, "ms_default_launch_natural_order": ms_plain_launch,
+            "tuned": best, "candidates": len(timings), "longest_chain": int(ch.lengths().max())}
+
+
+def bench_fd_grad_50(args, dev):
+    """50-link chain, 8192 states: FD, then the FD adjoint of L = ||qdd||^2 (inertia gradients on)."""
+    import torch
+    from paper_1609_04493_amd import api, synth
+    ch, st = synth.workload_50link(8192)
+    model = api.Model(ch, dev, torch.float32)
+    q, qd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.tau))
+    qdd, qdd_bar = torch.empty_like(q), torch.empty_like(q)
+    g = tuple(torch.empty_like(q) for _ in range(3)) + (torch.empty((50, 10), device=dev),)
+    ws = api.Workspace()
+
+    def step():
+        api.aba_fd(model, q, qd, tau, out=qdd, workspace=ws)
+        torch.mul(qdd, 2.0, out=qdd_bar)
+        api.aba_fd_vjp(model, q, qd, qdd, qdd_bar, out=g, workspace=ws)
+
+    ms = time_steps(step, args.steps, args.warmup, torch.cuda.current_stream(dev))
+    return {"workload": "50-link chain, 8192 states, FD + adjoint (dL/d(q, qd, tau, inertia), L = ||qdd||^2)",
+            "evals_per_s": 8192 / (ms * 1e-3), "ms_per_step": ms}
+
+
+def bench_rollout_100(args, dev):
+    """100-link chain, 65536 states, 100 Euler steps: gradient of ||q_T||^2, checkpoint every 10 steps."""
+    import torch
+    from paper_1609_04493_amd import api, rollout, synth
+    B, n, T, dt = 65536, 100, 100, 1e-3
+    ch, st = synth.workload_100link_rollout(B)
+    model = api.Model(ch, dev, torch.float32)
+    tau = torch.empty((T, B, n), dtype=torch.float32, device=dev)
+    for t in range(T):
+        tau[t] = torch.as_tensor(synth.rollout_torques(t, (B, n), synth.config_seed(5)))
+    q0, qd0 = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd))
+    reps = max(1, min(3, args.steps))
+    stream = torch.cuda.current_stream(dev)
+    fused = rollout.FusedRolloutGrad(model, q0, qd0, tau, dt, 10)
+    ms_fused = time_steps(fused, reps, 1, stream)
+    plain = rollout.PlainRolloutGrad(model, q0, qd0, tau, dt, 10)
+    ms_plain = time_steps(plain, reps, 1, stream)
+    del plain
+    graphed = rollout.GraphedRolloutGrad(model, q0, qd0, tau, dt, 10)
+    ms_graph = time_steps(graphed, reps, 1, stream)
+    return {"workload": "100-link chain, 65536 states, 100 semi-implicit Euler steps (dt 1e-3), gradient of "
+                        "||q_T||^2 w.r.t. q0, qd0, every tau_t and the inertia parameters, checkpoints every 10",
+            "rollout_gradients_per_s": {"fused": 1e3 / ms_fused, "graph": 1e3 / ms_graph, "plain": 1e3 / ms_plain},
+            "state_steps_per_s_fused": B * T / (ms_fused * 1e-3),
+            "ms": {"fused": ms_fused, "graph": ms_graph, "plain": ms_plain}}
 
 
 def main():
@@ -202,6 +279,13 @@ def main():
         "error_vs_fp64_oracle": {"sample_states": len(idx), "tau": err_stats(et), "qdd": err_stats(eq),
                                  "metric": "per-state ||x - x*|| / ||x*||"},
     }
+    if not args.no_other_workloads:
+        others = {}
+        for name, fn in (("uneven_4096_chains", bench_uneven), ("fd_grad_50_links", bench_fd_grad_50),
+                         ("rollout_grad_100_links", bench_rollout_100)):
+            others[name] = fn(args, dev)
+            print(f"{name}: {json.dumps(others[name])}", file=sys.stderr, flush=True)
+        out["other_workloads"] = others
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ch, st)
     print(json.dumps(out), flush=True)

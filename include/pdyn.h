@@ -70,6 +70,11 @@ typedef struct pdyn_model {
    * scalar type, or NULL: then every call derives them again inside its
    * workspace (one extra small kernel per call). */
   const void* prepared;
+  /* One chain per state only: a permutation [n_chains] of the chains in the
+   * order lanes take them (e.g. longest first, so that each wavefront holds
+   * chains of similar length and the longest start first), or NULL for the
+   * natural order. Results are written in the natural layout either way. */
+  const int32_t* order;
 } pdyn_model;
 
 /*
@@ -92,6 +97,13 @@ typedef struct pdyn_batch {
   double base_vel[6];
   double base_acc[6];
   const void* tip_wrench;
+  /* Launch shape (0 = library default): threads per workgroup for the
+   * inverse/forward dynamics and rollout kernels (a multiple of 64, at most
+   * 256; the adjoint kernels always use 64), and an upper bound on the number
+   * of workgroups -- fewer than the work needs makes the launch persistent,
+   * each workgroup striding over the remaining work in a fixed order. */
+  int32_t block_threads;
+  int32_t max_blocks;
 } pdyn_batch;
 
 /* Operation selector for pdyn_workspace_bytes. */

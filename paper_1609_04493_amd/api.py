@@ -29,12 +29,12 @@ class PdynError(RuntimeError):
 class _Model(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_links_max", ctypes.c_int32), ("n_links_total", ctypes.c_int64),
                 ("link_ptr", ctypes.c_void_p), ("placement", ctypes.c_void_p), ("twist", ctypes.c_void_p),
-                ("inertia", ctypes.c_void_p), ("prepared", ctypes.c_void_p)]
+                ("inertia", ctypes.c_void_p), ("prepared", ctypes.c_void_p), ("order", ctypes.c_void_p)]
 
 
 class _Batch(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int32), ("base_vel", ctypes.c_double * 6), ("base_acc", ctypes.c_double * 6),
-                ("tip_wrench", ctypes.c_void_p)]
+                ("tip_wrench", ctypes.c_void_p), ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,16 +111,21 @@ class Model:
         self.n_links_total = int(lp[-1])
         self.link_ptr_host = lp
         self.link_ptr = torch.as_tensor(lp).to(self.device) if self.n_chains > 1 else None
+        # longest chains first (stable): wavefronts of similar lengths, longest work dispatched first
+        self.order_host = np.argsort(-self.lengths, kind="stable").astype(np.int32) if self.n_chains > 1 else None
+        self.order = torch.as_tensor(self.order_host).to(self.device) if self.n_chains > 1 else None
+        self.use_order = True
         self.prepared = None
         if prepare:
             self.prepare()
 
     def c_struct(self, with_prepared=True) -> _Model:
         prep = self.prepared if with_prepared else None
+        order = self.order if (self.use_order and self.order is not None) else None
         return _Model(self.n_chains, self.n_links_max, self.n_links_total,
                       0 if self.link_ptr is None else self.link_ptr.data_ptr(),
                       self.placement.data_ptr(), self.twist.data_ptr(), self.inertia.data_ptr(),
-                      0 if prep is None else prep.data_ptr())
+                      0 if prep is None else prep.data_ptr(), 0 if order is None else order.data_ptr())
 
     @property
     def scalar_bytes(self) -> int:
@@ -151,9 +156,18 @@ class Model:
         return (n_states, self.n_links_max) if self.n_chains == 1 else (self.n_links_total,)
 
 
-def _batch_struct(n_states, base_vel, base_acc, tip):
+# Launch shape per call: (block_threads, max_blocks); 0 = library default. Set by the autotuner.
+_launch_override = {}
+
+
+def set_launch(op: int, block_threads: int = 0, max_blocks: int = 0):
+    _launch_override[op] = (int(block_threads), int(max_blocks))
+
+
+def _batch_struct(n_states, base_vel, base_acc, tip, op=None):
     b = _Batch()
     b.n_states = n_states
+    b.block_threads, b.max_blocks = _launch_override.get(op, (0, 0))
     for k in range(6):
         b.base_vel[k] = float(base_vel[k])
         b.base_acc[k] = float(base_acc[k])
@@ -206,7 +220,7 @@ def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace):
     L = lib()
     fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
     m = model.c_struct()
-    b = _batch_struct(n_states, base_vel, base_acc, tip)
+    b = _batch_struct(n_states, base_vel, base_acc, tip, op)
     scalar = model.scalar_bytes
     nbytes = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), scalar)
     if nbytes == 0:

@@ -1,0 +1,79 @@
+"""Launch-shape autotuner for the dynamics kernels.
+
+For one operation on one model/batch, times every candidate launch shape
+(threads per workgroup, workgroup cap -- a cap below the work makes the launch
+persistent) and, for one chain per state, the chain order (natural, or longest
+first), with HIP events, and keeps the fastest. Results are recorded in a
+JSON table keyed by (operation, precision, model kind, links, states), which
+``apply`` installs into the binding so that later calls use them.
+"""
+
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import torch
+
+from . import api
+
+BLOCKS = (64, 128, 256)
+CAPS = (0, 256, 512, 1024)
+
+
+def key_of(op: int, model: api.Model, n_states: int) -> str:
+    kind = "shared" if model.n_chains == 1 else "per_state"
+    prec = "f64" if model.dtype == torch.float64 else "f32"
+    return f"{op}:{prec}:{kind}:{model.n_links_max}:{n_states}"
+
+
+def _time(fn, reps=20, warmup=3):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(op: int, model: api.Model, call, n_states: int, reps: int = 20):
+    """Time `call()` (which issues `op` on `model`) for every candidate; return (best, timings)."""
+    orders = (True, False) if model.n_chains > 1 else (True,)
+    timings = []
+    saved = api._launch_override.get(op)
+    saved_order = model.use_order
+    try:
+        for bt, cap, use_order in itertools.product(BLOCKS, CAPS, orders):
+            if cap and cap * bt >= n_states:
+                continue  # not persistent: same as uncapped
+            api.set_launch(op, bt, cap)
+            model.use_order = use_order
+            timings.append({"block_threads": bt, "max_blocks": cap, "order": use_order, "ms": _time(call, reps)})
+    finally:
+        model.use_order = saved_order
+        if saved is None:
+            api._launch_override.pop(op, None)
+        else:
+            api._launch_override[op] = saved
+    best = min(timings, key=lambda r: r["ms"])
+    return best, timings
+
+
+def record(path: str, op: int, model: api.Model, n_states: int, best: dict):
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table[key_of(op, model, n_states)] = best
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
+def apply(best: dict, op: int, model: api.Model):
+    api.set_launch(op, best["block_threads"], best["max_blocks"])
+    model.use_order = bool(best.get("order", True))

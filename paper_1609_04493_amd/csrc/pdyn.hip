@@ -23,7 +23,8 @@ namespace pdyn {
 namespace {
 
 constexpr int kMaxLinks = 1 << 16;
-constexpr int kBlock = 64;
+constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
+constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -49,44 +50,55 @@ template <class T> struct BoundaryArgs {
   T V0[6], dV0[6];
 };
 
+// Lane -> state: lane_index (0 .. n_states-1, possibly through `order`).
+__device__ __forceinline__ int state_of(int lane_index, const int32_t* __restrict__ order) {
+  return order ? order[lane_index] : lane_index;
+}
+
 template <class T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_dynamics(int n_states, int n_chains, int n_max,
-                                                     const int32_t* __restrict__ link_ptr,
-                                                     const T* __restrict__ table,
-                                                     const double* __restrict__ wtable, const T* q, const T* qd,
-                                                     const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
-                                                     const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_states) return;
-  int n;
-  int64_t link0, dof0;
-  if (n_chains == 1) {
-    n = n_max;
-    link0 = 0;
-    dof0 = (int64_t)s * n_max;
-  } else {
-    link0 = link_ptr[s];
-    n = link_ptr[s + 1] - (int)link0;
-    dof0 = link0;
+__global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chains, int n_max,
+                                                        const int32_t* __restrict__ link_ptr,
+                                                        const int32_t* __restrict__ order,
+                                                        const T* __restrict__ table,
+                                                        const double* __restrict__ wtable, const T* q, const T* qd,
+                                                        const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
+                                                        const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch) {
+  const long n_work = ((long)n_states + blockDim.x - 1) / blockDim.x;
+  for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {  // persistent when gridDim.x < n_work
+    const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
+    if (lane_index >= n_states) continue;
+    const int s = state_of(lane_index, order);
+    int n;
+    int64_t link0, dof0;
+    if (n_chains == 1) {
+      n = n_max;
+      link0 = 0;
+      dof0 = (int64_t)s * n_max;
+    } else {
+      link0 = link_ptr[s];
+      n = link_ptr[s + 1] - (int)link0;
+      dof0 = link0;
+    }
+    JointIO<T> io;
+    io.q = q + dof0;
+    io.qd = qd + dof0;
+    io.qdd_in = qdd_in ? qdd_in + dof0 : nullptr;
+    io.tau_in = tau_in ? tau_in + dof0 : nullptr;
+    io.tau_out = tau_out ? tau_out + dof0 : nullptr;
+    io.qdd_out = qdd_out ? qdd_out + dof0 : nullptr;
+    Boundary<T> bd;
+    bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+    bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+    if (tip) {
+      const T* t = tip + 6 * (int64_t)s;
+      bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+    } else {
+      bd.Ftip = sp_zero<T>();
+    }
+    // scratch column = lane: consecutive lanes touch consecutive words
+    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value};
+    dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
   }
-  JointIO<T> io;
-  io.q = q + dof0;
-  io.qd = qd + dof0;
-  io.qdd_in = qdd_in ? qdd_in + dof0 : nullptr;
-  io.tau_in = tau_in ? tau_in + dof0 : nullptr;
-  io.tau_out = tau_out ? tau_out + dof0 : nullptr;
-  io.qdd_out = qdd_out ? qdd_out + dof0 : nullptr;
-  Boundary<T> bd;
-  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
-  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
-  if (tip) {
-    const T* t = tip + 6 * (int64_t)s;
-    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
-  } else {
-    bd.Ftip = sp_zero<T>();
-  }
-  Scratch<T> scr{scratch + s, (long)n_states, ScratchWords<MODE>::value};
-  dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
 }
 
 // ---- adjoints ------------------------------------------------------------------
@@ -131,7 +143,7 @@ template <class T, int PI> struct PiSink {
 // rounded up to a whole wave, then [4][64][n_max] outputs of idle lanes.
 template <class T, int OP, int PI>
 __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
-                                                const T* __restrict__ table, const double* __restrict__ wtable,
+                                                const int32_t* __restrict__ order, const T* __restrict__ table, const double* __restrict__ wtable,
                                                 const T* q, const T* qd, const T* qdd, const T* bar_in, T* q_bar,
                                                 T* qd_bar, T* qdd_bar, T* tau_bar, T* pi_out, long n_waves,
                                                 const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
@@ -139,7 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
   const int lane_state = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = lane_state < n_states;
   if (PI != kPiWave && !active) return;
-  const int s = active ? lane_state : n_states - 1;  // idle lanes of a shared chain redo the last state
+  const int s = active ? state_of(lane_state, order) : n_states - 1;  // idle lanes of a shared chain redo the last state
   int n;
   int64_t link0, dof0;
   if (n_chains == 1) {
@@ -255,17 +267,23 @@ __device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
 
 // Forward rollout, one lane per state, all steps in one launch.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_rollout(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
-                                                    const T* __restrict__ table, const double* __restrict__ wtable,
-                                                    int steps, T dt, int every, const T* tau_seq, T* q, T* qd,
-                                                    T* ckpt_q, T* ckpt_qd, long dofs, BoundaryArgs<T> ba, T* scratch) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_states) return;
-  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
-  Scratch<T> scr{scratch + s, (long)n_states, ScratchWords<kModeFD>::value};
-  rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every, q + c.dof0,
-                    qd + c.dof0, DevRows<T>{tau_seq + c.dof0, dofs}, DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs},
-                    boundary_of(ba), scr);
+__global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chains, int n_max,
+                                                       const int32_t* __restrict__ link_ptr,
+                                                       const int32_t* __restrict__ order, const T* __restrict__ table,
+                                                       const double* __restrict__ wtable, int steps, T dt, int every,
+                                                       const T* tau_seq, T* q, T* qd, T* ckpt_q, T* ckpt_qd, long dofs,
+                                                       BoundaryArgs<T> ba, T* scratch) {
+  const long n_work = ((long)n_states + blockDim.x - 1) / blockDim.x;
+  for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {
+    const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
+    if (lane_index >= n_states) continue;
+    const int s = state_of(lane_index, order);
+    const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value};
+    rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every,
+                      q + c.dof0, qd + c.dof0, DevRows<T>{tau_seq + c.dof0, dofs},
+                      DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs}, boundary_of(ba), scr);
+  }
 }
 
 // Adjoint of a rollout, one lane per state. Workspace regions (all per state):
@@ -273,17 +291,19 @@ __global__ void __launch_bounds__(kBlock) k_rollout(int n_states, int n_chains, 
 // pi accumulators [n_max][10][n_states] (shared chain; zeroed here).
 template <class T, int PI>
 __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chains, int n_max,
-                                                        const int32_t* __restrict__ link_ptr, const T* __restrict__ table,
+                                                        const int32_t* __restrict__ link_ptr,
+                                                        const int32_t* __restrict__ order, const T* __restrict__ table,
                                                         const double* __restrict__ wtable, int steps, T dt, int every,
                                                         const T* tau_seq, const T* ckpt_q, const T* ckpt_qd,
                                                         const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar,
                                                         T* tau_bar_seq, T* pi_out, long dofs, BoundaryArgs<T> ba,
                                                         T* scratch, T* rows_ws, T* pi_acc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_states) return;
+  const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lane_index >= n_states) return;
+  const int s = state_of(lane_index, order);
   const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
   const long row_len = (long)(3 * every + 6) * n_max;
-  T* r = rows_ws + (long)s * row_len;
+  T* r = rows_ws + (long)lane_index * row_len;
   RolloutRows<T> rows{r, q0_bar + c.dof0, qd0_bar + c.dof0, r + 3L * every * n_max, r + (3L * every + 1) * n_max,
                       r + (3L * every + 2) * n_max, r + (3L * every + 3) * n_max, r + (3L * every + 4) * n_max,
                       r + (3L * every + 5) * n_max, c.n};
@@ -291,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
     rows.lq[i] = qT_bar[c.dof0 + i];
     rows.lqd[i] = qdT_bar[c.dof0 + i];
   }
-  Scratch<T> scr{scratch + s, (long)n_states, kVjpWords};
+  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
   DevRows<T> tau{tau_seq + c.dof0, dofs};
   DevCkpt<T> ck{const_cast<T*>(ckpt_q) + c.dof0, const_cast<T*>(ckpt_qd) + c.dof0, dofs};
   DevMutRows<T> tb{tau_bar_seq + c.dof0, dofs};
@@ -303,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   } else {
     AccumSink<T> sink;
     if (PI == kPiWave) {  // shared chain: a private column per state, summed afterwards
-      sink.acc = pi_acc + s;
+      sink.acc = pi_acc + lane_index;
       sink.stride = n_states;
     } else {  // one chain per state: its own rows of the output
       sink.acc = pi_out + c.link0 * 10;
@@ -350,6 +370,9 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (m->n_chains < 1 || m->n_links_max < 1 || m->n_links_total < 1 || b->n_states < 0) return PDYN_EINVAL;
   if (!m->placement || !m->twist || !m->inertia) return PDYN_EINVAL;
   if (m->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
+  if (b->block_threads < 0 || b->block_threads % 64 != 0 || b->block_threads > kMaxBlock) return PDYN_EINVAL;
+  if (b->max_blocks < 0) return PDYN_EINVAL;
+  if (m->order && (m->n_chains == 1 || (uintptr_t)m->order % sizeof(int32_t) != 0)) return PDYN_EINVAL;
   if (m->n_chains == 1) {
     if (m->n_links_total != m->n_links_max) return PDYN_EINVAL;
   } else {
@@ -395,6 +418,15 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Workgroup size and count of the tunable kernels (validated in check_model_batch).
+void launch_shape(const pdyn_batch* b, unsigned* grid, unsigned* block) {
+  const unsigned bt = b->block_threads > 0 ? (unsigned)b->block_threads : (unsigned)kBlock;
+  unsigned g = (unsigned)((b->n_states + bt - 1) / bt);
+  if (b->max_blocks > 0 && g > (unsigned)b->max_blocks) g = (unsigned)b->max_blocks;
+  *grid = g > 0 ? g : 1;
+  *block = bt;
+}
 
 template <class T>
 int check_ptrs(std::initializer_list<const void*> ptrs) {
@@ -450,9 +482,10 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   }
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
-  unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,
-                     m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+  unsigned grid, block;
+  launch_shape(b, &grid, &block);
+  hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
+                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                      static_cast<const T*>(b->tip_wrench), ba, scratch);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
@@ -509,9 +542,10 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   const long dofs = (m->n_chains == 1) ? (long)b->n_states * m->n_links_max : (long)m->n_links_total;
-  const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_rollout<T>, dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains, m->n_links_max,
-                     m->link_ptr, reinterpret_cast<const T*>(tbase), reinterpret_cast<const double*>(tbase + woff),
+  unsigned grid, block;
+  launch_shape(b, &grid, &block);
+  hipLaunchKernelGGL(k_rollout<T>, dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,
+                     m->link_ptr, m->order, reinterpret_cast<const T*>(tbase), reinterpret_cast<const double*>(tbase + woff),
                      steps, (T)dt, every, tau_seq, q, qd, ckpt_q, ckpt_qd, dofs, ba,
                      reinterpret_cast<T*>(base + so));
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
@@ -544,7 +578,7 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   T* acc = reinterpret_cast<T*>(base + ao);
 #define PDYN_LAUNCH_RVJP(PI)                                                                                     \
   hipLaunchKernelGGL((k_rollout_vjp<T, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
-                     m->n_links_max, m->link_ptr, reinterpret_cast<const T*>(tbase),                             \
+                     m->n_links_max, m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                   \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
                      ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
                      reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc)
@@ -599,7 +633,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   const T* tip = static_cast<const T*>(b->tip_wrench);
 #define PDYN_LAUNCH_VJP(PI, PIOUT)                                                                            \
   hipLaunchKernelGGL((k_vjp<T, OP, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
-                     m->n_links_max, m->link_ptr, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar,   \
+                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar, \
                      tau_bar, PIOUT, L.n_waves, tip, ba, scratch, L.stride)
   if (!inertia_bar) {
     PDYN_LAUNCH_VJP(kPiNone, static_cast<T*>(nullptr));

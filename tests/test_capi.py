@@ -124,3 +124,21 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(api, "_lib", None)
     with pytest.raises(api.PdynError):
         api.lib()
+
+
+def test_launch_shape_and_order_validation():
+    L = api.lib()
+    m, keep = _fake_model()
+    x = np.zeros((8, 4), np.float32)
+    p = x.ctypes.data
+    b = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)
+    b.block_threads = 100  # not a multiple of 64
+    assert _call_id(m, b, (p, p, p, p)) == -1
+    b.block_threads = 512  # above the largest workgroup
+    assert _call_id(m, b, (p, p, p, p)) == -1
+    b.block_threads, b.max_blocks = 64, -3
+    assert _call_id(m, b, (p, p, p, p)) == -1
+    order = np.arange(8, dtype=np.int32)
+    m.order = order.ctypes.data  # an order with a shared chain is meaningless
+    b2 = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)
+    assert _call_id(m, b2, (p, p, p, p)) == -1

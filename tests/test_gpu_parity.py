@@ -168,3 +168,49 @@ def test_fp32_empty_batch(device):
     model = api.Model(ch, device, torch.float32)
     z = torch.zeros((0, 5), device=device)
     assert api.rnea_id(model, z, z, z).shape == (0, 5)
+
+
+def test_launch_shapes_orders_and_persistence_are_bitwise_identical(device):
+    """Block sizes, a persistent (capped) grid and the chain order change scheduling only, not results."""
+    print("case: launch shapes", flush=True)
+    ch = synth.make_chains(list(np.random.default_rng(4).integers(1, 60, 300)), 4)
+    st = synth.make_states((ch.n_links_total,), 4)
+    model = api.Model(ch, device, torch.float32)
+    ref = run_all(model, st, device, torch.float32)
+    for bt, cap, use_order in ((128, 0, True), (256, 1, True), (64, 2, False), (192, 0, False)):
+        for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+            api.set_launch(op, bt, cap)
+        model.use_order = use_order
+        got = run_all(model, st, device, torch.float32)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), (bt, cap, use_order)
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0)
+    model.use_order = True
+    cr, sr = ch.rounded(), st.rounded()
+    et = rel_ragged(ref[2], oracle.rnea(cr, sr.q, sr.qd, sr.qdd), ch.link_ptr)
+    assert et.max() <= TOL32
+
+
+def test_uneven_id_fd_in_a_captured_graph(device):
+    """ID+FD of 4096 uneven chains captured once in a HIP graph; every replay equals the eager call."""
+    print("case: uneven graph capture", flush=True)
+    ch, st = synth.workload_uneven()
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: to_dev(a, device, torch.float32)
+    q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+    out = (torch.empty_like(q), torch.empty_like(q))
+    ws = api.Workspace()
+    api.id_fd(model, q, qd, qdd, tau, out=out, workspace=ws)  # sizes the workspace outside capture
+    eager = [x.clone() for x in out]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.id_fd(model, q, qd, qdd, tau, out=out, workspace=ws)
+    for rep in range(3):
+        out[0].fill_(float("nan"))
+        out[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], eager[0]) and torch.equal(out[1], eager[1]), f"replay {rep}"
+        api.rnea_id(model, q, qd, qdd)  # eager work between replays
