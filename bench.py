@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-other-workloads", action="store_true", help="only the 32-link headline workload")
     p.add_argument("--profile-only", action="store_true", help="launch the timed steps only (for rocprofv3)")
+    p.add_argument("--profile-copy", type=int, default=0, metavar="MIB",
+                   help="only copy a MIB-mebibyte buffer a few times (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -174,6 +176,14 @@ def main():
     from paper_1609_04493_amd import api, synth
     api.lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
+    if args.profile_copy:
+        src = torch.ones(args.profile_copy * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copied {args.profile_copy} MiB x 3", flush=True)
+        return 0
     ch, st = synth.workload_32link(N_STATES)
     model = api.Model(ch, dev, torch.float32)
     q, qd, qdd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.qdd, st.tau))

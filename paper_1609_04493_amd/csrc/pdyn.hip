@@ -55,7 +55,9 @@ __device__ __forceinline__ int state_of(int lane_index, const int32_t* __restric
   return order ? order[lane_index] : lane_index;
 }
 
-template <class T, int MODE>
+// SHARED: one chain shared by every state, known at compile time, so that the
+// link records are read with wave-uniform (scalar) loads.
+template <class T, int MODE, bool SHARED>
 __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chains, int n_max,
                                                         const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
@@ -67,10 +69,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
   for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {  // persistent when gridDim.x < n_work
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
     if (lane_index >= n_states) continue;
-    const int s = state_of(lane_index, order);
+    const int s = SHARED ? lane_index : state_of(lane_index, order);
     int n;
     int64_t link0, dof0;
-    if (n_chains == 1) {
+    if (SHARED) {
       n = n_max;
       link0 = 0;
       dof0 = (int64_t)s * n_max;
@@ -484,9 +486,14 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   unsigned grid, block;
   launch_shape(b, &grid, &block);
-  hipLaunchKernelGGL((k_dynamics<T, MODE>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
-                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
-                     static_cast<const T*>(b->tip_wrench), ba, scratch);
+  if (m->n_chains == 1)
+    hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
+                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                       static_cast<const T*>(b->tip_wrench), ba, scratch);
+  else
+    hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
+                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                       static_cast<const T*>(b->tip_wrench), ba, scratch);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }

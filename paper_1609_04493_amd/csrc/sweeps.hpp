@@ -111,10 +111,8 @@ template <class T> PD_HD Link<T> load_link(const T* rec) {
 // b = (1 - cos theta)/k^2 and e = (theta - sin theta)(w.v)/k^3, the matrix
 // exponential of the twist is R_e = cos(theta) I + a [w] + b w w^T,
 // p_e = a v + b (w x v) + e w.
-template <class T> PD_HD Pose<T> joint_transform(const Link<T>& L, T q) {
+template <class T> PD_HD Pose<T> joint_transform_sc(const Link<T>& L, T q, T s, T c) {
   T th = L.k * q;
-  T s, c;
-  sin_cos(th, &s, &c);
   T a = s * L.ik;
   T b = (T(1) - c) * L.ik2;
   T e = (th - s) * L.pc;
@@ -129,13 +127,20 @@ template <class T> PD_HD Pose<T> joint_transform(const Link<T>& L, T q) {
   return g;
 }
 
-// f_{i-1,i} in double from a double-precision link record, with sin and cos
-// of k q taken in T and renormalised (s^2 + c^2 = 1 - d with |d| ~ 1e-7, so one
+// (sin, cos) of the joint angle k q, in T; every pass of one state uses the same pair.
+template <class T> PD_HD void joint_sincos(const Link<T>& L, T q, T* s, T* c) { sin_cos(L.k * q, s, c); }
+
+template <class T> PD_HD Pose<T> joint_transform(const Link<T>& L, T q) {
+  T s, c;
+  joint_sincos(L, q, &s, &c);
+  return joint_transform_sc(L, q, s, c);
+}
+
+// f_{i-1,i} in double from a double-precision link record and the (sin, cos)
+// pair in T, renormalised (s^2 + c^2 = 1 - d with |d| ~ 1e-7, so one
 // first-order step r = 1.5 - 0.5 (s^2 + c^2) is exact to ~1e-14).
-template <class T> PD_HD Pose<double> joint_transform_wide(const Link<double>& L, T q) {
+template <class T> PD_HD Pose<double> joint_transform_wide_sc(const Link<double>& L, T q, T sT, T cT) {
   const double th = L.k * (double)q;
-  T sT, cT;
-  sin_cos((T)th, &sT, &cT);
   double s = sT, c = cT;
   const double r = 1.5 - 0.5 * (s * s + c * c);
   s *= r;
@@ -154,13 +159,22 @@ template <class T> PD_HD Pose<double> joint_transform_wide(const Link<double>& L
   return g;
 }
 
+template <class T> PD_HD Pose<double> joint_transform_wide(const Link<double>& L, const Link<T>& Lt, T q) {
+  T s, c;
+  joint_sincos(Lt, q, &s, &c);
+  return joint_transform_wide_sc(L, q, s, c);
+}
+
 // Which outputs a pass produces.
 enum : int { kModeID = 1, kModeFD = 2, kModeIDFD = 3 };
 
 template <int MODE> struct ScratchWords {
   // sweep 1 writes Fhat (ID) and/or Fhat_bias (FD); sweep 2 overwrites link i's
-  // slot with U_i (6), 1/D_i and c-hat_i for sweep 3.
-  static constexpr int value = (MODE == kModeIDFD) ? 12 : (MODE == kModeFD ? 8 : 6);
+  // slot with U_i (6), 1/D_i and c-hat_i for sweep 3. The last two words hold
+  // (sin, cos) of the joint angle, computed once in sweep 1.
+  static constexpr int kData = (MODE == kModeIDFD) ? 12 : (MODE == kModeFD ? 8 : 6);
+  static constexpr int kSinCos = kData;
+  static constexpr int value = kData + 2;
 };
 
 // Strided view of the per-link scratch of one state.
@@ -210,13 +224,18 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   constexpr bool kID = (MODE & kModeID) != 0;
   constexpr bool kFD = (MODE & kModeFD) != 0;
   constexpr int kOffB = kID ? 6 : 0;  // scratch offset of the bias wrench
+  constexpr int kSC = ScratchWords<MODE>::kSinCos;
 
   // ---- sweep 1: base to tip
   {
     Sp<T> V = bd.V0, dV = bd.dV0, dVb = bd.dV0;
     for (int i = 0; i < n; ++i) {
       const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = joint_transform(L, io.q[i]);
+      T sn, cs;
+      joint_sincos(L, io.q[i], &sn, &cs);
+      scr.at(i, kSC) = sn;
+      scr.at(i, kSC + 1) = cs;
+      const Pose<T> g = joint_transform_sc(L, io.q[i], sn, cs);
       const Sp<T> XV = X_twist(g, V);
       const Sp<T> Sqd = io.qd[i] * L.S;
       V = XV + Sqd;
@@ -277,7 +296,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
         scr.at(i, 6) = invD;
         scr.at(i, 7) = chat;
       }
-      gcw = joint_transform_wide(Lw, io.q[i]);
+      gcw = joint_transform_wide_sc(Lw, io.q[i], scr.at(i, kSC), scr.at(i, kSC + 1));
       gc = cast_pose<T>(gcw);
     }
   }
@@ -287,7 +306,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
     Sp<T> lam = sp_zero<T>();
     for (int i = 0; i < n; ++i) {
       const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = joint_transform(L, io.q[i]);
+      const Pose<T> g = joint_transform_sc(L, io.q[i], scr.at(i, kSC), scr.at(i, kSC + 1));
       const Sp<T> U = scr.get(i, 0);
       const T invD = scr.at(i, 6), chat = scr.at(i, 7);
       const Sp<T> a = X_twist(g, lam);
@@ -385,7 +404,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, const T* q, 
       if (i < n - 1) F = XT_wrench(gcw, F);
       F = F + cast_sp<double>(scr.get(i, 0));
       scr.put(i, 0, cast_sp<T>(F));
-      gcw = joint_transform_wide(Lw, q[i]);
+      gcw = joint_transform_wide(Lw, load_link(table + (long)i * kLinkWords), q[i]);
     }
   }
   // sweep 3 (base to tip): Fbar, V, A again; the wrench part of q_bar; pi_bar
@@ -480,7 +499,7 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
       scr.put(i, 0, U);
       scr.at(i, 6) = invD;
       scr.at(i, 7) = (T)chat_w;
-      gcw = joint_transform_wide(Lw, io.q[i]);
+      gcw = joint_transform_wide(Lw, L, io.q[i]);
       gc = cast_pose<T>(gcw);
     }
   }
