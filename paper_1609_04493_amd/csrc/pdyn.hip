@@ -6,7 +6,8 @@
 //   k_dynamics         per state: the sweeps of sweeps.hpp (ID, FD or both).
 //   k_vjp              per state: the adjoint sweeps (ID or FD vector-Jacobian
 //                      product), inertia cotangents summed per wave.
-//   k_reduce_partials  per (link, parameter): sum of the per-wave partials.
+//   k_reduce_lanes     per (link, parameter): sum over states of the per-lane
+//                      inertia cotangents (fixed order).
 //   k_rollout          per state: T steps of forward dynamics + semi-implicit
 //                      Euler in one launch, (q, qd) checkpoints every k steps.
 //   k_rollout_vjp      per state: the rollout adjoint, segment by segment from
@@ -103,37 +104,51 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
   }
 }
 
-// ---- adjoints ------------------------------------------------------------------
-//
-// One lane per state as above. With a shared chain the inertia-parameter
-// cotangents of the 64 states of a wave are summed in registers by a fixed
-// xor-butterfly (every lane ends with the same, order-independent sum) and
-// lane 0 writes one partial per wave; k_reduce_partials then sums the waves in
-// a fixed order, so the result is deterministic. Lanes past the last state run
-// a copy of the last state with zero weight so that every lane takes part in
-// the butterflies. With one chain per state each lane writes its own links.
-
-enum : int { kVjpID = 0, kVjpFD = 1 };
-enum : int { kPiNone = 0, kPiWave = 1, kPiDirect = 2 };
-
-template <class T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+struct ChainOf {
+  int n;
+  int64_t link0, dof0;
+};
+__device__ __forceinline__ ChainOf chain_of(int s, int n_chains, int n_max, const int32_t* link_ptr) {
+  ChainOf c;
+  if (n_chains == 1) {
+    c.n = n_max;
+    c.link0 = 0;
+    c.dof0 = (int64_t)s * n_max;
+  } else {
+    c.link0 = link_ptr[s];
+    c.n = link_ptr[s + 1] - (int)c.link0;
+    c.dof0 = c.link0;
+  }
+  return c;
 }
 
+template <class T>
+__device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
+  Boundary<T> bd;
+  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  bd.Ftip = sp_zero<T>();
+  return bd;
+}
+
+// ---- adjoints ------------------------------------------------------------------
+//
+// One lane per state as above. With a shared chain each lane writes its
+// inertia-parameter cotangents to its own column of [link][10][state]
+// (consecutive lanes, consecutive words) and k_reduce_lanes sums the columns
+// in a fixed order, so the result is deterministic. With one chain per state
+// each lane writes its own links directly.
+
+enum : int { kVjpID = 0, kVjpFD = 1 };
+enum : int { kPiNone = 0, kPiLanes = 1, kPiDirect = 2 };
+
 template <class T, int PI> struct PiSink {
-  T* out;        // kPiWave: partials [link][10][n_waves] at (.., wave); kPiDirect: [links of this chain][10]
-  long stride;   // kPiWave: n_waves
-  T weight;      // 0 for lanes past the last state
-  bool leader;   // lane 0 of the wave
+  T* out;        // kPiLanes: this lane's column of [link][10][n_lanes]; kPiDirect: [links of this chain][10]
+  long stride;   // kPiLanes: n_lanes
   __device__ void put(int i, const T g[10]) {
-    if (PI == kPiWave) {
+    if (PI == kPiLanes) {
 #pragma unroll
-      for (int k = 0; k < 10; ++k) {
-        const T v = wave_sum(weight * g[k]);
-        if (leader) out[((long)i * 10 + k) * stride] = v;
-      }
+      for (int k = 0; k < 10; ++k) out[((long)i * 10 + k) * stride] = g[k];
     } else if (PI == kPiDirect) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) out[(long)i * 10 + k] = g[k];
@@ -141,71 +156,63 @@ template <class T, int PI> struct PiSink {
   }
 };
 
-// Scratch of the adjoints: [n_max][kVjpWords][stride] with stride = states
-// rounded up to a whole wave, then [4][64][n_max] outputs of idle lanes.
+// Scratch of the adjoints: [n_max][kVjpWords][n_states].
 template <class T, int OP, int PI>
 __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
-                                                const int32_t* __restrict__ order, const T* __restrict__ table, const double* __restrict__ wtable,
-                                                const T* q, const T* qd, const T* qdd, const T* bar_in, T* q_bar,
-                                                T* qd_bar, T* qdd_bar, T* tau_bar, T* pi_out, long n_waves,
-                                                const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
-                                                long stride) {
-  const int lane_state = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = lane_state < n_states;
-  if (PI != kPiWave && !active) return;
-  const int s = active ? state_of(lane_state, order) : n_states - 1;  // idle lanes of a shared chain redo the last state
-  int n;
-  int64_t link0, dof0;
-  if (n_chains == 1) {
-    n = n_max;
-    link0 = 0;
-    dof0 = (int64_t)s * n_max;
-  } else {
-    link0 = link_ptr[s];
-    n = link_ptr[s + 1] - (int)link0;
-    dof0 = link0;
-  }
+                                                const int32_t* __restrict__ order, const T* __restrict__ table,
+                                                const double* __restrict__ wtable, const T* q, const T* qd,
+                                                const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
+                                                T* tau_bar, T* pi_out, const T* __restrict__ tip, BoundaryArgs<T> ba,
+                                                T* scratch) {
+  const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lane_index >= n_states) return;
+  const int s = state_of(lane_index, order);
+  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
   VjpIO<T> io;
-  io.q = q + dof0;
-  io.qd = qd + dof0;
-  io.qdd = qdd + dof0;
-  io.bar_in = bar_in + dof0;
-  if (active) {
-    io.q_bar = q_bar + dof0;
-    io.qd_bar = qd_bar + dof0;
-    io.qdd_bar = (OP == kVjpID) ? qdd_bar + dof0 : nullptr;
-    io.tau_bar = (OP == kVjpFD) ? tau_bar + dof0 : nullptr;
-  } else {
-    T* idle = scratch + (long)n_max * kVjpWords * stride + (long)(lane_state - n_states) * n_max;
-    const long part = 64L * n_max;
-    io.q_bar = idle;
-    io.qd_bar = idle + part;
-    io.qdd_bar = (OP == kVjpID) ? idle + 2 * part : nullptr;
-    io.tau_bar = (OP == kVjpFD) ? idle + 3 * part : nullptr;
-  }
-  Boundary<T> bd;
-  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
-  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  io.q = q + c.dof0;
+  io.qd = qd + c.dof0;
+  io.qdd = qdd + c.dof0;
+  io.bar_in = bar_in + c.dof0;
+  io.q_bar = q_bar + c.dof0;
+  io.qd_bar = qd_bar + c.dof0;
+  io.qdd_bar = (OP == kVjpID) ? qdd_bar + c.dof0 : nullptr;
+  io.tau_bar = (OP == kVjpFD) ? tau_bar + c.dof0 : nullptr;
+  Boundary<T> bd = boundary_of(ba);
   if (tip) {
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
-  } else {
-    bd.Ftip = sp_zero<T>();
   }
-  Scratch<T> scr{scratch + lane_state, stride, kVjpWords};
+  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
   PiSink<T, PI> sink;
   sink.out = nullptr;
   sink.stride = 0;
-  sink.weight = active ? T(1) : T(0);
-  sink.leader = (threadIdx.x % 64) == 0;
-  if (PI == kPiWave) {
-    sink.out = pi_out + lane_state / 64;
-    sink.stride = n_waves;
+  if (PI == kPiLanes) {
+    sink.out = pi_out + lane_index;
+    sink.stride = n_states;
   } else if (PI == kPiDirect) {
-    sink.out = pi_out + link0 * 10;
+    sink.out = pi_out + c.link0 * 10;
   }
-  if (OP == kVjpID) id_vjp_one_state(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr, sink);
-  else fd_vjp_one_state(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr, sink);
+  const T* tab = table + c.link0 * kLinkWords;
+  const double* wtab = wtable + c.link0 * kLinkWords;
+  if (OP == kVjpID) id_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
+  else fd_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
+}
+
+// out[i] = sum over j < n_in of in[i * n_in + j], one workgroup per output, fixed
+// order (strided partial sums in double, then a fixed tree), so deterministic.
+template <class T>
+__global__ void __launch_bounds__(256) k_reduce_lanes(int n_in, const T* __restrict__ in, T* __restrict__ out) {
+  __shared__ double part[256];
+  const long i = blockIdx.x;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n_in; j += 256) acc += (double)in[i * n_in + j];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = (T)part[0];
 }
 
 // ---- rollouts -------------------------------------------------------------------
@@ -240,33 +247,6 @@ struct NoSink {
   template <class T> __device__ void put(int, const T*) {}
 };
 
-struct ChainOf {
-  int n;
-  int64_t link0, dof0;
-};
-__device__ __forceinline__ ChainOf chain_of(int s, int n_chains, int n_max, const int32_t* link_ptr) {
-  ChainOf c;
-  if (n_chains == 1) {
-    c.n = n_max;
-    c.link0 = 0;
-    c.dof0 = (int64_t)s * n_max;
-  } else {
-    c.link0 = link_ptr[s];
-    c.n = link_ptr[s + 1] - (int)c.link0;
-    c.dof0 = c.link0;
-  }
-  return c;
-}
-
-template <class T>
-__device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
-  Boundary<T> bd;
-  bd.V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
-  bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
-  bd.Ftip = sp_zero<T>();
-  return bd;
-}
-
 // Forward rollout, one lane per state, all steps in one launch.
 template <class T>
 __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chains, int n_max,
@@ -283,14 +263,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
     const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value};
     rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every,
-                      q + c.dof0, qd + c.dof0, DevRows<T>{tau_seq + c.dof0, dofs},
+                      SPtr<T>(q + c.dof0), SPtr<T>(qd + c.dof0), DevRows<T>{tau_seq + c.dof0, dofs},
                       DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs}, boundary_of(ba), scr);
   }
 }
 
-// Adjoint of a rollout, one lane per state. Workspace regions (all per state):
-// adjoint scratch [n_max][kVjpWords][n_states]; rows [n_states][(3 every + 6) n_max];
-// pi accumulators [n_max][10][n_states] (shared chain; zeroed here).
+// Adjoint of a rollout, one lane per state. Workspace regions, all
+// lane-interleaved: adjoint scratch [n_max][kVjpWords][n_states]; working rows
+// [(3 every + 6) n_max][n_states]; pi accumulators [n_max][10][n_states]
+// (shared chain; zeroed here).
 template <class T, int PI>
 __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chains, int n_max,
                                                         const int32_t* __restrict__ link_ptr,
@@ -304,11 +285,13 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   if (lane_index >= n_states) return;
   const int s = state_of(lane_index, order);
   const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
-  const long row_len = (long)(3 * every + 6) * n_max;
-  T* r = rows_ws + (long)lane_index * row_len;
-  RolloutRows<T> rows{r, q0_bar + c.dof0, qd0_bar + c.dof0, r + 3L * every * n_max, r + (3L * every + 1) * n_max,
-                      r + (3L * every + 2) * n_max, r + (3L * every + 3) * n_max, r + (3L * every + 4) * n_max,
-                      r + (3L * every + 5) * n_max, c.n};
+  // working rows, lane-interleaved: element i of row r at rows_ws[(r n_max + i) n_states + lane]
+  const long S = n_states;
+  T* const rb = rows_ws + lane_index;
+  auto row = [&](int r) { return SPtr<T>(rb + (long)r * n_max * S, S); };
+  RolloutRows<T> rows{SPtr<T>(rb, S), SPtr<T>(q0_bar + c.dof0), SPtr<T>(qd0_bar + c.dof0), row(3 * every),
+                      row(3 * every + 1), row(3 * every + 2), row(3 * every + 3), row(3 * every + 4),
+                      row(3 * every + 5), n_max};
   for (int i = 0; i < c.n; ++i) {
     rows.lq[i] = qT_bar[c.dof0 + i];
     rows.lqd[i] = qdT_bar[c.dof0 + i];
@@ -324,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
     rollout_vjp_one_state(c.n, tab, wtab, steps, dt, every, tau, ck, tb, rows, boundary_of(ba), scr, sink);
   } else {
     AccumSink<T> sink;
-    if (PI == kPiWave) {  // shared chain: a private column per state, summed afterwards
+    if (PI == kPiLanes) {  // shared chain: a private column per state, summed afterwards
       sink.acc = pi_acc + lane_index;
       sink.stride = n_states;
     } else {  // one chain per state: its own rows of the output
@@ -336,22 +319,10 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   }
 }
 
-// out[i] = sum over w of partials[i][w], w in increasing order.
-template <class T>
-__global__ void __launch_bounds__(256) k_reduce_partials(int n_out, int n_waves, const T* __restrict__ partials,
-                                                        T* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_out) return;
-  T acc = T(0);
-  for (int w = 0; w < n_waves; ++w) acc += partials[(long)i * n_waves + w];
-  out[i] = acc;
-}
-
 // ---- host side ------------------------------------------------------------------
 
 struct Layout {
   size_t table_off, wtable_off, scratch_off, scratch_bytes, partial_off, total;
-  long stride, n_waves;
 };
 
 int scratch_words(int op) {
@@ -400,18 +371,12 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
   L->wtable_off = woff;
   L->scratch_off = m->prepared ? 0 : tb;
   const size_t nm = (size_t)m->n_links_max;
+  L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
   if (is_vjp(op)) {
-    // [n_max][words][stride] + idle-lane outputs [4][64][n_max], then the
-    // per-wave inertia partials [n_max][10][n_waves].
-    L->n_waves = (b->n_states + 63) / 64;
-    L->stride = L->n_waves * 64;
-    L->scratch_bytes = align_up((nm * (size_t)words * (size_t)L->stride + 4 * 64 * nm) * scalar);
+    // then the per-lane inertia cotangents [n_max][10][n_states] (shared chain)
     L->partial_off = L->scratch_off + L->scratch_bytes;
-    L->total = L->partial_off + align_up(nm * 10 * (size_t)L->n_waves * scalar);
+    L->total = L->partial_off + align_up(nm * 10 * (size_t)b->n_states * scalar);
   } else {
-    L->n_waves = 0;
-    L->stride = b->n_states;
-    L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
     L->partial_off = 0;
     L->total = L->scratch_off + L->scratch_bytes;
   }
@@ -592,10 +557,8 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   if (!inertia_bar) {
     PDYN_LAUNCH_RVJP(kPiNone);
   } else if (m->n_chains == 1) {
-    PDYN_LAUNCH_RVJP(kPiWave);
-    const int n_out = m->n_links_max * 10;
-    hipLaunchKernelGGL(k_reduce_partials<T>, dim3((n_out + 255) / 256), dim3(256), 0, s, n_out, b->n_states, acc,
-                       inertia_bar);
+    PDYN_LAUNCH_RVJP(kPiLanes);
+    hipLaunchKernelGGL(k_reduce_lanes<T>, dim3(m->n_links_max * 10), dim3(256), 0, s, b->n_states, acc, inertia_bar);
   } else {
     PDYN_LAUNCH_RVJP(kPiDirect);
   }
@@ -641,14 +604,13 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
 #define PDYN_LAUNCH_VJP(PI, PIOUT)                                                                            \
   hipLaunchKernelGGL((k_vjp<T, OP, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
                      m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar, \
-                     tau_bar, PIOUT, L.n_waves, tip, ba, scratch, L.stride)
+                     tau_bar, PIOUT, tip, ba, scratch)
   if (!inertia_bar) {
     PDYN_LAUNCH_VJP(kPiNone, static_cast<T*>(nullptr));
   } else if (m->n_chains == 1) {
-    PDYN_LAUNCH_VJP(kPiWave, partials);
-    const int n_out = m->n_links_max * 10;
-    hipLaunchKernelGGL(k_reduce_partials<T>, dim3((n_out + 255) / 256), dim3(256), 0, s, n_out, (int)L.n_waves,
-                       partials, inertia_bar);
+    PDYN_LAUNCH_VJP(kPiLanes, partials);
+    hipLaunchKernelGGL(k_reduce_lanes<T>, dim3(m->n_links_max * 10), dim3(256), 0, s, b->n_states, partials,
+                       inertia_bar);
   } else {
     PDYN_LAUNCH_VJP(kPiDirect, inertia_bar);
   }

@@ -193,14 +193,28 @@ template <class T> struct Scratch {
   }
 };
 
+// A per-state array with element i at p[i * s]: s = 1 for the caller's
+// row-major arrays, s = number of states for lane-interleaved working rows
+// (consecutive lanes then touch consecutive words).
+template <class T> struct SPtr {
+  T* p;
+  long s;
+  PD_HD SPtr() : p(nullptr), s(1) {}
+  PD_HD SPtr(T* p_) : p(p_), s(1) {}
+  PD_HD SPtr(T* p_, long s_) : p(p_), s(s_) {}
+  template <class U> PD_HD SPtr(const SPtr<U>& o) : p(o.p), s(o.s) {}
+  PD_HD T& operator[](long i) const { return p[i * s]; }
+  PD_HD explicit operator bool() const { return p != nullptr; }
+};
+
 // Joint arrays of one state (element i of the chain at ptr[i]).
 template <class T> struct JointIO {
-  const T* q;
-  const T* qd;
-  const T* qdd_in;   // ID input accelerations (kModeID)
-  const T* tau_in;   // FD input torques (kModeFD)
-  T* tau_out;        // ID output
-  T* qdd_out;        // FD output
+  SPtr<const T> q;
+  SPtr<const T> qd;
+  SPtr<const T> qdd_in;   // ID input accelerations (kModeID)
+  SPtr<const T> tau_in;   // FD input torques (kModeFD)
+  SPtr<T> tau_out;        // ID output
+  SPtr<T> qdd_out;        // FD output
 };
 
 template <class T> struct Boundary {
@@ -209,7 +223,7 @@ template <class T> struct Boundary {
 
 // Default consumer of the forward-dynamics output: qdd_out[i] = qdd_i.
 template <class T> struct StoreQdd {
-  T* out;
+  SPtr<T> out;
   PD_HD void operator()(int i, T qdd) const { out[i] = qdd; }
 };
 
@@ -364,14 +378,14 @@ PD_HD void add_inertia_grad(T m, const V3<T>& c, const Sp<T>& x, const Sp<T>& y,
 }
 
 template <class T> struct VjpIO {
-  const T* q;
-  const T* qd;
-  const T* qdd;      // ID: input accelerations; FD: the forward output qdd = FD(q, qd, tau)
-  const T* bar_in;   // ID: tau_bar; FD: qdd_bar
-  T* q_bar;
-  T* qd_bar;
-  T* qdd_bar;        // ID only
-  T* tau_bar;        // FD only (receives u = M^-1 qdd_bar)
+  SPtr<const T> q;
+  SPtr<const T> qd;
+  SPtr<const T> qdd;      // ID: input accelerations; FD: the forward output qdd = FD(q, qd, tau)
+  SPtr<const T> bar_in;   // ID: tau_bar; FD: qdd_bar
+  SPtr<T> q_bar;
+  SPtr<T> qd_bar;
+  SPtr<T> qdd_bar;        // ID only
+  SPtr<T> tau_bar;        // FD only (receives u = M^-1 qdd_bar)
 };
 
 // Scratch words per link of the adjoint passes: Fbar, V, A (6 each), the
@@ -392,9 +406,9 @@ PD_HD void vjp_forward_fhat(int i, const Link<T>& L, const Pose<T>& g, T qd, T q
 // Sweeps 2-4 of an ID adjoint with cotangent sgn * tb (Fhat already in scratch
 // slot 0). pi_bar contributions go to sink.put(i, g[10]).
 template <class T, class Sink>
-PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, const T* q, const T* qd, const T* qdd,
-                       const T* tb, T sgn, T* q_bar, T* qd_bar, T* qdd_bar, const Boundary<T>& bd,
-                       const Scratch<T>& scr, Sink& sink) {
+PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> qd,
+                       SPtr<const T> qdd, SPtr<const T> tb, T sgn, SPtr<T> q_bar, SPtr<T> qd_bar, SPtr<T> qdd_bar,
+                       const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   // sweep 2 (tip to base): wrenches F_i in double, stored rounded in slot 0
   {
     Sp<double> F = cast_sp<double>(bd.Ftip);
@@ -518,8 +532,8 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
       vjp_forward_fhat(i, L, g, io.qd[i], io.qdd[i], V, A, scr);
     }
   }
-  id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.tau_bar, T(-1), io.q_bar, io.qd_bar,
-              static_cast<T*>(nullptr), bd, scr, sink);
+  id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, SPtr<const T>(io.tau_bar), T(-1), io.q_bar, io.qd_bar,
+              SPtr<T>(), bd, scr, sink);
 }
 
 
@@ -536,8 +550,8 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
 // ============================================================================
 
 template <class T> struct EulerStep {
-  T* q;
-  T* qd;
+  SPtr<T> q;
+  SPtr<T> qd;
   T dt;
   PD_HD void operator()(int i, T qdd) const {
     const T v = qd[i] + dt * qdd;
@@ -547,9 +561,9 @@ template <class T> struct EulerStep {
 };
 
 template <class T> struct EulerStepKeep {  // also records qdd_t for the reverse pass
-  T* q;
-  T* qd;
-  T* qdd_keep;
+  SPtr<T> q;
+  SPtr<T> qd;
+  SPtr<T> qdd_keep;
   T dt;
   PD_HD void operator()(int i, T qdd) const {
     qdd_keep[i] = qdd;
@@ -562,15 +576,16 @@ template <class T> struct EulerStepKeep {  // also records qdd_t for the reverse
 // Forward rollout of one state: q, qd (length n) are advanced in place; tau(t)
 // returns the torque row of step t; ckpt(c) returns (q, qd) rows of checkpoint c.
 template <class T, class TauRow, class CkptRow>
-PD_HD void rollout_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every, T* q, T* qd,
-                             const TauRow& tau, const CkptRow& ckpt, const Boundary<T>& bd, const Scratch<T>& scr) {
+PD_HD void rollout_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every, SPtr<T> q,
+                             SPtr<T> qd, const TauRow& tau, const CkptRow& ckpt, const Boundary<T>& bd,
+                             const Scratch<T>& scr) {
   for (int t = 0; t < steps; ++t) {
     if (t % every == 0) {
-      T* cq = ckpt.q(t / every);
-      T* cqd = ckpt.qd(t / every);
+      const SPtr<T> cq = ckpt.q(t / every);
+      const SPtr<T> cqd = ckpt.qd(t / every);
       for (int i = 0; i < n; ++i) { cq[i] = q[i]; cqd[i] = qd[i]; }
     }
-    JointIO<T> io{q, qd, nullptr, tau(t), nullptr, nullptr};
+    JointIO<T> io{q, qd, SPtr<const T>(), tau(t), SPtr<T>(), SPtr<T>()};
     dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr, EulerStep<T>{q, qd, dt});
   }
 }
@@ -580,19 +595,20 @@ PD_HD void rollout_one_state(int n, const T* table, const double* wtable, int st
 //   lq, lqd: running cotangents; w, qddbar: temporaries; qbar, qdbar: FD
 //   adjoint outputs; cur_q, cur_qd: the state being recomputed.
 template <class T> struct RolloutRows {
-  T* seg;    // [every][3][n]
-  T* lq;
-  T* lqd;
-  T* w;
-  T* qddbar;
-  T* qbar;
-  T* qdbar;
-  T* cur_q;
-  T* cur_qd;
-  int n;
-  PD_HD T* seg_q(int j) const { return seg + (long)(3 * j) * n; }
-  PD_HD T* seg_qd(int j) const { return seg + (long)(3 * j + 1) * n; }
-  PD_HD T* seg_qdd(int j) const { return seg + (long)(3 * j + 2) * n; }
+  SPtr<T> seg;    // rows 3j, 3j+1, 3j+2 (each n long): q, qd, qdd of segment step j
+  SPtr<T> lq;
+  SPtr<T> lqd;
+  SPtr<T> w;
+  SPtr<T> qddbar;
+  SPtr<T> qbar;
+  SPtr<T> qdbar;
+  SPtr<T> cur_q;
+  SPtr<T> cur_qd;
+  int n;      // row length (elements)
+  PD_HD SPtr<T> row(int r) const { return SPtr<T>(seg.p + (long)r * n * seg.s, seg.s); }
+  PD_HD SPtr<T> seg_q(int j) const { return row(3 * j); }
+  PD_HD SPtr<T> seg_qd(int j) const { return row(3 * j + 1); }
+  PD_HD SPtr<T> seg_qdd(int j) const { return row(3 * j + 2); }
 };
 
 // Adjoint of L(q_T, qd_T) for one state. On entry rows.lq / rows.lqd hold
@@ -607,13 +623,13 @@ PD_HD void rollout_vjp_one_state(int n, const T* table, const double* wtable, in
     const int t0 = c * every;
     const int t1 = (t0 + every < steps) ? t0 + every : steps;
     // recompute the segment from its checkpoint, keeping (q_t, qd_t, qdd_t)
-    const T* cq = ckpt.q(c);
-    const T* cqd = ckpt.qd(c);
+    const SPtr<const T> cq = ckpt.q(c);
+    const SPtr<const T> cqd = ckpt.qd(c);
     for (int i = 0; i < n; ++i) { rows.cur_q[i] = cq[i]; rows.cur_qd[i] = cqd[i]; }
     for (int t = t0; t < t1; ++t) {
       const int j = t - t0;
       for (int i = 0; i < n; ++i) { rows.seg_q(j)[i] = rows.cur_q[i]; rows.seg_qd(j)[i] = rows.cur_qd[i]; }
-      JointIO<T> io{rows.cur_q, rows.cur_qd, nullptr, tau(t), nullptr, nullptr};
+      JointIO<T> io{rows.cur_q, rows.cur_qd, SPtr<const T>(), tau(t), SPtr<T>(), SPtr<T>()};
       dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr,
                                      EulerStepKeep<T>{rows.cur_q, rows.cur_qd, rows.seg_qdd(j), dt});
     }
@@ -622,7 +638,7 @@ PD_HD void rollout_vjp_one_state(int n, const T* table, const double* wtable, in
       const int j = t - t0;
       for (int i = 0; i < n; ++i) rows.w[i] = rows.lqd[i] + dt * rows.lq[i];
       for (int i = 0; i < n; ++i) rows.qddbar[i] = dt * rows.w[i];
-      VjpIO<T> io{rows.seg_q(j), rows.seg_qd(j), rows.seg_qdd(j), rows.qddbar, rows.qbar, rows.qdbar, nullptr,
+      VjpIO<T> io{rows.seg_q(j), rows.seg_qd(j), rows.seg_qdd(j), rows.qddbar, rows.qbar, rows.qdbar, SPtr<T>(),
                   taubar(t)};
       fd_vjp_one_state(n, table, wtable, io, bd, scr, sink);
       for (int i = 0; i < n; ++i) {

@@ -155,8 +155,8 @@ static int run_rollout(int with_grad, int n_states, int n, const T* placement, c
     CkptOf<T> ck{ckq + (long)s * n, ckqd + (long)s * n, bn};
     if (!with_grad) {
       Scratch<T> scr8{scratch.data(), 1, ScratchWords<kModeFD>::value};
-      rollout_one_state(n, table.data(), wtable.data(), steps, dt, every, q + (long)s * n, qd + (long)s * n, tau, ck,
-                        bd, scr8);
+      rollout_one_state(n, table.data(), wtable.data(), steps, dt, every, SPtr<T>(q + (long)s * n),
+                        SPtr<T>(qd + (long)s * n), tau, ck, bd, scr8);
     } else {
       std::vector<T> seg((size_t)every * 3 * n), rowbuf((size_t)8 * n);
       RolloutRows<T> rows{seg.data(), q0_bar + (long)s * n, qd0_bar + (long)s * n, rowbuf.data(),
