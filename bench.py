@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--profile-only", action="store_true", help="launch the timed steps only (for rocprofv3)")
     p.add_argument("--profile-copy", type=int, default=0, metavar="MIB",
                    help="only copy a MIB-mebibyte buffer a few times (HBM counter calibration)")
+    p.add_argument("--variant", type=int, default=0,
+                   help="with --profile-only: forward-dynamics kernel variant (0 = library default)")
     return p.parse_args()
 
 
@@ -193,6 +195,7 @@ def main():
 
     fused = lambda: api.id_fd(model, q, qd, qdd, tau, out=(tau_out, qdd_out), workspace=ws)
     if args.profile_only:
+        api.set_launch(api.OP_ID_FD, 0, 0, args.variant)
         for _ in range(args.warmup + args.steps):
             fused()
         torch.cuda.synchronize()
@@ -206,6 +209,16 @@ def main():
     torch.cuda.synchronize()
     ms_fused = time_steps(fused, args.steps, args.warmup, stream)
     print(f"fused ID+FD: {ms_fused * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    variants = {}
+    for v in (1, 2):
+        api.set_launch(api.OP_ID_FD, 0, 0, v)
+        api.set_launch(api.OP_ABA_FD, 0, 0, v)
+        variants[v] = {"id_fd_us": 1e3 * time_steps(fused, args.steps, args.warmup, stream),
+                       "fd_us": 1e3 * time_steps(lambda: api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws),
+                                                 args.steps, args.warmup, stream)}
+        print(f"variant {v}: {variants[v]}", file=sys.stderr, flush=True)
+    api.set_launch(api.OP_ID_FD, 0, 0, 0)
+    api.set_launch(api.OP_ABA_FD, 0, 0, 0)
     ms_plain = time_steps(plain, args.steps, args.warmup, stream)
     print(f"separate ID, FD calls: {ms_plain * 1e3:.1f} us/step", file=sys.stderr, flush=True)
     ms_id = time_steps(lambda: api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws), args.steps, args.warmup, stream)
@@ -279,6 +292,8 @@ def main():
                      "frac": achieved / PEAK_VALU_FLOPS, "traffic": None,
                      "kernel": "k_dynamics<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
                      "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
+        "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
+                            "2": dict(variants[2], form="articulated-inertia pass on its own wavefront")},
         "plain": {"form": "separate pdyn_rnea_id + pdyn_aba_fd calls", "value": N_STATES / (ms_plain * 1e-3),
                   "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
         "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),

@@ -104,6 +104,13 @@ typedef struct pdyn_batch {
    * each workgroup striding over the remaining work in a fixed order. */
   int32_t block_threads;
   int32_t max_blocks;
+  /* Kernel variant for forward dynamics and fused ID+FD (0 = library
+   * default): 1 = one wavefront runs every recursion of its 64 states;
+   * 2 = role split -- per group of 64 states one wavefront runs the
+   * articulated-body inertia recursion (7) while others run the Newton-Euler
+   * passes, then the z-hat / lambda recursions of (8) (block_threads and
+   * max_blocks do not apply). Results agree to rounding. */
+  int32_t variant;
 } pdyn_batch;
 
 /* Operation selector for pdyn_workspace_bytes. */

@@ -2,8 +2,10 @@
 
 For one operation on one model/batch, times every candidate launch shape
 (threads per workgroup, workgroup cap -- a cap below the work makes the launch
-persistent) and, for one chain per state, the chain order (natural, or longest
-first), with HIP events, and keeps the fastest. Results are recorded in a
+persistent), the kernel variant for forward dynamics (one wavefront per 64
+states, or the role split across wavefronts) and, for one chain per state,
+the chain order (natural, or longest first), with HIP events, and keeps the
+fastest. Results are recorded in a
 JSON table keyed by (operation, precision, model kind, links, states), which
 ``apply`` installs into the binding so that later calls use them.
 """
@@ -47,13 +49,21 @@ def tune(op: int, model: api.Model, call, n_states: int, reps: int = 20):
     timings = []
     saved = api._launch_override.get(op)
     saved_order = model.use_order
+    variants = (1, 2) if op in (api.OP_ABA_FD, api.OP_ID_FD) else (1,)
     try:
         for bt, cap, use_order in itertools.product(BLOCKS, CAPS, orders):
             if cap and cap * bt >= n_states:
                 continue  # not persistent: same as uncapped
-            api.set_launch(op, bt, cap)
+            api.set_launch(op, bt, cap, 1)
             model.use_order = use_order
-            timings.append({"block_threads": bt, "max_blocks": cap, "order": use_order, "ms": _time(call, reps)})
+            timings.append({"block_threads": bt, "max_blocks": cap, "order": use_order, "variant": 1,
+                            "ms": _time(call, reps)})
+        if 2 in variants:
+            for use_order in orders:
+                api.set_launch(op, 0, 0, 2)
+                model.use_order = use_order
+                timings.append({"block_threads": 0, "max_blocks": 0, "order": use_order, "variant": 2,
+                                "ms": _time(call, reps)})
     finally:
         model.use_order = saved_order
         if saved is None:
@@ -75,5 +85,5 @@ def record(path: str, op: int, model: api.Model, n_states: int, best: dict):
 
 
 def apply(best: dict, op: int, model: api.Model):
-    api.set_launch(op, best["block_threads"], best["max_blocks"])
+    api.set_launch(op, best["block_threads"], best["max_blocks"], best.get("variant", 0))
     model.use_order = bool(best.get("order", True))

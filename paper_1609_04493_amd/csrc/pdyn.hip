@@ -4,6 +4,8 @@
 //   k_link_table       per link: the derived 32-word record (rotation of M_i
 //                      from its quaternion, twist norms, h = m c, I_O) -- a map.
 //   k_dynamics         per state: the sweeps of sweeps.hpp (ID, FD or both).
+//   k_dynamics_split   per 64 states, 2-3 wavefronts: the articulated-inertia
+//                      pass beside the Newton-Euler passes (FD, ID+FD).
 //   k_vjp              per state: the adjoint sweeps (ID or FD vector-Jacobian
 //                      product), inertia cotangents summed per wave.
 //   k_reduce_lanes     per (link, parameter): sum over states of the per-lane
@@ -26,6 +28,7 @@ namespace {
 constexpr int kMaxLinks = 1 << 16;
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
+constexpr int kDefaultVariant = 1;  // forward dynamics: one wavefront per 64 states
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -129,6 +132,62 @@ __device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
   bd.dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
   bd.Ftip = sp_zero<T>();
   return bd;
+}
+
+// Role-split forward dynamics (variant 2): per group of 64 states, wavefront 0
+// runs the articulated-body inertia pass, wavefront 1 the bias Newton-Euler
+// pass, and for ID+FD wavefront 2 the inverse dynamics; after one workgroup
+// barrier wavefront 1 runs the bias wrench / z-hat pass and the lambda pass.
+template <class T, int MODE, bool SHARED>
+__global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+                                                        const int32_t* __restrict__ order,
+                                                        const T* __restrict__ table,
+                                                        const double* __restrict__ wtable, const T* q, const T* qd,
+                                                        const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
+                                                        const T* __restrict__ tip, BoundaryArgs<T> ba, T* scr_id,
+                                                        T* scr_bias, T* scr_abi) {
+  const int role = threadIdx.x / 64;  // wave-uniform
+  const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
+  const bool active = lane_index < n_states;
+  int s = 0, n = 0;
+  int64_t link0 = 0, dof0 = 0;
+  if (active) {
+    s = SHARED ? lane_index : state_of(lane_index, order);
+    if (SHARED) {
+      n = n_max;
+      dof0 = (int64_t)s * n_max;
+    } else {
+      link0 = link_ptr[s];
+      n = link_ptr[s + 1] - (int)link0;
+      dof0 = link0;
+    }
+  }
+  const T* tab = table + link0 * kLinkWords;
+  const double* wtab = wtable + link0 * kLinkWords;
+  Boundary<T> bd = boundary_of(ba);
+  if (active && tip) {
+    const T* t = tip + 6 * (int64_t)s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  }
+  const Scratch<T> abi{scr_abi + lane_index, (long)n_states, kAbiWords};
+  const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
+  const SPtr<const T> qs(q + dof0), qds(qd + dof0);
+  if (active) {
+    if (role == 0) {
+      split_abi_pass(n, tab, wtab, qs, abi);
+    } else if (role == 1) {
+      split_bias_forward(n, tab, qs, qds, bd, bias);
+    } else {
+      JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
+      const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value};
+      dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr);
+    }
+  }
+  __syncthreads();
+  if (active && role == 1) {
+    split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
+    split_lambda(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
+  }
 }
 
 // ---- adjoints ------------------------------------------------------------------
@@ -345,6 +404,7 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (m->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
   if (b->block_threads < 0 || b->block_threads % 64 != 0 || b->block_threads > kMaxBlock) return PDYN_EINVAL;
   if (b->max_blocks < 0) return PDYN_EINVAL;
+  if (b->variant < 0 || b->variant > 2) return PDYN_EINVAL;
   if (m->order && (m->n_chains == 1 || (uintptr_t)m->order % sizeof(int32_t) != 0)) return PDYN_EINVAL;
   if (m->n_chains == 1) {
     if (m->n_links_total != m->n_links_max) return PDYN_EINVAL;
@@ -372,6 +432,12 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
   L->scratch_off = m->prepared ? 0 : tb;
   const size_t nm = (size_t)m->n_links_max;
   L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
+  if (op == PDYN_OP_ABA_FD || op == PDYN_OP_ID_FD) {  // room for the role-split variant too
+    const size_t need = align_up(nm * (size_t)ScratchWords<kModeID>::value * (size_t)b->n_states * scalar) +
+                        align_up(nm * (size_t)kBiasWords * (size_t)b->n_states * scalar) +
+                        align_up(nm * (size_t)kAbiWords * (size_t)b->n_states * scalar);
+    if (need > L->scratch_bytes) L->scratch_bytes = need;
+  }
   if (is_vjp(op)) {
     // then the per-lane inertia cotangents [n_max][10][n_states] (shared chain)
     L->partial_off = L->scratch_off + L->scratch_bytes;
@@ -449,6 +515,26 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   }
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const int variant = b->variant ? b->variant : kDefaultVariant;
+  if ((MODE & kModeFD) && variant == 2) {
+    const unsigned g = (unsigned)((b->n_states + 63) / 64);
+    const unsigned blk = (MODE == kModeIDFD) ? 192 : 128;
+    const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
+    T* scr_id = scratch;
+    T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
+                                       align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
+    T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
+    if (m->n_chains == 1)
+      hipLaunchKernelGGL((k_dynamics_split<T, MODE, true>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,
+                         m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                         static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);
+    else
+      hipLaunchKernelGGL((k_dynamics_split<T, MODE, false>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,
+                         m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                         static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
   unsigned grid, block;
   launch_shape(b, &grid, &block);
   if (m->n_chains == 1)

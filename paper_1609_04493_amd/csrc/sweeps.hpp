@@ -207,6 +207,26 @@ template <class T> struct SPtr {
   PD_HD explicit operator bool() const { return p != nullptr; }
 };
 
+// Runs body(i, load(i)) for the n links i = first, first + step, ... (step = +1
+// or -1) in that order, loading the inputs of the next link before the body of
+// the current one runs, so that their memory latency overlaps its arithmetic.
+// Unrolled by two with two input sets that alternate, so no register copies
+// (which would wait for the loads) separate one link from the next.
+template <class LoadF, class BodyF>
+PD_HD void pipelined(int n, int first, int step, const LoadF& load, const BodyF& body) {
+  if (n <= 0) return;
+  auto a = load(first);
+  int k = 0;
+  for (; k + 1 < n; k += 2) {
+    const int i = first + k * step;
+    const auto b = load(i + step);
+    body(i, a);
+    a = load(k + 2 < n ? i + 2 * step : i);
+    body(i + step, b);
+  }
+  if (k < n) body(first + k * step, a);
+}
+
 // Joint arrays of one state (element i of the chain at ptr[i]).
 template <class T> struct JointIO {
   SPtr<const T> q;
@@ -240,94 +260,141 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   constexpr int kOffB = kID ? 6 : 0;  // scratch offset of the bias wrench
   constexpr int kSC = ScratchWords<MODE>::kSinCos;
 
+  // Every sweep runs through pipelined(): the per-link inputs of the next link
+  // are loaded while the current link computes.
+
   // ---- sweep 1: base to tip
   {
+    struct In {
+      T q, qd, qdd;
+    };
     Sp<T> V = bd.V0, dV = bd.dV0, dVb = bd.dV0;
-    for (int i = 0; i < n; ++i) {
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      T sn, cs;
-      joint_sincos(L, io.q[i], &sn, &cs);
-      scr.at(i, kSC) = sn;
-      scr.at(i, kSC + 1) = cs;
-      const Pose<T> g = joint_transform_sc(L, io.q[i], sn, cs);
-      const Sp<T> XV = X_twist(g, V);
-      const Sp<T> Sqd = io.qd[i] * L.S;
-      V = XV + Sqd;
-      const Sp<T> cor = ad_twist(Sqd, XV);            // ad_{S qd} X V_{i-1}
-      const Sp<T> gyro = adT_wrench(V, mul(L.J, V));  // ad^T_V (J V)
-      if (kID) {
-        dV = X_twist(g, dV) + io.qdd_in[i] * L.S - cor;
-        scr.put(i, 0, mul(L.J, dV) - gyro);
-      }
-      if (kFD) {
-        dVb = X_twist(g, dVb) - cor;
-        scr.put(i, kOffB, mul(L.J, dVb) - gyro);
-      }
-    }
+    pipelined(
+        n, 0, 1,
+        [&](int i) {
+          In x;
+          x.q = io.q[i];
+          x.qd = io.qd[i];
+          x.qdd = kID ? io.qdd_in[i] : T(0);
+          return x;
+        },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          T sn, cs;
+          joint_sincos(L, x.q, &sn, &cs);
+          scr.at(i, kSC) = sn;
+          scr.at(i, kSC + 1) = cs;
+          const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
+          const Sp<T> XV = X_twist(g, V);
+          const Sp<T> Sqd = x.qd * L.S;
+          V = XV + Sqd;
+          const Sp<T> cor = ad_twist(Sqd, XV);            // ad_{S qd} X V_{i-1}
+          const Sp<T> gyro = adT_wrench(V, mul(L.J, V));  // ad^T_V (J V)
+          if (kID) {
+            dV = X_twist(g, dV) + x.qdd * L.S - cor;
+            scr.put(i, 0, mul(L.J, dV) - gyro);
+          }
+          if (kFD) {
+            dVb = X_twist(g, dVb) - cor;
+            scr.put(i, kOffB, mul(L.J, dVb) - gyro);
+          }
+        });
   }
 
   // ---- sweep 2: tip to base
   {
+    struct In {
+      Sp<T> fh, fb;
+      T sn, cs, q, tau;
+    };
     Sp<double> F = cast_sp<double>(bd.Ftip), Fb = F;
     Sp<double> zA = sp_zero<double>();  // z-hat_{i+1} + U_{i+1} c-hat_{i+1}
     Sym6<T> JA;
     Pose<double> gcw;  // f_{i,i+1} of the child link, double
     Pose<T> gc;        // the same, rounded to T
-    for (int i = n - 1; i >= 0; --i) {
-      const bool has_child = (i < n - 1);
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
-      if (kID) {
-        Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
-        F = Fc + cast_sp<double>(scr.get(i, 0));
-        io.tau_out[i] = (T)dot(Lw.S, F);
-      }
-      if (kFD) {
-        Sp<double> Fc = has_child ? XT_wrench(gcw, Fb) : Fb;
-        Fb = Fc + cast_sp<double>(scr.get(i, kOffB));
-        const double tauhat = (double)io.tau_in[i] - dot(Lw.S, Fb);
-        // articulated-body inertia, eq. (7): Jhat_i = J_i + X^T (Jhat_{i+1} - U U^T / D) X
-        Sym6<T> Jh = sym6_from_inertia(L.J);
-        Sp<double> z = sp_zero<double>();
-        if (has_child) {
-          const Sym6<T> P = congruence_to_parent(gc, JA);
-          Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
-          Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+    pipelined(
+        n, n - 1, -1,
+        [&](int i) {
+          In x;
+          if (kID) x.fh = scr.get(i, 0);
+          if (kFD) {
+            x.fb = scr.get(i, kOffB);
+            x.tau = io.tau_in[i];
+          }
+          x.sn = scr.at(i, kSC);
+          x.cs = scr.at(i, kSC + 1);
+          x.q = io.q[i];
+          return x;
+        },
+        [&](int i, const In& x) {
+          const bool has_child = (i < n - 1);
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          if (kID) {
+            Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
+            F = Fc + cast_sp<double>(x.fh);
+            io.tau_out[i] = (T)dot(Lw.S, F);
+          }
+          if (kFD) {
+            Sp<double> Fc = has_child ? XT_wrench(gcw, Fb) : Fb;
+            Fb = Fc + cast_sp<double>(x.fb);
+            const double tauhat = (double)x.tau - dot(Lw.S, Fb);
+            // articulated-body inertia, eq. (7): Jhat_i = J_i + X^T (Jhat_{i+1} - U U^T / D) X
+            Sym6<T> Jh = sym6_from_inertia(L.J);
+            Sp<double> z = sp_zero<double>();
+            if (has_child) {
+              const Sym6<T> P = congruence_to_parent(gc, JA);
+              Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+              Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
 #pragma unroll
-          for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
-          Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
-          Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
-          // z-hat_i = X^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}), eq. (8) with Y, Pi expanded
-          z = XT_wrench(gcw, zA);
-        }
-        const Sp<T> U = mul(Jh, L.S);
-        const T invD = T(1) / dot(L.S, U);
-        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
-        const T chat = (T)chat_w;
-        JA = sym6_minus_outer(Jh, U, invD);
-        zA = z + chat_w * cast_sp<double>(U);
-        scr.put(i, 0, U);
-        scr.at(i, 6) = invD;
-        scr.at(i, 7) = chat;
-      }
-      gcw = joint_transform_wide_sc(Lw, io.q[i], scr.at(i, kSC), scr.at(i, kSC + 1));
-      gc = cast_pose<T>(gcw);
-    }
+              for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+              Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+              Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+              // z-hat_i = X^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}), eq. (8) with Y, Pi expanded
+              z = XT_wrench(gcw, zA);
+            }
+            const Sp<T> U = mul(Jh, L.S);
+            const T invD = T(1) / dot(L.S, U);
+            const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
+            const T chat = (T)chat_w;
+            JA = sym6_minus_outer(Jh, U, invD);
+            zA = z + chat_w * cast_sp<double>(U);
+            scr.put(i, 0, U);
+            scr.at(i, 6) = invD;
+            scr.at(i, 7) = chat;
+          }
+          gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
+          gc = cast_pose<T>(gcw);
+        });
   }
 
   // ---- sweep 3: base to tip
   if (kFD) {
+    struct In {
+      Sp<T> U;
+      T invD, chat, sn, cs, q;
+    };
     Sp<T> lam = sp_zero<T>();
-    for (int i = 0; i < n; ++i) {
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = joint_transform_sc(L, io.q[i], scr.at(i, kSC), scr.at(i, kSC + 1));
-      const Sp<T> U = scr.get(i, 0);
-      const T invD = scr.at(i, 6), chat = scr.at(i, 7);
-      const Sp<T> a = X_twist(g, lam);
-      const T qdd = chat - dot(U, a) * invD;
-      lam = a + qdd * L.S;
-      epi(i, qdd);
-    }
+    pipelined(
+        n, 0, 1,
+        [&](int i) {
+          In x;
+          x.U = scr.get(i, 0);
+          x.invD = scr.at(i, 6);
+          x.chat = scr.at(i, 7);
+          x.sn = scr.at(i, kSC);
+          x.cs = scr.at(i, kSC + 1);
+          x.q = io.q[i];
+          return x;
+        },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+          const Sp<T> a = X_twist(g, lam);
+          const T qdd = x.chat - dot(x.U, a) * x.invD;
+          lam = a + qdd * L.S;
+          epi(i, qdd);
+        });
   }
 }
 
@@ -335,6 +402,144 @@ template <class T, int MODE>
 PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
                               const Boundary<T>& bd, const Scratch<T>& scr) {
   dynamics_one_state<T, MODE>(n, table, wtable, io, bd, scr, StoreQdd<T>{io.qdd_out});
+}
+
+// ============================================================================
+// Role-split forward dynamics: the same recursions as dynamics_one_state, cut
+// into passes that separate workgroup wavefronts run for the same state (one
+// lane each), so that the articulated-body inertia recursion -- the largest
+// serial piece, which depends on q only -- runs beside the Newton-Euler passes
+// instead of after them. Hand-offs go through per-state scratch:
+//   abi:   [link][7]  U_i (6), 1/D_i                    (pass A  ->  pass B2, C)
+//   bias:  [link][10] Fhat_bias (6), c-hat (1), pad, sin, cos  (B1 -> B2 -> C)
+// ============================================================================
+
+constexpr int kAbiWords = 7;
+constexpr int kBiasWords = 10;
+
+// Pass A (tip to base): Jhat_i, U_i = Jhat_i S_i, 1/D_i.
+template <class T>
+PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Scratch<T>& abi) {
+  Sym6<T> JA;
+  Pose<T> gc;
+  pipelined(
+      n, n - 1, -1, [&](int i) { return q[i]; },
+      [&](int i, T qi) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        Sym6<T> Jh = sym6_from_inertia(L.J);
+        if (i < n - 1) {
+          const Sym6<T> P = congruence_to_parent(gc, JA);
+          Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+          Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+          Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+          Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+        }
+        const Sp<T> U = mul(Jh, L.S);
+        const T invD = T(1) / dot(L.S, U);
+        JA = sym6_minus_outer(Jh, U, invD);
+        abi.put(i, 0, U);
+        abi.at(i, 6) = invD;
+        gc = cast_pose<T>(joint_transform_wide(Lw, L, qi));
+      });
+}
+
+// Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
+template <class T>
+PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
+                              const Scratch<T>& bias) {
+  struct In {
+    T q, qd;
+  };
+  Sp<T> V = bd.V0, dVb = bd.dV0;
+  pipelined(
+      n, 0, 1, [&](int i) { return In{q[i], qd[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        T sn, cs;
+        joint_sincos(L, x.q, &sn, &cs);
+        bias.at(i, 8) = sn;
+        bias.at(i, 9) = cs;
+        const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
+        const Sp<T> XV = X_twist(g, V);
+        const Sp<T> Sqd = x.qd * L.S;
+        V = XV + Sqd;
+        dVb = X_twist(g, dVb) - ad_twist(Sqd, XV);
+        bias.put(i, 0, mul(L.J, dVb) - adT_wrench(V, mul(L.J, V)));
+      });
+}
+
+// Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
+template <class T>
+PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> tau_in,
+                               const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi) {
+  struct In {
+    Sp<T> fb, U;
+    T invD, sn, cs, q, tau;
+  };
+  Sp<double> Fb = cast_sp<double>(bd.Ftip), zA = sp_zero<double>();
+  Pose<double> gcw;
+  pipelined(
+      n, n - 1, -1,
+      [&](int i) {
+        In x;
+        x.fb = bias.get(i, 0);
+        x.sn = bias.at(i, 8);
+        x.cs = bias.at(i, 9);
+        x.U = abi.get(i, 0);
+        x.invD = abi.at(i, 6);
+        x.q = q[i];
+        x.tau = tau_in[i];
+        return x;
+      },
+      [&](int i, const In& x) {
+        const bool has_child = (i < n - 1);
+        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        Sp<double> z = sp_zero<double>();
+        if (has_child) {
+          Fb = XT_wrench(gcw, Fb);
+          z = XT_wrench(gcw, zA);
+        }
+        Fb = Fb + cast_sp<double>(x.fb);
+        const double tauhat = (double)x.tau - dot(Lw.S, Fb);
+        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)x.invD;
+        zA = z + chat_w * cast_sp<double>(x.U);
+        bias.at(i, 6) = (T)chat_w;
+        gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
+      });
+}
+
+// Pass C (base to tip): lambda, qdd.
+template <class T, class Epi>
+PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>& bias, const Scratch<T>& abi,
+                        const Epi& epi) {
+  struct In {
+    Sp<T> U;
+    T invD, chat, sn, cs, q;
+  };
+  Sp<T> lam = sp_zero<T>();
+  pipelined(
+      n, 0, 1,
+      [&](int i) {
+        In x;
+        x.U = abi.get(i, 0);
+        x.invD = abi.at(i, 6);
+        x.chat = bias.at(i, 6);
+        x.sn = bias.at(i, 8);
+        x.cs = bias.at(i, 9);
+        x.q = q[i];
+        return x;
+      },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        const Sp<T> a = X_twist(g, lam);
+        const T qdd = x.chat - dot(x.U, a) * x.invD;
+        lam = a + qdd * L.S;
+        epi(i, qdd);
+      });
 }
 
 // ============================================================================
@@ -389,8 +594,23 @@ template <class T> struct VjpIO {
 };
 
 // Scratch words per link of the adjoint passes: Fbar, V, A (6 each), the
-// wrench part of q_bar (1), padding (1).
-constexpr int kVjpWords = 20;
+// wrench part of q_bar (1), padding (1), then (sin, cos) of the joint angle,
+// computed by the first pass and reused by the others.
+constexpr int kVjpWords = 22;
+constexpr int kVjpSC = 20;
+
+template <class T> PD_HD void store_sincos(const Scratch<T>& scr, int i, const Link<T>& L, T q) {
+  T sn, cs;
+  joint_sincos(L, q, &sn, &cs);
+  scr.at(i, kVjpSC) = sn;
+  scr.at(i, kVjpSC + 1) = cs;
+}
+template <class T> PD_HD Pose<T> stored_transform(const Scratch<T>& scr, int i, const Link<T>& L, T q) {
+  return joint_transform_sc(L, q, scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1));
+}
+template <class T> PD_HD Pose<double> stored_transform_wide(const Scratch<T>& scr, int i, const Link<double>& Lw, T q) {
+  return joint_transform_wide_sc(Lw, q, scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1));
+}
 
 // Sweep 1 of the inverse dynamics: V, A and Fhat_i into scratch slot 0.
 template <class T>
@@ -418,7 +638,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
       if (i < n - 1) F = XT_wrench(gcw, F);
       F = F + cast_sp<double>(scr.get(i, 0));
       scr.put(i, 0, cast_sp<T>(F));
-      gcw = joint_transform_wide(Lw, load_link(table + (long)i * kLinkWords), q[i]);
+      gcw = stored_transform_wide(scr, i, Lw, q[i]);
     }
   }
   // sweep 3 (base to tip): Fbar, V, A again; the wrench part of q_bar; pi_bar
@@ -426,7 +646,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
     Sp<T> V = bd.V0, A = bd.dV0, Fb = sp_zero<T>();
     for (int i = 0; i < n; ++i) {
       const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = joint_transform(L, q[i]);
+      const Pose<T> g = stored_transform(scr, i, L, q[i]);
       const Sp<T> XV = X_twist(g, V);
       const Sp<T> Sqd = qd[i] * L.S;
       V = XV + Sqd;
@@ -461,7 +681,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
       if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
       qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
       q_bar[i] = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
-      const Pose<T> g = joint_transform(L, q[i]);
+      const Pose<T> g = stored_transform(scr, i, L, q[i]);
       Ac = XT_wrench(g, Ab);
       yc = XT_wrench(g, yb);
     }
@@ -474,7 +694,8 @@ PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const V
   Sp<T> V = bd.V0, A = bd.dV0;
   for (int i = 0; i < n; ++i) {
     const Link<T> L = load_link(table + (long)i * kLinkWords);
-    vjp_forward_fhat(i, L, joint_transform(L, io.q[i]), io.qd[i], io.qdd[i], V, A, scr);
+    store_sincos(scr, i, L, io.q[i]);
+    vjp_forward_fhat(i, L, stored_transform(scr, i, L, io.q[i]), io.qd[i], io.qdd[i], V, A, scr);
   }
   id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.bar_in, T(1), io.q_bar, io.qd_bar, io.qdd_bar, bd, scr,
               sink);
@@ -513,7 +734,8 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
       scr.put(i, 0, U);
       scr.at(i, 6) = invD;
       scr.at(i, 7) = (T)chat_w;
-      gcw = joint_transform_wide(Lw, L, io.q[i]);
+      store_sincos(scr, i, L, io.q[i]);
+      gcw = stored_transform_wide(scr, i, Lw, io.q[i]);
       gc = cast_pose<T>(gcw);
     }
   }
@@ -522,7 +744,7 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
     Sp<T> lam = sp_zero<T>(), V = bd.V0, A = bd.dV0;
     for (int i = 0; i < n; ++i) {
       const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = joint_transform(L, io.q[i]);
+      const Pose<T> g = stored_transform(scr, i, L, io.q[i]);
       const Sp<T> U = scr.get(i, 0);
       const T invD = scr.at(i, 6), chat = scr.at(i, 7);
       const Sp<T> a = X_twist(g, lam);

@@ -8,6 +8,8 @@
 
 using namespace pdyn;
 
+constexpr int kSplitFD = 5, kSplitIDFD = 7;  // FD, ID+FD through the role-split passes
+
 template <class T>
 static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
                const T* twist, const T* inertia, const T* q, const T* qd, const T* qdd_in, const T* tau_in,
@@ -20,7 +22,13 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
     for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
   }
   int words = mode == kModeIDFD ? ScratchWords<kModeIDFD>::value : (mode == kModeFD ? ScratchWords<kModeFD>::value : ScratchWords<kModeID>::value);
+  if (mode == kSplitFD || mode == kSplitIDFD) words = ScratchWords<kModeID>::value;
   std::vector<T> scratch((size_t)n_max * words * n_states, T(-7777));  // poisoned
+  std::vector<T> abi_scr, bias_scr;
+  if (mode == kSplitFD || mode == kSplitIDFD) {
+    abi_scr.assign((size_t)n_max * kAbiWords * n_states, T(-7777));
+    bias_scr.assign((size_t)n_max * kBiasWords * n_states, T(-7777));
+  }
   Boundary<T> bd;
   bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
   bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
@@ -33,6 +41,23 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
                   tau_out ? tau_out + dof0 : nullptr, qdd_out ? qdd_out + dof0 : nullptr};
     bd.Ftip = tip ? Sp<T>{v3(tip[6 * s], tip[6 * s + 1], tip[6 * s + 2]), v3(tip[6 * s + 3], tip[6 * s + 4], tip[6 * s + 5])} : sp_zero<T>();
     Scratch<T> scr{scratch.data() + s, (long)n_states, words};
+    if (mode == kSplitFD || mode == kSplitIDFD) {
+      // the role-split passes of k_dynamics_split, run one after another
+      const T* tab = table.data() + link0 * kLinkWords;
+      const double* wtab = wtable.data() + link0 * kLinkWords;
+      const Scratch<T> abi{abi_scr.data() + s, (long)n_states, kAbiWords};
+      const Scratch<T> bias{bias_scr.data() + s, (long)n_states, kBiasWords};
+      if (mode == kSplitIDFD) {
+        JointIO<T> id_io{io.q, io.qd, io.qdd_in, SPtr<const T>(), io.tau_out, SPtr<T>()};
+        const Scratch<T> idscr{scratch.data() + s, (long)n_states, ScratchWords<kModeID>::value};
+        dynamics_one_state<T, kModeID>(n, tab, wtab, id_io, bd, idscr);
+      }
+      split_bias_forward(n, tab, io.q, io.qd, bd, bias);
+      split_abi_pass(n, tab, wtab, io.q, abi);
+      split_bias_backward(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
+      split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out});
+      continue;
+    }
     if (mode == kModeID) dynamics_one_state<T, kModeID>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);
     else if (mode == kModeFD) dynamics_one_state<T, kModeFD>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);
     else dynamics_one_state<T, kModeIDFD>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);

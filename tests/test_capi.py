@@ -104,7 +104,7 @@ def test_workspace_query():
     w_fd = L.pdyn_workspace_bytes(1, ctypes.byref(m), ctypes.byref(b), 4)
     w_idfd = L.pdyn_workspace_bytes(2, ctypes.byref(m), ctypes.byref(b), 4)
     w_idfd64 = L.pdyn_workspace_bytes(2, ctypes.byref(m), ctypes.byref(b), 8)
-    assert 0 < w_id < w_fd < w_idfd < w_idfd64
+    assert 0 < w_id < w_fd <= w_idfd < w_idfd64
     assert all(w % 256 == 0 for w in (w_id, w_fd, w_idfd))
     # scratch alone is [links][words][states] scalars
     assert w_idfd >= 32 * 12 * 1000 * 4

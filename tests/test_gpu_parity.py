@@ -214,3 +214,49 @@ def test_uneven_id_fd_in_a_captured_graph(device):
         torch.cuda.synchronize()
         assert torch.equal(out[0], eager[0]) and torch.equal(out[1], eager[1]), f"replay {rep}"
         api.rnea_id(model, q, qd, qdd)  # eager work between replays
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_forward_dynamics_variants(device, variant):
+    """Both kernel variants (one wavefront per 64 states; role split) against the oracle:
+    the 32-link workload at 16384 states, ragged chains, an odd batch and FP64 with boundary terms."""
+    print(f"case: variant {variant}", flush=True)
+    for op in (api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, variant)
+    try:
+        ch, st = synth.workload_32link(16384)
+        model = api.Model(ch, device, torch.float32)
+        t1, q1, t2, q2 = run_all(model, st, device, torch.float32)
+        cr, sr = ch.rounded(), st.rounded()
+        ref_t = oracle.rnea(cr, sr.q, sr.qd, sr.qdd, threads=THREADS)
+        ref_q = oracle.aba(cr, sr.q, sr.qd, sr.tau, threads=THREADS)
+        eq = rel_rows(q2, ref_q)
+        print(f"variant {variant}: qdd max rel err {eq.max():.2e}", flush=True)
+        assert eq.max() <= TOL32 and rel_rows(q1, ref_q).max() <= TOL32
+        assert rel_rows(t2, ref_t).max() <= TOL32
+        ch = synth.make_chains(list(np.random.default_rng(5).integers(1, 70, 333)), 5)
+        st = synth.make_states((ch.n_links_total,), 5)
+        model = api.Model(ch, device, torch.float32)
+        t1, q1, t2, q2 = run_all(model, st, device, torch.float32)
+        cr, sr = ch.rounded(), st.rounded()
+        lens = ch.lengths()
+        eq = rel_ragged(q2, oracle.aba(cr, sr.q, sr.qd, sr.tau), ch.link_ptr)
+        assert eq[lens <= 32].max() <= TOL32 and eq.max() <= 1e-2
+        assert np.array_equal(q1, q2)
+        ch = synth.make_chains([11], 31)
+        st = synth.make_states((70, 11), 31)
+        rng = np.random.default_rng(31)
+        tip = rng.standard_normal((70, 6))
+        V0, dV0 = tuple(rng.standard_normal(6)), tuple(rng.standard_normal(6))
+        model = api.Model(ch, device, torch.float64)
+        t1, q1, t2, q2 = run_all(model, st, device, torch.float64, base_vel=V0, base_acc=dV0,
+                                 tip=to_dev(tip, device, torch.float64))
+        for s in range(70):
+            rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], np.array(V0), np.array(dV0), tip[s])
+            rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], np.array(V0), np.array(dV0), tip[s])
+            assert np.linalg.norm(t2[s] - rt) <= 1e-12 * np.linalg.norm(rt)
+            assert np.linalg.norm(q1[s] - rq) <= 1e-11 * np.linalg.norm(rq)
+            assert np.linalg.norm(q2[s] - rq) <= 1e-11 * np.linalg.norm(rq)
+    finally:
+        for op in (api.OP_ABA_FD, api.OP_ID_FD):
+            api.set_launch(op, 0, 0, 0)

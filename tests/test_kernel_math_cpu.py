@@ -19,6 +19,7 @@ from paper_1609_04493_amd import synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_cpu", "sweeps_on_cpu.hip")
 MODE_ID, MODE_FD, MODE_IDFD = 1, 2, 3
+SPLIT_FD, SPLIT_IDFD = 5, 7  # the role-split passes (articulated inertia beside the Newton-Euler passes)
 
 
 @pytest.fixture(scope="module")
@@ -107,6 +108,37 @@ def test_fp32_sweeps_32_links(cpu_lib):
     ref_qdd = oracle.aba(chr_, str_.q, str_.qd, str_.tau)
     assert rel_err_rows(tau, ref_tau).max() <= 1e-4
     assert rel_err_rows(qdd, ref_qdd).max() <= 1e-4
+
+
+def test_role_split_passes_match_oracle(cpu_lib):
+    """The role-split passes: FP64 to rounding (with boundary terms, ragged chains), FP32 at 32 links."""
+    ch = synth.make_chains([9], 17)
+    st = synth.make_states((16, 9), 17)
+    rng = np.random.default_rng(17)
+    tip = rng.standard_normal((16, 6))
+    V0, dV0 = rng.standard_normal(6), rng.standard_normal(6)
+    tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch, st, np.float64, tip, V0, dV0)
+    _, qdd_fd = run_cpu(cpu_lib, SPLIT_FD, ch, st, np.float64, tip, V0, dV0)
+    assert np.array_equal(qdd, qdd_fd)
+    for s in range(16):
+        rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], V0, dV0, tip[s])
+        rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s])
+        assert np.linalg.norm(tau[s] - rt) <= 1e-12 * np.linalg.norm(rt)
+        assert np.linalg.norm(qdd[s] - rq) <= 1e-11 * np.linalg.norm(rq)
+    ch = synth.make_chains([1, 2, 13, 5, 30], 23)
+    st = synth.make_states((ch.n_links_total,), 23)
+    _, qdd = run_cpu(cpu_lib, SPLIT_FD, ch, st, np.float64)
+    ref = oracle.aba(ch, st.q, st.qd, st.tau)
+    for c in range(ch.n_chains):
+        a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+        assert np.linalg.norm(qdd[a:b] - ref[a:b]) <= 1e-10 * np.linalg.norm(ref[a:b])
+    ch, st = synth.workload_32link(256)
+    tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch.astype(np.float32), st.astype(np.float32), np.float32)
+    cr, sr = ch.rounded(), st.rounded()
+    e = rel_err_rows(qdd, oracle.aba(cr, sr.q, sr.qd, sr.tau))
+    print(f"split fp32 qdd max rel err {e.max():.2e}")
+    assert e.max() <= 1e-4
+    assert rel_err_rows(tau, oracle.rnea(cr, sr.q, sr.qd, sr.qdd)).max() <= 1e-4
 
 
 # ---- adjoints -----------------------------------------------------------------------
