@@ -290,7 +290,7 @@ def main():
                    "precision": "f32 bulk; f64 wrench and articulated-bias accumulations"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_FLOPS / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_FLOPS, "traffic": None,
-                     "kernel": "k_dynamics<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
+                     "kernel": "k_dynamics_split<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
                      "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
         "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
                             "2": dict(variants[2], form="articulated-inertia pass on its own wavefront")},

@@ -105,7 +105,8 @@ typedef struct pdyn_batch {
   int32_t block_threads;
   int32_t max_blocks;
   /* Kernel variant for forward dynamics and fused ID+FD (0 = library
-   * default): 1 = one wavefront runs every recursion of its 64 states;
+   * default, which is 2): 1 = one wavefront runs every recursion of its 64
+   * states;
    * 2 = role split -- per group of 64 states one wavefront runs the
    * articulated-body inertia recursion (7) while others run the Newton-Euler
    * passes, then the z-hat / lambda recursions of (8) (block_threads and

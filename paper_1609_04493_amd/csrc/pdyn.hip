@@ -28,7 +28,7 @@ namespace {
 constexpr int kMaxLinks = 1 << 16;
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
-constexpr int kDefaultVariant = 1;  // forward dynamics: one wavefront per 64 states
+constexpr int kDefaultVariant = 2;  // forward dynamics: the role-split kernel
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -111,9 +111,12 @@ struct ChainOf {
   int n;
   int64_t link0, dof0;
 };
-__device__ __forceinline__ ChainOf chain_of(int s, int n_chains, int n_max, const int32_t* link_ptr) {
+// SHARED (one chain for every state) is a compile-time flag so that n stays
+// wave-uniform and the link records load through the scalar unit.
+template <bool SHARED>
+__device__ __forceinline__ ChainOf chain_of(int s, int n_max, const int32_t* link_ptr) {
   ChainOf c;
-  if (n_chains == 1) {
+  if (SHARED) {
     c.n = n_max;
     c.link0 = 0;
     c.dof0 = (int64_t)s * n_max;
@@ -136,8 +139,9 @@ __device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
 
 // Role-split forward dynamics (variant 2): per group of 64 states, wavefront 0
 // runs the articulated-body inertia pass, wavefront 1 the bias Newton-Euler
-// pass, and for ID+FD wavefront 2 the inverse dynamics; after one workgroup
-// barrier wavefront 1 runs the bias wrench / z-hat pass and the lambda pass.
+// pass, and for ID+FD wavefront 2 the inverse dynamics (outside the barrier);
+// after one workgroup barrier wavefront 1 runs the bias wrench / z-hat pass and
+// the lambda pass.
 template <class T, int MODE, bool SHARED>
 __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
@@ -149,12 +153,12 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
   const int role = threadIdx.x / 64;  // wave-uniform
   const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
   const bool active = lane_index < n_states;
-  int s = 0, n = 0;
+  // with a shared chain n stays uniform, so link records load through the scalar unit
+  int s = 0, n = SHARED ? n_max : 0;
   int64_t link0 = 0, dof0 = 0;
   if (active) {
     s = SHARED ? lane_index : state_of(lane_index, order);
     if (SHARED) {
-      n = n_max;
       dof0 = (int64_t)s * n_max;
     } else {
       link0 = link_ptr[s];
@@ -172,16 +176,21 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
   const Scratch<T> abi{scr_abi + lane_index, (long)n_states, kAbiWords};
   const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
-  if (active) {
-    if (role == 0) {
-      split_abi_pass(n, tab, wtab, qs, abi);
-    } else if (role == 1) {
-      split_bias_forward(n, tab, qs, qds, bd, bias);
-    } else {
+  if (role == 2) {
+    // Inverse dynamics shares nothing with the other two wavefronts: it ends
+    // here, and a workgroup barrier waits only for wavefronts still running.
+    if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
       const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value};
       dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr);
     }
+    return;
+  }
+  if (active) {
+    if (role == 0)
+      split_abi_pass(n, tab, wtab, qs, abi);
+    else
+      split_bias_forward(n, tab, qs, qds, bd, bias);
   }
   __syncthreads();
   if (active && role == 1) {
@@ -216,7 +225,7 @@ template <class T, int PI> struct PiSink {
 };
 
 // Scratch of the adjoints: [n_max][kVjpWords][n_states].
-template <class T, int OP, int PI>
+template <class T, int OP, int PI, bool SHARED>
 __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
                                                 const int32_t* __restrict__ order, const T* __restrict__ table,
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
@@ -226,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
   const int s = state_of(lane_index, order);
-  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+  const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
   VjpIO<T> io;
   io.q = q + c.dof0;
   io.qd = qd + c.dof0;
@@ -307,7 +316,7 @@ struct NoSink {
 };
 
 // Forward rollout, one lane per state, all steps in one launch.
-template <class T>
+template <class T, bool SHARED>
 __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chains, int n_max,
                                                        const int32_t* __restrict__ link_ptr,
                                                        const int32_t* __restrict__ order, const T* __restrict__ table,
@@ -319,7 +328,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
     if (lane_index >= n_states) continue;
     const int s = state_of(lane_index, order);
-    const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+    const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value};
     rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every,
                       SPtr<T>(q + c.dof0), SPtr<T>(qd + c.dof0), DevRows<T>{tau_seq + c.dof0, dofs},
@@ -331,7 +340,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
 // lane-interleaved: adjoint scratch [n_max][kVjpWords][n_states]; working rows
 // [(3 every + 6) n_max][n_states]; pi accumulators [n_max][10][n_states]
 // (shared chain; zeroed here).
-template <class T, int PI>
+template <class T, int PI, bool SHARED>
 __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chains, int n_max,
                                                         const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order, const T* __restrict__ table,
@@ -343,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
   const int s = state_of(lane_index, order);
-  const ChainOf c = chain_of(s, n_chains, n_max, link_ptr);
+  const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
   // working rows, lane-interleaved: element i of row r at rows_ws[(r n_max + i) n_states + lane]
   const long S = n_states;
   T* const rb = rows_ws + lane_index;
@@ -602,10 +611,16 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   const long dofs = (m->n_chains == 1) ? (long)b->n_states * m->n_links_max : (long)m->n_links_total;
   unsigned grid, block;
   launch_shape(b, &grid, &block);
-  hipLaunchKernelGGL(k_rollout<T>, dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,
-                     m->link_ptr, m->order, reinterpret_cast<const T*>(tbase), reinterpret_cast<const double*>(tbase + woff),
-                     steps, (T)dt, every, tau_seq, q, qd, ckpt_q, ckpt_qd, dofs, ba,
-                     reinterpret_cast<T*>(base + so));
+#define PDYN_LAUNCH_ROLLOUT(SH)                                                                                  \
+  hipLaunchKernelGGL((k_rollout<T, SH>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,   \
+                     m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                                    \
+                     reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, q, qd, ckpt_q,   \
+                     ckpt_qd, dofs, ba, reinterpret_cast<T*>(base + so))
+  if (m->n_chains == 1)
+    PDYN_LAUNCH_ROLLOUT(true);
+  else
+    PDYN_LAUNCH_ROLLOUT(false);
+#undef PDYN_LAUNCH_ROLLOUT
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -634,19 +649,22 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   const long dofs = (m->n_chains == 1) ? (long)b->n_states * m->n_links_max : (long)m->n_links_total;
   const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
   T* acc = reinterpret_cast<T*>(base + ao);
-#define PDYN_LAUNCH_RVJP(PI)                                                                                     \
-  hipLaunchKernelGGL((k_rollout_vjp<T, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
+#define PDYN_LAUNCH_RVJP(PI, SH)                                                                                 \
+  hipLaunchKernelGGL((k_rollout_vjp<T, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
                      m->n_links_max, m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                   \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
                      ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
                      reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc)
   if (!inertia_bar) {
-    PDYN_LAUNCH_RVJP(kPiNone);
+    if (m->n_chains == 1)
+      PDYN_LAUNCH_RVJP(kPiNone, true);
+    else
+      PDYN_LAUNCH_RVJP(kPiNone, false);
   } else if (m->n_chains == 1) {
-    PDYN_LAUNCH_RVJP(kPiLanes);
+    PDYN_LAUNCH_RVJP(kPiLanes, true);
     hipLaunchKernelGGL(k_reduce_lanes<T>, dim3(m->n_links_max * 10), dim3(256), 0, s, b->n_states, acc, inertia_bar);
   } else {
-    PDYN_LAUNCH_RVJP(kPiDirect);
+    PDYN_LAUNCH_RVJP(kPiDirect, false);
   }
 #undef PDYN_LAUNCH_RVJP
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
@@ -687,18 +705,21 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* qdd_bar = (OP == kVjpID) ? out3 : nullptr;
   T* tau_bar = (OP == kVjpFD) ? out3 : nullptr;
   const T* tip = static_cast<const T*>(b->tip_wrench);
-#define PDYN_LAUNCH_VJP(PI, PIOUT)                                                                            \
-  hipLaunchKernelGGL((k_vjp<T, OP, PI>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
+#define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
+  hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
                      m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar, \
                      tau_bar, PIOUT, tip, ba, scratch)
   if (!inertia_bar) {
-    PDYN_LAUNCH_VJP(kPiNone, static_cast<T*>(nullptr));
+    if (m->n_chains == 1)
+      PDYN_LAUNCH_VJP(kPiNone, true, static_cast<T*>(nullptr));
+    else
+      PDYN_LAUNCH_VJP(kPiNone, false, static_cast<T*>(nullptr));
   } else if (m->n_chains == 1) {
-    PDYN_LAUNCH_VJP(kPiLanes, partials);
+    PDYN_LAUNCH_VJP(kPiLanes, true, partials);
     hipLaunchKernelGGL(k_reduce_lanes<T>, dim3(m->n_links_max * 10), dim3(256), 0, s, b->n_states, partials,
                        inertia_bar);
   } else {
-    PDYN_LAUNCH_VJP(kPiDirect, inertia_bar);
+    PDYN_LAUNCH_VJP(kPiDirect, false, inertia_bar);
   }
 #undef PDYN_LAUNCH_VJP
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;

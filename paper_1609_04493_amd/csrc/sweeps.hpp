@@ -599,19 +599,6 @@ template <class T> struct VjpIO {
 constexpr int kVjpWords = 22;
 constexpr int kVjpSC = 20;
 
-template <class T> PD_HD void store_sincos(const Scratch<T>& scr, int i, const Link<T>& L, T q) {
-  T sn, cs;
-  joint_sincos(L, q, &sn, &cs);
-  scr.at(i, kVjpSC) = sn;
-  scr.at(i, kVjpSC + 1) = cs;
-}
-template <class T> PD_HD Pose<T> stored_transform(const Scratch<T>& scr, int i, const Link<T>& L, T q) {
-  return joint_transform_sc(L, q, scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1));
-}
-template <class T> PD_HD Pose<double> stored_transform_wide(const Scratch<T>& scr, int i, const Link<double>& Lw, T q) {
-  return joint_transform_wide_sc(Lw, q, scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1));
-}
-
 // Sweep 1 of the inverse dynamics: V, A and Fhat_i into scratch slot 0.
 template <class T>
 PD_HD void vjp_forward_fhat(int i, const Link<T>& L, const Pose<T>& g, T qd, T qdd, Sp<T>& V, Sp<T>& A,
@@ -631,72 +618,103 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
                        const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   // sweep 2 (tip to base): wrenches F_i in double, stored rounded in slot 0
   {
+    struct In {
+      Sp<T> fh;
+      T sn, cs, q;
+    };
     Sp<double> F = cast_sp<double>(bd.Ftip);
     Pose<double> gcw;
-    for (int i = n - 1; i >= 0; --i) {
-      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
-      if (i < n - 1) F = XT_wrench(gcw, F);
-      F = F + cast_sp<double>(scr.get(i, 0));
-      scr.put(i, 0, cast_sp<T>(F));
-      gcw = stored_transform_wide(scr, i, Lw, q[i]);
-    }
+    pipelined(
+        n, n - 1, -1,
+        [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
+        [&](int i, const In& x) {
+          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          if (i < n - 1) F = XT_wrench(gcw, F);
+          F = F + cast_sp<double>(x.fh);
+          scr.put(i, 0, cast_sp<T>(F));
+          gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
+        });
   }
   // sweep 3 (base to tip): Fbar, V, A again; the wrench part of q_bar; pi_bar
   {
+    struct In {
+      Sp<T> F;
+      T sn, cs, q, qd, qdd, tb;
+    };
     Sp<T> V = bd.V0, A = bd.dV0, Fb = sp_zero<T>();
-    for (int i = 0; i < n; ++i) {
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = stored_transform(scr, i, L, q[i]);
-      const Sp<T> XV = X_twist(g, V);
-      const Sp<T> Sqd = qd[i] * L.S;
-      V = XV + Sqd;
-      A = X_twist(g, A) + qdd[i] * L.S - ad_twist(Sqd, XV);
-      Fb = X_twist(g, Fb) + (sgn * tb[i]) * L.S;
-      const Sp<T> F = scr.get(i, 0);
-      const T qbp = -dot(ad_twist(L.S, Fb), F);
-      T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-      const V3<T> c = (T(1) / L.J.m) * L.J.h;
-      add_inertia_grad(L.J.m, c, Fb, A, T(1), gpi);
-      add_inertia_grad(L.J.m, c, ad_twist(V, Fb), V, T(-1), gpi);
-      sink.put(i, gpi);
-      scr.put(i, 0, Fb);
-      scr.put(i, 6, V);
-      scr.put(i, 12, A);
-      scr.at(i, 18) = qbp;
-    }
+    pipelined(
+        n, 0, 1,
+        [&](int i) {
+          return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i], tb[i]};
+        },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+          const Sp<T> XV = X_twist(g, V);
+          const Sp<T> Sqd = x.qd * L.S;
+          V = XV + Sqd;
+          A = X_twist(g, A) + x.qdd * L.S - ad_twist(Sqd, XV);
+          Fb = X_twist(g, Fb) + (sgn * x.tb) * L.S;
+          const T qbp = -dot(ad_twist(L.S, Fb), x.F);
+          T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+          const V3<T> c = (T(1) / L.J.m) * L.J.h;
+          add_inertia_grad(L.J.m, c, Fb, A, T(1), gpi);
+          add_inertia_grad(L.J.m, c, ad_twist(V, Fb), V, T(-1), gpi);
+          sink.put(i, gpi);
+          scr.put(i, 0, Fb);
+          scr.put(i, 6, V);
+          scr.put(i, 12, A);
+          scr.at(i, 18) = qbp;
+        });
   }
   // sweep 4 (tip to base): adjoints of the velocity / acceleration recursion
   {
+    struct In {
+      Sp<T> Fb, V, A;
+      T qbp, sn, cs, q, qd, qdd;
+    };
     Sp<T> Ac = sp_zero<T>(), yc = sp_zero<T>();
-    for (int i = n - 1; i >= 0; --i) {
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Sp<T> Fb = scr.get(i, 0), V = scr.get(i, 6), A = scr.get(i, 12);
-      const T qbp = scr.at(i, 18);
-      const Sp<T> Ab = mul(L.J, Fb) + Ac;
-      const Sp<T> Vb = adT_wrench(Fb, mul(L.J, V)) - mul(L.J, ad_twist(V, Fb)) + yc;
-      const Sp<T> Sqd = qd[i] * L.S;
-      const Sp<T> y = V - Sqd;
-      const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
-      const Sp<T> XA = A - qdd[i] * L.S + ad_twist(Sqd, y);
-      if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
-      qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
-      q_bar[i] = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
-      const Pose<T> g = stored_transform(scr, i, L, q[i]);
-      Ac = XT_wrench(g, Ab);
-      yc = XT_wrench(g, yb);
-    }
+    pipelined(
+        n, n - 1, -1,
+        [&](int i) {
+          return In{scr.get(i, 0), scr.get(i, 6), scr.get(i, 12), scr.at(i, 18), scr.at(i, kVjpSC),
+                    scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i]};
+        },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
+          const Sp<T> Vb = adT_wrench(x.Fb, mul(L.J, x.V)) - mul(L.J, ad_twist(x.V, x.Fb)) + yc;
+          const Sp<T> Sqd = x.qd * L.S;
+          const Sp<T> y = x.V - Sqd;
+          const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
+          const Sp<T> XA = x.A - x.qdd * L.S + ad_twist(Sqd, y);
+          if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
+          qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
+          q_bar[i] = x.qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+          Ac = XT_wrench(g, Ab);
+          yc = XT_wrench(g, yb);
+        });
   }
 }
 
 template <class T, class Sink>
 PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const VjpIO<T>& io,
                             const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
+  struct In {
+    T q, qd, qdd;
+  };
   Sp<T> V = bd.V0, A = bd.dV0;
-  for (int i = 0; i < n; ++i) {
-    const Link<T> L = load_link(table + (long)i * kLinkWords);
-    store_sincos(scr, i, L, io.q[i]);
-    vjp_forward_fhat(i, L, stored_transform(scr, i, L, io.q[i]), io.qd[i], io.qdd[i], V, A, scr);
-  }
+  pipelined(
+      n, 0, 1, [&](int i) { return In{io.q[i], io.qd[i], io.qdd[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        T sn, cs;
+        joint_sincos(L, x.q, &sn, &cs);
+        scr.at(i, kVjpSC) = sn;
+        scr.at(i, kVjpSC + 1) = cs;
+        vjp_forward_fhat(i, L, joint_transform_sc(L, x.q, sn, cs), x.qd, x.qdd, V, A, scr);
+      });
   id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, io.bar_in, T(1), io.q_bar, io.qd_bar, io.qdd_bar, bd, scr,
               sink);
 }
@@ -706,53 +724,69 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
                             const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   // u = M^-1 qdd_bar: articulated-body inertia and z-hat (tip to base) with tau-hat = qdd_bar
   {
+    struct In {
+      T q, bar;
+    };
     Sp<double> zA = sp_zero<double>();
     Sym6<T> JA;
     Pose<double> gcw;
     Pose<T> gc;
-    for (int i = n - 1; i >= 0; --i) {
-      const bool has_child = (i < n - 1);
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
-      Sym6<T> Jh = sym6_from_inertia(L.J);
-      Sp<double> z = sp_zero<double>();
-      if (has_child) {
-        const Sym6<T> P = congruence_to_parent(gc, JA);
-        Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
-        Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+    pipelined(
+        n, n - 1, -1, [&](int i) { return In{io.q[i], io.bar_in[i]}; },
+        [&](int i, const In& x) {
+          const bool has_child = (i < n - 1);
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          Sym6<T> Jh = sym6_from_inertia(L.J);
+          Sp<double> z = sp_zero<double>();
+          if (has_child) {
+            const Sym6<T> P = congruence_to_parent(gc, JA);
+            Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+            Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
-        Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
-        Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
-        z = XT_wrench(gcw, zA);
-      }
-      const Sp<T> U = mul(Jh, L.S);
-      const T invD = T(1) / dot(L.S, U);
-      const double chat_w = ((double)io.bar_in[i] - dot(Lw.S, z)) * (double)invD;
-      JA = sym6_minus_outer(Jh, U, invD);
-      zA = z + chat_w * cast_sp<double>(U);
-      scr.put(i, 0, U);
-      scr.at(i, 6) = invD;
-      scr.at(i, 7) = (T)chat_w;
-      store_sincos(scr, i, L, io.q[i]);
-      gcw = stored_transform_wide(scr, i, Lw, io.q[i]);
-      gc = cast_pose<T>(gcw);
-    }
+            for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+            Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+            Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+            z = XT_wrench(gcw, zA);
+          }
+          const Sp<T> U = mul(Jh, L.S);
+          const T invD = T(1) / dot(L.S, U);
+          const double chat_w = ((double)x.bar - dot(Lw.S, z)) * (double)invD;
+          JA = sym6_minus_outer(Jh, U, invD);
+          zA = z + chat_w * cast_sp<double>(U);
+          scr.put(i, 0, U);
+          scr.at(i, 6) = invD;
+          scr.at(i, 7) = (T)chat_w;
+          T sn, cs;
+          joint_sincos(L, x.q, &sn, &cs);
+          scr.at(i, kVjpSC) = sn;
+          scr.at(i, kVjpSC + 1) = cs;
+          gcw = joint_transform_wide_sc(Lw, x.q, sn, cs);
+          gc = cast_pose<T>(gcw);
+        });
   }
   // lambda (base to tip) gives u; in the same pass, sweep 1 of ID at (q, qd, qdd)
   {
+    struct In {
+      Sp<T> U;
+      T invD, chat, sn, cs, q, qd, qdd;
+    };
     Sp<T> lam = sp_zero<T>(), V = bd.V0, A = bd.dV0;
-    for (int i = 0; i < n; ++i) {
-      const Link<T> L = load_link(table + (long)i * kLinkWords);
-      const Pose<T> g = stored_transform(scr, i, L, io.q[i]);
-      const Sp<T> U = scr.get(i, 0);
-      const T invD = scr.at(i, 6), chat = scr.at(i, 7);
-      const Sp<T> a = X_twist(g, lam);
-      const T u = chat - dot(U, a) * invD;
-      lam = a + u * L.S;
-      io.tau_bar[i] = u;
-      vjp_forward_fhat(i, L, g, io.qd[i], io.qdd[i], V, A, scr);
-    }
+    pipelined(
+        n, 0, 1,
+        [&](int i) {
+          return In{scr.get(i, 0), scr.at(i, 6), scr.at(i, 7), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1),
+                    io.q[i], io.qd[i], io.qdd[i]};
+        },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+          const Sp<T> a = X_twist(g, lam);
+          const T u = x.chat - dot(x.U, a) * x.invD;
+          lam = a + u * L.S;
+          io.tau_bar[i] = u;
+          vjp_forward_fhat(i, L, g, x.qd, x.qdd, V, A, scr);
+        });
   }
   id_vjp_tail(n, table, wtable, io.q, io.qd, io.qdd, SPtr<const T>(io.tau_bar), T(-1), io.q_bar, io.qd_bar,
               SPtr<T>(), bd, scr, sink);

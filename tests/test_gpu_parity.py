@@ -176,10 +176,12 @@ def test_launch_shapes_orders_and_persistence_are_bitwise_identical(device):
     ch = synth.make_chains(list(np.random.default_rng(4).integers(1, 60, 300)), 4)
     st = synth.make_states((ch.n_links_total,), 4)
     model = api.Model(ch, device, torch.float32)
+    for op in (api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, 1)
     ref = run_all(model, st, device, torch.float32)
     for bt, cap, use_order in ((128, 0, True), (256, 1, True), (64, 2, False), (192, 0, False)):
         for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
-            api.set_launch(op, bt, cap)
+            api.set_launch(op, bt, cap, 1)  # launch shapes apply to the one-wavefront variant
         model.use_order = use_order
         got = run_all(model, st, device, torch.float32)
         for x, y in zip(got, ref):
