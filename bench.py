@@ -243,6 +243,18 @@ def main():
                         args.warmup, stream)
     ms_fdv = time_steps(lambda: api.aba_fd_vjp(model, q, qd, qdd_out, qdd_bar, out=gfd, workspace=ws), args.steps,
                         args.warmup, stream)
+    vjp_variants = {}
+    for v in (1, 2):
+        api.set_launch(api.OP_RNEA_ID_VJP, 0, 0, v)
+        api.set_launch(api.OP_ABA_FD_VJP, 0, 0, v)
+        vjp_variants[str(v)] = {
+            "id_vjp_us": 1e3 * time_steps(lambda: api.rnea_id_vjp(model, q, qd, qdd, tau_bar, out=gid, workspace=ws),
+                                          args.steps, args.warmup, stream),
+            "fd_vjp_us": 1e3 * time_steps(lambda: api.aba_fd_vjp(model, q, qd, qdd_out, qdd_bar, out=gfd,
+                                                                 workspace=ws), args.steps, args.warmup, stream)}
+        print(f"adjoint variant {v}: {vjp_variants[str(v)]}", file=sys.stderr, flush=True)
+    api.set_launch(api.OP_RNEA_ID_VJP, 0, 0, 0)
+    api.set_launch(api.OP_ABA_FD_VJP, 0, 0, 0)
 
     # stated error: the fused outputs against the FP64 oracle on a sample of states
     import oracle
@@ -298,6 +310,7 @@ def main():
                   "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
         "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),
                                "id_vjp": N_STATES / (ms_idv * 1e-3), "fd_vjp": N_STATES / (ms_fdv * 1e-3)},
+        "adjoint_variants": vjp_variants,
         "grad": {"form": "fused ID+FD, then pdyn_rnea_id_vjp and pdyn_aba_fd_vjp (L = ||qdd||^2), inertia gradients on",
                  "value": N_STATES / (ms_grad * 1e-3), "unit": "evals/s", "ms_per_step": ms_grad,
                  "max_rel_err_vs_oracle_4_states": gerr},

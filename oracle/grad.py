@@ -60,28 +60,29 @@ def _jac(fun, args, which, ch):
     return np.stack(cols, axis=1)
 
 
-def rnea_jacobians(ch, q, qd, qdd, V0=ZERO6, dV0=GRAVITY_ACC):
-    """d tau / d(q, qd, qdd, pi) at one state: dict of [n, n] (and [n, 10n] for pi)."""
-    f = lambda c, a, b, d: rnea1(c, a, b, d, V0, dV0)
+def rnea_jacobians(ch, q, qd, qdd, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
+    """d tau / d(q, qd, qdd, pi) at one state: dict of [n, n] (and [n, 10n] for pi).
+    Ftip is the wrench F_{n+1} on the last link (eq. (2)), held fixed."""
+    f = lambda c, a, b, d: rnea1(c, a, b, d, V0, dV0, Ftip)
     return {k: _jac(f, (q, qd, qdd), w, ch) for k, w in (("q", 0), ("qd", 1), ("qdd", 2), ("pi", "pi"))}
 
 
-def aba_jacobians(ch, q, qd, tau, V0=ZERO6, dV0=GRAVITY_ACC):
-    """d qdd / d(q, qd, tau, pi) at one state."""
-    f = lambda c, a, b, d: aba1(c, a, b, d, V0, dV0)
+def aba_jacobians(ch, q, qd, tau, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
+    """d qdd / d(q, qd, tau, pi) at one state (tip wrench Ftip held fixed)."""
+    f = lambda c, a, b, d: aba1(c, a, b, d, V0, dV0, Ftip)
     return {k: _jac(f, (q, qd, tau), w, ch) for k, w in (("q", 0), ("qd", 1), ("tau", 2), ("pi", "pi"))}
 
 
-def rnea_vjp(ch, q, qd, qdd, tau_bar, V0=ZERO6, dV0=GRAVITY_ACC):
+def rnea_vjp(ch, q, qd, qdd, tau_bar, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
     """(q_bar, qd_bar, qdd_bar, pi_bar[n,10]) = (d tau/d x)^T tau_bar at one state."""
-    J = rnea_jacobians(ch, q, qd, qdd, V0, dV0)
+    J = rnea_jacobians(ch, q, qd, qdd, V0, dV0, Ftip)
     n = len(q)
     return (J["q"].T @ tau_bar, J["qd"].T @ tau_bar, J["qdd"].T @ tau_bar, (J["pi"].T @ tau_bar).reshape(n, 10))
 
 
-def aba_vjp(ch, q, qd, tau, qdd_bar, V0=ZERO6, dV0=GRAVITY_ACC):
+def aba_vjp(ch, q, qd, tau, qdd_bar, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
     """(q_bar, qd_bar, tau_bar, pi_bar[n,10]) = (d qdd/d x)^T qdd_bar at one state."""
-    J = aba_jacobians(ch, q, qd, tau, V0, dV0)
+    J = aba_jacobians(ch, q, qd, tau, V0, dV0, Ftip)
     n = len(q)
     return (J["q"].T @ qdd_bar, J["qd"].T @ qdd_bar, J["tau"].T @ qdd_bar, (J["pi"].T @ qdd_bar).reshape(n, 10))
 

@@ -138,11 +138,35 @@ __device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
 }
 
 // Role-split forward dynamics (variant 2): per group of 64 states, wavefront 0
-// runs the articulated-body inertia pass, wavefront 1 the bias Newton-Euler
-// pass, and for ID+FD wavefront 2 the inverse dynamics (outside the barrier);
-// after one workgroup barrier wavefront 1 runs the bias wrench / z-hat pass and
-// the lambda pass.
-template <class T, int MODE, bool SHARED>
+// runs the articulated-body inertia pass (A), wavefront 1 the bias
+// Newton-Euler pass (B1), and for ID+FD wavefront 2 the inverse dynamics,
+// which shares nothing with the others and ends on its own. Wavefront 1 then
+// runs the bias wrench / z-hat pass (B2) and the lambda pass.
+//
+// OVERLAP: A keeps U_i, 1/D_i in LDS and publishes its progress (links done,
+// counted from the tip) in an LDS word after each link; B2 follows A link by
+// link instead of waiting for all of it. Only B2 waits, and only for A, which
+// never waits, so the wait always ends; its spin bound only guards against a
+// broken invariant. Without OVERLAP (the chain's articulated terms do not fit
+// in LDS) A writes them to global scratch and a workgroup barrier orders A
+// before B2.
+constexpr int kSpinLimit = 1 << 20;  // ~30 ms of s_sleep 1; a correct wait lasts one link of pass A
+
+struct LdsProgress {
+  int* p;
+  __device__ void operator()(int k) const { __hip_atomic_store(p, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+};
+struct LdsWait {
+  int* p;
+  __device__ void operator()(int k) const {
+    for (int spin = 0; spin < kSpinLimit; ++spin) {
+      if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= k) return;
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+};
+
+template <class T, int MODE, bool SHARED, bool OVERLAP>
 __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
                                                         const T* __restrict__ table,
@@ -150,8 +174,15 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
                                                         const T* __restrict__ tip, BoundaryArgs<T> ba, T* scr_id,
                                                         T* scr_bias, T* scr_abi) {
+  extern __shared__ __align__(16) unsigned char lds_abi[];  // [link][kAbiWords][64 lanes] with OVERLAP
+  __shared__ int progress;
+  if (OVERLAP) {
+    if (threadIdx.x == 0) progress = 0;
+    __syncthreads();
+  }
   const int role = threadIdx.x / 64;  // wave-uniform
-  const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
+  const int lane = (int)(threadIdx.x % 64);
+  const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
   // with a shared chain n stays uniform, so link records load through the scalar unit
   int s = 0, n = SHARED ? n_max : 0;
@@ -173,12 +204,12 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
   }
-  const Scratch<T> abi{scr_abi + lane_index, (long)n_states, kAbiWords};
+  const Scratch<T> abi = OVERLAP ? Scratch<T>{reinterpret_cast<T*>(lds_abi) + lane, 64L, kAbiWords}
+                                 : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords};
   const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
   if (role == 2) {
-    // Inverse dynamics shares nothing with the other two wavefronts: it ends
-    // here, and a workgroup barrier waits only for wavefronts still running.
+    // inverse dynamics: ends here; a workgroup barrier waits only for wavefronts still running
     if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
       const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value};
@@ -187,14 +218,21 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
     return;
   }
   if (active) {
-    if (role == 0)
-      split_abi_pass(n, tab, wtab, qs, abi);
-    else
+    if (role == 0) {
+      if (OVERLAP)
+        split_abi_pass(n, tab, wtab, qs, abi, LdsProgress{&progress});
+      else
+        split_abi_pass(n, tab, wtab, qs, abi);
+    } else {
       split_bias_forward(n, tab, qs, qds, bd, bias);
+    }
   }
-  __syncthreads();
+  if (!OVERLAP) __syncthreads();
   if (active && role == 1) {
-    split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
+    if (OVERLAP)
+      split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi, LdsWait{&progress});
+    else
+      split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
     split_lambda(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
   }
 }
@@ -264,6 +302,69 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
   const double* wtab = wtable + c.link0 * kLinkWords;
   if (OP == kVjpID) id_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
   else fd_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
+}
+
+// Role-split adjoint (variant 2): per group of 64 states, wavefront X runs the
+// Fbar recursion (and for FD first the articulated-body solve for u), while
+// wavefront Y runs the Newton-Euler sweeps (V, A, Fhat, then F); after one
+// workgroup barrier X forms the inertia-parameter cotangents and Y runs the
+// tip-to-base adjoint sweep. Scratch: Y's [n_max][kVjpWords][n_states], X's
+// [n_max][kVjpXWords][n_states].
+template <class T, int OP, int PI, bool SHARED>
+__global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+                                                   const int32_t* __restrict__ order, const T* __restrict__ table,
+                                                   const double* __restrict__ wtable, const T* q, const T* qd,
+                                                   const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
+                                                   T* tau_bar, T* pi_out, const T* __restrict__ tip,
+                                                   BoundaryArgs<T> ba, T* scratch, T* xscratch) {
+  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y
+  const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
+  const bool active = lane_index < n_states;
+  int s = 0, n = SHARED ? n_max : 0;
+  int64_t link0 = 0, dof0 = 0;
+  if (active) {
+    s = SHARED ? lane_index : state_of(lane_index, order);
+    if (SHARED) {
+      dof0 = (int64_t)s * n_max;
+    } else {
+      link0 = link_ptr[s];
+      n = link_ptr[s + 1] - (int)link0;
+      dof0 = link0;
+    }
+  }
+  const T* tab = table + link0 * kLinkWords;
+  const double* wtab = wtable + link0 * kLinkWords;
+  Boundary<T> bd = boundary_of(ba);
+  if (active && tip) {
+    const T* t = tip + 6 * (int64_t)s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  }
+  const Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
+  const Scratch<T> xs{xscratch + lane_index, (long)n_states, kVjpXWords};
+  const SPtr<const T> qs(q + dof0), qds(qd + dof0), qdds(qdd + dof0), bar(bar_in + dof0);
+  if (active) {
+    if (role == 0) {
+      if (OP == kVjpID)
+        vjp_fbar_pass(n, tab, qs, bar, T(1), xs);
+      else
+        fdvjp_solve_pass(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs);
+    } else {
+      vjp_newton_euler_pass(n, tab, wtab, qs, qds, qdds, bd, scr);
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  if (role == 0) {
+    if (PI != kPiNone) {
+      PiSink<T, PI> sink;
+      sink.out = (PI == kPiLanes) ? pi_out + lane_index : pi_out + link0 * 10;
+      sink.stride = (PI == kPiLanes) ? n_states : 1;
+      vjp_inertia_pass(n, tab, xs, scr, sink);
+    }
+  } else {
+    vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0),
+                  OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>());
+  }
 }
 
 // out[i] = sum over j < n_in of in[i * n_in + j], one workgroup per output, fixed
@@ -390,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
 // ---- host side ------------------------------------------------------------------
 
 struct Layout {
-  size_t table_off, wtable_off, scratch_off, scratch_bytes, partial_off, total;
+  size_t table_off, wtable_off, scratch_off, scratch_bytes, partial_off, xscratch_off, total;
 };
 
 int scratch_words(int op) {
@@ -448,11 +549,14 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
     if (need > L->scratch_bytes) L->scratch_bytes = need;
   }
   if (is_vjp(op)) {
-    // then the per-lane inertia cotangents [n_max][10][n_states] (shared chain)
+    // then the per-lane inertia cotangents [n_max][10][n_states] (shared chain),
+    // then the second scratch of the role-split adjoint [n_max][kVjpXWords][n_states]
     L->partial_off = L->scratch_off + L->scratch_bytes;
-    L->total = L->partial_off + align_up(nm * 10 * (size_t)b->n_states * scalar);
+    L->xscratch_off = L->partial_off + align_up(nm * 10 * (size_t)b->n_states * scalar);
+    L->total = L->xscratch_off + align_up(nm * (size_t)kVjpXWords * (size_t)b->n_states * scalar);
   } else {
     L->partial_off = 0;
+    L->xscratch_off = 0;
     L->total = L->scratch_off + L->scratch_bytes;
   }
   if (L->total < kAlign) L->total = kAlign;
@@ -490,6 +594,19 @@ int launch_link_table(const pdyn_model* m, char* dst, hipStream_t s) {
                      reinterpret_cast<T*>(dst), reinterpret_cast<double*>(dst + woff));
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
+}
+
+// Largest LDS allocation of one workgroup on the current device (queried once per device).
+size_t max_lds_bytes() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return 0;
+    cached[dev] = v;
+  }
+  return (size_t)cached[dev] - 1024;  // room for the kernel's static LDS
 }
 
 template <class T, int MODE>
@@ -533,14 +650,24 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
                                        align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
     T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
-    if (m->n_chains == 1)
-      hipLaunchKernelGGL((k_dynamics_split<T, MODE, true>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,
-                         m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
-                         static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);
-    else
-      hipLaunchKernelGGL((k_dynamics_split<T, MODE, false>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,
-                         m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
-                         static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);
+    const size_t lds = nm * kAbiWords * 64 * sizeof(T);
+    const bool overlap = lds <= max_lds_bytes();
+    const bool shared = m->n_chains == 1;
+#define PDYN_LAUNCH_SPLIT(SH, OV)                                                                                 \
+  do {                                                                                                            \
+    if (OV && lds > 65536 &&                                                                                      \
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dynamics_split<T, MODE, SH, OV>),                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)                  \
+      return PDYN_ELAUNCH;                                                                                        \
+    hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, OV>), dim3(g), dim3(blk), OV ? lds : 0, s, b->n_states,     \
+                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
+                       qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);             \
+  } while (0)
+    if (shared && overlap) PDYN_LAUNCH_SPLIT(true, true);
+    else if (shared) PDYN_LAUNCH_SPLIT(true, false);
+    else if (overlap) PDYN_LAUNCH_SPLIT(false, true);
+    else PDYN_LAUNCH_SPLIT(false, false);
+#undef PDYN_LAUNCH_SPLIT
     if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
     return PDYN_OK;
   }
@@ -705,10 +832,20 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* qdd_bar = (OP == kVjpID) ? out3 : nullptr;
   T* tau_bar = (OP == kVjpFD) ? out3 : nullptr;
   const T* tip = static_cast<const T*>(b->tip_wrench);
+  const bool split = (b->variant ? b->variant : kDefaultVariant) == 2;
+  const unsigned grid64 = (unsigned)((b->n_states + 63) / 64);
+  T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
-  hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,            \
-                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar, \
-                     tau_bar, PIOUT, tip, ba, scratch)
+  do {                                                                                                        \
+    if (split)                                                                                                \
+      hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH>), dim3(grid64), dim3(128), 0, s, b->n_states,            \
+                         m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
+                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch);                                \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
+                         m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
+                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch);                                          \
+  } while (0)
   if (!inertia_bar) {
     if (m->n_chains == 1)
       PDYN_LAUNCH_VJP(kPiNone, true, static_cast<T*>(nullptr));

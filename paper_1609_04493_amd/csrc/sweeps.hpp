@@ -211,20 +211,24 @@ template <class T> struct SPtr {
 // or -1) in that order, loading the inputs of the next link before the body of
 // the current one runs, so that their memory latency overlaps its arithmetic.
 // Unrolled by two with two input sets that alternate, so no register copies
-// (which would wait for the loads) separate one link from the next.
+// (which would wait for the loads) separate one link from the next. When n
+// differs between the lanes of a wavefront, every lane still handles its k-th
+// link in the same trip of the loop (the second link of a trip is
+// predicated), so "k links done" means the same for all lanes.
 template <class LoadF, class BodyF>
 PD_HD void pipelined(int n, int first, int step, const LoadF& load, const BodyF& body) {
   if (n <= 0) return;
   auto a = load(first);
-  int k = 0;
-  for (; k + 1 < n; k += 2) {
+  for (int k = 0; k < n; k += 2) {
     const int i = first + k * step;
-    const auto b = load(i + step);
+    const bool two = k + 1 < n;
+    const auto b = load(two ? i + step : i);
     body(i, a);
-    a = load(k + 2 < n ? i + 2 * step : i);
-    body(i + step, b);
+    if (two) {
+      a = load(k + 2 < n ? i + 2 * step : i);
+      body(i + step, b);
+    }
   }
-  if (k < n) body(first + k * step, a);
 }
 
 // Joint arrays of one state (element i of the chain at ptr[i]).
@@ -417,9 +421,19 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
 constexpr int kAbiWords = 7;
 constexpr int kBiasWords = 10;
 
+// Hand-off hooks between the passes when they overlap: pass A reports after
+// each link (done(k) once its k-th link from the tip is stored) and pass B2
+// calls need(k) before it reads the articulated terms of its k-th link from
+// the tip. The defaults do nothing (the passes are then ordered by a barrier,
+// or run one after another).
+struct NoHandoff {
+  PD_HD void operator()(int) const {}
+};
+
 // Pass A (tip to base): Jhat_i, U_i = Jhat_i S_i, 1/D_i.
-template <class T>
-PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Scratch<T>& abi) {
+template <class T, class Done = NoHandoff>
+PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Scratch<T>& abi,
+                          const Done& done = Done()) {
   Sym6<T> JA;
   Pose<T> gc;
   pipelined(
@@ -442,6 +456,7 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
         JA = sym6_minus_outer(Jh, U, invD);
         abi.put(i, 0, U);
         abi.at(i, 6) = invD;
+        done(n - i);
         gc = cast_pose<T>(joint_transform_wide(Lw, L, qi));
       });
 }
@@ -472,9 +487,10 @@ PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const
 }
 
 // Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
-template <class T>
+template <class T, class Need = NoHandoff>
 PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> tau_in,
-                               const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi) {
+                               const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi,
+                               const Need& need = Need()) {
   struct In {
     Sp<T> fb, U;
     T invD, sn, cs, q, tau;
@@ -488,6 +504,7 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
         x.fb = bias.get(i, 0);
         x.sn = bias.at(i, 8);
         x.cs = bias.at(i, 9);
+        need(n - i);
         x.U = abi.get(i, 0);
         x.invD = abi.at(i, 6);
         x.q = q[i];
@@ -792,6 +809,200 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
               SPtr<T>(), bd, scr, sink);
 }
 
+
+// ---- role-split adjoints ------------------------------------------------------
+// The same adjoints, cut into passes for two wavefronts per group of states:
+//   X: the articulated-body solve u = M^-1 qdd_bar (FD only) and the Fbar
+//      recursion, which needs only the transforms and the torque cotangent;
+//   Y: sweep 1 of ID (V, A, Fhat) and the wrench sweep (F).
+// After one workgroup barrier X forms the inertia-parameter cotangents
+// (pointwise per link) while Y runs the tip-to-base adjoint sweep. Per-link
+// data: Y's in the adjoint scratch (kVjpWords layout: Fhat then F in [0..5],
+// V [6..11], A [12..17], (sin, cos) [20, 21]); X's in a second array of
+// kVjpXWords: U then Fbar [0..5], 1/D [6], c-hat [7], (sin, cos) [8, 9].
+constexpr int kVjpXWords = 10;
+
+// X, ID adjoint: Fbar_i = X_i Fbar_{i-1} + sgn tb_i S_i (base to tip).
+template <class T>
+PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> tb, T sgn, const Scratch<T>& xs) {
+  struct In {
+    T q, tb;
+  };
+  Sp<T> Fb = sp_zero<T>();
+  pipelined(
+      n, 0, 1, [&](int i) { return In{q[i], tb[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        Fb = X_twist(joint_transform(L, x.q), Fb) + (sgn * x.tb) * L.S;
+        xs.put(i, 0, Fb);
+      });
+}
+
+// X, FD adjoint: u = M^-1 qdd_bar by the articulated-body solve with tau-hat :=
+// qdd_bar (tip to base: Jhat, U, 1/D, c-hat; base to tip: lambda, u), writing
+// u to tau_bar and, in the base-to-tip pass, Fbar_i = X_i Fbar_{i-1} - u_i S_i.
+template <class T>
+PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> bar,
+                            SPtr<T> tau_bar, const Scratch<T>& xs) {
+  {
+    struct In {
+      T q, bar;
+    };
+    Sp<double> zA = sp_zero<double>();
+    Sym6<T> JA;
+    Pose<double> gcw;
+    Pose<T> gc;
+    pipelined(
+        n, n - 1, -1, [&](int i) { return In{q[i], bar[i]}; },
+        [&](int i, const In& x) {
+          const bool has_child = (i < n - 1);
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          Sym6<T> Jh = sym6_from_inertia(L.J);
+          Sp<double> z = sp_zero<double>();
+          if (has_child) {
+            const Sym6<T> P = congruence_to_parent(gc, JA);
+            Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+            Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+            Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+            Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+            z = XT_wrench(gcw, zA);
+          }
+          const Sp<T> U = mul(Jh, L.S);
+          const T invD = T(1) / dot(L.S, U);
+          const double chat_w = ((double)x.bar - dot(Lw.S, z)) * (double)invD;
+          JA = sym6_minus_outer(Jh, U, invD);
+          zA = z + chat_w * cast_sp<double>(U);
+          T sn, cs;
+          joint_sincos(L, x.q, &sn, &cs);
+          xs.put(i, 0, U);
+          xs.at(i, 6) = invD;
+          xs.at(i, 7) = (T)chat_w;
+          xs.at(i, 8) = sn;
+          xs.at(i, 9) = cs;
+          gcw = joint_transform_wide_sc(Lw, x.q, sn, cs);
+          gc = cast_pose<T>(gcw);
+        });
+  }
+  {
+    struct In {
+      Sp<T> U;
+      T invD, chat, sn, cs, q;
+    };
+    Sp<T> lam = sp_zero<T>(), Fb = sp_zero<T>();
+    pipelined(
+        n, 0, 1,
+        [&](int i) { return In{xs.get(i, 0), xs.at(i, 6), xs.at(i, 7), xs.at(i, 8), xs.at(i, 9), q[i]}; },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+          const Sp<T> a = X_twist(g, lam);
+          const T u = x.chat - dot(x.U, a) * x.invD;
+          lam = a + u * L.S;
+          tau_bar[i] = u;
+          Fb = X_twist(g, Fb) - u * L.S;
+          xs.put(i, 0, Fb);
+        });
+  }
+}
+
+// Y: sweep 1 of ID at (q, qd, qdd) keeping Fhat, V, A and (sin, cos), then the
+// wrench sweep (tip to base, in double) leaving F_i in slot 0.
+template <class T>
+PD_HD void vjp_newton_euler_pass(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> qd,
+                                 SPtr<const T> qdd, const Boundary<T>& bd, const Scratch<T>& scr) {
+  {
+    struct In {
+      T q, qd, qdd;
+    };
+    Sp<T> V = bd.V0, A = bd.dV0;
+    pipelined(
+        n, 0, 1, [&](int i) { return In{q[i], qd[i], qdd[i]}; },
+        [&](int i, const In& x) {
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          T sn, cs;
+          joint_sincos(L, x.q, &sn, &cs);
+          scr.at(i, kVjpSC) = sn;
+          scr.at(i, kVjpSC + 1) = cs;
+          vjp_forward_fhat(i, L, joint_transform_sc(L, x.q, sn, cs), x.qd, x.qdd, V, A, scr);
+          scr.put(i, 6, V);
+          scr.put(i, 12, A);
+        });
+  }
+  {
+    struct In {
+      Sp<T> fh;
+      T sn, cs, q;
+    };
+    Sp<double> F = cast_sp<double>(bd.Ftip);
+    Pose<double> gcw;
+    pipelined(
+        n, n - 1, -1,
+        [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
+        [&](int i, const In& x) {
+          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          if (i < n - 1) F = XT_wrench(gcw, F);
+          F = F + cast_sp<double>(x.fh);
+          scr.put(i, 0, cast_sp<T>(F));
+          gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
+        });
+  }
+}
+
+// X, after the barrier: inertia-parameter cotangents of every link (pointwise).
+template <class T, class Sink>
+PD_HD void vjp_inertia_pass(int n, const T* table, const Scratch<T>& xs, const Scratch<T>& scr, Sink& sink) {
+  struct In {
+    Sp<T> Fb, V, A;
+  };
+  pipelined(
+      n, 0, 1, [&](int i) { return In{xs.get(i, 0), scr.get(i, 6), scr.get(i, 12)}; },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+        const V3<T> c = (T(1) / L.J.m) * L.J.h;
+        add_inertia_grad(L.J.m, c, x.Fb, x.A, T(1), gpi);
+        add_inertia_grad(L.J.m, c, ad_twist(x.V, x.Fb), x.V, T(-1), gpi);
+        sink.put(i, gpi);
+      });
+}
+
+// Y, after the barrier: the tip-to-base adjoint sweep (as sweep 4 of
+// id_vjp_tail, with the wrench part of q_bar formed here from Fbar and F).
+template <class T>
+PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
+                         const Scratch<T>& xs, const Scratch<T>& scr, SPtr<T> q_bar, SPtr<T> qd_bar,
+                         SPtr<T> qdd_bar) {
+  struct In {
+    Sp<T> Fb, F, V, A;
+    T sn, cs, q, qd, qdd;
+  };
+  Sp<T> Ac = sp_zero<T>(), yc = sp_zero<T>();
+  pipelined(
+      n, n - 1, -1,
+      [&](int i) {
+        return In{xs.get(i, 0), scr.get(i, 0), scr.get(i, 6), scr.get(i, 12), scr.at(i, kVjpSC),
+                  scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i]};
+      },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const T qbp = -dot(ad_twist(L.S, x.Fb), x.F);
+        const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
+        const Sp<T> Vb = adT_wrench(x.Fb, mul(L.J, x.V)) - mul(L.J, ad_twist(x.V, x.Fb)) + yc;
+        const Sp<T> Sqd = x.qd * L.S;
+        const Sp<T> y = x.V - Sqd;
+        const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
+        const Sp<T> XA = x.A - x.qdd * L.S + ad_twist(Sqd, y);
+        if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
+        qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
+        q_bar[i] = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        Ac = XT_wrench(g, Ab);
+        yc = XT_wrench(g, yb);
+      });
+}
 
 // ============================================================================
 // Rollouts: semi-implicit Euler driven by the forward dynamics,

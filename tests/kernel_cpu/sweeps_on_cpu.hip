@@ -101,6 +101,7 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
     for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
   }
   std::vector<T> scratch((size_t)n_max * kVjpWords * n_states, T(-7777));
+  std::vector<T> xscratch((size_t)n_max * kVjpXWords * n_states, T(-7777));
   Boundary<T> bd;
   bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
   bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
@@ -114,8 +115,19 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
     bd.Ftip = tip ? Sp<T>{v3(tip[6 * s], tip[6 * s + 1], tip[6 * s + 2]), v3(tip[6 * s + 3], tip[6 * s + 4], tip[6 * s + 5])} : sp_zero<T>();
     Scratch<T> scr{scratch.data() + s, (long)n_states, kVjpWords};
     SumSink<T> sink{pi_bar + 10 * link0};
-    if (op == 0) id_vjp_one_state(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr, sink);
-    else fd_vjp_one_state(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr, sink);
+    const T* tab = table.data() + link0 * kLinkWords;
+    const double* wtab = wtable.data() + link0 * kLinkWords;
+    if (op == 0) id_vjp_one_state(n, tab, wtab, io, bd, scr, sink);
+    else if (op == 1) fd_vjp_one_state(n, tab, wtab, io, bd, scr, sink);
+    else {
+      // ops 2 (ID) and 3 (FD): the role-split passes of k_vjp_split, in an order their hand-offs allow
+      const Scratch<T> xs{xscratch.data() + s, (long)n_states, kVjpXWords};
+      if (op == 2) vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
+      else fdvjp_solve_pass(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs);
+      vjp_newton_euler_pass(n, tab, wtab, io.q, io.qd, io.qdd, bd, scr);
+      vjp_inertia_pass(n, tab, xs, scr, sink);
+      vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, op == 2 ? io.qdd_bar : SPtr<T>());
+    }
   }
   return 0;
 }
@@ -212,3 +224,4 @@ int cpu_rollout_f32(int with_grad, int n_states, int n, const float* pl, const f
                             qdT_bar, q0_bar, qd0_bar, tau_bar_seq, pi_bar, V0, dV0);
 }
 }
+

@@ -187,3 +187,59 @@ def test_inertia_gradient_is_deterministic(device):
     a = api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), bar)[3].cpu().numpy()
     b = api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), bar)[3].cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_adjoint_variants(device, variant):
+    """Both adjoint kernels (one wavefront per 64 states; role split) against the oracle: FP64 with base motion
+    and tip wrenches on ragged chains, and the FP32 32-link FD adjoint on sampled states of a full batch."""
+    print(f"case: adjoint variant {variant}", flush=True)
+    for op in (api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):
+        api.set_launch(op, 0, 0, variant)
+    try:
+        ch = synth.make_chains([5, 12, 1, 30, 9], 33)
+        st = synth.make_states((ch.n_links_total,), 33)
+        rng = np.random.default_rng(33)
+        bar = rng.standard_normal(ch.n_links_total)
+        tip = rng.standard_normal((ch.n_chains, 6))
+        V0, dV0 = rng.standard_normal(6), rng.standard_normal(6)
+        model = api.Model(ch, device, torch.float64)
+        d = lambda a: dev_t(a, device, torch.float64)
+        kw = dict(base_vel=tuple(V0), base_acc=tuple(dV0), tip=d(tip))
+        qb, qdb, qddb, pib = (x.cpu().numpy() for x in
+                              api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), d(bar), **kw))
+        qdd = np.zeros_like(st.q)
+        for c in range(ch.n_chains):
+            a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+            qdd[a:b] = oracle.aba1(ch.chain(c), st.q[a:b], st.qd[a:b], st.tau[a:b], V0, dV0, tip[c])
+        fb, fdb, ftb, fpib = (x.cpu().numpy() for x in
+                              api.aba_fd_vjp(model, d(st.q), d(st.qd), d(qdd), d(bar), **kw))
+        for c in range(ch.n_chains):
+            a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+            sub = ch.chain(c)
+            r = grad.rnea_vjp(sub, st.q[a:b], st.qd[a:b], st.qdd[a:b], bar[a:b], V0, dV0, tip[c])
+            for x, y in zip((qb[a:b], qdb[a:b], qddb[a:b], pib[a:b]), r):
+                assert rel(x, y) <= 1e-11
+            r = grad.aba_vjp(sub, st.q[a:b], st.qd[a:b], st.tau[a:b], bar[a:b], V0, dV0, tip[c])
+            for x, y in zip((fb[a:b], fdb[a:b], ftb[a:b], fpib[a:b]), r):
+                assert rel(x, y) <= 1e-10
+        ch, st = synth.workload_32link(16384)
+        model = api.Model(ch, device, torch.float32)
+        d = lambda a: dev_t(a, device, torch.float32)
+        q, qd, tau = d(st.q), d(st.qd), d(st.tau)
+        qdd = api.aba_fd(model, q, qd, tau)
+        idx = np.random.default_rng(8).choice(16384, 12, replace=False)
+        mask = torch.zeros(16384, 1, device=device)
+        mask[torch.as_tensor(idx)] = 1.0
+        barf = (2.0 * qdd * mask).contiguous()
+        qb, qdb, tb, pib = (x.cpu().numpy() for x in api.aba_fd_vjp(model, q, qd, qdd, barf))
+        cr, sr = ch.rounded(), st.rounded()
+        (rq, rqd, rt), rpi = fd_refs(cr, sr, barf.cpu().numpy().astype(np.float64), idx)
+        errs = {k: max(rel(x[s], r[k2]) for k2, s in enumerate(idx)) for k, x, r in
+                (("q", qb, rq), ("qd", qdb, rqd), ("tau", tb, rt))}
+        errs["pi"] = rel(pib, rpi)
+        print(f"variant {variant}: fp32 FD adjoint errors (32 links)", errs, flush=True)
+        assert errs["q"] <= 1e-3 and max(errs["qd"], errs["tau"], errs["pi"]) <= 1e-4
+    finally:
+        for op in (api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):
+            api.set_launch(op, 0, 0, 0)

@@ -185,6 +185,28 @@ def test_fp64_adjoint_sweeps_match_oracle(cpu_lib):
     assert np.linalg.norm(pib - ref_pi) <= 1e-11 * np.linalg.norm(ref_pi)
 
 
+def test_role_split_adjoint_passes_match_the_fused_adjoints(cpu_lib):
+    """The role-split adjoint passes equal the one-lane adjoints to rounding (FP64, boundary terms, ragged
+    chains) and match the oracle's vector-Jacobian products."""
+    from oracle import grad
+    ch = synth.make_chains([1, 7, 12], 45)
+    st = synth.make_states((ch.n_links_total,), 45)
+    bar = np.random.default_rng(45).standard_normal(ch.n_links_total)
+    qdd_fd = oracle.aba(ch, st.q, st.qd, st.tau)
+    for op_fused, op_split, qdd in ((0, 2, st.qdd), (1, 3, qdd_fd)):
+        a, pa = run_vjp_cpu(cpu_lib, op_fused, ch, st.q, st.qd, qdd, bar, np.float64)
+        b, pb = run_vjp_cpu(cpu_lib, op_split, ch, st.q, st.qd, qdd, bar, np.float64)
+        for x, y in zip(a, b):
+            assert np.abs(x - y).max() <= 1e-11 * (np.abs(x).max() + 1e-300)
+        assert np.abs(pa - pb).max() <= 1e-11 * np.abs(pa).max()
+    (qb, qdb, _, tb), pib = run_vjp_cpu(cpu_lib, 3, ch, st.q, st.qd, qdd_fd, bar, np.float64)
+    for c in range(ch.n_chains):
+        lo, hi = ch.link_ptr[c], ch.link_ptr[c + 1]
+        r = grad.aba_vjp(ch.chain(c), st.q[lo:hi], st.qd[lo:hi], st.tau[lo:hi], bar[lo:hi])
+        for x, y in zip((qb[lo:hi], qdb[lo:hi], tb[lo:hi], pib[lo:hi]), r):
+            assert np.linalg.norm(x - y) <= 1e-11 * np.linalg.norm(y) + 1e-14
+
+
 def test_fp64_adjoint_sweeps_ragged(cpu_lib):
     from oracle import grad
     ch = synth.make_chains([2, 9, 1], 43)
@@ -243,3 +265,4 @@ def test_fp64_rollout_sweeps_match_oracle(cpu_lib):
         assert np.linalg.norm(tb[:, s, :] - gt) <= 1e-12 * np.linalg.norm(gt)
         pref += gpi
     assert np.linalg.norm(pb - pref) <= 1e-12 * np.linalg.norm(pref)
+
