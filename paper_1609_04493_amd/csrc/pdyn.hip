@@ -166,20 +166,67 @@ struct LdsWait {
   }
 };
 
+// With OVERLAP pass A is itself split: wavefront 2 forms the joint transforms
+// (A1) and hands them to wavefront 0 (A2) through an LDS ring of kPoseSlots
+// transforms; A1 waits only for a free slot and A2 only for a transform, so
+// neither waits on itself through the other. The inverse dynamics is then
+// wavefront 3.
+constexpr int kPoseSlots = 8;
+constexpr int kPoseWords = 12;
+
+template <class T> struct PoseRingPut {
+  T* ring;     // [kPoseSlots][kPoseWords][64 lanes]
+  int* used;   // transforms consumed by A2
+  int* ready;  // transforms written by A1
+  int lane;
+  __device__ void operator()(int k, const Pose<T>& g) const {
+    LdsWait{used}(k - kPoseSlots + 1);
+    T* w = ring + (long)(k % kPoseSlots) * kPoseWords * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) w[j * 64] = g.R.m[j];
+    w[9 * 64] = g.p.x;
+    w[10 * 64] = g.p.y;
+    w[11 * 64] = g.p.z;
+    LdsProgress{ready}(k + 1);
+  }
+};
+template <class T> struct PoseRingGet {
+  const T* ring;
+  int* ready;
+  int lane;
+  __device__ Pose<T> operator()(int k) const {
+    LdsWait{ready}(k + 1);
+    const T* r = ring + (long)(k % kPoseSlots) * kPoseWords * 64 + lane;
+    Pose<T> g;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) g.R.m[j] = r[j * 64];
+    g.p = v3(r[9 * 64], r[10 * 64], r[11 * 64]);
+    return g;
+  }
+};
+
 template <class T, int MODE, bool SHARED, bool OVERLAP>
-__global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+__global__ void __launch_bounds__(256) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
                                                         const T* __restrict__ table,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
                                                         const T* __restrict__ tip, BoundaryArgs<T> ba, T* scr_id,
                                                         T* scr_bias, T* scr_abi) {
-  extern __shared__ __align__(16) unsigned char lds_abi[];  // [link][kAbiWords][64 lanes] with OVERLAP
-  __shared__ int progress;
+  // with OVERLAP: [link][kAbiWords][64 lanes], then the transform ring
+  extern __shared__ __align__(16) unsigned char lds_abi[];
+  __shared__ int progress, pose_ready, pose_used;
   if (OVERLAP) {
-    if (threadIdx.x == 0) progress = 0;
+    if (threadIdx.x == 0) {
+      progress = 0;
+      pose_ready = 0;
+      pose_used = 0;
+    }
     __syncthreads();
   }
+  // roles: 0 articulated inertia (A, or A2), 1 bias passes (B), then with
+  // OVERLAP 2 transforms (A1) and 3 inverse dynamics, else 2 inverse dynamics
+  constexpr int kRoleID = OVERLAP ? 3 : 2;
   const int role = threadIdx.x / 64;  // wave-uniform
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
@@ -208,7 +255,12 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
                                  : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords};
   const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
-  if (role == 2) {
+  T* const ring = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiWords * 64;
+  if (OVERLAP && role == 2) {
+    if (active) split_pose_pass(n, tab, wtab, qs, PoseRingPut<T>{ring, &pose_used, &pose_ready, lane});
+    return;
+  }
+  if (role == kRoleID) {
     // inverse dynamics: ends here; a workgroup barrier waits only for wavefronts still running
     if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
@@ -220,7 +272,8 @@ __global__ void __launch_bounds__(192) k_dynamics_split(int n_states, int n_max,
   if (active) {
     if (role == 0) {
       if (OVERLAP)
-        split_abi_pass(n, tab, wtab, qs, abi, LdsProgress{&progress});
+        split_abi_from_poses(n, tab, abi, PoseRingGet<T>{ring, &pose_ready, lane}, LdsProgress{&pose_used},
+                             LdsProgress{&progress});
       else
         split_abi_pass(n, tab, wtab, qs, abi);
     } else {
@@ -644,15 +697,16 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   const int variant = b->variant ? b->variant : kDefaultVariant;
   if ((MODE & kModeFD) && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
-    const unsigned blk = (MODE == kModeIDFD) ? 192 : 128;
     const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
     T* scr_id = scratch;
     T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
                                        align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
     T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
-    const size_t lds = nm * kAbiWords * 64 * sizeof(T);
+    const size_t lds = (nm * kAbiWords + (size_t)kPoseSlots * kPoseWords) * 64 * sizeof(T);
     const bool overlap = lds <= max_lds_bytes();
     const bool shared = m->n_chains == 1;
+    // wavefronts: A (or A2), B, [A1 with overlap], [ID for ID+FD]
+    const unsigned blk = 128 + (overlap ? 64 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
 #define PDYN_LAUNCH_SPLIT(SH, OV)                                                                                 \
   do {                                                                                                            \
     if (OV && lds > 65536 &&                                                                                      \

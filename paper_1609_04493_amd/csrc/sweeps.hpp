@@ -461,6 +461,51 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
       });
 }
 
+// Pass A cut in two, for two more wavefronts: A1 forms the joint transforms
+// (tip to base) and hands each to A2 through put(k, pose), k = 0, 1, ... from
+// the tip; A2 runs the articulated-body inertia recursion with the child's
+// transform from get(k) (k >= 1: the transform of its (k-1)-th link from the
+// tip), reporting done(k) as pass A does.
+template <class T, class Put>
+PD_HD void split_pose_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Put& put) {
+  pipelined(
+      n, n - 1, -1, [&](int i) { return q[i]; },
+      [&](int i, T qi) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        put(n - 1 - i, cast_pose<T>(joint_transform_wide(Lw, L, qi)));
+      });
+}
+
+template <class T, class Get, class Release, class Done>
+PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, const Get& get,
+                                const Release& release, const Done& done) {
+  Sym6<T> JA;
+  // load(i): the transform of link i's child (link i + 1), none at the tip
+  pipelined(
+      n, n - 1, -1, [&](int i) { return i < n - 1 ? get(n - 2 - i) : Pose<T>(); },
+      [&](int i, const Pose<T>& gc) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        Sym6<T> Jh = sym6_from_inertia(L.J);
+        if (i < n - 1) {
+          const Sym6<T> P = congruence_to_parent(gc, JA);
+          Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+          Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+          Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+          Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+          release(n - 1 - i);  // transforms 0 .. n-2-i from the tip are used
+        }
+        const Sp<T> U = mul(Jh, L.S);
+        const T invD = T(1) / dot(L.S, U);
+        JA = sym6_minus_outer(Jh, U, invD);
+        abi.put(i, 0, U);
+        abi.at(i, 6) = invD;
+        done(n - i);
+      });
+}
+
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
 template <class T>
 PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,

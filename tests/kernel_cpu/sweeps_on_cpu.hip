@@ -9,6 +9,7 @@
 using namespace pdyn;
 
 constexpr int kSplitFD = 5, kSplitIDFD = 7;  // FD, ID+FD through the role-split passes
+constexpr int kPoseRing = 16;                // with the articulated pass cut into A1 (transforms) and A2
 
 template <class T>
 static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
@@ -21,6 +22,8 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
     make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, &wtable[i * kLinkWords]);
     for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
   }
+  const bool pose_ring = (mode & kPoseRing) != 0;
+  mode &= ~kPoseRing;
   int words = mode == kModeIDFD ? ScratchWords<kModeIDFD>::value : (mode == kModeFD ? ScratchWords<kModeFD>::value : ScratchWords<kModeID>::value);
   if (mode == kSplitFD || mode == kSplitIDFD) words = ScratchWords<kModeID>::value;
   std::vector<T> scratch((size_t)n_max * words * n_states, T(-7777));  // poisoned
@@ -53,7 +56,14 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
         dynamics_one_state<T, kModeID>(n, tab, wtab, id_io, bd, idscr);
       }
       split_bias_forward(n, tab, io.q, io.qd, bd, bias);
-      split_abi_pass(n, tab, wtab, io.q, abi);
+      if (pose_ring) {
+        // A1 then A2 through a plain array of transforms (the kernel uses an LDS ring)
+        std::vector<Pose<T>> poses((size_t)n);
+        split_pose_pass(n, tab, wtab, io.q, [&](int k, const Pose<T>& g) { poses[(size_t)k] = g; });
+        split_abi_from_poses(n, tab, abi, [&](int k) { return poses[(size_t)k]; }, NoHandoff(), NoHandoff());
+      } else {
+        split_abi_pass(n, tab, wtab, io.q, abi);
+      }
       split_bias_backward(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
       split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out});
       continue;

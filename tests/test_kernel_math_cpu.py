@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_cpu", "sweeps_on_cpu.hip")
 MODE_ID, MODE_FD, MODE_IDFD = 1, 2, 3
 SPLIT_FD, SPLIT_IDFD = 5, 7  # the role-split passes (articulated inertia beside the Newton-Euler passes)
+POSE_RING = 16  # flag: the articulated pass cut into a transform pass and the inertia recursion
 
 
 @pytest.fixture(scope="module")
@@ -120,6 +121,10 @@ def test_role_split_passes_match_oracle(cpu_lib):
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch, st, np.float64, tip, V0, dV0)
     _, qdd_fd = run_cpu(cpu_lib, SPLIT_FD, ch, st, np.float64, tip, V0, dV0)
     assert np.array_equal(qdd, qdd_fd)
+    # the articulated pass cut in two (transforms handed over) gives the same bits
+    for mode in (SPLIT_FD, SPLIT_IDFD):
+        t2, q2 = run_cpu(cpu_lib, mode | POSE_RING, ch, st, np.float64, tip, V0, dV0)
+        assert np.array_equal(q2, qdd)
     for s in range(16):
         rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], V0, dV0, tip[s])
         rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s])
@@ -132,8 +137,12 @@ def test_role_split_passes_match_oracle(cpu_lib):
     for c in range(ch.n_chains):
         a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
         assert np.linalg.norm(qdd[a:b] - ref[a:b]) <= 1e-10 * np.linalg.norm(ref[a:b])
+    _, q2 = run_cpu(cpu_lib, SPLIT_FD | POSE_RING, ch, st, np.float64)
+    assert np.array_equal(q2, qdd)
     ch, st = synth.workload_32link(256)
+    _, q2 = run_cpu(cpu_lib, SPLIT_FD | POSE_RING, ch.astype(np.float32), st.astype(np.float32), np.float32)
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch.astype(np.float32), st.astype(np.float32), np.float32)
+    assert np.array_equal(q2, qdd)
     cr, sr = ch.rounded(), st.rounded()
     e = rel_err_rows(qdd, oracle.aba(cr, sr.q, sr.qd, sr.tau))
     print(f"split fp32 qdd max rel err {e.max():.2e}")
