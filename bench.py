@@ -36,6 +36,35 @@ BYTES_PER_LINK = {"id": 16, "fd": 16, "id_fd": 24}  # joint inputs + outputs, FP
 PEAK_VALU_FLOPS = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, unpacked FP32 = FP64 vector
 
 
+COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_dynamics_split_idfd_32link_16384_counters.md")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1609_04493_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None if the kernel sources changed since."""
+    try:
+        with open(COUNTERS) as f:
+            kv = dict(line.strip().split(": ", 1) for line in f if line.strip().startswith("traffic-"))
+    except OSError:
+        return None
+    if kv.get("traffic-sources-sha256") != kernel_sources_sha256():
+        return None
+    return int(kv["traffic-fetch-bytes-per-launch"]) + int(kv["traffic-write-bytes-per-launch"])
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -301,7 +330,8 @@ def main():
                    "n_links": N_LINKS, "n_states": N_STATES,
                    "precision": "f32 bulk; f64 wrench and articulated-bias accumulations"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_FLOPS / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_FLOPS, "traffic": None,
+                     "frac": achieved / PEAK_VALU_FLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (HBM read + write, PMC)", "algorithmic_bytes": 24 * links,
                      "kernel": "k_dynamics_split<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
                      "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
         "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
