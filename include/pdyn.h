@@ -104,17 +104,19 @@ typedef struct pdyn_batch {
    * each workgroup striding over the remaining work in a fixed order. */
   int32_t block_threads;
   int32_t max_blocks;
-  /* Kernel variant (0 = library default, which is 2). For forward dynamics
-   * and fused ID+FD: 1 = one wavefront runs every recursion of its 64
-   * states; 2 = role split -- per group of 64 states one wavefront runs the
-   * articulated-body inertia recursion (7) while others run the Newton-Euler
-   * passes (and, for ID+FD, the inverse dynamics), then the z-hat / lambda
-   * recursions of (8). For the adjoints (pdyn_*_vjp): 1 = one wavefront per
-   * 64 states; 2 = role split -- one wavefront runs the cotangent recursions
-   * (for FD first the articulated-body solve), another the Newton-Euler
-   * sweeps, then the inertia-parameter terms and the tip-to-base adjoint sweep
-   * run side by side. block_threads and max_blocks apply to variant 1 only.
-   * Every variant gives the same results to rounding. */
+  /* Kernel variant; 0 = library default: 2 for the adjoints, and for forward
+   * dynamics and ID+FD 2 up to 128 states per compute unit, else 1.
+   * Forward dynamics and fused ID+FD: 1 = one wavefront runs every recursion
+   * of its 64 states; 2 = role split -- per group of 64 states one wavefront
+   * runs the articulated-body inertia recursion (7) while others run the
+   * Newton-Euler passes (and, for ID+FD, the inverse dynamics), then the
+   * z-hat / lambda recursions of (8). Adjoints (pdyn_*_vjp): 1 = one
+   * wavefront per 64 states; 2 = role split -- one wavefront runs the
+   * cotangent recursions (for FD first the articulated-body solve), another
+   * the Newton-Euler sweeps, then the inertia-parameter terms and the
+   * tip-to-base adjoint sweep run side by side. block_threads and max_blocks
+   * apply to variant 1 only. Every variant gives the same results to
+   * rounding. */
   int32_t variant;
 } pdyn_batch;
 

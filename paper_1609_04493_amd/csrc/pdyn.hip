@@ -28,7 +28,10 @@ namespace {
 constexpr int kMaxLinks = 1 << 16;
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
-constexpr int kDefaultVariant = 2;  // forward dynamics: the role-split kernel
+// Default kernel variant: the role split (2) for the adjoints; for forward
+// dynamics and ID+FD the role split while a one-wavefront launch would leave
+// SIMDs idle (up to 128 states per CU), else the one-wavefront kernel (1),
+// whose fewer instructions win once every SIMD holds several wavefronts.
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -139,17 +142,19 @@ __device__ __forceinline__ Boundary<T> boundary_of(const BoundaryArgs<T>& ba) {
 
 // Role-split forward dynamics (variant 2): per group of 64 states, wavefront 0
 // runs the articulated-body inertia pass (A), wavefront 1 the bias
-// Newton-Euler pass (B1), and for ID+FD wavefront 2 the inverse dynamics,
-// which shares nothing with the others and ends on its own. Wavefront 1 then
-// runs the bias wrench / z-hat pass (B2) and the lambda pass.
+// Newton-Euler pass (B1), and for ID+FD another wavefront the inverse
+// dynamics, which shares nothing with A and B and ends on its own. Wavefront 1
+// then runs the bias wrench / z-hat pass (B2) and the lambda pass. With
+// OVERLAP two transform wavefronts (P_f, P_b, below) feed A, B1 and the
+// inverse dynamics.
 //
 // OVERLAP: A keeps U_i, 1/D_i in LDS and publishes its progress (links done,
 // counted from the tip) in an LDS word after each link; B2 follows A link by
-// link instead of waiting for all of it. Only B2 waits, and only for A, which
-// never waits, so the wait always ends; its spin bound only guards against a
-// broken invariant. Without OVERLAP (the chain's articulated terms do not fit
-// in LDS) A writes them to global scratch and a workgroup barrier orders A
-// before B2.
+// link instead of waiting for all of it. Only B2 waits here, and only for A,
+// which never waits, so the wait always ends; its spin bound only guards
+// against a broken invariant. Without OVERLAP (the chain's articulated terms do
+// not fit in LDS) A writes them to global scratch and a workgroup barrier
+// orders A before B2.
 constexpr int kSpinLimit = 1 << 20;  // ~30 ms of s_sleep 1; a correct wait lasts one link of pass A
 
 struct LdsProgress {
@@ -166,47 +171,85 @@ struct LdsWait {
   }
 };
 
-// With OVERLAP pass A is itself split: wavefront 2 forms the joint transforms
-// (A1) and hands them to wavefront 0 (A2) through an LDS ring of kPoseSlots
-// transforms; A1 waits only for a free slot and A2 only for a transform, so
-// neither waits on itself through the other. The inverse dynamics is then
-// wavefront 3.
+// With OVERLAP two more wavefronts form every joint transform: P_f base to tip
+// for the passes that start at the base (B1 and the inverse dynamics, which
+// then form none), and P_b tip to base for pass A, which then runs only the
+// articulated-body recursion. Each order goes through its own LDS ring of
+// kPoseSlots entries. Producers wait only for free slots, consumers only for
+// entries, so every wait ends.
 constexpr int kPoseSlots = 8;
-constexpr int kPoseWords = 12;
+constexpr int kPoseWordsF = 14;  // R (9), p (3), sin, cos
+constexpr int kPoseWordsB = 12;  // R (9), p (3)
 
-template <class T> struct PoseRingPut {
-  T* ring;     // [kPoseSlots][kPoseWords][64 lanes]
-  int* used;   // transforms consumed by A2
-  int* ready;  // transforms written by A1
+template <class T> __device__ __forceinline__ void put_pose(T* w, const Pose<T>& g) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) w[j * 64] = g.R.m[j];
+  w[9 * 64] = g.p.x;
+  w[10 * 64] = g.p.y;
+  w[11 * 64] = g.p.z;
+}
+template <class T> __device__ __forceinline__ Pose<T> get_pose(const T* r) {
+  Pose<T> g;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) g.R.m[j] = r[j * 64];
+  g.p = v3(r[9 * 64], r[10 * 64], r[11 * 64]);
+  return g;
+}
+
+template <class T> struct RingPutF {  // base-to-tip entries
+  T* ring;       // [kPoseSlots][kPoseWordsF][64 lanes]
+  int* ready;    // entries written
+  int* used_b;   // entries taken by B1
+  int* used_id;  // entries taken by the inverse dynamics (null without it)
+  int lane;
+  __device__ void operator()(int i, const Pose<T>& g, T sn, T cs) const {
+    LdsWait{used_b}(i - kPoseSlots + 1);
+    if (used_id) LdsWait{used_id}(i - kPoseSlots + 1);
+    T* w = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
+    put_pose(w, g);
+    w[12 * 64] = sn;
+    w[13 * 64] = cs;
+    LdsProgress{ready}(i + 1);
+  }
+};
+// A pose source (see FormPose) that takes link i's entry from the base-to-tip ring.
+template <class T> struct RingTakeF {
+  const T* ring;
+  int* ready;
+  int* used;
+  int lane;
+  __device__ void operator()(int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) const {
+    LdsWait{ready}(i + 1);
+    const T* r = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
+    *g = get_pose(r);
+    *sn = r[12 * 64];
+    *cs = r[13 * 64];
+    LdsProgress{used}(i + 1);
+  }
+};
+template <class T> struct RingPutB {  // tip-to-base entries for pass A
+  T* ring;  // [kPoseSlots][kPoseWordsB][64 lanes]
+  int* ready;
+  int* used;
   int lane;
   __device__ void operator()(int k, const Pose<T>& g) const {
     LdsWait{used}(k - kPoseSlots + 1);
-    T* w = ring + (long)(k % kPoseSlots) * kPoseWords * 64 + lane;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) w[j * 64] = g.R.m[j];
-    w[9 * 64] = g.p.x;
-    w[10 * 64] = g.p.y;
-    w[11 * 64] = g.p.z;
+    put_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane, g);
     LdsProgress{ready}(k + 1);
   }
 };
-template <class T> struct PoseRingGet {
+template <class T> struct RingGetB {
   const T* ring;
   int* ready;
   int lane;
   __device__ Pose<T> operator()(int k) const {
     LdsWait{ready}(k + 1);
-    const T* r = ring + (long)(k % kPoseSlots) * kPoseWords * 64 + lane;
-    Pose<T> g;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) g.R.m[j] = r[j * 64];
-    g.p = v3(r[9 * 64], r[10 * 64], r[11 * 64]);
-    return g;
+    return get_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane);
   }
 };
 
 template <class T, int MODE, bool SHARED, bool OVERLAP>
-__global__ void __launch_bounds__(256) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+__global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
                                                         const T* __restrict__ table,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
@@ -215,18 +258,23 @@ __global__ void __launch_bounds__(256) k_dynamics_split(int n_states, int n_max,
                                                         T* scr_bias, T* scr_abi) {
   // with OVERLAP: [link][kAbiWords][64 lanes], then the transform ring
   extern __shared__ __align__(16) unsigned char lds_abi[];
-  __shared__ int progress, pose_ready, pose_used;
+  __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a;
   if (OVERLAP) {
     if (threadIdx.x == 0) {
       progress = 0;
-      pose_ready = 0;
-      pose_used = 0;
+      ready_f = 0;
+      used_b = 0;
+      used_id = 0;
+      ready_b = 0;
+      used_a = 0;
     }
     __syncthreads();
   }
-  // roles: 0 articulated inertia (A, or A2), 1 bias passes (B), then with
-  // OVERLAP 2 transforms (A1) and 3 inverse dynamics, else 2 inverse dynamics
-  constexpr int kRoleID = OVERLAP ? 3 : 2;
+  // roles: 0 articulated inertia (A), 1 bias passes (B), then with OVERLAP
+  // 2 transforms base to tip (P_f), 3 transforms tip to base (P_b) and
+  // 4 inverse dynamics, else 2 inverse dynamics
+  constexpr bool kWithID = MODE == kModeIDFD;
+  constexpr int kRoleID = OVERLAP ? 4 : 2;
   const int role = threadIdx.x / 64;  // wave-uniform
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
@@ -255,9 +303,15 @@ __global__ void __launch_bounds__(256) k_dynamics_split(int n_states, int n_max,
                                  : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords};
   const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
-  T* const ring = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiWords * 64;
+  T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiWords * 64;
+  T* const ring_b = ring_f + (long)kPoseSlots * kPoseWordsF * 64;
   if (OVERLAP && role == 2) {
-    if (active) split_pose_pass(n, tab, wtab, qs, PoseRingPut<T>{ring, &pose_used, &pose_ready, lane});
+    if (active)
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_f, &used_b, kWithID ? &used_id : nullptr, lane});
+    return;
+  }
+  if (OVERLAP && role == 3) {
+    if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane});
     return;
   }
   if (role == kRoleID) {
@@ -265,19 +319,26 @@ __global__ void __launch_bounds__(256) k_dynamics_split(int n_states, int n_max,
     if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
       const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value};
-      dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr);
+      if (OVERLAP)
+        dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr, StoreQdd<T>{SPtr<T>()},
+                                       RingTakeF<T>{ring_f, &ready_f, &used_id, lane});
+      else
+        dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr);
     }
     return;
   }
   if (active) {
     if (role == 0) {
       if (OVERLAP)
-        split_abi_from_poses(n, tab, abi, PoseRingGet<T>{ring, &pose_ready, lane}, LdsProgress{&pose_used},
+        split_abi_from_poses(n, tab, abi, RingGetB<T>{ring_b, &ready_b, lane}, LdsProgress{&used_a},
                              LdsProgress{&progress});
       else
         split_abi_pass(n, tab, wtab, qs, abi);
     } else {
-      split_bias_forward(n, tab, qs, qds, bd, bias);
+      if (OVERLAP)
+        split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane});
+      else
+        split_bias_forward(n, tab, qs, qds, bd, bias);
     }
   }
   if (!OVERLAP) __syncthreads();
@@ -649,6 +710,25 @@ int launch_link_table(const pdyn_model* m, char* dst, hipStream_t s) {
   return PDYN_OK;
 }
 
+// Compute units of the current device (queried once per device).
+int cu_count() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 0;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+int pick_variant(const pdyn_batch* b, bool forward) {
+  if (b->variant) return b->variant;
+  if (!forward) return 2;
+  return (int64_t)b->n_states <= (int64_t)128 * cu_count() ? 2 : 1;
+}
+
 // Largest LDS allocation of one workgroup on the current device (queried once per device).
 size_t max_lds_bytes() {
   static int cached[64];
@@ -694,7 +774,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   }
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
-  const int variant = b->variant ? b->variant : kDefaultVariant;
+  const int variant = pick_variant(b, true);
   if ((MODE & kModeFD) && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
@@ -702,11 +782,11 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
                                        align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
     T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
-    const size_t lds = (nm * kAbiWords + (size_t)kPoseSlots * kPoseWords) * 64 * sizeof(T);
+    const size_t lds = (nm * kAbiWords + (size_t)kPoseSlots * (kPoseWordsF + kPoseWordsB)) * 64 * sizeof(T);
     const bool overlap = lds <= max_lds_bytes();
     const bool shared = m->n_chains == 1;
-    // wavefronts: A (or A2), B, [A1 with overlap], [ID for ID+FD]
-    const unsigned blk = 128 + (overlap ? 64 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
+    // wavefronts: A, B, [P_f and P_b with overlap], [ID for ID+FD]
+    const unsigned blk = 128 + (overlap ? 128 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
 #define PDYN_LAUNCH_SPLIT(SH, OV)                                                                                 \
   do {                                                                                                            \
     if (OV && lds > 65536 &&                                                                                      \
@@ -886,7 +966,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* qdd_bar = (OP == kVjpID) ? out3 : nullptr;
   T* tau_bar = (OP == kVjpFD) ? out3 : nullptr;
   const T* tip = static_cast<const T*>(b->tip_wrench);
-  const bool split = (b->variant ? b->variant : kDefaultVariant) == 2;
+  const bool split = pick_variant(b, false) == 2;
   const unsigned grid64 = (unsigned)((b->n_states + 63) / 64);
   T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \

@@ -251,14 +251,25 @@ template <class T> struct StoreQdd {
   PD_HD void operator()(int i, T qdd) const { out[i] = qdd; }
 };
 
+// Where a base-to-tip pass gets the joint transform of link i and the (sin, cos)
+// of its angle: by default it forms them; a caller may hand them in instead
+// (see the role-split kernel, where one wavefront forms them for two others).
+template <class T> struct FormPose {
+  PD_HD void operator()(int, const Link<T>& L, T q, Pose<T>* g, T* sn, T* cs) const {
+    joint_sincos(L, q, sn, cs);
+    *g = joint_transform_sc(L, q, *sn, *cs);
+  }
+};
+
 // The three sweeps for one state of an n-link chain whose link records start at
 // `table` (scalar T) and `wtable` (the same records in double). MODE selects ID
 // (tau_out), FD (qdd_out) or both. Each qdd_i is handed to epi(i, qdd_i) as
 // soon as the last sweep produces it (after the last read of q_i), so a caller
 // can fold an integrator update into the pass.
-template <class T, int MODE, class Epi>
+template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>>
 PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
-                              const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi) {
+                              const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi,
+                              const PoseSrc& pose = PoseSrc()) {
   constexpr bool kID = (MODE & kModeID) != 0;
   constexpr bool kFD = (MODE & kModeFD) != 0;
   constexpr int kOffB = kID ? 6 : 0;  // scratch offset of the bias wrench
@@ -285,10 +296,10 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
         [&](int i, const In& x) {
           const Link<T> L = load_link(table + (long)i * kLinkWords);
           T sn, cs;
-          joint_sincos(L, x.q, &sn, &cs);
+          Pose<T> g;
+          pose(i, L, x.q, &g, &sn, &cs);
           scr.at(i, kSC) = sn;
           scr.at(i, kSC + 1) = cs;
-          const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
           const Sp<T> XV = X_twist(g, V);
           const Sp<T> Sqd = x.qd * L.S;
           V = XV + Sqd;
@@ -461,13 +472,24 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
       });
 }
 
-// Pass A cut in two, for two more wavefronts: A1 forms the joint transforms
-// (tip to base) and hands each to A2 through put(k, pose), k = 0, 1, ... from
-// the tip; A2 runs the articulated-body inertia recursion with the child's
-// transform from get(k) (k >= 1: the transform of its (k-1)-th link from the
-// tip), reporting done(k) as pass A does.
+// Passes P_f and P_b: the joint transforms for the other wavefronts of the
+// role-split kernel. P_f hands link k's transform and (sin, cos) to
+// put(k, pose, sin, cos), base to tip, for B1 and the inverse dynamics; P_b
+// hands the transform of the k-th link from the tip (double, rounded to T, as
+// pass A forms it) to put(k, pose), for the articulated-body recursion.
 template <class T, class Put>
-PD_HD void split_pose_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Put& put) {
+PD_HD void split_pose_fwd(int n, const T* table, SPtr<const T> q, const Put& put) {
+  pipelined(
+      n, 0, 1, [&](int k) { return q[k]; },
+      [&](int k, T qk) {
+        const Link<T> L = load_link(table + (long)k * kLinkWords);
+        T sn, cs;
+        joint_sincos(L, qk, &sn, &cs);
+        put(k, joint_transform_sc(L, qk, sn, cs), sn, cs);
+      });
+}
+template <class T, class Put>
+PD_HD void split_pose_bwd(int n, const T* table, const double* wtable, SPtr<const T> q, const Put& put) {
   pipelined(
       n, n - 1, -1, [&](int i) { return q[i]; },
       [&](int i, T qi) {
@@ -477,6 +499,9 @@ PD_HD void split_pose_pass(int n, const T* table, const double* wtable, SPtr<con
       });
 }
 
+// Pass A with the transforms handed in: get(k) is the transform of the k-th
+// link from the tip, as pass A forms it; release(m) reports that the first m
+// of them are used; done(k) as in pass A.
 template <class T, class Get, class Release, class Done>
 PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, const Get& get,
                                 const Release& release, const Done& done) {
@@ -507,9 +532,9 @@ PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, co
 }
 
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
-template <class T>
+template <class T, class PoseSrc = FormPose<T>>
 PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
-                              const Scratch<T>& bias) {
+                              const Scratch<T>& bias, const PoseSrc& pose = PoseSrc()) {
   struct In {
     T q, qd;
   };
@@ -519,10 +544,10 @@ PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const
       [&](int i, const In& x) {
         const Link<T> L = load_link(table + (long)i * kLinkWords);
         T sn, cs;
-        joint_sincos(L, x.q, &sn, &cs);
+        Pose<T> g;
+        pose(i, L, x.q, &g, &sn, &cs);
         bias.at(i, 8) = sn;
         bias.at(i, 9) = cs;
-        const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
         const Sp<T> XV = X_twist(g, V);
         const Sp<T> Sqd = x.qd * L.S;
         V = XV + Sqd;

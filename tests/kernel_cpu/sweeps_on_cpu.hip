@@ -9,7 +9,7 @@
 using namespace pdyn;
 
 constexpr int kSplitFD = 5, kSplitIDFD = 7;  // FD, ID+FD through the role-split passes
-constexpr int kPoseRing = 16;                // with the articulated pass cut into A1 (transforms) and A2
+constexpr int kPoseRing = 16;                // with the transforms of B1 and ID handed in by pass P
 
 template <class T>
 static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
@@ -50,20 +50,38 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
       const double* wtab = wtable.data() + link0 * kLinkWords;
       const Scratch<T> abi{abi_scr.data() + s, (long)n_states, kAbiWords};
       const Scratch<T> bias{bias_scr.data() + s, (long)n_states, kBiasWords};
+      // pass P's transforms through a plain array (the kernel uses an LDS ring)
+      struct Entry {
+        Pose<T> g;
+        T sn, cs;
+      };
+      std::vector<Entry> poses((size_t)n);
+      auto take = [&](int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) {
+        *g = poses[(size_t)i].g;
+        *sn = poses[(size_t)i].sn;
+        *cs = poses[(size_t)i].cs;
+      };
+      std::vector<Pose<T>> poses_b((size_t)n);
+      if (pose_ring) {
+        split_pose_fwd(n, tab, io.q, [&](int i, const Pose<T>& g, T sn, T cs) { poses[(size_t)i] = Entry{g, sn, cs}; });
+        split_pose_bwd(n, tab, wtab, io.q, [&](int k, const Pose<T>& g) { poses_b[(size_t)k] = g; });
+      }
       if (mode == kSplitIDFD) {
         JointIO<T> id_io{io.q, io.qd, io.qdd_in, SPtr<const T>(), io.tau_out, SPtr<T>()};
         const Scratch<T> idscr{scratch.data() + s, (long)n_states, ScratchWords<kModeID>::value};
-        dynamics_one_state<T, kModeID>(n, tab, wtab, id_io, bd, idscr);
+        if (pose_ring)
+          dynamics_one_state<T, kModeID>(n, tab, wtab, id_io, bd, idscr, StoreQdd<T>{SPtr<T>()}, take);
+        else
+          dynamics_one_state<T, kModeID>(n, tab, wtab, id_io, bd, idscr);
       }
-      split_bias_forward(n, tab, io.q, io.qd, bd, bias);
-      if (pose_ring) {
-        // A1 then A2 through a plain array of transforms (the kernel uses an LDS ring)
-        std::vector<Pose<T>> poses((size_t)n);
-        split_pose_pass(n, tab, wtab, io.q, [&](int k, const Pose<T>& g) { poses[(size_t)k] = g; });
-        split_abi_from_poses(n, tab, abi, [&](int k) { return poses[(size_t)k]; }, NoHandoff(), NoHandoff());
-      } else {
+      if (pose_ring)
+        split_bias_forward(n, tab, io.q, io.qd, bd, bias, take);
+      else
+        split_bias_forward(n, tab, io.q, io.qd, bd, bias);
+      if (pose_ring)
+        split_abi_from_poses(n, tab, abi, [&](int k) { return poses_b[(size_t)k]; }, NoHandoff(), NoHandoff());
+      else
         split_abi_pass(n, tab, wtab, io.q, abi);
-      }
       split_bias_backward(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
       split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out});
       continue;

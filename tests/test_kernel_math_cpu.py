@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_cpu", "sweeps_on_cpu.hip")
 MODE_ID, MODE_FD, MODE_IDFD = 1, 2, 3
 SPLIT_FD, SPLIT_IDFD = 5, 7  # the role-split passes (articulated inertia beside the Newton-Euler passes)
-POSE_RING = 16  # flag: the articulated pass cut into a transform pass and the inertia recursion
+POSE_RING = 16  # flag: B1 and the inverse dynamics take their transforms from pass P
 
 
 @pytest.fixture(scope="module")
@@ -121,10 +121,12 @@ def test_role_split_passes_match_oracle(cpu_lib):
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch, st, np.float64, tip, V0, dV0)
     _, qdd_fd = run_cpu(cpu_lib, SPLIT_FD, ch, st, np.float64, tip, V0, dV0)
     assert np.array_equal(qdd, qdd_fd)
-    # the articulated pass cut in two (transforms handed over) gives the same bits
+    # transforms formed once by pass P and handed to B1 and the inverse dynamics: the same bits
     for mode in (SPLIT_FD, SPLIT_IDFD):
         t2, q2 = run_cpu(cpu_lib, mode | POSE_RING, ch, st, np.float64, tip, V0, dV0)
         assert np.array_equal(q2, qdd)
+        if mode == SPLIT_IDFD:
+            assert np.array_equal(t2, tau)
     for s in range(16):
         rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], V0, dV0, tip[s])
         rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s])
