@@ -120,6 +120,17 @@ typedef struct pdyn_batch {
   int32_t variant;
 } pdyn_batch;
 
+/* Status word. The first 256 bytes of every workspace hold a 32-bit word into
+ * which the kernels OR these bits when a numerical fault occurs (the call
+ * itself still returns PDYN_OK; faulty values propagate as NaN/inf):
+ *   PDYN_STATUS_NONFINITE  an output (tau, qdd, q_bar, u = tau_bar) is not finite;
+ *   PDYN_STATUS_PIVOT      an articulated-body pivot D_i = S_i^T Jhat_i S_i (Sec. II-B,
+ *                          eq. (7)) is not positive: the inertia parameters are not
+ *                          physical for this configuration.
+ * A new workspace must start with this word zero; pdyn_read_status clears it. */
+#define PDYN_STATUS_NONFINITE 1u
+#define PDYN_STATUS_PIVOT 2u
+
 /* Operation selector for pdyn_workspace_bytes. */
 enum {
   PDYN_OP_RNEA_ID = 0,
@@ -152,6 +163,13 @@ int pdyn_max_links(void);
 
 /* Human-readable text for a status code (static storage). */
 const char* pdyn_strerror(int status);
+
+/* Reads the status word of workspace ws (the same pointer passed to the
+ * operations) into *bits after all work queued on stream (0 = default stream)
+ * has finished, and clears it. Synchronises the stream, so it is not for use
+ * inside a captured graph. Returns PDYN_EINVAL for a null pointer,
+ * PDYN_EALIGN if ws is not 256-byte aligned, PDYN_ELAUNCH if a HIP call fails. */
+int pdyn_read_status(void* ws, void* stream, uint32_t* bits);
 
 /*
  * Inverse dynamics, eq. (3): tau = ID(q, qd, qdd, V_0, dV_0, F_{n+1}) by the

@@ -6,9 +6,11 @@ kernels behind the C ABI of include/pdyn.h. This package is the thin Python
 binding; ``synth`` is the seeded input generator.
 """
 
-from .api import (GRAVITY_ACC, Model, PdynError, Workspace, aba_fd, aba_fd_vjp, id_fd, lib, rnea_id,
-                  rnea_id_vjp)
+from .api import (GRAVITY_ACC, STATUS_NONFINITE, STATUS_PIVOT, Model, PdynError, Workspace, aba_fd, aba_fd_vjp,
+                  id_fd, lib, read_status, rnea_id, rnea_id_vjp)
 from .autograd import forward_dynamics, inverse_dynamics
+from .jacobian import fd_jacobians, id_jacobians
 
-__all__ = ["GRAVITY_ACC", "Model", "PdynError", "Workspace", "aba_fd", "aba_fd_vjp", "forward_dynamics", "id_fd",
-           "inverse_dynamics", "lib", "rnea_id", "rnea_id_vjp"]
+__all__ = ["GRAVITY_ACC", "STATUS_NONFINITE", "STATUS_PIVOT", "Model", "PdynError", "Workspace", "aba_fd",
+           "aba_fd_vjp", "fd_jacobians", "forward_dynamics", "id_fd", "id_jacobians", "inverse_dynamics", "lib",
+           "read_status", "rnea_id", "rnea_id_vjp"]

@@ -81,8 +81,21 @@ def lib():
                 getattr(L, name).restype = ci
             L.pdyn_rollout_workspace_bytes.argtypes = [ci, ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ci, ci]
             L.pdyn_rollout_workspace_bytes.restype = ctypes.c_size_t
+            L.pdyn_read_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
+            L.pdyn_read_status.restype = ctypes.c_int
             _lib = L
     return _lib
+
+
+# status bits of a workspace (see Workspace.read_status)
+STATUS_NONFINITE = 1
+STATUS_PIVOT = 2
+
+
+def read_status(device=None, workspace=None) -> int:
+    """Status bits of the calls on `device` that used the default (or the given) workspace; clears them."""
+    ws = workspace if workspace is not None else _workspace(device or "cuda")
+    return ws.read_status()
 
 
 def _check(status: int, what: str):
@@ -183,16 +196,32 @@ class Workspace:
         self.buf = None
 
     def get(self, nbytes: int, device) -> torch.Tensor:
-        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
-            self.buf = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+        if self.buf is None or self.buf.numel() < nbytes + 256 or self.buf.device != device:
+            # zeroed once: the first word of a workspace is the status word of the calls using it
+            self.buf = torch.zeros(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
         off = (-self.buf.data_ptr()) % 256
         return self.buf[off:]
+
+    def read_status(self) -> int:
+        """Status bits (STATUS_NONFINITE, STATUS_PIVOT) of the calls that used this workspace since the
+        last read; clears them. Synchronises the current stream."""
+        if self.buf is None:
+            return 0
+        off = (-self.buf.data_ptr()) % 256
+        bits = ctypes.c_uint32(0)
+        stream = torch.cuda.current_stream(self.buf.device).cuda_stream
+        _check(lib().pdyn_read_status(ctypes.c_void_p(self.buf.data_ptr() + off), ctypes.c_void_p(stream),
+                                      ctypes.byref(bits)), "pdyn_read_status")
+        return int(bits.value)
 
 
 _default_ws = {}
 
 
 def _workspace(device):
+    device = torch.device(device)
+    if device.type == "cuda" and device.index is None:
+        device = torch.device("cuda", torch.cuda.current_device())
     key = (str(device), threading.get_ident())
     if key not in _default_ws:
         _default_ws[key] = Workspace()

@@ -28,6 +28,9 @@ namespace {
 constexpr int kMaxLinks = 1 << 16;
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
+constexpr size_t kStatusBytes = 256;  // status word at the start of every workspace (padded for alignment)
+static_assert(kStatusNonFinite == PDYN_STATUS_NONFINITE && kStatusPivot == PDYN_STATUS_PIVOT,
+              "status bits of the kernels and of the C ABI");
 // Default kernel variant: the role split (2) for the adjoints; for forward
 // dynamics and ID+FD the role split while a one-wavefront launch would leave
 // SIMDs idle (up to 128 states per CU), else the one-wavefront kernel (1),
@@ -71,7 +74,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
                                                         const T* __restrict__ table,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
-                                                        const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch) {
+                                                        const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
+                                                        unsigned* status) {
   const long n_work = ((long)n_states + blockDim.x - 1) / blockDim.x;
   for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {  // persistent when gridDim.x < n_work
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
@@ -105,7 +109,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
       bd.Ftip = sp_zero<T>();
     }
     // scratch column = lane: consecutive lanes touch consecutive words
-    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value};
+    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value, status};
     dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
   }
 }
@@ -255,7 +259,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
                                                         const T* __restrict__ tip, BoundaryArgs<T> ba, T* scr_id,
-                                                        T* scr_bias, T* scr_abi) {
+                                                        T* scr_bias, T* scr_abi, unsigned* status) {
   // with OVERLAP: [link][kAbiWords][64 lanes], then the transform ring
   extern __shared__ __align__(16) unsigned char lds_abi[];
   __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a;
@@ -299,9 +303,9 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
   }
-  const Scratch<T> abi = OVERLAP ? Scratch<T>{reinterpret_cast<T*>(lds_abi) + lane, 64L, kAbiWords}
-                                 : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords};
-  const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords};
+  const Scratch<T> abi = OVERLAP ? Scratch<T>{reinterpret_cast<T*>(lds_abi) + lane, 64L, kAbiWords, status}
+                                 : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords, status};
+  const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords, status};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
   T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiWords * 64;
   T* const ring_b = ring_f + (long)kPoseSlots * kPoseWordsF * 64;
@@ -318,7 +322,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
     // inverse dynamics: ends here; a workgroup barrier waits only for wavefronts still running
     if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
-      const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value};
+      const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value, status};
       if (OVERLAP)
         dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr, StoreQdd<T>{SPtr<T>()},
                                        RingTakeF<T>{ring_f, &ready_f, &used_id, lane});
@@ -383,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
                                                 const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
                                                 T* tau_bar, T* pi_out, const T* __restrict__ tip, BoundaryArgs<T> ba,
-                                                T* scratch) {
+                                                T* scratch, unsigned* status) {
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
   const int s = state_of(lane_index, order);
@@ -402,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
   }
-  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
+  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords, status};
   PiSink<T, PI> sink;
   sink.out = nullptr;
   sink.stride = 0;
@@ -430,7 +434,8 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
                                                    const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
                                                    T* tau_bar, T* pi_out, const T* __restrict__ tip,
-                                                   BoundaryArgs<T> ba, T* scratch, T* xscratch) {
+                                                   BoundaryArgs<T> ba, T* scratch, T* xscratch,
+                                                   unsigned* status) {
   const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y
   const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
   const bool active = lane_index < n_states;
@@ -453,8 +458,8 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
   }
-  const Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
-  const Scratch<T> xs{xscratch + lane_index, (long)n_states, kVjpXWords};
+  const Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords, status};
+  const Scratch<T> xs{xscratch + lane_index, (long)n_states, kVjpXWords, status};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0), qdds(qdd + dof0), bar(bar_in + dof0);
   if (active) {
     if (role == 0) {
@@ -537,14 +542,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
                                                        const int32_t* __restrict__ order, const T* __restrict__ table,
                                                        const double* __restrict__ wtable, int steps, T dt, int every,
                                                        const T* tau_seq, T* q, T* qd, T* ckpt_q, T* ckpt_qd, long dofs,
-                                                       BoundaryArgs<T> ba, T* scratch) {
+                                                       BoundaryArgs<T> ba, T* scratch, unsigned* status) {
   const long n_work = ((long)n_states + blockDim.x - 1) / blockDim.x;
   for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
     if (lane_index >= n_states) continue;
     const int s = state_of(lane_index, order);
     const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
-    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value};
+    Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value, status};
     rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every,
                       SPtr<T>(q + c.dof0), SPtr<T>(qd + c.dof0), DevRows<T>{tau_seq + c.dof0, dofs},
                       DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs}, boundary_of(ba), scr);
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
                                                         const T* tau_seq, const T* ckpt_q, const T* ckpt_qd,
                                                         const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar,
                                                         T* tau_bar_seq, T* pi_out, long dofs, BoundaryArgs<T> ba,
-                                                        T* scratch, T* rows_ws, T* pi_acc) {
+                                                        T* scratch, T* rows_ws, T* pi_acc, unsigned* status) {
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
   const int s = state_of(lane_index, order);
@@ -579,7 +584,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
     rows.lq[i] = qT_bar[c.dof0 + i];
     rows.lqd[i] = qdT_bar[c.dof0 + i];
   }
-  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords};
+  Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords, status};
   DevRows<T> tau{tau_seq + c.dof0, dofs};
   DevCkpt<T> ck{const_cast<T*>(ckpt_q) + c.dof0, const_cast<T*>(ckpt_qd) + c.dof0, dofs};
   DevMutRows<T> tb{tau_bar_seq + c.dof0, dofs};
@@ -673,7 +678,7 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
     L->xscratch_off = 0;
     L->total = L->scratch_off + L->scratch_bytes;
   }
-  if (L->total < kAlign) L->total = kAlign;
+  L->total += kStatusBytes;
   return PDYN_OK;
 }
 
@@ -764,7 +769,8 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   if (ws_bytes < L.total) return PDYN_EWORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+  unsigned* status = static_cast<unsigned*>(ws);  // the first kStatusBytes of every workspace
+  char* base = static_cast<char*>(ws) + kStatusBytes;
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
   const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
@@ -795,7 +801,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
       return PDYN_ELAUNCH;                                                                                        \
     hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, OV>), dim3(g), dim3(blk), OV ? lds : 0, s, b->n_states,     \
                        m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
-                       qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi);             \
+                       qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi, status);     \
   } while (0)
     if (shared && overlap) PDYN_LAUNCH_SPLIT(true, true);
     else if (shared) PDYN_LAUNCH_SPLIT(true, false);
@@ -810,11 +816,11 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   if (m->n_chains == 1)
     hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
                        m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
-                       static_cast<const T*>(b->tip_wrench), ba, scratch);
+                       static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   else
     hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
                        m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
-                       static_cast<const T*>(b->tip_wrench), ba, scratch);
+                       static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -829,14 +835,14 @@ size_t rollout_layout(int with_grad, const pdyn_model* m, const pdyn_batch* b, i
   if (!with_grad) {
     off += align_up(nm * (size_t)ScratchWords<kModeFD>::value * B * scalar);
     *rows_off = *acc_off = off;
-    return off < kAlign ? kAlign : off;
+    return off + kStatusBytes;
   }
   off += align_up(nm * (size_t)kVjpWords * B * scalar);
   *rows_off = off;
   off += align_up(B * (size_t)(3 * every + 6) * nm * scalar);
   *acc_off = off;
   off += align_up(nm * 10 * B * scalar);
-  return off;
+  return off + kStatusBytes;
 }
 
 template <class T>
@@ -862,7 +868,8 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   size_t so, ro, ao;
   if (ws_bytes < rollout_layout(0, m, b, every, sizeof(T), &so, &ro, &ao)) return PDYN_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+  unsigned* status = static_cast<unsigned*>(ws);  // the first kStatusBytes of every workspace
+  char* base = static_cast<char*>(ws) + kStatusBytes;
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
@@ -876,7 +883,7 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   hipLaunchKernelGGL((k_rollout<T, SH>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,   \
                      m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                                    \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, q, qd, ckpt_q,   \
-                     ckpt_qd, dofs, ba, reinterpret_cast<T*>(base + so))
+                     ckpt_qd, dofs, ba, reinterpret_cast<T*>(base + so), status)
   if (m->n_chains == 1)
     PDYN_LAUNCH_ROLLOUT(true);
   else
@@ -900,7 +907,8 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   size_t so, ro, ao;
   if (ws_bytes < rollout_layout(1, m, b, every, sizeof(T), &so, &ro, &ao)) return PDYN_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+  unsigned* status = static_cast<unsigned*>(ws);  // the first kStatusBytes of every workspace
+  char* base = static_cast<char*>(ws) + kStatusBytes;
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
@@ -915,7 +923,7 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
                      m->n_links_max, m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                   \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
                      ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
-                     reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc)
+                     reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc, status)
   if (!inertia_bar) {
     if (m->n_chains == 1)
       PDYN_LAUNCH_RVJP(kPiNone, true);
@@ -951,7 +959,8 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   if (ws_bytes < L.total) return PDYN_EWORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+  unsigned* status = static_cast<unsigned*>(ws);  // the first kStatusBytes of every workspace
+  char* base = static_cast<char*>(ws) + kStatusBytes;
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   T* partials = reinterpret_cast<T*>(base + L.partial_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
@@ -974,11 +983,11 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
     if (split)                                                                                                \
       hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH>), dim3(grid64), dim3(128), 0, s, b->n_states,            \
                          m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
-                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch);                                \
+                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);                        \
     else                                                                                                      \
       hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
                          m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
-                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch);                                          \
+                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch, status);                                  \
   } while (0)
   if (!inertia_bar) {
     if (m->n_chains == 1)
@@ -1003,6 +1012,18 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
 using namespace pdyn;
 
 extern "C" {
+
+int pdyn_read_status(void* ws, void* stream, uint32_t* bits) {
+  if (!ws || !bits) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t v = 0;
+  if (hipMemcpyAsync(&v, ws, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return PDYN_ELAUNCH;
+  if (hipMemsetAsync(ws, 0, sizeof(v), s) != hipSuccess) return PDYN_ELAUNCH;
+  if (hipStreamSynchronize(s) != hipSuccess) return PDYN_ELAUNCH;
+  *bits = v;
+  return PDYN_OK;
+}
 
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return 0;

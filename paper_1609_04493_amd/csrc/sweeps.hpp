@@ -177,11 +177,28 @@ template <int MODE> struct ScratchWords {
   static constexpr int value = kData + 2;
 };
 
-// Strided view of the per-link scratch of one state.
+// Numerical faults a pass reports (same values as PDYN_STATUS_* in pdyn.h):
+// a non-finite output, and a non-positive articulated-body pivot D_i
+// (non-physical inertia parameters).
+constexpr unsigned kStatusNonFinite = 1u;
+constexpr unsigned kStatusPivot = 2u;
+
+// Strided view of the per-link scratch of one state. It also carries the
+// call's status word (null: faults are not reported).
 template <class T> struct Scratch {
   T* base;        // &scratch[0][0][state]
   long stride;    // number of states
   int words;      // components per link
+  unsigned* status = nullptr;
+  PD_HD void flag(unsigned bit) const {
+    if (status) __hip_atomic_fetch_or(status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  PD_HD void check_finite(T x) const {
+    if (!__builtin_isfinite(x)) flag(kStatusNonFinite);
+  }
+  PD_HD void check_pivot(T d) const {
+    if (!(d > T(0))) flag(kStatusPivot);
+  }
   PD_HD T& at(int link, int comp) const { return base[((long)link * words + comp) * stride]; }
   PD_HD void put(int link, int comp, const Sp<T>& x) const {
     at(link, comp + 0) = x.a.x; at(link, comp + 1) = x.a.y; at(link, comp + 2) = x.a.z;
@@ -348,7 +365,9 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           if (kID) {
             Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
             F = Fc + cast_sp<double>(x.fh);
-            io.tau_out[i] = (T)dot(Lw.S, F);
+            const T tau = (T)dot(Lw.S, F);
+            io.tau_out[i] = tau;
+            scr.check_finite(tau);
           }
           if (kFD) {
             Sp<double> Fc = has_child ? XT_wrench(gcw, Fb) : Fb;
@@ -369,7 +388,9 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
               z = XT_wrench(gcw, zA);
             }
             const Sp<T> U = mul(Jh, L.S);
-            const T invD = T(1) / dot(L.S, U);
+            const T D = dot(L.S, U);
+            scr.check_pivot(D);
+            const T invD = T(1) / D;
             const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
             const T chat = (T)chat_w;
             JA = sym6_minus_outer(Jh, U, invD);
@@ -408,6 +429,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           const Sp<T> a = X_twist(g, lam);
           const T qdd = x.chat - dot(x.U, a) * x.invD;
           lam = a + qdd * L.S;
+          scr.check_finite(qdd);
           epi(i, qdd);
         });
   }
@@ -463,7 +485,9 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
           Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
         }
         const Sp<T> U = mul(Jh, L.S);
-        const T invD = T(1) / dot(L.S, U);
+        const T D = dot(L.S, U);
+        abi.check_pivot(D);
+        const T invD = T(1) / D;
         JA = sym6_minus_outer(Jh, U, invD);
         abi.put(i, 0, U);
         abi.at(i, 6) = invD;
@@ -523,7 +547,9 @@ PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, co
           release(n - 1 - i);  // transforms 0 .. n-2-i from the tip are used
         }
         const Sp<T> U = mul(Jh, L.S);
-        const T invD = T(1) / dot(L.S, U);
+        const T D = dot(L.S, U);
+        abi.check_pivot(D);
+        const T invD = T(1) / D;
         JA = sym6_minus_outer(Jh, U, invD);
         abi.put(i, 0, U);
         abi.at(i, 6) = invD;
@@ -625,6 +651,7 @@ PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>
         const Sp<T> a = X_twist(g, lam);
         const T qdd = x.chat - dot(x.U, a) * x.invD;
         lam = a + qdd * L.S;
+        abi.check_finite(qdd);
         epi(i, qdd);
       });
 }
@@ -777,7 +804,9 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
           const Sp<T> XA = x.A - x.qdd * L.S + ad_twist(Sqd, y);
           if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
           qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
-          q_bar[i] = x.qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+          const T qb = x.qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+          q_bar[i] = qb;
+          scr.check_finite(qb);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           Ac = XT_wrench(g, Ab);
           yc = XT_wrench(g, yb);
@@ -837,7 +866,9 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
             z = XT_wrench(gcw, zA);
           }
           const Sp<T> U = mul(Jh, L.S);
-          const T invD = T(1) / dot(L.S, U);
+          const T D = dot(L.S, U);
+          scr.check_pivot(D);
+          const T invD = T(1) / D;
           const double chat_w = ((double)x.bar - dot(Lw.S, z)) * (double)invD;
           JA = sym6_minus_outer(Jh, U, invD);
           zA = z + chat_w * cast_sp<double>(U);
@@ -872,6 +903,7 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
           const T u = x.chat - dot(x.U, a) * x.invD;
           lam = a + u * L.S;
           io.tau_bar[i] = u;
+          scr.check_finite(u);
           vjp_forward_fhat(i, L, g, x.qd, x.qdd, V, A, scr);
         });
   }
@@ -941,7 +973,9 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
             z = XT_wrench(gcw, zA);
           }
           const Sp<T> U = mul(Jh, L.S);
-          const T invD = T(1) / dot(L.S, U);
+          const T D = dot(L.S, U);
+          xs.check_pivot(D);
+          const T invD = T(1) / D;
           const double chat_w = ((double)x.bar - dot(Lw.S, z)) * (double)invD;
           JA = sym6_minus_outer(Jh, U, invD);
           zA = z + chat_w * cast_sp<double>(U);
@@ -972,6 +1006,7 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
           const T u = x.chat - dot(x.U, a) * x.invD;
           lam = a + u * L.S;
           tau_bar[i] = u;
+          xs.check_finite(u);
           Fb = X_twist(g, Fb) - u * L.S;
           xs.put(i, 0, Fb);
         });
@@ -1067,7 +1102,9 @@ PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> q
         const Sp<T> XA = x.A - x.qdd * L.S + ad_twist(Sqd, y);
         if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
         qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
-        q_bar[i] = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+        const T qb = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+        q_bar[i] = qb;
+        scr.check_finite(qb);
         const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
         Ac = XT_wrench(g, Ab);
         yc = XT_wrench(g, yb);

@@ -142,3 +142,25 @@ def test_launch_shape_and_order_validation():
     m.order = order.ctypes.data  # an order with a shared chain is meaningless
     b2 = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)
     assert _call_id(m, b2, (p, p, p, p)) == -1
+
+
+def test_read_status_validation():
+    """pdyn_read_status rejects a null workspace or result pointer and a misaligned workspace before any
+    device call."""
+    L = api.lib()
+    bits = ctypes.c_uint32(7)
+    buf = np.zeros(1024, np.uint8)
+    p = buf.ctypes.data + ((-buf.ctypes.data) % 256)
+    assert L.pdyn_read_status(None, None, ctypes.byref(bits)) == -1
+    assert L.pdyn_read_status(ctypes.c_void_p(p), None, None) == -1
+    assert L.pdyn_read_status(ctypes.c_void_p(p + 4), None, ctypes.byref(bits)) == -2
+    assert bits.value == 7  # untouched on error
+
+
+def test_workspace_holds_the_status_word():
+    """Every workspace size includes the 256-byte status block at its start."""
+    L = api.lib()
+    m, keep = _fake_model(n=1)
+    b = api._batch_struct(1, api.ZERO6, api.GRAVITY_ACC, None)
+    for op in range(5):
+        assert L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), 4) >= 256 + 256

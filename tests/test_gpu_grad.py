@@ -243,3 +243,45 @@ def test_adjoint_variants(device, variant):
     finally:
         for op in (api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):
             api.set_launch(op, 0, 0, 0)
+
+
+def test_jacobian_mode_50_links_8192_states(device):
+    """Full FD Jacobians of the 50-link, 8192-state workload by stacked one-hot cotangents: 64 sampled
+    states against the oracle's complex-step Jacobians; at every state dqdd/dtau (= M^-1) times the ID
+    Jacobian dtau/dqdd (= M) is the identity."""
+    print("case: jacobian mode 50 links x 8192", flush=True)
+    from paper_1609_04493_amd import jacobian
+    ch, st = synth.workload_50link(8192)
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: dev_t(a, device, torch.float32)
+    q, qd, tau = d(st.q), d(st.qd), d(st.tau)
+    Jq, Jqd, Jt = jacobian.fd_jacobians(model, q, qd, tau)
+    assert Jq.shape == (8192, 50, 50)
+    cr, sr = ch.rounded(), st.rounded()
+    idx = np.random.default_rng(9).choice(8192, 64, replace=False)
+    f = lambda c, a, b, t: oracle.aba1(c, a, b, t)
+    worst = {"q": 0.0, "qd": 0.0, "tau": 0.0}
+    for s in idx:
+        args = (sr.q[s], sr.qd[s], sr.tau[s])
+        for k, (name, J) in enumerate((("q", Jq), ("qd", Jqd), ("tau", Jt))):
+            ref = grad._jac(f, args, k, cr)
+            worst[name] = max(worst[name], rel(J[s].cpu().numpy(), ref))
+    print("jacobian mode rel errors (Frobenius, 64 states)", worst, flush=True)
+    assert worst["q"] <= 1e-3 and worst["qd"] <= 1e-4 and worst["tau"] <= 1e-4
+    qdd = api.aba_fd(model, q, qd, tau)
+    _, _, M = jacobian.id_jacobians(model, q[:256], qd[:256], qdd[:256])
+    eye = torch.eye(50, device=device).expand(256, 50, 50)
+    prod = torch.bmm(M.contiguous(), Jt[:256].contiguous())
+    err = ((prod - eye).norm(dim=(1, 2)) / 50 ** 0.5).max().item()
+    print(f"FP32: max ||M M^-1 - I|| / sqrt(n) over 256 states: {err:.2e} (bounded by eps cond(M))", flush=True)
+    assert err <= 1e-2
+    # in FP64 the same identity holds to rounding, and M is symmetric
+    m64 = api.Model(ch, device, torch.float64)
+    d64 = lambda a: dev_t(a, device, torch.float64)
+    q6, qd6, t6 = d64(st.q[:16]), d64(st.qd[:16]), d64(st.tau[:16])
+    _, _, Minv = jacobian.fd_jacobians(m64, q6, qd6, t6)
+    _, _, M6 = jacobian.id_jacobians(m64, q6, qd6, api.aba_fd(m64, q6, qd6, t6))
+    eye6 = torch.eye(50, device=device, dtype=torch.float64).expand(16, 50, 50)
+    assert (torch.bmm(M6.contiguous(), Minv.contiguous()) - eye6).abs().max().item() <= 1e-8
+    assert (M6 - M6.transpose(1, 2)).abs().max().item() <= 1e-12 * M6.abs().max().item()
+    assert (Minv - Minv.transpose(1, 2)).abs().max().item() <= 1e-9 * Minv.abs().max().item()

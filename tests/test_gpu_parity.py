@@ -262,3 +262,34 @@ def test_forward_dynamics_variants(device, variant):
     finally:
         for op in (api.OP_ABA_FD, api.OP_ID_FD):
             api.set_launch(op, 0, 0, 0)
+
+
+def test_status_word_reports_numerical_faults(device):
+    """Non-physical inertia (negative mass) sets the pivot bit, a NaN input the non-finite bit; healthy
+    calls leave the word clear; reading clears it."""
+    print("case: status word", flush=True)
+    ch = synth.make_chains([12], 9)
+    st = synth.make_states((130, 12), 9)
+    d = lambda a: to_dev(a, device, torch.float32)
+    ws = api.Workspace()
+    model = api.Model(ch, device, torch.float32)
+    q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+    for variant in (1, 2):
+        for op in (api.OP_ABA_FD, api.OP_ID_FD, api.OP_ABA_FD_VJP, api.OP_RNEA_ID_VJP):
+            api.set_launch(op, 0, 0, variant)
+        api.id_fd(model, q, qd, qdd, tau, workspace=ws)
+        qdd_fd = api.aba_fd(model, q, qd, tau, workspace=ws)
+        api.aba_fd_vjp(model, q, qd, qdd_fd, qdd_fd, workspace=ws)
+        assert ws.read_status() == 0, variant
+        bad = q.clone()
+        bad[7, 3] = float("nan")
+        api.id_fd(model, bad, qd, qdd, tau, workspace=ws)
+        assert ws.read_status() & api.STATUS_NONFINITE, variant
+        assert ws.read_status() == 0  # cleared by the read
+        heavy = synth.make_chains([12], 9)
+        heavy.inertia[5, 0] = -3.0  # negative mass: D_i <= 0 somewhere down the chain
+        m2 = api.Model(heavy, device, torch.float32)
+        api.aba_fd(m2, q, qd, tau, workspace=ws)
+        assert ws.read_status() & api.STATUS_PIVOT, variant
+    for op in (api.OP_ABA_FD, api.OP_ID_FD, api.OP_ABA_FD_VJP, api.OP_RNEA_ID_VJP):
+        api.set_launch(op, 0, 0, 0)
