@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "dynamics evals/s (ID+FD, ±grad) at 32 links FP32 vs plain, at stated error"
 N_LINKS, N_STATES = 32, 16384
 # Algorithmic flops per link (structured spatial algebra, counted once per link;
-# derivation in the design doc): ID 433, FD 1045, ID+FD sharing transforms and velocities 1212.
-FLOPS_PER_LINK = {"id": 433, "fd": 1045, "id_fd": 1212}
+# derivation in the design doc): ID 433, FD 1045, ID+FD sharing transforms and velocities 1212,
+# ID adjoint 1076, FD adjoint 1699.
+FLOPS_PER_LINK = {"id": 433, "fd": 1045, "id_fd": 1212, "id_vjp": 1076, "fd_vjp": 1699}
 BYTES_PER_LINK = {"id": 16, "fd": 16, "id_fd": 24}  # joint inputs + outputs, FP32
 PEAK_VALU_FLOPS = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, unpacked FP32 = FP64 vector
 
@@ -116,9 +117,20 @@ def cpu_baseline(ch, st):
         el = time.perf_counter() - t0
         if el >= 10.0 or reps >= 20:
             break
+    t1 = time.perf_counter()
+    oracle.rnea(cr, sr.q[:1024], sr.qd[:1024], sr.qdd[:1024], threads=1)
+    oracle.aba(cr, sr.q[:1024], sr.qd[:1024], sr.tau[:1024], threads=1)
+    one = 1024 / (time.perf_counter() - t1)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": reps * len(sr.q) / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"the full {len(sr.q)}-state, {N_LINKS}-link batch (ID + FD per state), {reps} pass(es), "
-                      f"{el:.1f} s wall, {threads} Python threads each running the C oracle on a contiguous slice of states"}
+                      f"{el:.1f} s wall, {threads} Python threads each running the C oracle on a contiguous slice of states",
+            "one_thread_evals_per_s": one, "cpu_model": model}
 
 
 def bench_uneven(args, dev):
@@ -166,8 +178,16 @@ def bench_fd_grad_50(args, dev):
         api.aba_fd_vjp(model, q, qd, qdd, qdd_bar, out=g, workspace=ws)
 
     ms = time_steps(step, args.steps, args.warmup, torch.cuda.current_stream(dev))
+    from paper_1609_04493_amd import jacobian
+    jac = lambda: jacobian.fd_jacobians(model, q, qd, tau, qdd=qdd, workspace=ws)
+    ms_jac = time_steps(jac, max(1, min(5, args.steps)), 1, torch.cuda.current_stream(dev))
+    flops = FLOPS_PER_LINK["fd"] + FLOPS_PER_LINK["fd_vjp"]
     return {"workload": "50-link chain, 8192 states, FD + adjoint (dL/d(q, qd, tau, inertia), L = ||qdd||^2)",
-            "evals_per_s": 8192 / (ms * 1e-3), "ms_per_step": ms}
+            "evals_per_s": 8192 / (ms * 1e-3), "ms_per_step": ms,
+            "roofline_frac": flops * 50 * 8192 / (ms * 1e-3) / PEAK_VALU_FLOPS,
+            "jacobian_mode": {"what": "full dqdd/dq, dqdd/dqd, dqdd/dtau of all 8192 states (50 one-hot cotangents "
+                                      "per state, 409600 adjoint rows)", "ms": ms_jac,
+                              "state_jacobians_per_s": 8192 / (ms_jac * 1e-3)}}
 
 
 def bench_rollout_100(args, dev):
@@ -285,6 +305,20 @@ def main():
     api.set_launch(api.OP_RNEA_ID_VJP, 0, 0, 0)
     api.set_launch(api.OP_ABA_FD_VJP, 0, 0, 0)
 
+    # cold inputs: rotate 64 copies of the inputs (512 MiB) so that every step reads them from HBM
+    n_cold = 64
+    cold = [tuple(x.clone() for x in (q, qd, qdd, tau)) for _ in range(n_cold)]
+    cold_i = [0]
+
+    def fused_cold():
+        c = cold[cold_i[0] % n_cold]
+        cold_i[0] += 1
+        api.id_fd(model, *c, out=(tau_out, qdd_out), workspace=ws)
+
+    ms_cold = time_steps(fused_cold, max(args.steps, n_cold), args.warmup, stream)
+    del cold
+    print(f"fused ID+FD, cold inputs: {ms_cold * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+
     # stated error: the fused outputs against the FP64 oracle on a sample of states
     import oracle
     fused()
@@ -313,6 +347,13 @@ def main():
 
     links = N_LINKS * N_STATES
     achieved = FLOPS_PER_LINK["id_fd"] * links / (ms_fused * 1e-3)
+    per_op = {}
+    for name, ms in (("id", ms_id), ("fd", ms_fd), ("id_fd", ms_fused), ("id_vjp", ms_idv), ("fd_vjp", ms_fdv)):
+        fl = FLOPS_PER_LINK[name] * links / (ms * 1e-3)
+        per_op[name] = {"us": ms * 1e3, "evals_per_s": N_STATES / (ms * 1e-3), "tflops": fl / 1e12,
+                        "roofline_frac": fl / PEAK_VALU_FLOPS}
+    # conditioning of the mass matrix on the sampled states (FP64 oracle)
+    conds = np.array([np.linalg.cond(oracle.mass_matrix(cr, sr.q[s])) for s in idx[:256]])
     out = {
         "metric": METRIC,
         "value": N_STATES / (ms_fused * 1e-3),
@@ -340,9 +381,16 @@ def main():
                   "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
         "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),
                                "id_vjp": N_STATES / (ms_idv * 1e-3), "fd_vjp": N_STATES / (ms_fdv * 1e-3)},
+        "per_op": per_op,
+        "cold": {"form": "fused ID+FD, inputs rotated over 64 copies (512 MiB) so each step reads them from HBM",
+                 "ms_per_step": ms_cold, "value": N_STATES / (ms_cold * 1e-3)},
+        "mass_matrix_condition": {"states": int(len(conds)), "p50": float(np.median(conds)),
+                                  "p99": float(np.quantile(conds, 0.99)), "max": float(conds.max())},
         "adjoint_variants": vjp_variants,
         "grad": {"form": "fused ID+FD, then pdyn_rnea_id_vjp and pdyn_aba_fd_vjp (L = ||qdd||^2), inertia gradients on",
                  "value": N_STATES / (ms_grad * 1e-3), "unit": "evals/s", "ms_per_step": ms_grad,
+                 "roofline_frac": (FLOPS_PER_LINK["id_fd"] + FLOPS_PER_LINK["id_vjp"] + FLOPS_PER_LINK["fd_vjp"])
+                 * links / (ms_grad * 1e-3) / PEAK_VALU_FLOPS,
                  "max_rel_err_vs_oracle_4_states": gerr},
         "error_vs_fp64_oracle": {"sample_states": len(idx), "tau": err_stats(et), "qdd": err_stats(eq),
                                  "metric": "per-state ||x - x*|| / ||x*||"},
