@@ -104,8 +104,11 @@ typedef struct pdyn_batch {
    * each workgroup striding over the remaining work in a fixed order. */
   int32_t block_threads;
   int32_t max_blocks;
-  /* Kernel variant; 0 = library default: 2 for the adjoints, and for forward
-   * dynamics and ID+FD 2 up to 128 states per compute unit, else 1.
+  /* Kernel variant; 0 = library default: 2 for the adjoints, and for inverse
+   * dynamics, forward dynamics and ID+FD 2 up to 128 states per compute unit,
+   * else 1. Inverse dynamics: 1 = one wavefront per 64 states; 2 = one
+   * wavefront forms the joint transforms (eq. 1) and hands them to another
+   * that runs the two Newton-Euler sweeps (eqs. 1, 2).
    * Forward dynamics and fused ID+FD: 1 = one wavefront runs every recursion
    * of its 64 states; 2 = role split -- per group of 64 states one wavefront
    * runs the articulated-body inertia recursion (7) while others run the

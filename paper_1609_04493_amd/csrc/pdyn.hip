@@ -355,6 +355,59 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   }
 }
 
+// Role-split inverse dynamics (variant 2): per group of 64 states, wavefront 1
+// (P_f) forms the joint transforms base to tip and hands them through an LDS
+// ring to wavefront 0, which runs the two Newton-Euler sweeps without forming
+// any. P_f waits only for free slots and wavefront 0 only for entries.
+template <class T, bool SHARED>
+__global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+                                                  const int32_t* __restrict__ order, const T* __restrict__ table,
+                                                  const double* __restrict__ wtable, const T* q, const T* qd,
+                                                  const T* qdd_in, T* tau_out, const T* __restrict__ tip,
+                                                  BoundaryArgs<T> ba, T* scratch, unsigned* status) {
+  __shared__ T ring[kPoseSlots * kPoseWordsF * 64];
+  __shared__ int ready, used;
+  if (threadIdx.x == 0) {
+    ready = 0;
+    used = 0;
+  }
+  __syncthreads();
+  const int role = threadIdx.x / 64;  // wave-uniform
+  const int lane = (int)(threadIdx.x % 64);
+  const int lane_index = blockIdx.x * 64 + lane;
+  const bool active = lane_index < n_states;
+  int s = 0, n = SHARED ? n_max : 0;
+  int64_t link0 = 0, dof0 = 0;
+  if (active) {
+    s = SHARED ? lane_index : state_of(lane_index, order);
+    if (SHARED) {
+      dof0 = (int64_t)s * n_max;
+    } else {
+      link0 = link_ptr[s];
+      n = link_ptr[s + 1] - (int)link0;
+      dof0 = link0;
+    }
+  }
+  const T* tab = table + link0 * kLinkWords;
+  const double* wtab = wtable + link0 * kLinkWords;
+  const SPtr<const T> qs(q + dof0);
+  if (role == 1) {
+    if (active) split_pose_fwd(n, tab, qs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
+    return;
+  }
+  if (!active) return;
+  Boundary<T> bd = boundary_of(ba);
+  if (tip) {
+    const T* t = tip + 6 * (int64_t)s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  }
+  JointIO<T> io{qs, SPtr<const T>(qd + dof0), SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0),
+                SPtr<T>()};
+  const Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeID>::value, status};
+  dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, scr, StoreQdd<T>{SPtr<T>()},
+                                 RingTakeF<T>{ring, &ready, &used, lane});
+}
+
 // ---- adjoints ------------------------------------------------------------------
 //
 // One lane per state as above. With a shared chain each lane writes its
@@ -781,6 +834,19 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   const int variant = pick_variant(b, true);
+  if (MODE == kModeID && variant == 2) {
+    const unsigned g = (unsigned)((b->n_states + 63) / 64);
+    if (m->n_chains == 1)
+      hipLaunchKernelGGL((k_id_split<T, true>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
+                         m->order, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+                         scratch, status);
+    else
+      hipLaunchKernelGGL((k_id_split<T, false>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
+                         m->order, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+                         scratch, status);
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
   if ((MODE & kModeFD) && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;

@@ -176,7 +176,7 @@ def test_launch_shapes_orders_and_persistence_are_bitwise_identical(device):
     ch = synth.make_chains(list(np.random.default_rng(4).integers(1, 60, 300)), 4)
     st = synth.make_states((ch.n_links_total,), 4)
     model = api.Model(ch, device, torch.float32)
-    for op in (api.OP_ABA_FD, api.OP_ID_FD):
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
         api.set_launch(op, 0, 0, 1)
     ref = run_all(model, st, device, torch.float32)
     for bt, cap, use_order in ((128, 0, True), (256, 1, True), (64, 2, False), (192, 0, False)):
@@ -223,7 +223,7 @@ def test_forward_dynamics_variants(device, variant):
     """Both kernel variants (one wavefront per 64 states; role split) against the oracle:
     the 32-link workload at 16384 states, ragged chains, an odd batch and FP64 with boundary terms."""
     print(f"case: variant {variant}", flush=True)
-    for op in (api.OP_ABA_FD, api.OP_ID_FD):
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
         api.set_launch(op, 0, 0, variant)
     try:
         ch, st = synth.workload_32link(16384)
@@ -235,7 +235,7 @@ def test_forward_dynamics_variants(device, variant):
         eq = rel_rows(q2, ref_q)
         print(f"variant {variant}: qdd max rel err {eq.max():.2e}", flush=True)
         assert eq.max() <= TOL32 and rel_rows(q1, ref_q).max() <= TOL32
-        assert rel_rows(t2, ref_t).max() <= TOL32
+        assert rel_rows(t2, ref_t).max() <= TOL32 and rel_rows(t1, ref_t).max() <= TOL32
         ch = synth.make_chains(list(np.random.default_rng(5).integers(1, 70, 333)), 5)
         st = synth.make_states((ch.n_links_total,), 5)
         model = api.Model(ch, device, torch.float32)
@@ -245,6 +245,7 @@ def test_forward_dynamics_variants(device, variant):
         eq = rel_ragged(q2, oracle.aba(cr, sr.q, sr.qd, sr.tau), ch.link_ptr)
         assert eq[lens <= 32].max() <= TOL32 and eq.max() <= 1e-2
         assert np.array_equal(q1, q2)
+        assert rel_ragged(t1, oracle.rnea(cr, sr.q, sr.qd, sr.qdd), ch.link_ptr).max() <= TOL32
         ch = synth.make_chains([11], 31)
         st = synth.make_states((70, 11), 31)
         rng = np.random.default_rng(31)
@@ -257,10 +258,11 @@ def test_forward_dynamics_variants(device, variant):
             rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], np.array(V0), np.array(dV0), tip[s])
             rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], np.array(V0), np.array(dV0), tip[s])
             assert np.linalg.norm(t2[s] - rt) <= 1e-12 * np.linalg.norm(rt)
+            assert np.linalg.norm(t1[s] - rt) <= 1e-12 * np.linalg.norm(rt)
             assert np.linalg.norm(q1[s] - rq) <= 1e-11 * np.linalg.norm(rq)
             assert np.linalg.norm(q2[s] - rq) <= 1e-11 * np.linalg.norm(rq)
     finally:
-        for op in (api.OP_ABA_FD, api.OP_ID_FD):
+        for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
             api.set_launch(op, 0, 0, 0)
 
 
