@@ -481,7 +481,13 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // workgroup barrier X forms the inertia-parameter cotangents and Y runs the
 // tip-to-base adjoint sweep. Scratch: Y's [n_max][kVjpWords][n_states], X's
 // [n_max][kVjpXWords][n_states].
-template <class T, int OP, int PI, bool SHARED>
+//
+// OVERLAP (ID adjoint, when the wrenches fit in LDS): X's Fbar pass also hands
+// its transforms to Y's Newton-Euler pass through an LDS ring; after the
+// barrier X runs the wrench sweep, writing F_i to LDS with a progress word,
+// and Y's adjoint sweep follows it link by link. X then forms the
+// inertia-parameter cotangents.
+template <class T, int OP, int PI, bool SHARED, bool OVERLAP>
 __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                    const int32_t* __restrict__ order, const T* __restrict__ table,
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
@@ -489,8 +495,20 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
                                                    T* tau_bar, T* pi_out, const T* __restrict__ tip,
                                                    BoundaryArgs<T> ba, T* scratch, T* xscratch,
                                                    unsigned* status) {
+  constexpr bool kOv = OVERLAP && OP == kVjpID;  // the hand-offs exist for the ID adjoint only
+  extern __shared__ __align__(16) unsigned char lds_vjp[];  // kOv: ring, then F [n_max][6][64]
+  __shared__ int ready, used, fprog;
+  if (kOv) {
+    if (threadIdx.x == 0) {
+      ready = 0;
+      used = 0;
+      fprog = 0;
+    }
+    __syncthreads();
+  }
   const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y
-  const int lane_index = blockIdx.x * 64 + (int)(threadIdx.x % 64);
+  const int lane = (int)(threadIdx.x % 64);
+  const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
   int s = 0, n = SHARED ? n_max : 0;
   int64_t link0 = 0, dof0 = 0;
@@ -514,19 +532,27 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
   const Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords, status};
   const Scratch<T> xs{xscratch + lane_index, (long)n_states, kVjpXWords, status};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0), qdds(qdd + dof0), bar(bar_in + dof0);
+  T* const ring = reinterpret_cast<T*>(lds_vjp);
+  const Scratch<T> fl{ring + (long)kPoseSlots * kPoseWordsF * 64 + lane, 64L, 6, status};
   if (active) {
     if (role == 0) {
-      if (OP == kVjpID)
+      if (kOv)
+        vjp_fbar_pass(n, tab, qs, bar, T(1), xs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
+      else if (OP == kVjpID)
         vjp_fbar_pass(n, tab, qs, bar, T(1), xs);
       else
         fdvjp_solve_pass(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs);
     } else {
-      vjp_newton_euler_pass(n, tab, wtab, qs, qds, qdds, bd, scr);
+      if (kOv)
+        vjp_ne_forward(n, tab, qs, qds, qdds, bd, scr, RingTakeF<T>{ring, &ready, &used, lane});
+      else
+        vjp_newton_euler_pass(n, tab, wtab, qs, qds, qdds, bd, scr);
     }
   }
   __syncthreads();
   if (!active) return;
   if (role == 0) {
+    if (kOv) vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
     if (PI != kPiNone) {
       PiSink<T, PI> sink;
       sink.out = (PI == kPiLanes) ? pi_out + lane_index : pi_out + link0 * 10;
@@ -534,8 +560,12 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
       vjp_inertia_pass(n, tab, xs, scr, sink);
     }
   } else {
-    vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0),
-                  OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>());
+    const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>();
+    if (kOv)
+      vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, fl,
+                    LdsWait{&fprog});
+    else
+      vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, scr);
   }
 }
 
@@ -1044,12 +1074,25 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   const bool split = pick_variant(b, false) == 2;
   const unsigned grid64 = (unsigned)((b->n_states + 63) / 64);
   T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
+  // ID adjoint: the wrenches of every link in LDS, after the transform ring
+  const size_t lds = ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T);
+  const bool overlap = OP == kVjpID && lds <= max_lds_bytes();
+#define PDYN_LAUNCH_VJP_SPLIT(PI, SH, OV, PIOUT)                                                              \
+  do {                                                                                                        \
+    if (OV && lds > 65536 &&                                                                                  \
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_split<T, OP, PI, SH, OV>),                   \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)              \
+      return PDYN_ELAUNCH;                                                                                    \
+    hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH, OV>), dim3(grid64), dim3(128), OV ? lds : 0, s,            \
+                       b->n_states, m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in,   \
+                       q_bar, qd_bar, qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);           \
+  } while (0)
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
   do {                                                                                                        \
-    if (split)                                                                                                \
-      hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH>), dim3(grid64), dim3(128), 0, s, b->n_states,            \
-                         m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
-                         qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);                        \
+    if (split && overlap)                                                                                     \
+      PDYN_LAUNCH_VJP_SPLIT(PI, SH, true, PIOUT);                                                             \
+    else if (split)                                                                                           \
+      PDYN_LAUNCH_VJP_SPLIT(PI, SH, false, PIOUT);                                                            \
     else                                                                                                      \
       hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
                          m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
@@ -1068,6 +1111,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
     PDYN_LAUNCH_VJP(kPiDirect, false, inertia_bar);
   }
 #undef PDYN_LAUNCH_VJP
+#undef PDYN_LAUNCH_VJP_SPLIT
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }

@@ -924,9 +924,15 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
 // kVjpXWords: U then Fbar [0..5], 1/D [6], c-hat [7], (sin, cos) [8, 9].
 constexpr int kVjpXWords = 10;
 
-// X, ID adjoint: Fbar_i = X_i Fbar_{i-1} + sgn tb_i S_i (base to tip).
-template <class T>
-PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> tb, T sgn, const Scratch<T>& xs) {
+// X, ID adjoint: Fbar_i = X_i Fbar_{i-1} + sgn tb_i S_i (base to tip). Each
+// joint transform and its (sin, cos) also go to put(i, pose, sin, cos), which
+// may hand them to the Newton-Euler pass of another wavefront.
+struct NoPut {
+  template <class P, class T> PD_HD void operator()(int, const P&, T, T) const {}
+};
+template <class T, class Put = NoPut>
+PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> tb, T sgn, const Scratch<T>& xs,
+                         const Put& put = Put()) {
   struct In {
     T q, tb;
   };
@@ -935,7 +941,11 @@ PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> t
       n, 0, 1, [&](int i) { return In{q[i], tb[i]}; },
       [&](int i, const In& x) {
         const Link<T> L = load_link(table + (long)i * kLinkWords);
-        Fb = X_twist(joint_transform(L, x.q), Fb) + (sgn * x.tb) * L.S;
+        T sn, cs;
+        joint_sincos(L, x.q, &sn, &cs);
+        const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
+        put(i, g, sn, cs);
+        Fb = X_twist(g, Fb) + (sgn * x.tb) * L.S;
         xs.put(i, 0, Fb);
       });
 }
@@ -1013,47 +1023,60 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
   }
 }
 
-// Y: sweep 1 of ID at (q, qd, qdd) keeping Fhat, V, A and (sin, cos), then the
-// wrench sweep (tip to base, in double) leaving F_i in slot 0.
+// Y: sweep 1 of ID at (q, qd, qdd) keeping Fhat, V, A and (sin, cos); the
+// transforms come from pose (formed here by default).
+template <class T, class PoseSrc = FormPose<T>>
+PD_HD void vjp_ne_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
+                          const Boundary<T>& bd, const Scratch<T>& scr, const PoseSrc& pose = PoseSrc()) {
+  struct In {
+    T q, qd, qdd;
+  };
+  Sp<T> V = bd.V0, A = bd.dV0;
+  pipelined(
+      n, 0, 1, [&](int i) { return In{q[i], qd[i], qdd[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        T sn, cs;
+        Pose<T> g;
+        pose(i, L, x.q, &g, &sn, &cs);
+        scr.at(i, kVjpSC) = sn;
+        scr.at(i, kVjpSC + 1) = cs;
+        vjp_forward_fhat(i, L, g, x.qd, x.qdd, V, A, scr);
+        scr.put(i, 6, V);
+        scr.put(i, 12, A);
+      });
+}
+
+// The wrench sweep (tip to base, in double) from the Fhat and (sin, cos) that
+// vjp_ne_forward left in scr, writing F_i to fout (component 0) and reporting
+// done(k) once the k-th link from the tip is written.
+template <class T, class Done = NoHandoff>
+PD_HD void vjp_wrench_pass(int n, const double* wtable, SPtr<const T> q, const Boundary<T>& bd, const Scratch<T>& scr,
+                           const Scratch<T>& fout, const Done& done = Done()) {
+  struct In {
+    Sp<T> fh;
+    T sn, cs, q;
+  };
+  Sp<double> F = cast_sp<double>(bd.Ftip);
+  Pose<double> gcw;
+  pipelined(
+      n, n - 1, -1, [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
+      [&](int i, const In& x) {
+        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        if (i < n - 1) F = XT_wrench(gcw, F);
+        F = F + cast_sp<double>(x.fh);
+        fout.put(i, 0, cast_sp<T>(F));
+        done(n - i);
+        gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
+      });
+}
+
+// Y: sweep 1 of ID, then the wrench sweep leaving F_i in slot 0.
 template <class T>
 PD_HD void vjp_newton_euler_pass(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> qd,
                                  SPtr<const T> qdd, const Boundary<T>& bd, const Scratch<T>& scr) {
-  {
-    struct In {
-      T q, qd, qdd;
-    };
-    Sp<T> V = bd.V0, A = bd.dV0;
-    pipelined(
-        n, 0, 1, [&](int i) { return In{q[i], qd[i], qdd[i]}; },
-        [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
-          T sn, cs;
-          joint_sincos(L, x.q, &sn, &cs);
-          scr.at(i, kVjpSC) = sn;
-          scr.at(i, kVjpSC + 1) = cs;
-          vjp_forward_fhat(i, L, joint_transform_sc(L, x.q, sn, cs), x.qd, x.qdd, V, A, scr);
-          scr.put(i, 6, V);
-          scr.put(i, 12, A);
-        });
-  }
-  {
-    struct In {
-      Sp<T> fh;
-      T sn, cs, q;
-    };
-    Sp<double> F = cast_sp<double>(bd.Ftip);
-    Pose<double> gcw;
-    pipelined(
-        n, n - 1, -1,
-        [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
-        [&](int i, const In& x) {
-          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
-          if (i < n - 1) F = XT_wrench(gcw, F);
-          F = F + cast_sp<double>(x.fh);
-          scr.put(i, 0, cast_sp<T>(F));
-          gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
-        });
-  }
+  vjp_ne_forward(n, table, q, qd, qdd, bd, scr);
+  vjp_wrench_pass(n, wtable, q, bd, scr, scr);
 }
 
 // X, after the barrier: inertia-parameter cotangents of every link (pointwise).
@@ -1076,10 +1099,12 @@ PD_HD void vjp_inertia_pass(int n, const T* table, const Scratch<T>& xs, const S
 
 // Y, after the barrier: the tip-to-base adjoint sweep (as sweep 4 of
 // id_vjp_tail, with the wrench part of q_bar formed here from Fbar and F).
-template <class T>
+// fsrc holds F_i (component 0): scr itself, or another wavefront's LDS copy,
+// in which case need(k) waits until the k-th link from the tip is there.
+template <class T, class Need = NoHandoff>
 PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
                          const Scratch<T>& xs, const Scratch<T>& scr, SPtr<T> q_bar, SPtr<T> qd_bar,
-                         SPtr<T> qdd_bar) {
+                         SPtr<T> qdd_bar, const Scratch<T>& fsrc, const Need& need = Need()) {
   struct In {
     Sp<T> Fb, F, V, A;
     T sn, cs, q, qd, qdd;
@@ -1088,7 +1113,8 @@ PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> q
   pipelined(
       n, n - 1, -1,
       [&](int i) {
-        return In{xs.get(i, 0), scr.get(i, 0), scr.get(i, 6), scr.get(i, 12), scr.at(i, kVjpSC),
+        need(n - i);
+        return In{xs.get(i, 0), fsrc.get(i, 0), scr.get(i, 6), scr.get(i, 12), scr.at(i, kVjpSC),
                   scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i]};
       },
       [&](int i, const In& x) {

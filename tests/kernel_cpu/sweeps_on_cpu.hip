@@ -150,11 +150,33 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
     else {
       // ops 2 (ID) and 3 (FD): the role-split passes of k_vjp_split, in an order their hand-offs allow
       const Scratch<T> xs{xscratch.data() + s, (long)n_states, kVjpXWords};
+      if (op == 4) {
+        // ID adjoint with the hand-offs of the overlapped kernel: X's transforms feed Y's Newton-Euler
+        // pass, X's wrench sweep writes F to its own array, Y's adjoint sweep reads it there
+        struct Entry {
+          Pose<T> g;
+          T sn, cs;
+        };
+        std::vector<Entry> poses((size_t)n);
+        std::vector<T> fbuf((size_t)n * 6);
+        const Scratch<T> fl{fbuf.data(), 1, 6};
+        vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs,
+                      [&](int i, const Pose<T>& g, T sn, T cs) { poses[(size_t)i] = Entry{g, sn, cs}; });
+        vjp_ne_forward(n, tab, io.q, io.qd, io.qdd, bd, scr, [&](int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) {
+          *g = poses[(size_t)i].g;
+          *sn = poses[(size_t)i].sn;
+          *cs = poses[(size_t)i].cs;
+        });
+        vjp_wrench_pass(n, wtab, io.q, bd, scr, fl);
+        vjp_inertia_pass(n, tab, xs, scr, sink);
+        vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, io.qdd_bar, fl);
+        continue;
+      }
       if (op == 2) vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
       else fdvjp_solve_pass(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs);
       vjp_newton_euler_pass(n, tab, wtab, io.q, io.qd, io.qdd, bd, scr);
       vjp_inertia_pass(n, tab, xs, scr, sink);
-      vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, op == 2 ? io.qdd_bar : SPtr<T>());
+      vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, op == 2 ? io.qdd_bar : SPtr<T>(), scr);
     }
   }
   return 0;

@@ -210,6 +210,12 @@ def test_role_split_adjoint_passes_match_the_fused_adjoints(cpu_lib):
         for x, y in zip(a, b):
             assert np.abs(x - y).max() <= 1e-11 * (np.abs(x).max() + 1e-300)
         assert np.abs(pa - pb).max() <= 1e-11 * np.abs(pa).max()
+    # the ID adjoint with the overlapped kernel's hand-offs gives the same bits as the role split
+    a, pa = run_vjp_cpu(cpu_lib, 2, ch, st.q, st.qd, st.qdd, bar, np.float64)
+    b, pb = run_vjp_cpu(cpu_lib, 4, ch, st.q, st.qd, st.qdd, bar, np.float64)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(pa, pb)
     (qb, qdb, _, tb), pib = run_vjp_cpu(cpu_lib, 3, ch, st.q, st.qd, qdd_fd, bar, np.float64)
     for c in range(ch.n_chains):
         lo, hi = ch.link_ptr[c], ch.link_ptr[c + 1]
