@@ -252,7 +252,7 @@ template <class T> struct RingGetB {
   }
 };
 
-template <class T, int MODE, bool SHARED, bool OVERLAP>
+template <class T, int MODE, bool SHARED, int LDSMODE>
 __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
                                                         const T* __restrict__ table,
@@ -260,7 +260,13 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
                                                         const T* __restrict__ tip, BoundaryArgs<T> ba, T* scr_id,
                                                         T* scr_bias, T* scr_abi, unsigned* status) {
-  // with OVERLAP: [link][kAbiWords][64 lanes], then the transform ring
+  // LDSMODE: 0 no LDS hand-off (barrier); 1 U_i, 1/D_i in LDS and the
+  // transform wavefronts with their rings; 2 U_i alone in LDS (B2 forms 1/D_i,
+  // so that longer chains fit). LDS: [link][kAbiLds][64 lanes], then (mode 1)
+  // the two rings.
+  constexpr bool OVERLAP = LDSMODE != 0;
+  constexpr bool kRings = LDSMODE == 1;
+  constexpr int kAbiLds = kRings ? kAbiWords : 6;
   extern __shared__ __align__(16) unsigned char lds_abi[];
   __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a;
   if (OVERLAP) {
@@ -274,11 +280,11 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
     }
     __syncthreads();
   }
-  // roles: 0 articulated inertia (A), 1 bias passes (B), then with OVERLAP
+  // roles: 0 articulated inertia (A), 1 bias passes (B), then with the rings
   // 2 transforms base to tip (P_f), 3 transforms tip to base (P_b) and
   // 4 inverse dynamics, else 2 inverse dynamics
   constexpr bool kWithID = MODE == kModeIDFD;
-  constexpr int kRoleID = OVERLAP ? 4 : 2;
+  constexpr int kRoleID = kRings ? 4 : 2;
   const int role = threadIdx.x / 64;  // wave-uniform
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
@@ -303,18 +309,18 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
     const T* t = tip + 6 * (int64_t)s;
     bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
   }
-  const Scratch<T> abi = OVERLAP ? Scratch<T>{reinterpret_cast<T*>(lds_abi) + lane, 64L, kAbiWords, status}
+  const Scratch<T> abi = OVERLAP ? Scratch<T>{reinterpret_cast<T*>(lds_abi) + lane, 64L, kAbiLds, status}
                                  : Scratch<T>{scr_abi + lane_index, (long)n_states, kAbiWords, status};
   const Scratch<T> bias{scr_bias + lane_index, (long)n_states, kBiasWords, status};
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
-  T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiWords * 64;
+  T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiLds * 64;
   T* const ring_b = ring_f + (long)kPoseSlots * kPoseWordsF * 64;
-  if (OVERLAP && role == 2) {
+  if (kRings && role == 2) {
     if (active)
       split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_f, &used_b, kWithID ? &used_id : nullptr, lane});
     return;
   }
-  if (OVERLAP && role == 3) {
+  if (kRings && role == 3) {
     if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane});
     return;
   }
@@ -323,7 +329,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
     if (active) {
       JointIO<T> io{qs, qds, SPtr<const T>(qdd_in + dof0), SPtr<const T>(), SPtr<T>(tau_out + dof0), SPtr<T>()};
       const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value, status};
-      if (OVERLAP)
+      if (kRings)
         dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr, StoreQdd<T>{SPtr<T>()},
                                        RingTakeF<T>{ring_f, &ready_f, &used_id, lane});
       else
@@ -333,13 +339,15 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   }
   if (active) {
     if (role == 0) {
-      if (OVERLAP)
+      if (kRings)
         split_abi_from_poses(n, tab, abi, RingGetB<T>{ring_b, &ready_b, lane}, LdsProgress{&used_a},
                              LdsProgress{&progress});
+      else if (OVERLAP)
+        split_abi_pass(n, tab, wtab, qs, abi, LdsProgress{&progress});
       else
         split_abi_pass(n, tab, wtab, qs, abi);
     } else {
-      if (OVERLAP)
+      if (kRings)
         split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane});
       else
         split_bias_forward(n, tab, qs, qds, bd, bias);
@@ -884,25 +892,33 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
                                        align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
     T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
-    const size_t lds = (nm * kAbiWords + (size_t)kPoseSlots * (kPoseWordsF + kPoseWordsB)) * 64 * sizeof(T);
-    const bool overlap = lds <= max_lds_bytes();
+    // LDS hand-off of U_i with the transform rings if they fit, else of U_i alone, else none
+    const size_t lds_rings = (nm * kAbiWords + (size_t)kPoseSlots * (kPoseWordsF + kPoseWordsB)) * 64 * sizeof(T);
+    const size_t lds_abi = nm * 6 * 64 * sizeof(T);
+    const int ldsmode = lds_rings <= max_lds_bytes() ? 1 : (lds_abi <= max_lds_bytes() ? 2 : 0);
+    const size_t lds = ldsmode == 1 ? lds_rings : (ldsmode == 2 ? lds_abi : 0);
     const bool shared = m->n_chains == 1;
-    // wavefronts: A, B, [P_f and P_b with overlap], [ID for ID+FD]
-    const unsigned blk = 128 + (overlap ? 128 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
-#define PDYN_LAUNCH_SPLIT(SH, OV)                                                                                 \
+    // wavefronts: A, B, [P_f and P_b with the rings], [ID for ID+FD]
+    const unsigned blk = 128 + (ldsmode == 1 ? 128 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
+#define PDYN_LAUNCH_SPLIT(SH, LM)                                                                                 \
   do {                                                                                                            \
-    if (OV && lds > 65536 &&                                                                                      \
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dynamics_split<T, MODE, SH, OV>),                    \
+    if (lds > 65536 &&                                                                                            \
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dynamics_split<T, MODE, SH, LM>),                    \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)                  \
       return PDYN_ELAUNCH;                                                                                        \
-    hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, OV>), dim3(g), dim3(blk), OV ? lds : 0, s, b->n_states,     \
+    hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, LM>), dim3(g), dim3(blk), lds, s, b->n_states,              \
                        m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
                        qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi, status);     \
   } while (0)
-    if (shared && overlap) PDYN_LAUNCH_SPLIT(true, true);
-    else if (shared) PDYN_LAUNCH_SPLIT(true, false);
-    else if (overlap) PDYN_LAUNCH_SPLIT(false, true);
-    else PDYN_LAUNCH_SPLIT(false, false);
+    if (shared) {
+      if (ldsmode == 1) PDYN_LAUNCH_SPLIT(true, 1);
+      else if (ldsmode == 2) PDYN_LAUNCH_SPLIT(true, 2);
+      else PDYN_LAUNCH_SPLIT(true, 0);
+    } else {
+      if (ldsmode == 1) PDYN_LAUNCH_SPLIT(false, 1);
+      else if (ldsmode == 2) PDYN_LAUNCH_SPLIT(false, 2);
+      else PDYN_LAUNCH_SPLIT(false, 0);
+    }
 #undef PDYN_LAUNCH_SPLIT
     if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
     return PDYN_OK;

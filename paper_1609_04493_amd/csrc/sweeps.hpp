@@ -448,7 +448,9 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
 // serial piece, which depends on q only -- runs beside the Newton-Euler passes
 // instead of after them. Hand-offs go through per-state scratch:
 //   abi:   [link][7]  U_i (6), 1/D_i                    (pass A  ->  pass B2, C)
-//   bias:  [link][10] Fhat_bias (6), c-hat (1), pad, sin, cos  (B1 -> B2 -> C)
+//          or [link][6] U_i only (a view with words == 6, e.g. in LDS): B2
+//          then forms 1/D_i itself and keeps it in bias slot 7 for C
+//   bias:  [link][10] Fhat_bias (6), c-hat (1), 1/D (or unused), sin, cos  (B1 -> B2 -> C)
 // ============================================================================
 
 constexpr int kAbiWords = 7;
@@ -490,7 +492,7 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
         const T invD = T(1) / D;
         JA = sym6_minus_outer(Jh, U, invD);
         abi.put(i, 0, U);
-        abi.at(i, 6) = invD;
+        if (abi.words > 6) abi.at(i, 6) = invD;
         done(n - i);
         gc = cast_pose<T>(joint_transform_wide(Lw, L, qi));
       });
@@ -552,7 +554,7 @@ PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, co
         const T invD = T(1) / D;
         JA = sym6_minus_outer(Jh, U, invD);
         abi.put(i, 0, U);
-        abi.at(i, 6) = invD;
+        if (abi.words > 6) abi.at(i, 6) = invD;
         done(n - i);
       });
 }
@@ -602,7 +604,7 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
         x.cs = bias.at(i, 9);
         need(n - i);
         x.U = abi.get(i, 0);
-        x.invD = abi.at(i, 6);
+        x.invD = abi.words > 6 ? abi.at(i, 6) : T(0);
         x.q = q[i];
         x.tau = tau_in[i];
         return x;
@@ -610,6 +612,12 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
       [&](int i, const In& x) {
         const bool has_child = (i < n - 1);
         const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        T invD = x.invD;
+        if (abi.words == 6) {  // U only: form 1/D here and keep it for the lambda pass
+          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          invD = T(1) / dot(L.S, x.U);
+          bias.at(i, 7) = invD;
+        }
         Sp<double> z = sp_zero<double>();
         if (has_child) {
           Fb = XT_wrench(gcw, Fb);
@@ -617,7 +625,7 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
         }
         Fb = Fb + cast_sp<double>(x.fb);
         const double tauhat = (double)x.tau - dot(Lw.S, Fb);
-        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)x.invD;
+        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
         zA = z + chat_w * cast_sp<double>(x.U);
         bias.at(i, 6) = (T)chat_w;
         gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
@@ -638,7 +646,7 @@ PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>
       [&](int i) {
         In x;
         x.U = abi.get(i, 0);
-        x.invD = abi.at(i, 6);
+        x.invD = abi.words > 6 ? abi.at(i, 6) : bias.at(i, 7);
         x.chat = bias.at(i, 6);
         x.sn = bias.at(i, 8);
         x.cs = bias.at(i, 9);

@@ -10,6 +10,7 @@ using namespace pdyn;
 
 constexpr int kSplitFD = 5, kSplitIDFD = 7;  // FD, ID+FD through the role-split passes
 constexpr int kPoseRing = 16;                // with the transforms of B1 and ID handed in by pass P
+constexpr int kAbiUOnly = 32;                // the articulated hand-off holds U_i only (B2 forms 1/D_i)
 
 template <class T>
 static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
@@ -23,7 +24,8 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
     for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
   }
   const bool pose_ring = (mode & kPoseRing) != 0;
-  mode &= ~kPoseRing;
+  const bool abi6 = (mode & kAbiUOnly) != 0;
+  mode &= ~(kPoseRing | kAbiUOnly);
   int words = mode == kModeIDFD ? ScratchWords<kModeIDFD>::value : (mode == kModeFD ? ScratchWords<kModeFD>::value : ScratchWords<kModeID>::value);
   if (mode == kSplitFD || mode == kSplitIDFD) words = ScratchWords<kModeID>::value;
   std::vector<T> scratch((size_t)n_max * words * n_states, T(-7777));  // poisoned
@@ -48,7 +50,7 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
       // the role-split passes of k_dynamics_split, run one after another
       const T* tab = table.data() + link0 * kLinkWords;
       const double* wtab = wtable.data() + link0 * kLinkWords;
-      const Scratch<T> abi{abi_scr.data() + s, (long)n_states, kAbiWords};
+      const Scratch<T> abi{abi_scr.data() + s, (long)n_states, abi6 ? 6 : kAbiWords};
       const Scratch<T> bias{bias_scr.data() + s, (long)n_states, kBiasWords};
       // pass P's transforms through a plain array (the kernel uses an LDS ring)
       struct Entry {

@@ -295,3 +295,36 @@ def test_status_word_reports_numerical_faults(device):
         assert ws.read_status() & api.STATUS_PIVOT, variant
     for op in (api.OP_ABA_FD, api.OP_ID_FD, api.OP_ABA_FD_VJP, api.OP_RNEA_ID_VJP):
         api.set_launch(op, 0, 0, 0)
+
+
+@pytest.mark.parametrize("n,B,dtype", [(20, 300, torch.float32), (90, 300, torch.float32), (120, 200, torch.float32),
+                                        (30, 100, torch.float64)])
+def test_role_split_lds_modes(device, n, B, dtype):
+    """The role-split kernel's three hand-off modes, chosen by chain length: U_i in LDS with the transform
+    rings (FP32 up to 61 links), U_i alone in LDS (FP32 up to ~106 links, FP64 up to ~53), and the barrier
+    (longer chains). FD and ID+FD against the oracle."""
+    print(f"case: lds modes n={n} B={B} {dtype}", flush=True)
+    for op in (api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, 2)
+    try:
+        ch = synth.make_chains([n], 60 + n)
+        st = synth.make_states((B, n), 60 + n)
+        model = api.Model(ch, device, dtype)
+        d = lambda a: to_dev(a, device, dtype)
+        q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+        q1 = api.aba_fd(model, q, qd, tau).cpu().numpy()
+        t2, q2 = (x.cpu().numpy() for x in api.id_fd(model, q, qd, qdd, tau))
+        if dtype == torch.float64:
+            ref_q, ref_t = oracle.aba(ch, st.q, st.qd, st.tau), oracle.rnea(ch, st.q, st.qd, st.qdd)
+            tol_q, tol_t = 1e-9, 1e-12
+        else:
+            cr, sr = ch.rounded(), st.rounded()
+            ref_q, ref_t = oracle.aba(cr, sr.q, sr.qd, sr.tau), oracle.rnea(cr, sr.q, sr.qd, sr.qdd)
+            tol_q, tol_t = (TOL32 if n <= 32 else 1e-2), TOL32
+        eq = rel_rows(q1, ref_q)
+        print(f"n={n}: qdd max rel err {eq.max():.2e}", flush=True)
+        assert eq.max() <= tol_q and rel_rows(q2, ref_q).max() <= tol_q
+        assert rel_rows(t2, ref_t).max() <= tol_t
+    finally:
+        for op in (api.OP_ABA_FD, api.OP_ID_FD):
+            api.set_launch(op, 0, 0, 0)

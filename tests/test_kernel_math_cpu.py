@@ -21,6 +21,7 @@ SRC = os.path.join(HERE, "kernel_cpu", "sweeps_on_cpu.hip")
 MODE_ID, MODE_FD, MODE_IDFD = 1, 2, 3
 SPLIT_FD, SPLIT_IDFD = 5, 7  # the role-split passes (articulated inertia beside the Newton-Euler passes)
 POSE_RING = 16  # flag: B1 and the inverse dynamics take their transforms from pass P
+ABI_U_ONLY = 32  # flag: the articulated hand-off holds U_i only; B2 forms 1/D_i
 
 
 @pytest.fixture(scope="module")
@@ -127,6 +128,9 @@ def test_role_split_passes_match_oracle(cpu_lib):
         assert np.array_equal(q2, qdd)
         if mode == SPLIT_IDFD:
             assert np.array_equal(t2, tau)
+        # U_i alone handed over (1/D_i formed again by B2): the same up to rounding
+        _, q3 = run_cpu(cpu_lib, mode | POSE_RING | ABI_U_ONLY, ch, st, np.float64, tip, V0, dV0)
+        assert np.abs(q3 - qdd).max() <= 1e-12 * np.abs(qdd).max()
     for s in range(16):
         rt = oracle.rnea1(ch, st.q[s], st.qd[s], st.qdd[s], V0, dV0, tip[s])
         rq = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s])
@@ -143,6 +147,8 @@ def test_role_split_passes_match_oracle(cpu_lib):
     assert np.array_equal(q2, qdd)
     ch, st = synth.workload_32link(256)
     _, q2 = run_cpu(cpu_lib, SPLIT_FD | POSE_RING, ch.astype(np.float32), st.astype(np.float32), np.float32)
+    _, q3 = run_cpu(cpu_lib, SPLIT_FD | ABI_U_ONLY, ch.astype(np.float32), st.astype(np.float32), np.float32)
+    assert rel_err_rows(q3, oracle.aba(ch.rounded(), st.rounded().q, st.rounded().qd, st.rounded().tau)).max() <= 1e-4
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch.astype(np.float32), st.astype(np.float32), np.float32)
     assert np.array_equal(q2, qdd)
     cr, sr = ch.rounded(), st.rounded()
