@@ -268,6 +268,18 @@ def main():
         print(f"variant {v}: {variants[v]}", file=sys.stderr, flush=True)
     api.set_launch(api.OP_ID_FD, 0, 0, 0)
     api.set_launch(api.OP_ABA_FD, 0, 0, 0)
+    # the plain form: one launch per recursion sweep, intermediates in HBM, no graph
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, 3)
+    per_sweep = {
+        "id_us": 1e3 * time_steps(lambda: api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws), args.steps,
+                                  args.warmup, stream),
+        "fd_us": 1e3 * time_steps(lambda: api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws), args.steps,
+                                  args.warmup, stream),
+        "id_fd_us": 1e3 * time_steps(fused, args.steps, args.warmup, stream)}
+    print(f"one launch per sweep: {per_sweep}", file=sys.stderr, flush=True)
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, 0)
     ms_plain = time_steps(plain, args.steps, args.warmup, stream)
     print(f"separate ID, FD calls: {ms_plain * 1e3:.1f} us/step", file=sys.stderr, flush=True)
     ms_id = time_steps(lambda: api.rnea_id(model, q, qd, qdd, out=tau_out, workspace=ws), args.steps, args.warmup, stream)
@@ -376,7 +388,11 @@ def main():
                      "kernel": "k_dynamics_split<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
                      "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
         "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
-                            "2": dict(variants[2], form="articulated-inertia pass on its own wavefront")},
+                            "2": dict(variants[2], form="role split across wavefronts with LDS hand-offs"),
+                            "3": dict(per_sweep, form="plain: one launch per recursion sweep, HBM intermediates")},
+        "fused_over_plain_per_sweep": {"id": per_sweep["id_us"] / (ms_id * 1e3),
+                                       "fd": per_sweep["fd_us"] / (ms_fd * 1e3),
+                                       "id_fd": per_sweep["id_fd_us"] / (ms_fused * 1e3)},
         "plain": {"form": "separate pdyn_rnea_id + pdyn_aba_fd calls", "value": N_STATES / (ms_plain * 1e-3),
                   "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
         "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),

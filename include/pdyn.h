@@ -117,9 +117,12 @@ typedef struct pdyn_batch {
    * wavefront per 64 states; 2 = role split -- one wavefront runs the
    * cotangent recursions (for FD first the articulated-body solve), another
    * the Newton-Euler sweeps, then the inertia-parameter terms and the
-   * tip-to-base adjoint sweep run side by side. block_threads and max_blocks
-   * apply to variant 1 only. Every variant gives the same results to
-   * rounding. */
+   * tip-to-base adjoint sweep run side by side. 3 (forward operations; the
+   * adjoints take it as 1) = the plain form: the sweeps of variant 1 as
+   * separate launches, one per recursion sweep, with the per-link
+   * intermediates in the workspace (HBM) between them. block_threads and
+   * max_blocks apply to variants 1 and 3. Every variant gives the same
+   * results to rounding. */
   int32_t variant;
 } pdyn_batch;
 

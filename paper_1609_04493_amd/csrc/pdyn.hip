@@ -67,7 +67,7 @@ __device__ __forceinline__ int state_of(int lane_index, const int32_t* __restric
 
 // SHARED: one chain shared by every state, known at compile time, so that the
 // link records are read with wave-uniform (scalar) loads.
-template <class T, int MODE, bool SHARED>
+template <class T, int MODE, bool SHARED, int SWEEPS = kAllSweeps>
 __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chains, int n_max,
                                                         const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
@@ -110,7 +110,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
     }
     // scratch column = lane: consecutive lanes touch consecutive words
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value, status};
-    dynamics_one_state<T, MODE>(n, table + link0 * kLinkWords, wtable + link0 * kLinkWords, io, bd, scr);
+    dynamics_one_state<T, MODE, StoreQdd<T>, FormPose<T>, SWEEPS>(n, table + link0 * kLinkWords,
+                                                                  wtable + link0 * kLinkWords, io, bd, scr,
+                                                                  StoreQdd<T>{io.qdd_out});
   }
 }
 
@@ -724,7 +726,7 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (m->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
   if (b->block_threads < 0 || b->block_threads % 64 != 0 || b->block_threads > kMaxBlock) return PDYN_EINVAL;
   if (b->max_blocks < 0) return PDYN_EINVAL;
-  if (b->variant < 0 || b->variant > 2) return PDYN_EINVAL;
+  if (b->variant < 0 || b->variant > 3) return PDYN_EINVAL;
   if (m->order && (m->n_chains == 1 || (uintptr_t)m->order % sizeof(int32_t) != 0)) return PDYN_EINVAL;
   if (m->n_chains == 1) {
     if (m->n_links_total != m->n_links_max) return PDYN_EINVAL;
@@ -820,7 +822,7 @@ int cu_count() {
 }
 
 int pick_variant(const pdyn_batch* b, bool forward) {
-  if (b->variant) return b->variant;
+  if (b->variant) return (!forward && b->variant == 3) ? 1 : b->variant;
   if (!forward) return 2;
   return (int64_t)b->n_states <= (int64_t)128 * cu_count() ? 2 : 1;
 }
@@ -925,6 +927,25 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   }
   unsigned grid, block;
   launch_shape(b, &grid, &block);
+  if (variant == 3) {
+    // the plain form: one launch per sweep, per-link intermediates in the (HBM) scratch between them
+#define PDYN_LAUNCH_SWEEP(SH, SW)                                                                                 \
+  hipLaunchKernelGGL((k_dynamics<T, MODE, SH, SW>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,       \
+                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, \
+                     static_cast<const T*>(b->tip_wrench), ba, scratch, status)
+    if (m->n_chains == 1) {
+      PDYN_LAUNCH_SWEEP(true, kSweep1);
+      PDYN_LAUNCH_SWEEP(true, kSweep2);
+      if (MODE & kModeFD) PDYN_LAUNCH_SWEEP(true, kSweep3);
+    } else {
+      PDYN_LAUNCH_SWEEP(false, kSweep1);
+      PDYN_LAUNCH_SWEEP(false, kSweep2);
+      if (MODE & kModeFD) PDYN_LAUNCH_SWEEP(false, kSweep3);
+    }
+#undef PDYN_LAUNCH_SWEEP
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
   if (m->n_chains == 1)
     hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
                        m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,

@@ -283,7 +283,11 @@ template <class T> struct FormPose {
 // (tau_out), FD (qdd_out) or both. Each qdd_i is handed to epi(i, qdd_i) as
 // soon as the last sweep produces it (after the last read of q_i), so a caller
 // can fold an integrator update into the pass.
-template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>>
+// SWEEPS selects which of the three sweeps run (bit k for sweep k + 1), so that
+// a caller can run them as separate launches with the scratch in between.
+enum : int { kSweep1 = 1, kSweep2 = 2, kSweep3 = 4, kAllSweeps = 7 };
+
+template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>, int SWEEPS = kAllSweeps>
 PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
                               const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi,
                               const PoseSrc& pose = PoseSrc()) {
@@ -296,7 +300,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   // are loaded while the current link computes.
 
   // ---- sweep 1: base to tip
-  {
+  if (SWEEPS & kSweep1) {
     struct In {
       T q, qd, qdd;
     };
@@ -334,7 +338,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   }
 
   // ---- sweep 2: tip to base
-  {
+  if (SWEEPS & kSweep2) {
     struct In {
       Sp<T> fh, fb;
       T sn, cs, q, tau;
@@ -405,7 +409,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   }
 
   // ---- sweep 3: base to tip
-  if (kFD) {
+  if (kFD && (SWEEPS & kSweep3)) {
     struct In {
       Sp<T> U;
       T invD, chat, sn, cs, q;

@@ -138,6 +138,8 @@ def test_launch_shape_and_order_validation():
     assert _call_id(m, b, (p, p, p, p)) == -1
     b.block_threads, b.max_blocks = 64, -3
     assert _call_id(m, b, (p, p, p, p)) == -1
+    b.max_blocks, b.variant = 0, 4  # no such kernel variant
+    assert _call_id(m, b, (p, p, p, p)) == -1
     order = np.arange(8, dtype=np.int32)
     m.order = order.ctypes.data  # an order with a shared chain is meaningless
     b2 = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)

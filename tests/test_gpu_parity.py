@@ -218,9 +218,9 @@ def test_uneven_id_fd_in_a_captured_graph(device):
         api.rnea_id(model, q, qd, qdd)  # eager work between replays
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_forward_dynamics_variants(device, variant):
-    """Both kernel variants (one wavefront per 64 states; role split) against the oracle:
+    """The kernel variants (one wavefront per 64 states; role split; one launch per sweep) against the oracle:
     the 32-link workload at 16384 states, ragged chains, an odd batch and FP64 with boundary terms."""
     print(f"case: variant {variant}", flush=True)
     for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
