@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
     }
     // scratch column = lane: consecutive lanes touch consecutive words
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value, status};
-    dynamics_one_state<T, MODE, StoreQdd<T>, FormPose<T>, SWEEPS>(n, table + link0 * kLinkWords,
+    // one chain per state: link records differ between lanes, so they are prefetched like the other inputs
+    dynamics_one_state<T, MODE, StoreQdd<T>, FormPose<T>, SWEEPS, !SHARED>(n, table + link0 * kLinkWords,
                                                                   wtable + link0 * kLinkWords, io, bd, scr,
                                                                   StoreQdd<T>{io.qdd_out});
   }
@@ -335,7 +336,8 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
         dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr, StoreQdd<T>{SPtr<T>()},
                                        RingTakeF<T>{ring_f, &ready_f, &used_id, lane});
       else
-        dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr);
+        dynamics_one_state<T, kModeID, StoreQdd<T>, FormPose<T>, kAllSweeps, !SHARED>(n, tab, wtab, io, bd, idscr,
+                                                                                    StoreQdd<T>{SPtr<T>()});
     }
     return;
   }
@@ -345,23 +347,24 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
         split_abi_from_poses(n, tab, abi, RingGetB<T>{ring_b, &ready_b, lane}, LdsProgress{&used_a},
                              LdsProgress{&progress});
       else if (OVERLAP)
-        split_abi_pass(n, tab, wtab, qs, abi, LdsProgress{&progress});
+        split_abi_pass<T, LdsProgress, !SHARED>(n, tab, wtab, qs, abi, LdsProgress{&progress});
       else
-        split_abi_pass(n, tab, wtab, qs, abi);
+        split_abi_pass<T, NoHandoff, !SHARED>(n, tab, wtab, qs, abi);
     } else {
       if (kRings)
         split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane});
       else
-        split_bias_forward(n, tab, qs, qds, bd, bias);
+        split_bias_forward<T, FormPose<T>, !SHARED>(n, tab, qs, qds, bd, bias);
     }
   }
   if (!OVERLAP) __syncthreads();
   if (active && role == 1) {
     if (OVERLAP)
-      split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi, LdsWait{&progress});
+      split_bias_backward<T, LdsWait, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi,
+                                               LdsWait{&progress});
     else
-      split_bias_backward(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
-    split_lambda(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
+      split_bias_backward<T, NoHandoff, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
+    split_lambda<T, StoreQdd<T>, !SHARED>(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
   }
 }
 

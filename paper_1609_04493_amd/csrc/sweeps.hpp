@@ -287,7 +287,7 @@ template <class T> struct FormPose {
 // a caller can run them as separate launches with the scratch in between.
 enum : int { kSweep1 = 1, kSweep2 = 2, kSweep3 = 4, kAllSweeps = 7 };
 
-template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>, int SWEEPS = kAllSweeps>
+template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>, int SWEEPS = kAllSweeps, bool PF = false>
 PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
                               const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi,
                               const PoseSrc& pose = PoseSrc()) {
@@ -303,6 +303,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   if (SWEEPS & kSweep1) {
     struct In {
       T q, qd, qdd;
+      Link<T> L;
     };
     Sp<T> V = bd.V0, dV = bd.dV0, dVb = bd.dV0;
     pipelined(
@@ -312,10 +313,11 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.q = io.q[i];
           x.qd = io.qd[i];
           x.qdd = kID ? io.qdd_in[i] : T(0);
+          if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
           return x;
         },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
           T sn, cs;
           Pose<T> g;
           pose(i, L, x.q, &g, &sn, &cs);
@@ -342,6 +344,8 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
     struct In {
       Sp<T> fh, fb;
       T sn, cs, q, tau;
+      Link<T> L;
+      Link<double> Lw;
     };
     Sp<double> F = cast_sp<double>(bd.Ftip), Fb = F;
     Sp<double> zA = sp_zero<double>();  // z-hat_{i+1} + U_{i+1} c-hat_{i+1}
@@ -360,12 +364,16 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.sn = scr.at(i, kSC);
           x.cs = scr.at(i, kSC + 1);
           x.q = io.q[i];
+          if constexpr (PF) {
+            x.L = load_link(table + (long)i * kLinkWords);
+            x.Lw = load_link(wtable + (long)i * kLinkWords);
+          }
           return x;
         },
         [&](int i, const In& x) {
           const bool has_child = (i < n - 1);
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
-          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+          const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
           if (kID) {
             Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
             F = Fc + cast_sp<double>(x.fh);
@@ -413,6 +421,7 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
     struct In {
       Sp<T> U;
       T invD, chat, sn, cs, q;
+      Link<T> L;
     };
     Sp<T> lam = sp_zero<T>();
     pipelined(
@@ -425,10 +434,11 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.sn = scr.at(i, kSC);
           x.cs = scr.at(i, kSC + 1);
           x.q = io.q[i];
+          if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
           return x;
         },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           const Sp<T> a = X_twist(g, lam);
           const T qdd = x.chat - dot(x.U, a) * x.invD;
@@ -470,16 +480,31 @@ struct NoHandoff {
 };
 
 // Pass A (tip to base): Jhat_i, U_i = Jhat_i S_i, 1/D_i.
-template <class T, class Done = NoHandoff>
+template <class T, class Done = NoHandoff, bool PF = false>
 PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Scratch<T>& abi,
                           const Done& done = Done()) {
+  struct In {
+    T q;
+    Link<T> L;
+    Link<double> Lw;
+  };
   Sym6<T> JA;
   Pose<T> gc;
   pipelined(
-      n, n - 1, -1, [&](int i) { return q[i]; },
-      [&](int i, T qi) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
-        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+      n, n - 1, -1,
+      [&](int i) {
+        In x;
+        x.q = q[i];
+        if constexpr (PF) {
+          x.L = load_link(table + (long)i * kLinkWords);
+          x.Lw = load_link(wtable + (long)i * kLinkWords);
+        }
+        return x;
+      },
+      [&](int i, const In& x) {
+        const T qi = x.q;
+        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+        const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
         Sym6<T> Jh = sym6_from_inertia(L.J);
         if (i < n - 1) {
           const Sym6<T> P = congruence_to_parent(gc, JA);
@@ -564,17 +589,25 @@ PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, co
 }
 
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
-template <class T, class PoseSrc = FormPose<T>>
+template <class T, class PoseSrc = FormPose<T>, bool PF = false>
 PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
                               const Scratch<T>& bias, const PoseSrc& pose = PoseSrc()) {
   struct In {
     T q, qd;
+    Link<T> L;
   };
   Sp<T> V = bd.V0, dVb = bd.dV0;
   pipelined(
-      n, 0, 1, [&](int i) { return In{q[i], qd[i]}; },
+      n, 0, 1,
+      [&](int i) {
+        In x;
+        x.q = q[i];
+        x.qd = qd[i];
+        if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
+        return x;
+      },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
         T sn, cs;
         Pose<T> g;
         pose(i, L, x.q, &g, &sn, &cs);
@@ -589,13 +622,15 @@ PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const
 }
 
 // Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
-template <class T, class Need = NoHandoff>
+template <class T, class Need = NoHandoff, bool PF = false>
 PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> tau_in,
                                const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi,
                                const Need& need = Need()) {
   struct In {
     Sp<T> fb, U;
     T invD, sn, cs, q, tau;
+    Link<T> L;
+    Link<double> Lw;
   };
   Sp<double> Fb = cast_sp<double>(bd.Ftip), zA = sp_zero<double>();
   Pose<double> gcw;
@@ -611,14 +646,18 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
         x.invD = abi.words > 6 ? abi.at(i, 6) : T(0);
         x.q = q[i];
         x.tau = tau_in[i];
+        if constexpr (PF) {
+          x.Lw = load_link(wtable + (long)i * kLinkWords);
+          if (abi.words == 6) x.L = load_link(table + (long)i * kLinkWords);
+        }
         return x;
       },
       [&](int i, const In& x) {
         const bool has_child = (i < n - 1);
-        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
         T invD = x.invD;
         if (abi.words == 6) {  // U only: form 1/D here and keep it for the lambda pass
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
           invD = T(1) / dot(L.S, x.U);
           bias.at(i, 7) = invD;
         }
@@ -637,12 +676,13 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
 }
 
 // Pass C (base to tip): lambda, qdd.
-template <class T, class Epi>
+template <class T, class Epi, bool PF = false>
 PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>& bias, const Scratch<T>& abi,
                         const Epi& epi) {
   struct In {
     Sp<T> U;
     T invD, chat, sn, cs, q;
+    Link<T> L;
   };
   Sp<T> lam = sp_zero<T>();
   pipelined(
@@ -655,10 +695,11 @@ PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>
         x.sn = bias.at(i, 8);
         x.cs = bias.at(i, 9);
         x.q = q[i];
+        if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
         return x;
       },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
         const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
         const Sp<T> a = X_twist(g, lam);
         const T qdd = x.chat - dot(x.U, a) * x.invD;
