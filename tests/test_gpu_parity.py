@@ -297,8 +297,8 @@ def test_status_word_reports_numerical_faults(device):
         api.set_launch(op, 0, 0, 0)
 
 
-@pytest.mark.parametrize("n,B,dtype", [(20, 300, torch.float32), (90, 300, torch.float32), (120, 200, torch.float32),
-                                        (30, 100, torch.float64)])
+@pytest.mark.parametrize("n,B,dtype", [(20, 300, torch.float32), (50, 300, torch.float32), (90, 300, torch.float32),
+                                        (120, 200, torch.float32), (30, 100, torch.float64)])
 def test_role_split_lds_modes(device, n, B, dtype):
     """The role-split kernel's three hand-off modes, chosen by chain length: U_i in LDS with the transform
     rings (FP32 up to 61 links), U_i alone in LDS (FP32 up to ~106 links, FP64 up to ~53), and the barrier
