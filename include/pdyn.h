@@ -73,7 +73,10 @@ typedef struct pdyn_model {
   /* One chain per state only: a permutation [n_chains] of the chains in the
    * order lanes take them (e.g. longest first, so that each wavefront holds
    * chains of similar length and the longest start first), or NULL for the
-   * natural order. Results are written in the natural layout either way. */
+   * natural order. Results are written in the natural layout either way.
+   * The derived tables are laid out for this order (each wavefront's link
+   * records interleaved over its lanes), so a prepared model keeps the order
+   * it was prepared with; a new order takes effect when it is prepared again. */
   const int32_t* order;
 } pdyn_model;
 
@@ -153,7 +156,10 @@ enum {
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes);
 
 /* Bytes of the derived per-link tables of a model (scalar_bytes 4 or 8); 0 on
- * invalid arguments. */
+ * invalid arguments. One shared chain: 32 words per link in the scalar type
+ * and 32 in double. One chain per state: as much per record slot, with
+ * n_links_max slots for each group of 64 chains (chains shorter than the
+ * longest of their group leave slots unused), plus the lane order. */
 size_t pdyn_model_prepared_bytes(const pdyn_model* model, int scalar_bytes);
 
 /* Derive the per-link tables (rotation of each placement, twist norms, first

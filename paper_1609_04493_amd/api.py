@@ -130,10 +130,13 @@ class Model:
         self.order = torch.as_tensor(self.order_host).to(self.device) if self.n_chains > 1 else None
         self.use_order = True
         self.prepared = None
+        self._prepared_order = True
         if prepare:
             self.prepare()
 
     def c_struct(self, with_prepared=True) -> _Model:
+        if with_prepared and self.prepared is not None and self._prepared_order != self.use_order:
+            self.prepare()  # the tables of one chain per state are laid out for the lane order
         prep = self.prepared if with_prepared else None
         order = self.order if (self.use_order and self.order is not None) else None
         return _Model(self.n_chains, self.n_links_max, self.n_links_total,
@@ -160,6 +163,7 @@ class Model:
                "pdyn_model_prepare")
         self._prepared_buf = buf
         self.prepared = tab
+        self._prepared_order = self.use_order
         return self
 
     def invalidate(self):

@@ -60,9 +60,63 @@ template <class T> struct BoundaryArgs {
   T V0[6], dV0[6];
 };
 
+// One chain per state: the same records interleaved over the 64 lanes of each
+// wavefront (the layout of IlvRec), n_max records per group of 64 lane
+// indices; lane index j runs chain order[j] (chain j without an order), and
+// order_out[j] records that chain for the kernels. Records past a chain's end
+// and lanes past the last chain hold zeros. One thread per (group, record, lane).
+template <class T>
+__global__ void __launch_bounds__(256) k_link_table_ilv(int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
+                                                        const int32_t* __restrict__ order,
+                                                        const T* __restrict__ placement, const T* __restrict__ twist,
+                                                        const T* __restrict__ inertia, T* __restrict__ table,
+                                                        double* __restrict__ wtable, int32_t* __restrict__ order_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(t % 64);
+  const int64_t slot = t / 64;  // group * n_max + record
+  const int i = (int)(slot % n_max);
+  const int64_t j = (slot / n_max) * 64 + lane;
+  if (j >= ((int64_t)n_chains + 63) / 64 * 64) return;
+  double rec[kLinkWords];
+  bool live = false;
+  if (j < n_chains) {
+    const int c = order ? order[j] : (int)j;
+    const int64_t l0 = link_ptr[c];
+    if (i == 0) order_out[j] = c;
+    if (i < link_ptr[c + 1] - l0) {
+      make_link_record(placement + 7 * (l0 + i), twist + 6 * (l0 + i), inertia + 10 * (l0 + i), rec);
+      live = true;
+    }
+  }
+  if (!live) {
+#pragma unroll
+    for (int k = 0; k < kLinkWords; ++k) rec[k] = 0.0;
+  }
+  constexpr int V = IlvRec<T>::V, W = IlvRec<double>::V;
+  T* tp = table + slot * kLinkWords * 64 + lane * V;
+  double* wp = wtable + slot * kLinkWords * 64 + lane * W;
+#pragma unroll
+  for (int k = 0; k < kLinkWords; ++k) {
+    tp[(k / V) * 64 * V + k % V] = (T)rec[k];
+    wp[(k / W) * 64 * W + k % W] = rec[k];
+  }
+}
+
 // Lane -> state: lane_index (0 .. n_states-1, possibly through `order`).
 __device__ __forceinline__ int state_of(int lane_index, const int32_t* __restrict__ order) {
   return order ? order[lane_index] : lane_index;
+}
+
+// The link records a lane reads: the shared chain's, back to back (a
+// wave-uniform address), or the lane's piece of its wavefront's interleaved
+// block (k_link_table_ilv).
+template <bool SHARED, class T>
+__device__ __forceinline__ auto rec_view(const T* table, int lane_index, int n_max) {
+  if constexpr (SHARED)
+    return table;
+  else
+    return IlvRec<T>{table + ((int64_t)(lane_index / 64) * n_max * kLinkWords * 64 +
+                              (int64_t)(lane_index % 64) * IlvRec<T>::V)};
 }
 
 // SHARED: one chain shared by every state, known at compile time, so that the
@@ -111,8 +165,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
     // scratch column = lane: consecutive lanes touch consecutive words
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<MODE>::value, status};
     // one chain per state: link records differ between lanes, so they are prefetched like the other inputs
-    dynamics_one_state<T, MODE, StoreQdd<T>, FormPose<T>, SWEEPS, !SHARED>(n, table + link0 * kLinkWords,
-                                                                  wtable + link0 * kLinkWords, io, bd, scr,
+    dynamics_one_state<T, MODE, StoreQdd<T>, FormPose<T>, SWEEPS, !SHARED>(n, rec_view<SHARED>(table, lane_index, n_max),
+                                                                  rec_view<SHARED>(wtable, lane_index, n_max), io, bd, scr,
                                                                   StoreQdd<T>{io.qdd_out});
   }
 }
@@ -305,8 +359,8 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
       dof0 = link0;
     }
   }
-  const T* tab = table + link0 * kLinkWords;
-  const double* wtab = wtable + link0 * kLinkWords;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   Boundary<T> bd = boundary_of(ba);
   if (active && tip) {
     const T* t = tip + 6 * (int64_t)s;
@@ -401,8 +455,8 @@ __global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const
       dof0 = link0;
     }
   }
-  const T* tab = table + link0 * kLinkWords;
-  const double* wtab = wtable + link0 * kLinkWords;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   const SPtr<const T> qs(q + dof0);
   if (role == 1) {
     if (active) split_pose_fwd(n, tab, qs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
@@ -482,8 +536,8 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
   } else if (PI == kPiDirect) {
     sink.out = pi_out + c.link0 * 10;
   }
-  const T* tab = table + c.link0 * kLinkWords;
-  const double* wtab = wtable + c.link0 * kLinkWords;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   if (OP == kVjpID) id_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
   else fd_vjp_one_state(c.n, tab, wtab, io, bd, scr, sink);
 }
@@ -535,8 +589,8 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
       dof0 = link0;
     }
   }
-  const T* tab = table + link0 * kLinkWords;
-  const double* wtab = wtable + link0 * kLinkWords;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   Boundary<T> bd = boundary_of(ba);
   if (active && tip) {
     const T* t = tip + 6 * (int64_t)s;
@@ -646,7 +700,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
     const int s = state_of(lane_index, order);
     const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value, status};
-    rollout_one_state(c.n, table + c.link0 * kLinkWords, wtable + c.link0 * kLinkWords, steps, dt, every,
+    rollout_one_state(c.n, rec_view<SHARED>(table, lane_index, n_max), rec_view<SHARED>(wtable, lane_index, n_max), steps, dt, every,
                       SPtr<T>(q + c.dof0), SPtr<T>(qd + c.dof0), DevRows<T>{tau_seq + c.dof0, dofs},
                       DevCkpt<T>{ckpt_q + c.dof0, ckpt_qd + c.dof0, dofs}, boundary_of(ba), scr);
   }
@@ -684,8 +738,8 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   DevRows<T> tau{tau_seq + c.dof0, dofs};
   DevCkpt<T> ck{const_cast<T*>(ckpt_q) + c.dof0, const_cast<T*>(ckpt_qd) + c.dof0, dofs};
   DevMutRows<T> tb{tau_bar_seq + c.dof0, dofs};
-  const T* tab = table + c.link0 * kLinkWords;
-  const double* wtab = wtable + c.link0 * kLinkWords;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   if (PI == kPiNone) {
     NoSink sink;
     rollout_vjp_one_state(c.n, tab, wtab, steps, dt, every, tau, ck, tb, rows, boundary_of(ba), scr, sink);
@@ -740,11 +794,29 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   return PDYN_OK;
 }
 
-// The derived tables: [L][32] in the scalar type, then [L][32] in double.
-size_t tables_bytes(const pdyn_model* m, size_t scalar, size_t* wtable_off) {
-  size_t t = align_up((size_t)m->n_links_total * kLinkWords * scalar);
+// The derived tables: records in the scalar type, then the same in double.
+// One shared chain: [n][32] each. One chain per state: interleaved over the
+// lanes of each wavefront, n_max records per group of 64 lane indices
+// ([group][n_max][32][64] each, see k_link_table_ilv), then the lane -> chain
+// map [n_chains] that the kernels use with these tables.
+size_t ilv_slots(const pdyn_model* m) { return ((size_t)m->n_chains + 63) / 64 * (size_t)m->n_links_max; }
+size_t tables_bytes(const pdyn_model* m, size_t scalar, size_t* wtable_off, size_t* order_off = nullptr) {
+  const size_t recs = m->n_chains == 1 ? (size_t)m->n_links_total : ilv_slots(m) * 64;
+  const size_t t = align_up(recs * kLinkWords * scalar);
+  const size_t w = align_up(recs * kLinkWords * sizeof(double));
   if (wtable_off) *wtable_off = t;
-  return t + align_up((size_t)m->n_links_total * kLinkWords * sizeof(double));
+  if (order_off) *order_off = t + w;
+  return t + w + (m->n_chains == 1 ? 0 : align_up((size_t)m->n_chains * sizeof(int32_t)));
+}
+
+// Lane -> state map of the kernels: none with a shared chain; with one chain
+// per state, the copy that the table derivation wrote beside the tables it
+// built (so that the tables and the map always agree).
+const int32_t* lane_order(const pdyn_model* m, const char* tbase, size_t scalar) {
+  if (m->n_chains == 1) return nullptr;
+  size_t woff, ooff;
+  tables_bytes(m, scalar, &woff, &ooff);
+  return reinterpret_cast<const int32_t*>(tbase + ooff);
 }
 
 int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, Layout* L) {
@@ -800,13 +872,23 @@ int check_ptrs(std::initializer_list<const void*> ptrs) {
 
 template <class T>
 int launch_link_table(const pdyn_model* m, char* dst, hipStream_t s) {
-  size_t woff;
-  tables_bytes(m, sizeof(T), &woff);
-  int64_t nl = m->n_links_total;
-  unsigned grid = (unsigned)((nl + 255) / 256);
-  hipLaunchKernelGGL(k_link_table<T>, dim3(grid), dim3(256), 0, s, nl, static_cast<const T*>(m->placement),
-                     static_cast<const T*>(m->twist), static_cast<const T*>(m->inertia),
-                     reinterpret_cast<T*>(dst), reinterpret_cast<double*>(dst + woff));
+  size_t woff, ooff;
+  tables_bytes(m, sizeof(T), &woff, &ooff);
+  if (m->n_chains == 1) {
+    int64_t nl = m->n_links_total;
+    unsigned grid = (unsigned)((nl + 255) / 256);
+    hipLaunchKernelGGL(k_link_table<T>, dim3(grid), dim3(256), 0, s, nl, static_cast<const T*>(m->placement),
+                       static_cast<const T*>(m->twist), static_cast<const T*>(m->inertia),
+                       reinterpret_cast<T*>(dst), reinterpret_cast<double*>(dst + woff));
+  } else {
+    if (!m->link_ptr) return PDYN_EINVAL;
+    const size_t threads = ilv_slots(m) * 64;
+    if ((threads + 255) / 256 > 0x7fffffffu) return PDYN_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_link_table_ilv<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m->n_chains,
+                       m->n_links_max, m->link_ptr, m->order, static_cast<const T*>(m->placement),
+                       static_cast<const T*>(m->twist), static_cast<const T*>(m->inertia), reinterpret_cast<T*>(dst),
+                       reinterpret_cast<double*>(dst + woff), reinterpret_cast<int32_t*>(dst + ooff));
+  }
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -869,6 +951,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   char* base = static_cast<char*>(ws) + kStatusBytes;
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
   const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
   const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
   if (!m->prepared) {
@@ -881,11 +964,11 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     if (m->n_chains == 1)
       hipLaunchKernelGGL((k_id_split<T, true>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
-                         m->order, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+                         ord, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
                          scratch, status);
     else
       hipLaunchKernelGGL((k_id_split<T, false>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
-                         m->order, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+                         ord, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
                          scratch, status);
     if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
     return PDYN_OK;
@@ -912,7 +995,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)                  \
       return PDYN_ELAUNCH;                                                                                        \
     hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, LM>), dim3(g), dim3(blk), lds, s, b->n_states,              \
-                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
+                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
                        qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi, status);     \
   } while (0)
     if (shared) {
@@ -934,7 +1017,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     // the plain form: one launch per sweep, per-link intermediates in the (HBM) scratch between them
 #define PDYN_LAUNCH_SWEEP(SH, SW)                                                                                 \
   hipLaunchKernelGGL((k_dynamics<T, MODE, SH, SW>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,       \
-                     m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, \
+                     m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, \
                      static_cast<const T*>(b->tip_wrench), ba, scratch, status)
     if (m->n_chains == 1) {
       PDYN_LAUNCH_SWEEP(true, kSweep1);
@@ -951,11 +1034,11 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   }
   if (m->n_chains == 1)
     hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
-                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                        static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   else
     hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
-                       m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                        static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
@@ -1009,6 +1092,7 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
   if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
@@ -1017,7 +1101,7 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   launch_shape(b, &grid, &block);
 #define PDYN_LAUNCH_ROLLOUT(SH)                                                                                  \
   hipLaunchKernelGGL((k_rollout<T, SH>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,   \
-                     m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                                    \
+                     m->link_ptr, ord, reinterpret_cast<const T*>(tbase),                                    \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, q, qd, ckpt_q,   \
                      ckpt_qd, dofs, ba, reinterpret_cast<T*>(base + so), status)
   if (m->n_chains == 1)
@@ -1048,6 +1132,7 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
   if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
@@ -1056,7 +1141,7 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   T* acc = reinterpret_cast<T*>(base + ao);
 #define PDYN_LAUNCH_RVJP(PI, SH)                                                                                 \
   hipLaunchKernelGGL((k_rollout_vjp<T, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
-                     m->n_links_max, m->link_ptr, m->order, reinterpret_cast<const T*>(tbase),                   \
+                     m->n_links_max, m->link_ptr, ord, reinterpret_cast<const T*>(tbase),                   \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
                      ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
                      reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc, status)
@@ -1100,6 +1185,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   T* partials = reinterpret_cast<T*>(base + L.partial_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
   const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
   const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
   if (!m->prepared) {
@@ -1124,7 +1210,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)              \
       return PDYN_ELAUNCH;                                                                                    \
     hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH, OV>), dim3(grid64), dim3(128), OV ? lds : 0, s,            \
-                       b->n_states, m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in,   \
+                       b->n_states, m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in,   \
                        q_bar, qd_bar, qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);           \
   } while (0)
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
@@ -1135,7 +1221,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
       PDYN_LAUNCH_VJP_SPLIT(PI, SH, false, PIOUT);                                                            \
     else                                                                                                      \
       hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
-                         m->n_links_max, m->link_ptr, m->order, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
+                         m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
                          qdd_bar, tau_bar, PIOUT, tip, ba, scratch, status);                                  \
   } while (0)
   if (!inertia_bar) {
@@ -1194,7 +1280,8 @@ int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared
   if (scalar_bytes != 4 && scalar_bytes != 8) return PDYN_EINVAL;
   if (!model || model->n_chains < 1 || model->n_links_total < 1 || !prepared) return PDYN_EINVAL;
   if (!model->placement || !model->twist || !model->inertia) return PDYN_EINVAL;
-  if (!aligned(prepared, kAlign)) return PDYN_EALIGN;
+  if (model->n_chains > 1 && !model->link_ptr) return PDYN_EINVAL;
+  if (!aligned(prepared, kAlign) || (model->order && !aligned(model->order, sizeof(int32_t)))) return PDYN_EALIGN;
   size_t a = (size_t)scalar_bytes;
   if (!aligned(model->placement, a) || !aligned(model->twist, a) || !aligned(model->inertia, a)) return PDYN_EALIGN;
   if (prepared_bytes < tables_bytes(model, a, nullptr)) return PDYN_EWORKSPACE;

@@ -107,6 +107,30 @@ template <class T> PD_HD Link<T> load_link(const T* rec) {
   return L;
 }
 
+// Record i of a chain whose records lie back to back (one chain shared by
+// every state: the address is wave-uniform and loads through the scalar unit).
+template <class T> PD_HD Link<T> link_at(const T* table, long i) { return load_link(table + i * kLinkWords); }
+
+// Records of chains that differ between the lanes of a wavefront, interleaved
+// over its 64 lanes in 16-byte pieces: word w of record i of lane l lies at
+// base + i * kLinkWords * 64 + (w / V) * 64 * V + l * V + w % V, V = 16 / sizeof(T),
+// so that each load instruction of the wavefront reads 1 KiB contiguous.
+// `p` is the lane's start, base + l * V.
+template <class T> struct IlvRec {
+  static constexpr int V = 16 / (int)sizeof(T);
+  const T* p;
+};
+template <class T> PD_HD Link<T> link_at(IlvRec<T> t, long i) {
+  constexpr int V = IlvRec<T>::V;
+  const T* r = t.p + i * (kLinkWords * 64);
+  T w[kLinkWords];
+#pragma unroll
+  for (int c = 0; c < kLinkWords / V; ++c)
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[c * V + v] = r[c * 64 * V + v];
+  return load_link(w);
+}
+
 // f_{i-1,i} = M_i exp(S_i q_i). With theta = k q, a = sin(theta)/k,
 // b = (1 - cos theta)/k^2 and e = (theta - sin theta)(w.v)/k^3, the matrix
 // exponential of the twist is R_e = cos(theta) I + a [w] + b w w^T,
@@ -287,8 +311,8 @@ template <class T> struct FormPose {
 // a caller can run them as separate launches with the scratch in between.
 enum : int { kSweep1 = 1, kSweep2 = 2, kSweep3 = 4, kAllSweeps = 7 };
 
-template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>, int SWEEPS = kAllSweeps, bool PF = false>
-PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
+template <class T, int MODE, class Epi, class PoseSrc = FormPose<T>, int SWEEPS = kAllSweeps, bool PF = false, class Tab = const T*, class WTab = const double*>
+PD_HD void dynamics_one_state(int n, Tab table, WTab wtable, const JointIO<T>& io,
                               const Boundary<T>& bd, const Scratch<T>& scr, const Epi& epi,
                               const PoseSrc& pose = PoseSrc()) {
   constexpr bool kID = (MODE & kModeID) != 0;
@@ -313,11 +337,11 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.q = io.q[i];
           x.qd = io.qd[i];
           x.qdd = kID ? io.qdd_in[i] : T(0);
-          if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
+          if constexpr (PF) x.L = link_at(table, i);
           return x;
         },
         [&](int i, const In& x) {
-          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : link_at(table, i);
           T sn, cs;
           Pose<T> g;
           pose(i, L, x.q, &g, &sn, &cs);
@@ -365,15 +389,15 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.cs = scr.at(i, kSC + 1);
           x.q = io.q[i];
           if constexpr (PF) {
-            x.L = load_link(table + (long)i * kLinkWords);
-            x.Lw = load_link(wtable + (long)i * kLinkWords);
+            x.L = link_at(table, i);
+            x.Lw = link_at(wtable, i);
           }
           return x;
         },
         [&](int i, const In& x) {
           const bool has_child = (i < n - 1);
-          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
-          const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : link_at(table, i);
+          const Link<double> Lw = PF ? x.Lw : link_at(wtable, i);
           if (kID) {
             Sp<double> Fc = has_child ? XT_wrench(gcw, F) : F;
             F = Fc + cast_sp<double>(x.fh);
@@ -434,11 +458,11 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
           x.sn = scr.at(i, kSC);
           x.cs = scr.at(i, kSC + 1);
           x.q = io.q[i];
-          if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
+          if constexpr (PF) x.L = link_at(table, i);
           return x;
         },
         [&](int i, const In& x) {
-          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : link_at(table, i);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           const Sp<T> a = X_twist(g, lam);
           const T qdd = x.chat - dot(x.U, a) * x.invD;
@@ -449,8 +473,8 @@ PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const
   }
 }
 
-template <class T, int MODE>
-PD_HD void dynamics_one_state(int n, const T* table, const double* wtable, const JointIO<T>& io,
+template <class T, int MODE, class Tab = const T*, class WTab = const double*>
+PD_HD void dynamics_one_state(int n, Tab table, WTab wtable, const JointIO<T>& io,
                               const Boundary<T>& bd, const Scratch<T>& scr) {
   dynamics_one_state<T, MODE>(n, table, wtable, io, bd, scr, StoreQdd<T>{io.qdd_out});
 }
@@ -480,8 +504,8 @@ struct NoHandoff {
 };
 
 // Pass A (tip to base): Jhat_i, U_i = Jhat_i S_i, 1/D_i.
-template <class T, class Done = NoHandoff, bool PF = false>
-PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<const T> q, const Scratch<T>& abi,
+template <class T, class Done = NoHandoff, bool PF = false, class Tab = const T*, class WTab = const double*>
+PD_HD void split_abi_pass(int n, Tab table, WTab wtable, SPtr<const T> q, const Scratch<T>& abi,
                           const Done& done = Done()) {
   struct In {
     T q;
@@ -496,15 +520,15 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
         In x;
         x.q = q[i];
         if constexpr (PF) {
-          x.L = load_link(table + (long)i * kLinkWords);
-          x.Lw = load_link(wtable + (long)i * kLinkWords);
+          x.L = link_at(table, i);
+          x.Lw = link_at(wtable, i);
         }
         return x;
       },
       [&](int i, const In& x) {
         const T qi = x.q;
-        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
-        const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
+        const Link<T> L = PF ? x.L : link_at(table, i);
+        const Link<double> Lw = PF ? x.Lw : link_at(wtable, i);
         Sym6<T> Jh = sym6_from_inertia(L.J);
         if (i < n - 1) {
           const Sym6<T> P = congruence_to_parent(gc, JA);
@@ -532,24 +556,24 @@ PD_HD void split_abi_pass(int n, const T* table, const double* wtable, SPtr<cons
 // put(k, pose, sin, cos), base to tip, for B1 and the inverse dynamics; P_b
 // hands the transform of the k-th link from the tip (double, rounded to T, as
 // pass A forms it) to put(k, pose), for the articulated-body recursion.
-template <class T, class Put>
-PD_HD void split_pose_fwd(int n, const T* table, SPtr<const T> q, const Put& put) {
+template <class T, class Put, class Tab = const T*>
+PD_HD void split_pose_fwd(int n, Tab table, SPtr<const T> q, const Put& put) {
   pipelined(
       n, 0, 1, [&](int k) { return q[k]; },
       [&](int k, T qk) {
-        const Link<T> L = load_link(table + (long)k * kLinkWords);
+        const Link<T> L = link_at(table, k);
         T sn, cs;
         joint_sincos(L, qk, &sn, &cs);
         put(k, joint_transform_sc(L, qk, sn, cs), sn, cs);
       });
 }
-template <class T, class Put>
-PD_HD void split_pose_bwd(int n, const T* table, const double* wtable, SPtr<const T> q, const Put& put) {
+template <class T, class Put, class Tab = const T*, class WTab = const double*>
+PD_HD void split_pose_bwd(int n, Tab table, WTab wtable, SPtr<const T> q, const Put& put) {
   pipelined(
       n, n - 1, -1, [&](int i) { return q[i]; },
       [&](int i, T qi) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
-        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
+        const Link<double> Lw = link_at(wtable, i);
         put(n - 1 - i, cast_pose<T>(joint_transform_wide(Lw, L, qi)));
       });
 }
@@ -557,15 +581,15 @@ PD_HD void split_pose_bwd(int n, const T* table, const double* wtable, SPtr<cons
 // Pass A with the transforms handed in: get(k) is the transform of the k-th
 // link from the tip, as pass A forms it; release(m) reports that the first m
 // of them are used; done(k) as in pass A.
-template <class T, class Get, class Release, class Done>
-PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, const Get& get,
+template <class T, class Get, class Release, class Done, class Tab = const T*>
+PD_HD void split_abi_from_poses(int n, Tab table, const Scratch<T>& abi, const Get& get,
                                 const Release& release, const Done& done) {
   Sym6<T> JA;
   // load(i): the transform of link i's child (link i + 1), none at the tip
   pipelined(
       n, n - 1, -1, [&](int i) { return i < n - 1 ? get(n - 2 - i) : Pose<T>(); },
       [&](int i, const Pose<T>& gc) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         Sym6<T> Jh = sym6_from_inertia(L.J);
         if (i < n - 1) {
           const Sym6<T> P = congruence_to_parent(gc, JA);
@@ -589,8 +613,8 @@ PD_HD void split_abi_from_poses(int n, const T* table, const Scratch<T>& abi, co
 }
 
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
-template <class T, class PoseSrc = FormPose<T>, bool PF = false>
-PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
+template <class T, class PoseSrc = FormPose<T>, bool PF = false, class Tab = const T*>
+PD_HD void split_bias_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
                               const Scratch<T>& bias, const PoseSrc& pose = PoseSrc()) {
   struct In {
     T q, qd;
@@ -603,11 +627,11 @@ PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const
         In x;
         x.q = q[i];
         x.qd = qd[i];
-        if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
+        if constexpr (PF) x.L = link_at(table, i);
         return x;
       },
       [&](int i, const In& x) {
-        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+        const Link<T> L = PF ? x.L : link_at(table, i);
         T sn, cs;
         Pose<T> g;
         pose(i, L, x.q, &g, &sn, &cs);
@@ -622,8 +646,8 @@ PD_HD void split_bias_forward(int n, const T* table, SPtr<const T> q, SPtr<const
 }
 
 // Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
-template <class T, class Need = NoHandoff, bool PF = false>
-PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> tau_in,
+template <class T, class Need = NoHandoff, bool PF = false, class Tab = const T*, class WTab = const double*>
+PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> tau_in,
                                const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi,
                                const Need& need = Need()) {
   struct In {
@@ -647,17 +671,17 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
         x.q = q[i];
         x.tau = tau_in[i];
         if constexpr (PF) {
-          x.Lw = load_link(wtable + (long)i * kLinkWords);
-          if (abi.words == 6) x.L = load_link(table + (long)i * kLinkWords);
+          x.Lw = link_at(wtable, i);
+          if (abi.words == 6) x.L = link_at(table, i);
         }
         return x;
       },
       [&](int i, const In& x) {
         const bool has_child = (i < n - 1);
-        const Link<double> Lw = PF ? x.Lw : load_link(wtable + (long)i * kLinkWords);
+        const Link<double> Lw = PF ? x.Lw : link_at(wtable, i);
         T invD = x.invD;
         if (abi.words == 6) {  // U only: form 1/D here and keep it for the lambda pass
-          const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+          const Link<T> L = PF ? x.L : link_at(table, i);
           invD = T(1) / dot(L.S, x.U);
           bias.at(i, 7) = invD;
         }
@@ -676,8 +700,8 @@ PD_HD void split_bias_backward(int n, const T* table, const double* wtable, SPtr
 }
 
 // Pass C (base to tip): lambda, qdd.
-template <class T, class Epi, bool PF = false>
-PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>& bias, const Scratch<T>& abi,
+template <class T, class Epi, bool PF = false, class Tab = const T*>
+PD_HD void split_lambda(int n, Tab table, SPtr<const T> q, const Scratch<T>& bias, const Scratch<T>& abi,
                         const Epi& epi) {
   struct In {
     Sp<T> U;
@@ -695,11 +719,11 @@ PD_HD void split_lambda(int n, const T* table, SPtr<const T> q, const Scratch<T>
         x.sn = bias.at(i, 8);
         x.cs = bias.at(i, 9);
         x.q = q[i];
-        if constexpr (PF) x.L = load_link(table + (long)i * kLinkWords);
+        if constexpr (PF) x.L = link_at(table, i);
         return x;
       },
       [&](int i, const In& x) {
-        const Link<T> L = PF ? x.L : load_link(table + (long)i * kLinkWords);
+        const Link<T> L = PF ? x.L : link_at(table, i);
         const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
         const Sp<T> a = X_twist(g, lam);
         const T qdd = x.chat - dot(x.U, a) * x.invD;
@@ -779,8 +803,8 @@ PD_HD void vjp_forward_fhat(int i, const Link<T>& L, const Pose<T>& g, T qd, T q
 
 // Sweeps 2-4 of an ID adjoint with cotangent sgn * tb (Fhat already in scratch
 // slot 0). pi_bar contributions go to sink.put(i, g[10]).
-template <class T, class Sink>
-PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> qd,
+template <class T, class Sink, class Tab = const T*, class WTab = const double*>
+PD_HD void id_vjp_tail(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> qd,
                        SPtr<const T> qdd, SPtr<const T> tb, T sgn, SPtr<T> q_bar, SPtr<T> qd_bar, SPtr<T> qdd_bar,
                        const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   // sweep 2 (tip to base): wrenches F_i in double, stored rounded in slot 0
@@ -795,7 +819,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
         n, n - 1, -1,
         [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
         [&](int i, const In& x) {
-          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          const Link<double> Lw = link_at(wtable, i);
           if (i < n - 1) F = XT_wrench(gcw, F);
           F = F + cast_sp<double>(x.fh);
           scr.put(i, 0, cast_sp<T>(F));
@@ -815,7 +839,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
           return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i], tb[i]};
         },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           const Sp<T> XV = X_twist(g, V);
           const Sp<T> Sqd = x.qd * L.S;
@@ -848,7 +872,7 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
                     scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i]};
         },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
           const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
           const Sp<T> Vb = adT_wrench(x.Fb, mul(L.J, x.V)) - mul(L.J, ad_twist(x.V, x.Fb)) + yc;
           const Sp<T> Sqd = x.qd * L.S;
@@ -867,8 +891,8 @@ PD_HD void id_vjp_tail(int n, const T* table, const double* wtable, SPtr<const T
   }
 }
 
-template <class T, class Sink>
-PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const VjpIO<T>& io,
+template <class T, class Sink, class Tab = const T*, class WTab = const double*>
+PD_HD void id_vjp_one_state(int n, Tab table, WTab wtable, const VjpIO<T>& io,
                             const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   struct In {
     T q, qd, qdd;
@@ -877,7 +901,7 @@ PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const V
   pipelined(
       n, 0, 1, [&](int i) { return In{io.q[i], io.qd[i], io.qdd[i]}; },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         T sn, cs;
         joint_sincos(L, x.q, &sn, &cs);
         scr.at(i, kVjpSC) = sn;
@@ -888,8 +912,8 @@ PD_HD void id_vjp_one_state(int n, const T* table, const double* wtable, const V
               sink);
 }
 
-template <class T, class Sink>
-PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const VjpIO<T>& io,
+template <class T, class Sink, class Tab = const T*, class WTab = const double*>
+PD_HD void fd_vjp_one_state(int n, Tab table, WTab wtable, const VjpIO<T>& io,
                             const Boundary<T>& bd, const Scratch<T>& scr, Sink& sink) {
   // u = M^-1 qdd_bar: articulated-body inertia and z-hat (tip to base) with tau-hat = qdd_bar
   {
@@ -904,8 +928,8 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
         n, n - 1, -1, [&](int i) { return In{io.q[i], io.bar_in[i]}; },
         [&](int i, const In& x) {
           const bool has_child = (i < n - 1);
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
-          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
+          const Link<double> Lw = link_at(wtable, i);
           Sym6<T> Jh = sym6_from_inertia(L.J);
           Sp<double> z = sp_zero<double>();
           if (has_child) {
@@ -950,7 +974,7 @@ PD_HD void fd_vjp_one_state(int n, const T* table, const double* wtable, const V
                     io.q[i], io.qd[i], io.qdd[i]};
         },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           const Sp<T> a = X_twist(g, lam);
           const T u = x.chat - dot(x.U, a) * x.invD;
@@ -983,8 +1007,8 @@ constexpr int kVjpXWords = 10;
 struct NoPut {
   template <class P, class T> PD_HD void operator()(int, const P&, T, T) const {}
 };
-template <class T, class Put = NoPut>
-PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> tb, T sgn, const Scratch<T>& xs,
+template <class T, class Put = NoPut, class Tab = const T*>
+PD_HD void vjp_fbar_pass(int n, Tab table, SPtr<const T> q, SPtr<const T> tb, T sgn, const Scratch<T>& xs,
                          const Put& put = Put()) {
   struct In {
     T q, tb;
@@ -993,7 +1017,7 @@ PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> t
   pipelined(
       n, 0, 1, [&](int i) { return In{q[i], tb[i]}; },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         T sn, cs;
         joint_sincos(L, x.q, &sn, &cs);
         const Pose<T> g = joint_transform_sc(L, x.q, sn, cs);
@@ -1006,8 +1030,8 @@ PD_HD void vjp_fbar_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> t
 // X, FD adjoint: u = M^-1 qdd_bar by the articulated-body solve with tau-hat :=
 // qdd_bar (tip to base: Jhat, U, 1/D, c-hat; base to tip: lambda, u), writing
 // u to tau_bar and, in the base-to-tip pass, Fbar_i = X_i Fbar_{i-1} - u_i S_i.
-template <class T>
-PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> bar,
+template <class T, class Tab = const T*, class WTab = const double*>
+PD_HD void fdvjp_solve_pass(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> bar,
                             SPtr<T> tau_bar, const Scratch<T>& xs) {
   {
     struct In {
@@ -1021,8 +1045,8 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
         n, n - 1, -1, [&](int i) { return In{q[i], bar[i]}; },
         [&](int i, const In& x) {
           const bool has_child = (i < n - 1);
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
-          const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
+          const Link<double> Lw = link_at(wtable, i);
           Sym6<T> Jh = sym6_from_inertia(L.J);
           Sp<double> z = sp_zero<double>();
           if (has_child) {
@@ -1063,7 +1087,7 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
         n, 0, 1,
         [&](int i) { return In{xs.get(i, 0), xs.at(i, 6), xs.at(i, 7), xs.at(i, 8), xs.at(i, 9), q[i]}; },
         [&](int i, const In& x) {
-          const Link<T> L = load_link(table + (long)i * kLinkWords);
+          const Link<T> L = link_at(table, i);
           const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
           const Sp<T> a = X_twist(g, lam);
           const T u = x.chat - dot(x.U, a) * x.invD;
@@ -1078,8 +1102,8 @@ PD_HD void fdvjp_solve_pass(int n, const T* table, const double* wtable, SPtr<co
 
 // Y: sweep 1 of ID at (q, qd, qdd) keeping Fhat, V, A and (sin, cos); the
 // transforms come from pose (formed here by default).
-template <class T, class PoseSrc = FormPose<T>>
-PD_HD void vjp_ne_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
+template <class T, class PoseSrc = FormPose<T>, class Tab = const T*>
+PD_HD void vjp_ne_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
                           const Boundary<T>& bd, const Scratch<T>& scr, const PoseSrc& pose = PoseSrc()) {
   struct In {
     T q, qd, qdd;
@@ -1088,7 +1112,7 @@ PD_HD void vjp_ne_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> 
   pipelined(
       n, 0, 1, [&](int i) { return In{q[i], qd[i], qdd[i]}; },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         T sn, cs;
         Pose<T> g;
         pose(i, L, x.q, &g, &sn, &cs);
@@ -1103,8 +1127,8 @@ PD_HD void vjp_ne_forward(int n, const T* table, SPtr<const T> q, SPtr<const T> 
 // The wrench sweep (tip to base, in double) from the Fhat and (sin, cos) that
 // vjp_ne_forward left in scr, writing F_i to fout (component 0) and reporting
 // done(k) once the k-th link from the tip is written.
-template <class T, class Done = NoHandoff>
-PD_HD void vjp_wrench_pass(int n, const double* wtable, SPtr<const T> q, const Boundary<T>& bd, const Scratch<T>& scr,
+template <class T, class Done = NoHandoff, class WTab = const double*>
+PD_HD void vjp_wrench_pass(int n, WTab wtable, SPtr<const T> q, const Boundary<T>& bd, const Scratch<T>& scr,
                            const Scratch<T>& fout, const Done& done = Done()) {
   struct In {
     Sp<T> fh;
@@ -1115,7 +1139,7 @@ PD_HD void vjp_wrench_pass(int n, const double* wtable, SPtr<const T> q, const B
   pipelined(
       n, n - 1, -1, [&](int i) { return In{scr.get(i, 0), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i]}; },
       [&](int i, const In& x) {
-        const Link<double> Lw = load_link(wtable + (long)i * kLinkWords);
+        const Link<double> Lw = link_at(wtable, i);
         if (i < n - 1) F = XT_wrench(gcw, F);
         F = F + cast_sp<double>(x.fh);
         fout.put(i, 0, cast_sp<T>(F));
@@ -1125,23 +1149,23 @@ PD_HD void vjp_wrench_pass(int n, const double* wtable, SPtr<const T> q, const B
 }
 
 // Y: sweep 1 of ID, then the wrench sweep leaving F_i in slot 0.
-template <class T>
-PD_HD void vjp_newton_euler_pass(int n, const T* table, const double* wtable, SPtr<const T> q, SPtr<const T> qd,
+template <class T, class Tab = const T*, class WTab = const double*>
+PD_HD void vjp_newton_euler_pass(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> qd,
                                  SPtr<const T> qdd, const Boundary<T>& bd, const Scratch<T>& scr) {
   vjp_ne_forward(n, table, q, qd, qdd, bd, scr);
   vjp_wrench_pass(n, wtable, q, bd, scr, scr);
 }
 
 // X, after the barrier: inertia-parameter cotangents of every link (pointwise).
-template <class T, class Sink>
-PD_HD void vjp_inertia_pass(int n, const T* table, const Scratch<T>& xs, const Scratch<T>& scr, Sink& sink) {
+template <class T, class Sink, class Tab = const T*>
+PD_HD void vjp_inertia_pass(int n, Tab table, const Scratch<T>& xs, const Scratch<T>& scr, Sink& sink) {
   struct In {
     Sp<T> Fb, V, A;
   };
   pipelined(
       n, 0, 1, [&](int i) { return In{xs.get(i, 0), scr.get(i, 6), scr.get(i, 12)}; },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
         const V3<T> c = (T(1) / L.J.m) * L.J.h;
         add_inertia_grad(L.J.m, c, x.Fb, x.A, T(1), gpi);
@@ -1154,8 +1178,8 @@ PD_HD void vjp_inertia_pass(int n, const T* table, const Scratch<T>& xs, const S
 // id_vjp_tail, with the wrench part of q_bar formed here from Fbar and F).
 // fsrc holds F_i (component 0): scr itself, or another wavefront's LDS copy,
 // in which case need(k) waits until the k-th link from the tip is there.
-template <class T, class Need = NoHandoff>
-PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
+template <class T, class Need = NoHandoff, class Tab = const T*>
+PD_HD void vjp_back_pass(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
                          const Scratch<T>& xs, const Scratch<T>& scr, SPtr<T> q_bar, SPtr<T> qd_bar,
                          SPtr<T> qdd_bar, const Scratch<T>& fsrc, const Need& need = Need()) {
   struct In {
@@ -1171,7 +1195,7 @@ PD_HD void vjp_back_pass(int n, const T* table, SPtr<const T> q, SPtr<const T> q
                   scr.at(i, kVjpSC + 1), q[i], qd[i], qdd[i]};
       },
       [&](int i, const In& x) {
-        const Link<T> L = load_link(table + (long)i * kLinkWords);
+        const Link<T> L = link_at(table, i);
         const T qbp = -dot(ad_twist(L.S, x.Fb), x.F);
         const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
         const Sp<T> Vb = adT_wrench(x.Fb, mul(L.J, x.V)) - mul(L.J, ad_twist(x.V, x.Fb)) + yc;
@@ -1228,8 +1252,8 @@ template <class T> struct EulerStepKeep {  // also records qdd_t for the reverse
 
 // Forward rollout of one state: q, qd (length n) are advanced in place; tau(t)
 // returns the torque row of step t; ckpt(c) returns (q, qd) rows of checkpoint c.
-template <class T, class TauRow, class CkptRow>
-PD_HD void rollout_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every, SPtr<T> q,
+template <class T, class TauRow, class CkptRow, class Tab = const T*, class WTab = const double*>
+PD_HD void rollout_one_state(int n, Tab table, WTab wtable, int steps, T dt, int every, SPtr<T> q,
                              SPtr<T> qd, const TauRow& tau, const CkptRow& ckpt, const Boundary<T>& bd,
                              const Scratch<T>& scr) {
   for (int t = 0; t < steps; ++t) {
@@ -1266,8 +1290,8 @@ template <class T> struct RolloutRows {
 
 // Adjoint of L(q_T, qd_T) for one state. On entry rows.lq / rows.lqd hold
 // dL/dq_T, dL/dqd_T; on exit dL/dq_0, dL/dqd_0. taubar(t) receives dL/dtau_t.
-template <class T, class TauRow, class CkptRow, class TauBarRow, class Sink>
-PD_HD void rollout_vjp_one_state(int n, const T* table, const double* wtable, int steps, T dt, int every,
+template <class T, class TauRow, class CkptRow, class TauBarRow, class Sink, class Tab = const T*, class WTab = const double*>
+PD_HD void rollout_vjp_one_state(int n, Tab table, WTab wtable, int steps, T dt, int every,
                                  const TauRow& tau, const CkptRow& ckpt, const TauBarRow& taubar,
                                  const RolloutRows<T>& rows, const Boundary<T>& bd, const Scratch<T>& scr,
                                  Sink& sink) {

@@ -194,6 +194,46 @@ def test_launch_shapes_orders_and_persistence_are_bitwise_identical(device):
     assert et.max() <= TOL32
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_per_state_tables_fp64_orders_and_preparation(device, variant):
+    """One chain per state (link records interleaved over the lanes of each wavefront): FP64 with tip wrenches
+    and base motion against the oracle chain by chain, and bitwise the same outputs from per-call tables, from
+    prepared tables, and after the lane order changes (which lays the prepared tables out again)."""
+    print(f"case: per-state tables variant {variant}", flush=True)
+    for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+        api.set_launch(op, 0, 0, variant)
+    try:
+        lens = list(np.random.default_rng(12).integers(1, 40, 131))  # three wavefronts, the last one ragged
+        ch = synth.make_chains(lens, 12)
+        st = synth.make_states((ch.n_links_total,), 12)
+        rng = np.random.default_rng(12)
+        tip = rng.standard_normal((ch.n_chains, 6))
+        V0, dV0 = tuple(rng.standard_normal(6)), tuple(rng.standard_normal(6))
+        kw = dict(base_vel=V0, base_acc=dV0, tip=to_dev(tip, device, torch.float64))
+        model = api.Model(ch, device, torch.float64)
+        ref = run_all(model, st, device, torch.float64, **kw)
+        lp = ch.link_ptr
+        for c in range(ch.n_chains):
+            a, b = lp[c], lp[c + 1]
+            rt = oracle.rnea1(ch.chain(c), st.q[a:b], st.qd[a:b], st.qdd[a:b], np.array(V0), np.array(dV0), tip[c])
+            rq = oracle.aba1(ch.chain(c), st.q[a:b], st.qd[a:b], st.tau[a:b], np.array(V0), np.array(dV0), tip[c])
+            assert np.linalg.norm(ref[0][a:b] - rt) <= 1e-12 * np.linalg.norm(rt), c
+            assert np.linalg.norm(ref[2][a:b] - rt) <= 1e-12 * np.linalg.norm(rt), c
+            assert np.linalg.norm(ref[1][a:b] - rq) <= 1e-11 * np.linalg.norm(rq), c
+            assert np.linalg.norm(ref[3][a:b] - rq) <= 1e-11 * np.linalg.norm(rq), c
+        model.use_order = False  # prepared again for the natural order
+        got = run_all(model, st, device, torch.float64, **kw)
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+        model.invalidate()  # tables derived inside each call's workspace
+        for use_order in (False, True):
+            model.use_order = use_order
+            got = run_all(model, st, device, torch.float64, **kw)
+            assert all(np.array_equal(x, y) for x, y in zip(got, ref)), use_order
+    finally:
+        for op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD):
+            api.set_launch(op, 0, 0)
+
+
 def test_uneven_id_fd_in_a_captured_graph(device):
     """ID+FD of 4096 uneven chains captured once in a HIP graph; every replay equals the eager call."""
     print("case: uneven graph capture", flush=True)

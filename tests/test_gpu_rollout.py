@@ -45,6 +45,30 @@ def test_fp64_fused_rollout_and_gradient_small(device):
     assert abs(np.sum(pib * dpi) - ref) <= 1e-10 * abs(ref)
 
 
+def test_fp64_rollout_one_chain_per_state(device):
+    """Fused rollout and its gradient with one chain per state (70 chains of 1..9 links, two wavefronts)."""
+    print("case: fp64 rollout, one chain per state", flush=True)
+    ch = synth.make_chains([1, 6, 3, 9, 6] * 14, 8)
+    st = synth.make_states((ch.n_links_total,), 8)
+    T, dt, k = 13, 1e-2, 5
+    tau = 10 * np.random.default_rng(8).standard_normal((T, ch.n_links_total))
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    fg = rollout.FusedRolloutGrad(model, d(st.q), d(st.qd), d(tau), dt, k)
+    qT, (q0b, qd0b, tb, pib) = fg()
+    qT, q0b, qd0b, tb, pib = (x.cpu().numpy() for x in (qT, q0b, qd0b, tb, pib))
+    lp = ch.link_ptr
+    for c in (0, 3, 41, 69):
+        a, b = lp[c], lp[c + 1]
+        rq, _ = oracle.rollout1(ch.chain(c), T, dt, st.q[a:b], st.qd[a:b], tau[:, a:b])
+        assert np.linalg.norm(qT[a:b] - rq) <= 1e-12 * np.linalg.norm(rq), c
+        gq, gqd, gt, gpi = grad.rollout_gradient(ch.chain(c), T, dt, st.q[a:b], st.qd[a:b], tau[:, a:b])
+        assert np.linalg.norm(pib[a:b] - gpi) <= 1e-10 * np.linalg.norm(gpi), c
+        assert np.linalg.norm(q0b[a:b] - gq) <= 1e-11 * np.linalg.norm(gq), c
+        assert np.linalg.norm(qd0b[a:b] - gqd) <= 1e-11 * np.linalg.norm(gqd), c
+        assert np.linalg.norm(tb[:, a:b] - gt) <= 1e-11 * np.linalg.norm(gt), c
+
+
 def test_fp32_rollout_100_links_65536_states_sampled(device):
     """100 links, 65536 states, 100 steps at dt = 1e-3: sampled states against the oracle."""
     print("case: fp32 rollout 100 links x 65536 x 100 steps", flush=True)
