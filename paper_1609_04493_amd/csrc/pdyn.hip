@@ -222,11 +222,20 @@ struct LdsProgress {
   int* p;
   __device__ void operator()(int k) const { __hip_atomic_store(p, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 };
+// Waits until *p >= k. Progress words only grow, so the last value read is
+// kept: a wait it already covers returns without touching LDS (the acquire
+// that read it orders everything released up to it).
 struct LdsWait {
   int* p;
+  mutable int seen = 0;
   __device__ void operator()(int k) const {
+    if (k <= seen) return;
     for (int spin = 0; spin < kSpinLimit; ++spin) {
-      if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= k) return;
+      const int v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (v >= k) {
+        seen = v;
+        return;
+      }
       __builtin_amdgcn_s_sleep(1);
     }
   }
@@ -263,9 +272,10 @@ template <class T> struct RingPutF {  // base-to-tip entries
   int* used_b;   // entries taken by B1
   int* used_id;  // entries taken by the inverse dynamics (null without it)
   int lane;
+  LdsWait wait_b{used_b}, wait_id{used_id};
   __device__ void operator()(int i, const Pose<T>& g, T sn, T cs) const {
-    LdsWait{used_b}(i - kPoseSlots + 1);
-    if (used_id) LdsWait{used_id}(i - kPoseSlots + 1);
+    wait_b(i - kPoseSlots + 1);
+    if (used_id) wait_id(i - kPoseSlots + 1);
     T* w = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
     put_pose(w, g);
     w[12 * 64] = sn;
@@ -279,8 +289,9 @@ template <class T> struct RingTakeF {
   int* ready;
   int* used;
   int lane;
+  LdsWait wait{ready};
   __device__ void operator()(int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) const {
-    LdsWait{ready}(i + 1);
+    wait(i + 1);
     const T* r = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
     *g = get_pose(r);
     *sn = r[12 * 64];
@@ -288,13 +299,39 @@ template <class T> struct RingTakeF {
     LdsProgress{used}(i + 1);
   }
 };
+// Pass C's entries, base to tip, written by two producers (even links, odd
+// links) that each bump their own ready word: link i waits for ready[i % 2].
+template <class T> struct RingTakeF2 {
+  const T* ring;
+  int* ready;  // [2]
+  int* used;
+  int lane;
+  LdsWait wait0{ready}, wait1{ready + 1};
+  __device__ void operator()(int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) const {
+    if (i & 1)
+      wait1(i + 1);
+    else
+      wait0(i + 1);
+    const T* r = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
+    *g = get_pose(r);
+    *sn = r[12 * 64];
+    *cs = r[13 * 64];
+    LdsProgress{used}(i + 1);
+  }
+};
+// Pass C's epilogue in LDS: qdd_i into word 0 of link i's articulated entry.
+template <class T> struct StashQdd {
+  Scratch<T> abi;
+  __device__ void operator()(int i, T qdd) const { abi.at(i, 0) = qdd; }
+};
 template <class T> struct RingPutB {  // tip-to-base entries for pass A
   T* ring;  // [kPoseSlots][kPoseWordsB][64 lanes]
   int* ready;
   int* used;
   int lane;
+  LdsWait wait{used};
   __device__ void operator()(int k, const Pose<T>& g) const {
-    LdsWait{used}(k - kPoseSlots + 1);
+    wait(k - kPoseSlots + 1);
     put_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane, g);
     LdsProgress{ready}(k + 1);
   }
@@ -303,8 +340,9 @@ template <class T> struct RingGetB {
   const T* ring;
   int* ready;
   int lane;
+  LdsWait wait{ready};
   __device__ Pose<T> operator()(int k) const {
-    LdsWait{ready}(k + 1);
+    wait(k + 1);
     return get_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane);
   }
 };
@@ -325,7 +363,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   constexpr bool kRings = LDSMODE == 1;
   constexpr int kAbiLds = kRings ? kAbiWords : 6;
   extern __shared__ __align__(16) unsigned char lds_abi[];
-  __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a;
+  __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a, ready_l[2], used_l;
   if (OVERLAP) {
     if (threadIdx.x == 0) {
       progress = 0;
@@ -334,6 +372,9 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
       used_id = 0;
       ready_b = 0;
       used_a = 0;
+      ready_l[0] = 0;
+      ready_l[1] = 0;
+      used_l = 0;
     }
     __syncthreads();
   }
@@ -359,6 +400,12 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
       dof0 = link0;
     }
   }
+  // links of the wavefront's longest chain: the last value of its progress words
+  int n_wave = n;
+  if (!SHARED) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) n_wave = max(n_wave, __shfl_xor(n_wave, o));
+  }
   const auto tab = rec_view<SHARED>(table, lane_index, n_max);
   const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   Boundary<T> bd = boundary_of(ba);
@@ -372,13 +419,25 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
   T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiLds * 64;
   T* const ring_b = ring_f + (long)kPoseSlots * kPoseWordsF * 64;
+  // Pass C takes the transforms again through the base-to-tip ring, once B1
+  // and the inverse dynamics have taken every entry: P_f forms the even links,
+  // P_b (idle by then) the odd ones.
   if (kRings && role == 2) {
-    if (active)
+    if (active) {
       split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_f, &used_b, kWithID ? &used_id : nullptr, lane});
+      LdsWait{&used_b}(n_wave);
+      if (kWithID) LdsWait{&used_id}(n_wave);
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[0], &used_l, nullptr, lane}, 0, 2);
+    }
     return;
   }
   if (kRings && role == 3) {
-    if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane});
+    if (active) {
+      split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane});
+      LdsWait{&used_b}(n_wave);
+      if (kWithID) LdsWait{&used_id}(n_wave);
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[1], &used_l, nullptr, lane}, 1, 2);
+    }
     return;
   }
   if (role == kRoleID) {
@@ -413,12 +472,22 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   }
   if (!OVERLAP) __syncthreads();
   if (active && role == 1) {
-    if (OVERLAP)
+    if (kRings)
+      split_bias_backward<T, LdsWait, !SHARED, true>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias,
+                                                     abi, LdsWait{&progress});
+    else if (OVERLAP)
       split_bias_backward<T, LdsWait, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi,
                                                LdsWait{&progress});
     else
       split_bias_backward<T, NoHandoff, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
-    split_lambda<T, StoreQdd<T>, !SHARED>(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
+    if (kRings) {
+      // pass C runs out of LDS alone: qdd_i goes to word 0 of link i's entry (read by then), then out
+      split_lambda<T, StashQdd<T>, !SHARED, true>(n, tab, qs, bias, abi, StashQdd<T>{abi},
+                                                 RingTakeF2<T>{ring_f, ready_l, &used_l, lane});
+      T* const out = qdd_out + dof0;
+      for (int i = 0; i < n; ++i) out[i] = abi.at(i, 0);
+    } else
+      split_lambda<T, StoreQdd<T>, !SHARED>(n, tab, qs, bias, abi, StoreQdd<T>{SPtr<T>(qdd_out + dof0)});
   }
 }
 

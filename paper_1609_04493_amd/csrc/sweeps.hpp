@@ -27,6 +27,8 @@
 // renormalised in double, so the double transform is an exact rigid motion.
 #pragma once
 
+#include <type_traits>
+
 #include "spatial.hpp"
 
 namespace pdyn {
@@ -268,6 +270,32 @@ PD_HD void pipelined(int n, int first, int step, const LoadF& load, const BodyF&
     if (two) {
       a = load(k + 2 < n ? i + 2 * step : i);
       body(i + step, b);
+    }
+  }
+}
+
+// As pipelined, with the inputs of link k + D - 1 requested before the body of
+// link k runs, for passes whose body is too short to cover the latency of a
+// load from global memory. D input sets rotate in registers (unrolled by D);
+// near the end the surplus requests repeat the current link. Lanes stay in
+// lockstep as in pipelined.
+template <int D, class LoadF, class BodyF>
+PD_HD void pipelined_ahead(int n, int first, int step, const LoadF& load, const BodyF& body) {
+  static_assert(D >= 2, "at least one link ahead");
+  if (n <= 0) return;
+  using In = decltype(load(first));
+  In buf[D];
+#pragma unroll
+  for (int j = 0; j < D - 1; ++j) buf[j] = load(first + (j < n ? j : 0) * step);
+  for (int k = 0; k < n; k += D) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int kk = k + j;
+      if (kk < n) {
+        const int ahead = kk + D - 1;
+        buf[(j + D - 1) % D] = load(first + (ahead < n ? ahead : kk) * step);
+        body(first + kk * step, buf[j]);
+      }
     }
   }
 }
@@ -553,13 +581,14 @@ PD_HD void split_abi_pass(int n, Tab table, WTab wtable, SPtr<const T> q, const 
 
 // Passes P_f and P_b: the joint transforms for the other wavefronts of the
 // role-split kernel. P_f hands link k's transform and (sin, cos) to
-// put(k, pose, sin, cos), base to tip, for B1 and the inverse dynamics; P_b
-// hands the transform of the k-th link from the tip (double, rounded to T, as
-// pass A forms it) to put(k, pose), for the articulated-body recursion.
+// put(k, pose, sin, cos), base to tip, for B1 and the inverse dynamics (links
+// first, first + stride, ...: all by default); P_b hands the transform of the
+// k-th link from the tip (double, rounded to T, as pass A forms it) to
+// put(k, pose), for the articulated-body recursion.
 template <class T, class Put, class Tab = const T*>
-PD_HD void split_pose_fwd(int n, Tab table, SPtr<const T> q, const Put& put) {
+PD_HD void split_pose_fwd(int n, Tab table, SPtr<const T> q, const Put& put, int first = 0, int stride = 1) {
   pipelined(
-      n, 0, 1, [&](int k) { return q[k]; },
+      (n - first + stride - 1) / stride, first, stride, [&](int k) { return q[k]; },
       [&](int k, T qk) {
         const Link<T> L = link_at(table, k);
         T sn, cs;
@@ -646,7 +675,11 @@ PD_HD void split_bias_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> q
 }
 
 // Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
-template <class T, class Need = NoHandoff, bool PF = false, class Tab = const T*, class WTab = const double*>
+// FOLD (7-word articulated entries): once link i is done, its entry holds what
+// pass C needs, U_i / D_i in words 0-5 and c-hat_i in word 6, instead of c-hat
+// going to the bias scratch.
+template <class T, class Need = NoHandoff, bool PF = false, bool FOLD = false, class Tab = const T*,
+          class WTab = const double*>
 PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> tau_in,
                                const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi,
                                const Need& need = Need()) {
@@ -694,39 +727,66 @@ PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, S
         const double tauhat = (double)x.tau - dot(Lw.S, Fb);
         const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
         zA = z + chat_w * cast_sp<double>(x.U);
-        bias.at(i, 6) = (T)chat_w;
+        if constexpr (FOLD) {
+          abi.put(i, 0, invD * x.U);
+          abi.at(i, 6) = (T)chat_w;
+        } else {
+          bias.at(i, 6) = (T)chat_w;
+        }
         gcw = joint_transform_wide_sc(Lw, x.q, x.sn, x.cs);
       });
 }
 
-// Pass C (base to tip): lambda, qdd.
-template <class T, class Epi, bool PF = false, class Tab = const T*>
+// Pose source of pass C that forms each transform again from the (sin, cos)
+// pair stored by B1.
+struct StoredSinCos {};
+
+// Pass C (base to tip): lambda, qdd. `pose` (a pose source, see FormPose)
+// supplies the transforms, or with StoredSinCos the pass forms them. FOLD: the
+// articulated entries hold U_i / D_i and c-hat_i (B2 with FOLD).
+template <class T, class Epi, bool PF = false, bool FOLD = false, class PoseSrc = StoredSinCos, class Tab = const T*>
 PD_HD void split_lambda(int n, Tab table, SPtr<const T> q, const Scratch<T>& bias, const Scratch<T>& abi,
-                        const Epi& epi) {
+                        const Epi& epi, const PoseSrc& pose = PoseSrc()) {
+  constexpr bool kForm = std::is_same<PoseSrc, StoredSinCos>::value;
   struct In {
     Sp<T> U;
     T invD, chat, sn, cs, q;
     Link<T> L;
   };
   Sp<T> lam = sp_zero<T>();
-  pipelined(
+  pipelined_ahead<4>(
       n, 0, 1,
       [&](int i) {
         In x;
         x.U = abi.get(i, 0);
-        x.invD = abi.words > 6 ? abi.at(i, 6) : bias.at(i, 7);
-        x.chat = bias.at(i, 6);
-        x.sn = bias.at(i, 8);
-        x.cs = bias.at(i, 9);
-        x.q = q[i];
+        if constexpr (FOLD) {
+          x.invD = T(1);
+          x.chat = abi.at(i, 6);
+        } else {
+          x.invD = abi.words > 6 ? abi.at(i, 6) : bias.at(i, 7);
+          x.chat = bias.at(i, 6);
+        }
+        if constexpr (kForm) {
+          x.sn = bias.at(i, 8);
+          x.cs = bias.at(i, 9);
+          x.q = q[i];
+        } else {
+          x.sn = x.cs = x.q = T(0);
+        }
         if constexpr (PF) x.L = link_at(table, i);
         return x;
       },
       [&](int i, const In& x) {
         const Link<T> L = PF ? x.L : link_at(table, i);
-        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        Pose<T> g;
+        if constexpr (kForm) {
+          g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        } else {
+          T sn, cs;
+          pose(i, L, x.q, &g, &sn, &cs);
+        }
         const Sp<T> a = X_twist(g, lam);
-        const T qdd = x.chat - dot(x.U, a) * x.invD;
+        const T qdd = FOLD ? x.chat - dot(x.U, a) : x.chat - dot(x.U, a) * x.invD;
         lam = a + qdd * L.S;
         abi.check_finite(qdd);
         epi(i, qdd);

@@ -84,8 +84,26 @@ static int run(int mode, int n_states, int n_chains, int n_max, const int32_t* l
         split_abi_from_poses(n, tab, abi, [&](int k) { return poses_b[(size_t)k]; }, NoHandoff(), NoHandoff());
       else
         split_abi_pass(n, tab, wtab, io.q, abi);
-      split_bias_backward(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
-      split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out});
+      if (pose_ring && !abi6)  // as the kernel with its rings: pass C's inputs folded into the articulated entries
+        split_bias_backward<T, NoHandoff, false, true>(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
+      else
+        split_bias_backward(n, tab, wtab, io.q, io.tau_in, bd, bias, abi);
+      if (pose_ring) {  // pass C takes the transforms again, formed by two producers (even and odd links)
+        std::vector<Entry> poses2((size_t)n);
+        for (int first = 0; first < 2; ++first)
+          split_pose_fwd(n, tab, io.q, [&](int i, const Pose<T>& g, T sn, T cs) { poses2[(size_t)i] = Entry{g, sn, cs}; },
+                         first, 2);
+        auto take2 = [&](int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) {
+                       *g = poses2[(size_t)i].g;
+                       *sn = poses2[(size_t)i].sn;
+                       *cs = poses2[(size_t)i].cs;
+                     };
+        if (abi6)
+          split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out}, take2);
+        else
+          split_lambda<T, StoreQdd<T>, false, true>(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out}, take2);
+      } else
+        split_lambda(n, tab, io.q, bias, abi, StoreQdd<T>{io.qdd_out});
       continue;
     }
     if (mode == kModeID) dynamics_one_state<T, kModeID>(n, table.data() + link0 * kLinkWords, wtable.data() + link0 * kLinkWords, io, bd, scr);

@@ -122,10 +122,11 @@ def test_role_split_passes_match_oracle(cpu_lib):
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch, st, np.float64, tip, V0, dV0)
     _, qdd_fd = run_cpu(cpu_lib, SPLIT_FD, ch, st, np.float64, tip, V0, dV0)
     assert np.array_equal(qdd, qdd_fd)
-    # transforms formed once by pass P and handed to B1 and the inverse dynamics: the same bits
+    # transforms formed once by passes P and handed to the other passes: tau the same bits; qdd the same up to
+    # rounding, since with the rings pass C takes U_i / D_i (folded by B2) instead of dividing by D_i itself
     for mode in (SPLIT_FD, SPLIT_IDFD):
         t2, q2 = run_cpu(cpu_lib, mode | POSE_RING, ch, st, np.float64, tip, V0, dV0)
-        assert np.array_equal(q2, qdd)
+        assert np.abs(q2 - qdd).max() <= 1e-12 * np.abs(qdd).max()
         if mode == SPLIT_IDFD:
             assert np.array_equal(t2, tau)
         # U_i alone handed over (1/D_i formed again by B2): the same up to rounding
@@ -144,14 +145,16 @@ def test_role_split_passes_match_oracle(cpu_lib):
         a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
         assert np.linalg.norm(qdd[a:b] - ref[a:b]) <= 1e-10 * np.linalg.norm(ref[a:b])
     _, q2 = run_cpu(cpu_lib, SPLIT_FD | POSE_RING, ch, st, np.float64)
-    assert np.array_equal(q2, qdd)
+    for c in range(ch.n_chains):
+        a, b = ch.link_ptr[c], ch.link_ptr[c + 1]
+        assert np.linalg.norm(q2[a:b] - qdd[a:b]) <= 1e-12 * np.linalg.norm(qdd[a:b])
     ch, st = synth.workload_32link(256)
     _, q2 = run_cpu(cpu_lib, SPLIT_FD | POSE_RING, ch.astype(np.float32), st.astype(np.float32), np.float32)
     _, q3 = run_cpu(cpu_lib, SPLIT_FD | ABI_U_ONLY, ch.astype(np.float32), st.astype(np.float32), np.float32)
     assert rel_err_rows(q3, oracle.aba(ch.rounded(), st.rounded().q, st.rounded().qd, st.rounded().tau)).max() <= 1e-4
     tau, qdd = run_cpu(cpu_lib, SPLIT_IDFD, ch.astype(np.float32), st.astype(np.float32), np.float32)
-    assert np.array_equal(q2, qdd)
     cr, sr = ch.rounded(), st.rounded()
+    assert rel_err_rows(q2, oracle.aba(cr, sr.q, sr.qd, sr.tau)).max() <= 1e-4
     e = rel_err_rows(qdd, oracle.aba(cr, sr.q, sr.qd, sr.tau))
     print(f"split fp32 qdd max rel err {e.max():.2e}")
     assert e.max() <= 1e-4
