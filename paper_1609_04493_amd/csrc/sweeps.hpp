@@ -399,8 +399,9 @@ PD_HD void dynamics_one_state(int n, Tab table, WTab wtable, const JointIO<T>& i
       Link<T> L;
       Link<double> Lw;
     };
-    Sp<double> F = cast_sp<double>(bd.Ftip), Fb = F;
-    Sp<double> zA = sp_zero<double>();  // z-hat_{i+1} + U_{i+1} c-hat_{i+1}
+    // F: the wrench of inverse dynamics; Pw: bias wrench plus z-hat_i + U_i c-hat_i, one
+    // recursion (see split_bias_backward)
+    Sp<double> F = cast_sp<double>(bd.Ftip), Pw = F;
     Sym6<T> JA;
     Pose<double> gcw;  // f_{i,i+1} of the child link, double
     Pose<T> gc;        // the same, rounded to T
@@ -434,12 +435,10 @@ PD_HD void dynamics_one_state(int n, Tab table, WTab wtable, const JointIO<T>& i
             scr.check_finite(tau);
           }
           if (kFD) {
-            Sp<double> Fc = has_child ? XT_wrench(gcw, Fb) : Fb;
-            Fb = Fc + cast_sp<double>(x.fb);
-            const double tauhat = (double)x.tau - dot(Lw.S, Fb);
+            // bias wrench plus z-hat_i = X^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}), eq. (8) with Y, Pi expanded
+            const Sp<double> W = (has_child ? XT_wrench(gcw, Pw) : Pw) + cast_sp<double>(x.fb);
             // articulated-body inertia, eq. (7): Jhat_i = J_i + X^T (Jhat_{i+1} - U U^T / D) X
             Sym6<T> Jh = sym6_from_inertia(L.J);
-            Sp<double> z = sp_zero<double>();
             if (has_child) {
               const Sym6<T> P = congruence_to_parent(gc, JA);
               Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
@@ -448,17 +447,15 @@ PD_HD void dynamics_one_state(int n, Tab table, WTab wtable, const JointIO<T>& i
               for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
               Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
               Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
-              // z-hat_i = X^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}), eq. (8) with Y, Pi expanded
-              z = XT_wrench(gcw, zA);
             }
             const Sp<T> U = mul(Jh, L.S);
             const T D = dot(L.S, U);
             scr.check_pivot(D);
             const T invD = T(1) / D;
-            const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
+            const double chat_w = ((double)x.tau - dot(Lw.S, W)) * (double)invD;
             const T chat = (T)chat_w;
             JA = sym6_minus_outer(Jh, U, invD);
-            zA = z + chat_w * cast_sp<double>(U);
+            Pw = W + chat_w * cast_sp<double>(U);
             scr.put(i, 0, U);
             scr.at(i, 6) = invD;
             scr.at(i, 7) = chat;
@@ -675,6 +672,11 @@ PD_HD void split_bias_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> q
 }
 
 // Pass B2 (tip to base, after A): bias wrench in double, tau-hat, z-hat, c-hat.
+// The bias wrench F_i and the articulated term z-hat propagate through the
+// same transforms, so the pass carries their sum P_i = F_i + zA_i (zA_i =
+// z-hat_i + U_i c-hat_i) in one recursion: with W_i = X_{i+1}^T P_{i+1} + Fhat_i
+// = F_i + z-hat_i, c-hat_i = (tau_i - S_i^T W_i) / D_i (as tau-hat_i - S_i^T
+// z-hat_i = tau_i - S_i^T (F_i + z-hat_i)) and P_i = W_i + U_i c-hat_i.
 // FOLD (7-word articulated entries): once link i is done, its entry holds what
 // pass C needs, U_i / D_i in words 0-5 and c-hat_i in word 6, instead of c-hat
 // going to the bias scratch.
@@ -689,7 +691,7 @@ PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, S
     Link<T> L;
     Link<double> Lw;
   };
-  Sp<double> Fb = cast_sp<double>(bd.Ftip), zA = sp_zero<double>();
+  Sp<double> P = cast_sp<double>(bd.Ftip);  // at the tip: the tip wrench, in link n's frame
   Pose<double> gcw;
   pipelined(
       n, n - 1, -1,
@@ -718,15 +720,9 @@ PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, S
           invD = T(1) / dot(L.S, x.U);
           bias.at(i, 7) = invD;
         }
-        Sp<double> z = sp_zero<double>();
-        if (has_child) {
-          Fb = XT_wrench(gcw, Fb);
-          z = XT_wrench(gcw, zA);
-        }
-        Fb = Fb + cast_sp<double>(x.fb);
-        const double tauhat = (double)x.tau - dot(Lw.S, Fb);
-        const double chat_w = (tauhat - dot(Lw.S, z)) * (double)invD;
-        zA = z + chat_w * cast_sp<double>(x.U);
+        const Sp<double> W = (has_child ? XT_wrench(gcw, P) : P) + cast_sp<double>(x.fb);
+        const double chat_w = ((double)x.tau - dot(Lw.S, W)) * (double)invD;
+        P = W + chat_w * cast_sp<double>(x.U);
         if constexpr (FOLD) {
           abi.put(i, 0, invD * x.U);
           abi.at(i, 6) = (T)chat_w;
