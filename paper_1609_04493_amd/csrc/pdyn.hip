@@ -623,26 +623,32 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // barrier X runs the wrench sweep, writing F_i to LDS with a progress word,
 // and Y's adjoint sweep follows it link by link. X then forms the
 // inertia-parameter cotangents.
+// OVERLAP (FD adjoint, when the articulated terms fit in LDS): a third
+// wavefront A runs the articulated-body pass (U_i, 1/D_i into LDS with a
+// progress word) and X's solve follows it, keeping z-hat and c-hat only.
 template <class T, int OP, int PI, bool SHARED, bool OVERLAP>
-__global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+__global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                    const int32_t* __restrict__ order, const T* __restrict__ table,
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
                                                    const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
                                                    T* tau_bar, T* pi_out, const T* __restrict__ tip,
                                                    BoundaryArgs<T> ba, T* scratch, T* xscratch,
                                                    unsigned* status) {
-  constexpr bool kOv = OVERLAP && OP == kVjpID;  // the hand-offs exist for the ID adjoint only
-  extern __shared__ __align__(16) unsigned char lds_vjp[];  // kOv: ring, then F [n_max][6][64]
-  __shared__ int ready, used, fprog;
-  if (kOv) {
+  constexpr bool kOv = OVERLAP && OP == kVjpID;  // ID: ring and wrench hand-offs
+  constexpr bool kAw = OVERLAP && OP == kVjpFD;  // FD: the articulated-body wavefront A
+  // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64]
+  extern __shared__ __align__(16) unsigned char lds_vjp[];
+  __shared__ int ready, used, fprog, aprog;
+  if (kOv || kAw) {
     if (threadIdx.x == 0) {
       ready = 0;
       used = 0;
       fprog = 0;
+      aprog = 0;
     }
     __syncthreads();
   }
-  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y
+  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw)
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
@@ -670,12 +676,20 @@ __global__ void __launch_bounds__(128) k_vjp_split(int n_states, int n_max, cons
   const SPtr<const T> qs(q + dof0), qds(qd + dof0), qdds(qdd + dof0), bar(bar_in + dof0);
   T* const ring = reinterpret_cast<T*>(lds_vjp);
   const Scratch<T> fl{ring + (long)kPoseSlots * kPoseWordsF * 64 + lane, 64L, 6, status};
+  const Scratch<T> abi{reinterpret_cast<T*>(lds_vjp) + lane, 64L, kAbiWords, status};
+  if (kAw && role == 2) {
+    // ends here; the workgroup barrier below waits only for wavefronts still running
+    if (active) split_abi_pass<T, LdsProgress, !SHARED>(n, tab, wtab, qs, abi, LdsProgress{&aprog});
+    return;
+  }
   if (active) {
     if (role == 0) {
       if (kOv)
         vjp_fbar_pass(n, tab, qs, bar, T(1), xs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
       else if (OP == kVjpID)
         vjp_fbar_pass(n, tab, qs, bar, T(1), xs);
+      else if (kAw)
+        fdvjp_solve_with_abi(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs, abi, LdsWait{&aprog});
       else
         fdvjp_solve_pass(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs);
     } else {
@@ -1269,16 +1283,20 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   const bool split = pick_variant(b, false) == 2;
   const unsigned grid64 = (unsigned)((b->n_states + 63) / 64);
   T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
-  // ID adjoint: the wrenches of every link in LDS, after the transform ring
-  const size_t lds = ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T);
-  const bool overlap = OP == kVjpID && lds <= max_lds_bytes();
+  // ID adjoint: the wrenches of every link in LDS, after the transform ring; FD adjoint: the
+  // articulated terms of every link (third wavefront)
+  const size_t lds = OP == kVjpID
+                         ? ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T)
+                         : (size_t)m->n_links_max * kAbiWords * 64 * sizeof(T);
+  const bool overlap = lds <= max_lds_bytes();
+  const unsigned vjp_block = (OP == kVjpFD && overlap) ? 192 : 128;
 #define PDYN_LAUNCH_VJP_SPLIT(PI, SH, OV, PIOUT)                                                              \
   do {                                                                                                        \
     if (OV && lds > 65536 &&                                                                                  \
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_split<T, OP, PI, SH, OV>),                   \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)              \
       return PDYN_ELAUNCH;                                                                                    \
-    hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH, OV>), dim3(grid64), dim3(128), OV ? lds : 0, s,            \
+    hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH, OV>), dim3(grid64), dim3(OV ? vjp_block : 128), OV ? lds : 0, s, \
                        b->n_states, m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in,   \
                        q_bar, qd_bar, qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);           \
   } while (0)

@@ -1083,6 +1083,10 @@ PD_HD void vjp_fbar_pass(int n, Tab table, SPtr<const T> q, SPtr<const T> tb, T 
       });
 }
 
+template <class T, class Tab>
+PD_HD void fdvjp_lambda_pass(int n, Tab table, SPtr<const T> q, SPtr<T> tau_bar, const Scratch<T>& xs,
+                             const Scratch<T>& uv);
+
 // X, FD adjoint: u = M^-1 qdd_bar by the articulated-body solve with tau-hat :=
 // qdd_bar (tip to base: Jhat, U, 1/D, c-hat; base to tip: lambda, u), writing
 // u to tau_bar and, in the base-to-tip pass, Fbar_i = X_i Fbar_{i-1} - u_i S_i.
@@ -1133,27 +1137,74 @@ PD_HD void fdvjp_solve_pass(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr
           gc = cast_pose<T>(gcw);
         });
   }
+  fdvjp_lambda_pass(n, table, q, tau_bar, xs, xs);
+}
+
+// The base-to-tip half of the FD adjoint's solve: lambda and u, then Fbar.
+// U_i and 1/D_i come from words 0-6 of `uv` (X's own scratch, or the LDS
+// entries of pass A), c-hat_i and (sin, cos) from words 7-9 of xs; Fbar_i
+// replaces words 0-5 of xs.
+template <class T, class Tab>
+PD_HD void fdvjp_lambda_pass(int n, Tab table, SPtr<const T> q, SPtr<T> tau_bar, const Scratch<T>& xs,
+                             const Scratch<T>& uv) {
+  struct In {
+    Sp<T> U;
+    T invD, chat, sn, cs, q;
+  };
+  Sp<T> lam = sp_zero<T>(), Fb = sp_zero<T>();
+  pipelined(
+      n, 0, 1,
+      [&](int i) { return In{uv.get(i, 0), uv.at(i, 6), xs.at(i, 7), xs.at(i, 8), xs.at(i, 9), q[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = link_at(table, i);
+        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        const Sp<T> a = X_twist(g, lam);
+        const T u = x.chat - dot(x.U, a) * x.invD;
+        lam = a + u * L.S;
+        tau_bar[i] = u;
+        xs.check_finite(u);
+        Fb = X_twist(g, Fb) - u * L.S;
+        xs.put(i, 0, Fb);
+      });
+}
+
+// X of the FD adjoint when another wavefront runs the articulated-body pass
+// (split_abi_pass into `abi`, 7 words per link): the tip-to-base half keeps
+// z-hat and c-hat only, taking U_i and 1/D_i from abi once need(n - i) says
+// link i is there; then fdvjp_lambda_pass. Same arithmetic as fdvjp_solve_pass.
+template <class T, class Need, class Tab = const T*, class WTab = const double*>
+PD_HD void fdvjp_solve_with_abi(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> bar,
+                                SPtr<T> tau_bar, const Scratch<T>& xs, const Scratch<T>& abi, const Need& need) {
   {
     struct In {
+      T q, bar;
       Sp<T> U;
-      T invD, chat, sn, cs, q;
+      T invD;
     };
-    Sp<T> lam = sp_zero<T>(), Fb = sp_zero<T>();
+    Sp<double> zA = sp_zero<double>();
+    Pose<double> gcw;
     pipelined(
-        n, 0, 1,
-        [&](int i) { return In{xs.get(i, 0), xs.at(i, 6), xs.at(i, 7), xs.at(i, 8), xs.at(i, 9), q[i]}; },
+        n, n - 1, -1,
+        [&](int i) {
+          need(n - i);
+          return In{q[i], bar[i], abi.get(i, 0), abi.at(i, 6)};
+        },
         [&](int i, const In& x) {
+          const bool has_child = (i < n - 1);
           const Link<T> L = link_at(table, i);
-          const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
-          const Sp<T> a = X_twist(g, lam);
-          const T u = x.chat - dot(x.U, a) * x.invD;
-          lam = a + u * L.S;
-          tau_bar[i] = u;
-          xs.check_finite(u);
-          Fb = X_twist(g, Fb) - u * L.S;
-          xs.put(i, 0, Fb);
+          const Link<double> Lw = link_at(wtable, i);
+          const Sp<double> z = has_child ? XT_wrench(gcw, zA) : sp_zero<double>();
+          const double chat_w = ((double)x.bar - dot(Lw.S, z)) * (double)x.invD;
+          zA = z + chat_w * cast_sp<double>(x.U);
+          T sn, cs;
+          joint_sincos(L, x.q, &sn, &cs);
+          xs.at(i, 7) = (T)chat_w;
+          xs.at(i, 8) = sn;
+          xs.at(i, 9) = cs;
+          gcw = joint_transform_wide_sc(Lw, x.q, sn, cs);
         });
   }
+  fdvjp_lambda_pass(n, table, q, tau_bar, xs, abi);
 }
 
 // Y: sweep 1 of ID at (q, qd, qdd) keeping Fhat, V, A and (sin, cos); the

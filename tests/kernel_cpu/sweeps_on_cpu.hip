@@ -192,8 +192,17 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
         vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, io.qdd_bar, fl);
         continue;
       }
-      if (op == 2) vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
-      else fdvjp_solve_pass(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs);
+      if (op == 5) {
+        // FD adjoint as with the third wavefront: pass A into its own array, then X's solve from it
+        std::vector<T> abuf((size_t)n * kAbiWords);
+        const Scratch<T> abi{abuf.data(), 1, kAbiWords};
+        split_abi_pass(n, tab, wtab, io.q, abi);
+        fdvjp_solve_with_abi(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs, abi, NoHandoff());
+      } else if (op == 2) {
+        vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
+      } else {
+        fdvjp_solve_pass(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs);
+      }
       vjp_newton_euler_pass(n, tab, wtab, io.q, io.qd, io.qdd, bd, scr);
       vjp_inertia_pass(n, tab, xs, scr, sink);
       vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, op == 2 ? io.qdd_bar : SPtr<T>(), scr);

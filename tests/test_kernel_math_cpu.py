@@ -225,6 +225,12 @@ def test_role_split_adjoint_passes_match_the_fused_adjoints(cpu_lib):
     for x, y in zip(a[:3], b[:3]):
         assert np.array_equal(x, y)
     assert np.array_equal(pa, pb)
+    # the FD adjoint with the articulated-body pass on a third wavefront: the same bits
+    a, pa = run_vjp_cpu(cpu_lib, 3, ch, st.q, st.qd, qdd_fd, bar, np.float64)
+    b, pb = run_vjp_cpu(cpu_lib, 5, ch, st.q, st.qd, qdd_fd, bar, np.float64)
+    for k in (0, 1, 3):
+        assert np.array_equal(a[k], b[k])
+    assert np.array_equal(pa, pb)
     (qb, qdb, _, tb), pib = run_vjp_cpu(cpu_lib, 3, ch, st.q, st.qd, qdd_fd, bar, np.float64)
     for c in range(ch.n_chains):
         lo, hi = ch.link_ptr[c], ch.link_ptr[c + 1]
