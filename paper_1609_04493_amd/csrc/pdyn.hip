@@ -319,6 +319,49 @@ template <class T> struct RingTakeF2 {
     LdsProgress{used}(i + 1);
   }
 };
+// The adjoint sweep's hand-off: (Abar_i, Vbar_i, ybar_i) of the k-th link from
+// the tip, from the recursion wavefront to the one that forms the outputs.
+constexpr int kBackWords = 18;
+template <class T> struct RingPutBack {
+  T* ring;  // [kPoseSlots][kBackWords][64 lanes]
+  int* ready;
+  int* used;
+  int lane;
+  LdsWait wait{used};
+  __device__ void operator()(int k, const Sp<T>& a, const Sp<T>& v, const Sp<T>& y) const {
+    wait(k - kPoseSlots + 1);
+    T* w = ring + (long)(k % kPoseSlots) * kBackWords * 64 + lane;
+    const Sp<T> e[3] = {a, v, y};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      w[(6 * j + 0) * 64] = e[j].a.x;
+      w[(6 * j + 1) * 64] = e[j].a.y;
+      w[(6 * j + 2) * 64] = e[j].a.z;
+      w[(6 * j + 3) * 64] = e[j].b.x;
+      w[(6 * j + 4) * 64] = e[j].b.y;
+      w[(6 * j + 5) * 64] = e[j].b.z;
+    }
+    LdsProgress{ready}(k + 1);
+  }
+};
+template <class T> struct RingGetBack {
+  const T* ring;
+  int* ready;
+  int* used;
+  int lane;
+  LdsWait wait{ready};
+  __device__ void operator()(int k, Sp<T>* a, Sp<T>* v, Sp<T>* y) const {
+    wait(k + 1);
+    const T* r = ring + (long)(k % kPoseSlots) * kBackWords * 64 + lane;
+    Sp<T>* e[3] = {a, v, y};
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      *e[j] = {v3(r[(6 * j + 0) * 64], r[(6 * j + 1) * 64], r[(6 * j + 2) * 64]),
+               v3(r[(6 * j + 3) * 64], r[(6 * j + 4) * 64], r[(6 * j + 5) * 64])};
+    LdsProgress{used}(k + 1);
+  }
+};
+
 // Pass C's epilogue in LDS: qdd_i into word 0 of link i's articulated entry.
 template <class T> struct StashQdd {
   Scratch<T> abi;
@@ -626,7 +669,12 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // OVERLAP (FD adjoint, when the articulated terms fit in LDS): a third
 // wavefront A runs the articulated-body pass (U_i, 1/D_i into LDS with a
 // progress word) and X's solve follows it, keeping z-hat and c-hat only.
-template <class T, int OP, int PI, bool SHARED, bool OVERLAP>
+// OVERLAP == 2 (when one more ring fits): the adjoint sweep is cut in two
+// after the barrier. Y runs its recursion and hands (Abar_i, Vbar_i, ybar_i)
+// through an LDS ring to the third wavefront (A for FD, a wavefront of its
+// own for ID), which forms q_bar, qd_bar and qdd_bar link by link; X runs the
+// wrench sweep (ID) and the inertia-parameter cotangents.
+template <class T, int OP, int PI, bool SHARED, int OVERLAP>
 __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                    const int32_t* __restrict__ order, const T* __restrict__ table,
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
@@ -634,21 +682,25 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
                                                    T* tau_bar, T* pi_out, const T* __restrict__ tip,
                                                    BoundaryArgs<T> ba, T* scratch, T* xscratch,
                                                    unsigned* status) {
-  constexpr bool kOv = OVERLAP && OP == kVjpID;  // ID: ring and wrench hand-offs
-  constexpr bool kAw = OVERLAP && OP == kVjpFD;  // FD: the articulated-body wavefront A
-  // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64]
+  constexpr bool kOv = OVERLAP >= 1 && OP == kVjpID;  // ID: ring and wrench hand-offs
+  constexpr bool kAw = OVERLAP >= 1 && OP == kVjpFD;  // FD: the articulated-body wavefront A
+  constexpr bool kCut = OVERLAP == 2;                 // the adjoint sweep on two wavefronts
+  // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64]; then (kCut)
+  // the (Abar, Vbar, ybar) ring [kPoseSlots][kBackWords][64]
   extern __shared__ __align__(16) unsigned char lds_vjp[];
-  __shared__ int ready, used, fprog, aprog;
+  __shared__ int ready, used, fprog, aprog, bready, bused;
   if (kOv || kAw) {
     if (threadIdx.x == 0) {
       ready = 0;
       used = 0;
       fprog = 0;
       aprog = 0;
+      bready = 0;
+      bused = 0;
     }
     __syncthreads();
   }
-  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw)
+  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw) or the outputs (kCut)
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
@@ -677,12 +729,14 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
   T* const ring = reinterpret_cast<T*>(lds_vjp);
   const Scratch<T> fl{ring + (long)kPoseSlots * kPoseWordsF * 64 + lane, 64L, 6, status};
   const Scratch<T> abi{reinterpret_cast<T*>(lds_vjp) + lane, 64L, kAbiWords, status};
+  T* const bring = reinterpret_cast<T*>(lds_vjp) +
+                   (kOv ? ((long)kPoseSlots * kPoseWordsF + (long)n_max * 6) * 64 : (long)n_max * kAbiWords * 64);
   if (kAw && role == 2) {
-    // ends here; the workgroup barrier below waits only for wavefronts still running
     if (active) split_abi_pass<T, LdsProgress, !SHARED>(n, tab, wtab, qs, abi, LdsProgress{&aprog});
-    return;
+    // without the cut sweep it ends here; the workgroup barrier waits only for wavefronts still running
+    if (!kCut) return;
   }
-  if (active) {
+  if (active && role < 2) {
     if (role == 0) {
       if (kOv)
         vjp_fbar_pass(n, tab, qs, bar, T(1), xs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
@@ -701,6 +755,30 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
   }
   __syncthreads();
   if (!active) return;
+  if (kCut) {
+    const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>();
+    if (role == 0) {
+      if (kOv) vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
+      if (PI != kPiNone) {
+        PiSink<T, PI> sink;
+        sink.out = (PI == kPiLanes) ? pi_out + lane_index : pi_out + link0 * 10;
+        sink.stride = (PI == kPiLanes) ? n_states : 1;
+        vjp_inertia_pass(n, tab, xs, scr, sink);
+      }
+    } else if (role == 1) {
+      vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane});
+    } else {
+      PiSink<T, kPiNone> sink;  // the inertia cotangents are X's
+      const RingGetBack<T> get{bring, &bready, &bused, lane};
+      if (kOv)
+        vjp_back_outputs(n, tab, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, fl,
+                         LdsWait{&fprog}, get, sink);
+      else
+        vjp_back_outputs(n, tab, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, scr,
+                         NoHandoff(), get, sink);
+    }
+    return;
+  }
   if (role == 0) {
     if (kOv) vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
     if (PI != kPiNone) {
@@ -1285,11 +1363,13 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
   // ID adjoint: the wrenches of every link in LDS, after the transform ring; FD adjoint: the
   // articulated terms of every link (third wavefront)
-  const size_t lds = OP == kVjpID
-                         ? ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T)
-                         : (size_t)m->n_links_max * kAbiWords * 64 * sizeof(T);
-  const bool overlap = lds <= max_lds_bytes();
-  const unsigned vjp_block = (OP == kVjpFD && overlap) ? 192 : 128;
+  const size_t lds1 = OP == kVjpID
+                          ? ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T)
+                          : (size_t)m->n_links_max * kAbiWords * 64 * sizeof(T);
+  const size_t lds2 = lds1 + (size_t)kPoseSlots * kBackWords * 64 * sizeof(T);  // and the cut sweep's ring
+  const int ovl = lds2 <= max_lds_bytes() ? 2 : (lds1 <= max_lds_bytes() ? 1 : 0);
+  const size_t lds = ovl == 2 ? lds2 : lds1;
+  const unsigned vjp_block = (ovl == 2 || (OP == kVjpFD && ovl == 1)) ? 192 : 128;
 #define PDYN_LAUNCH_VJP_SPLIT(PI, SH, OV, PIOUT)                                                              \
   do {                                                                                                        \
     if (OV && lds > 65536 &&                                                                                  \
@@ -1302,10 +1382,12 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   } while (0)
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
   do {                                                                                                        \
-    if (split && overlap)                                                                                     \
-      PDYN_LAUNCH_VJP_SPLIT(PI, SH, true, PIOUT);                                                             \
+    if (split && ovl == 2)                                                                                    \
+      PDYN_LAUNCH_VJP_SPLIT(PI, SH, 2, PIOUT);                                                                \
+    else if (split && ovl == 1)                                                                               \
+      PDYN_LAUNCH_VJP_SPLIT(PI, SH, 1, PIOUT);                                                                \
     else if (split)                                                                                           \
-      PDYN_LAUNCH_VJP_SPLIT(PI, SH, false, PIOUT);                                                            \
+      PDYN_LAUNCH_VJP_SPLIT(PI, SH, 0, PIOUT);                                                                \
     else                                                                                                      \
       hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
                          m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \

@@ -1321,6 +1321,72 @@ PD_HD void vjp_back_pass(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, SP
       });
 }
 
+// The same sweep with vjp_inertia_pass, cut in two for two wavefronts.
+// vjp_back_recursion runs the tip-to-base recursion (Abar, Vbar, ybar and
+// their transport to the parent) and hands link i's (Abar_i, Vbar_i, ybar_i)
+// to put(k, ...), k = n - 1 - i. vjp_back_outputs takes them with get(k) and
+// forms q_bar, qd_bar, qdd_bar of link i, which need no recursion (fsrc and
+// need as in vjp_back_pass), and hands the inertia-parameter cotangents to
+// sink (a sink that drops them leaves them to vjp_inertia_pass). Together they
+// do the arithmetic of vjp_back_pass and vjp_inertia_pass.
+template <class T, class Put, class Tab = const T*>
+PD_HD void vjp_back_recursion(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, const Scratch<T>& xs,
+                              const Scratch<T>& scr, const Put& put) {
+  struct In {
+    Sp<T> Fb, V;
+    T sn, cs, q, qd;
+  };
+  Sp<T> Ac = sp_zero<T>(), yc = sp_zero<T>();
+  pipelined(
+      n, n - 1, -1,
+      [&](int i) { return In{xs.get(i, 0), scr.get(i, 6), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i], qd[i]}; },
+      [&](int i, const In& x) {
+        const Link<T> L = link_at(table, i);
+        const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
+        const Sp<T> Vb = adT_wrench(x.Fb, mul(L.J, x.V)) - mul(L.J, ad_twist(x.V, x.Fb)) + yc;
+        const Sp<T> Sqd = x.qd * L.S;
+        const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
+        put(n - 1 - i, Ab, Vb, yb);
+        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        Ac = XT_wrench(g, Ab);
+        yc = XT_wrench(g, yb);
+      });
+}
+template <class T, class Get, class Need, class Sink, class Tab = const T*>
+PD_HD void vjp_back_outputs(int n, Tab table, SPtr<const T> qd, SPtr<const T> qdd, const Scratch<T>& xs,
+                            const Scratch<T>& scr, SPtr<T> q_bar, SPtr<T> qd_bar, SPtr<T> qdd_bar,
+                            const Scratch<T>& fsrc, const Need& need, const Get& get, Sink& sink) {
+  struct In {
+    Sp<T> Fb, F, V, A;
+    T qd, qdd;
+  };
+  pipelined(
+      n, n - 1, -1,
+      [&](int i) {
+        need(n - i);
+        return In{xs.get(i, 0), fsrc.get(i, 0), scr.get(i, 6), scr.get(i, 12), qd[i], qdd[i]};
+      },
+      [&](int i, const In& x) {
+        const Link<T> L = link_at(table, i);
+        Sp<T> Ab, Vb, yb;
+        get(n - 1 - i, &Ab, &Vb, &yb);
+        const T qbp = -dot(ad_twist(L.S, x.Fb), x.F);
+        const Sp<T> Sqd = x.qd * L.S;
+        const Sp<T> y = x.V - Sqd;
+        const Sp<T> XA = x.A - x.qdd * L.S + ad_twist(Sqd, y);
+        if (qdd_bar) qdd_bar[i] = dot(L.S, Ab);
+        qd_bar[i] = dot(L.S, Vb) + dot(ad_twist(y, L.S), Ab);
+        const T qb = qbp - dot(ad_twist(L.S, XA), Ab) - dot(ad_twist(L.S, y), yb);
+        q_bar[i] = qb;
+        scr.check_finite(qb);
+        T gpi[10] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+        const V3<T> c = (T(1) / L.J.m) * L.J.h;
+        add_inertia_grad(L.J.m, c, x.Fb, x.A, T(1), gpi);
+        add_inertia_grad(L.J.m, c, ad_twist(x.V, x.Fb), x.V, T(-1), gpi);
+        sink.put(i, gpi);
+      });
+}
+
 // ============================================================================
 // Rollouts: semi-implicit Euler driven by the forward dynamics,
 //   qdd_t = FD(q_t, qd_t, tau_t);  qd_{t+1} = qd_t + dt qdd_t;  q_{t+1} = q_t + dt qd_{t+1},

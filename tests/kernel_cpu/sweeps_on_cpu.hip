@@ -192,20 +192,39 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
         vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, io.qdd_bar, fl);
         continue;
       }
-      if (op == 5) {
+      const int pre = op == 6 ? 2 : (op == 7 ? 3 : op);  // ops 6, 7: ops 2, 3 with the adjoint sweep cut in two
+      if (pre == 5) {
         // FD adjoint as with the third wavefront: pass A into its own array, then X's solve from it
         std::vector<T> abuf((size_t)n * kAbiWords);
         const Scratch<T> abi{abuf.data(), 1, kAbiWords};
         split_abi_pass(n, tab, wtab, io.q, abi);
         fdvjp_solve_with_abi(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs, abi, NoHandoff());
-      } else if (op == 2) {
+      } else if (pre == 2) {
         vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
       } else {
         fdvjp_solve_pass(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs);
       }
       vjp_newton_euler_pass(n, tab, wtab, io.q, io.qd, io.qdd, bd, scr);
-      vjp_inertia_pass(n, tab, xs, scr, sink);
-      vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, op == 2 ? io.qdd_bar : SPtr<T>(), scr);
+      const SPtr<T> qddb = pre == 2 ? io.qdd_bar : SPtr<T>();
+      if (op == 6 || op == 7) {
+        // the recursion hands (Abar, Vbar, ybar) of each link through an array (an LDS ring in the kernel)
+        std::vector<Sp<T>> hand((size_t)n * 3);
+        vjp_back_recursion(n, tab, io.q, io.qd, xs, scr, [&](int k, const Sp<T>& a, const Sp<T>& v, const Sp<T>& y) {
+          hand[3 * (size_t)k] = a;
+          hand[3 * (size_t)k + 1] = v;
+          hand[3 * (size_t)k + 2] = y;
+        });
+        vjp_back_outputs(n, tab, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, qddb, scr, NoHandoff(),
+                         [&](int k, Sp<T>* a, Sp<T>* v, Sp<T>* y) {
+                           *a = hand[3 * (size_t)k];
+                           *v = hand[3 * (size_t)k + 1];
+                           *y = hand[3 * (size_t)k + 2];
+                         },
+                         sink);
+      } else {
+        vjp_inertia_pass(n, tab, xs, scr, sink);
+        vjp_back_pass(n, tab, io.q, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, qddb, scr);
+      }
     }
   }
   return 0;

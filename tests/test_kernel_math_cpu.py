@@ -225,6 +225,13 @@ def test_role_split_adjoint_passes_match_the_fused_adjoints(cpu_lib):
     for x, y in zip(a[:3], b[:3]):
         assert np.array_equal(x, y)
     assert np.array_equal(pa, pb)
+    # the adjoint sweep cut into a recursion and a pointwise half (with the inertia cotangents): the same bits
+    for op_split, op_cut, qdd in ((2, 6, st.qdd), (3, 7, qdd_fd)):
+        a, pa = run_vjp_cpu(cpu_lib, op_split, ch, st.q, st.qd, qdd, bar, np.float64)
+        b, pb = run_vjp_cpu(cpu_lib, op_cut, ch, st.q, st.qd, qdd, bar, np.float64)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        assert np.array_equal(pa, pb)
     # the FD adjoint with the articulated-body pass on a third wavefront: the same bits
     a, pa = run_vjp_cpu(cpu_lib, 3, ch, st.q, st.qd, qdd_fd, bar, np.float64)
     b, pb = run_vjp_cpu(cpu_lib, 5, ch, st.q, st.qd, qdd_fd, bar, np.float64)
