@@ -245,6 +245,32 @@ def test_adjoint_variants(device, variant):
             api.set_launch(op, 0, 0, 0)
 
 
+@pytest.mark.parametrize("n", [6, 60])
+def test_adjoint_lds_levels(device, n):
+    """The role-split adjoints at the LDS levels the chain length selects (FP64: 6 links, the adjoint sweep on
+    two wavefronts with every hand-off in LDS; 60 links, no LDS hand-off), 67 states (a ragged second group),
+    cotangents on 4 sampled states, against the oracle."""
+    print(f"case: adjoint LDS level, fp64 {n} links", flush=True)
+    ch = synth.make_chains([n], 60 + n)
+    st = synth.make_states((67, n), 60 + n)
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    idx = np.array([0, 17, 63, 66])
+    bar = np.zeros((67, n))
+    bar[idx] = np.random.default_rng(n).standard_normal((len(idx), n))
+    qb, qdb, qddb, pib = (x.cpu().numpy() for x in api.rnea_id_vjp(model, d(st.q), d(st.qd), d(st.qdd), d(bar)))
+    (rq, rqd, rqdd), rpi = id_refs(ch, st, bar, idx)
+    for k, s in enumerate(idx):
+        assert max(rel(qb[s], rq[k]), rel(qdb[s], rqd[k]), rel(qddb[s], rqdd[k])) <= 1e-10, s
+    assert rel(pib, rpi) <= 1e-10
+    qdd = oracle.aba(ch, st.q, st.qd, st.tau)
+    fb, fdb, ftb, fpib = (x.cpu().numpy() for x in api.aba_fd_vjp(model, d(st.q), d(st.qd), d(qdd), d(bar)))
+    (rq, rqd, rt), rpi = fd_refs(ch, st, bar, idx)
+    for k, s in enumerate(idx):
+        assert max(rel(fb[s], rq[k]), rel(fdb[s], rqd[k]), rel(ftb[s], rt[k])) <= 1e-10, s
+    assert rel(fpib, rpi) <= 1e-10
+
+
 def test_jacobian_mode_50_links_8192_states(device):
     """Full FD Jacobians of the 50-link, 8192-state workload by stacked one-hot cotangents: 64 sampled
     states against the oracle's complex-step Jacobians; at every state dqdd/dtau (= M^-1) times the ID
