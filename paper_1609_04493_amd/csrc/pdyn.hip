@@ -668,14 +668,15 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // inertia-parameter cotangents.
 // OVERLAP (FD adjoint, when the articulated terms fit in LDS): a third
 // wavefront A runs the articulated-body pass (U_i, 1/D_i into LDS with a
-// progress word) and X's solve follows it, keeping z-hat and c-hat only.
+// progress word) and X's solve follows it, keeping z-hat and c-hat only; a
+// fourth, P_b, forms A's transforms and hands them over through a ring.
 // OVERLAP == 2 (when one more ring fits): the adjoint sweep is cut in two
 // after the barrier. Y runs its recursion and hands (Abar_i, Vbar_i, ybar_i)
 // through an LDS ring to the third wavefront (A for FD, a wavefront of its
 // own for ID), which forms q_bar, qd_bar and qdd_bar link by link; X runs the
 // wrench sweep (ID) and the inertia-parameter cotangents.
 template <class T, int OP, int PI, bool SHARED, int OVERLAP>
-__global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
+__global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                    const int32_t* __restrict__ order, const T* __restrict__ table,
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
                                                    const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
@@ -685,10 +686,10 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
   constexpr bool kOv = OVERLAP >= 1 && OP == kVjpID;  // ID: ring and wrench hand-offs
   constexpr bool kAw = OVERLAP >= 1 && OP == kVjpFD;  // FD: the articulated-body wavefront A
   constexpr bool kCut = OVERLAP == 2;                 // the adjoint sweep on two wavefronts
-  // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64]; then (kCut)
-  // the (Abar, Vbar, ybar) ring [kPoseSlots][kBackWords][64]
+  // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64], then P_b's ring
+  // [kPoseSlots][kPoseWordsB][64]; then (kCut) the (Abar, Vbar, ybar) ring [kPoseSlots][kBackWords][64]
   extern __shared__ __align__(16) unsigned char lds_vjp[];
-  __shared__ int ready, used, fprog, aprog, bready, bused;
+  __shared__ int ready, used, fprog, aprog, bready, bused, pready, pused;
   if (kOv || kAw) {
     if (threadIdx.x == 0) {
       ready = 0;
@@ -697,10 +698,13 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
       aprog = 0;
       bready = 0;
       bused = 0;
+      pready = 0;
+      pused = 0;
     }
     __syncthreads();
   }
-  const int role = threadIdx.x / 64;  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw) or the outputs (kCut)
+  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw) or the outputs (kCut), 3 = P_b (kAw)
+  const int role = threadIdx.x / 64;
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
@@ -729,11 +733,20 @@ __global__ void __launch_bounds__(192) k_vjp_split(int n_states, int n_max, cons
   T* const ring = reinterpret_cast<T*>(lds_vjp);
   const Scratch<T> fl{ring + (long)kPoseSlots * kPoseWordsF * 64 + lane, 64L, 6, status};
   const Scratch<T> abi{reinterpret_cast<T*>(lds_vjp) + lane, 64L, kAbiWords, status};
+  T* const pring = reinterpret_cast<T*>(lds_vjp) + (long)n_max * kAbiWords * 64;
   T* const bring = reinterpret_cast<T*>(lds_vjp) +
-                   (kOv ? ((long)kPoseSlots * kPoseWordsF + (long)n_max * 6) * 64 : (long)n_max * kAbiWords * 64);
+                   (kOv ? ((long)kPoseSlots * kPoseWordsF + (long)n_max * 6) * 64
+                        : (long)n_max * kAbiWords * 64 + (long)kPoseSlots * kPoseWordsB * 64);
+  if (kAw && role == 3) {
+    // ends here; the workgroup barrier waits only for wavefronts still running
+    if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{pring, &pready, &pused, lane});
+    return;
+  }
   if (kAw && role == 2) {
-    if (active) split_abi_pass<T, LdsProgress, !SHARED>(n, tab, wtab, qs, abi, LdsProgress{&aprog});
-    // without the cut sweep it ends here; the workgroup barrier waits only for wavefronts still running
+    if (active)
+      split_abi_from_poses(n, tab, abi, RingGetB<T>{pring, &pready, lane}, LdsProgress{&pused},
+                           LdsProgress{&aprog});
+    // without the cut sweep it ends here
     if (!kCut) return;
   }
   if (active && role < 2) {
@@ -1365,11 +1378,11 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   // articulated terms of every link (third wavefront)
   const size_t lds1 = OP == kVjpID
                           ? ((size_t)kPoseSlots * kPoseWordsF + (size_t)m->n_links_max * 6) * 64 * sizeof(T)
-                          : (size_t)m->n_links_max * kAbiWords * 64 * sizeof(T);
+                          : ((size_t)m->n_links_max * kAbiWords + (size_t)kPoseSlots * kPoseWordsB) * 64 * sizeof(T);
   const size_t lds2 = lds1 + (size_t)kPoseSlots * kBackWords * 64 * sizeof(T);  // and the cut sweep's ring
   const int ovl = lds2 <= max_lds_bytes() ? 2 : (lds1 <= max_lds_bytes() ? 1 : 0);
   const size_t lds = ovl == 2 ? lds2 : lds1;
-  const unsigned vjp_block = (ovl == 2 || (OP == kVjpFD && ovl == 1)) ? 192 : 128;
+  const unsigned vjp_block = (OP == kVjpFD && ovl >= 1) ? 256 : (ovl == 2 ? 192 : 128);
 #define PDYN_LAUNCH_VJP_SPLIT(PI, SH, OV, PIOUT)                                                              \
   do {                                                                                                        \
     if (OV && lds > 65536 &&                                                                                  \

@@ -194,10 +194,13 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
       }
       const int pre = op == 6 ? 2 : (op == 7 ? 3 : op);  // ops 6, 7: ops 2, 3 with the adjoint sweep cut in two
       if (pre == 5) {
-        // FD adjoint as with the third wavefront: pass A into its own array, then X's solve from it
+        // FD adjoint as with the third and fourth wavefronts: P_b's transforms (an array here, an LDS ring
+        // in the kernel) into pass A, A's terms into their own array, then X's solve from them
+        std::vector<Pose<T>> poses_b((size_t)n);
+        split_pose_bwd(n, tab, wtab, io.q, [&](int k, const Pose<T>& g) { poses_b[(size_t)k] = g; });
         std::vector<T> abuf((size_t)n * kAbiWords);
         const Scratch<T> abi{abuf.data(), 1, kAbiWords};
-        split_abi_pass(n, tab, wtab, io.q, abi);
+        split_abi_from_poses(n, tab, abi, [&](int k) { return poses_b[(size_t)k]; }, NoHandoff(), NoHandoff());
         fdvjp_solve_with_abi(n, tab, wtab, io.q, io.bar_in, io.tau_bar, xs, abi, NoHandoff());
       } else if (pre == 2) {
         vjp_fbar_pass(n, tab, io.q, io.bar_in, T(1), xs);
