@@ -673,8 +673,9 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // OVERLAP == 2 (when one more ring fits): the adjoint sweep is cut in two
 // after the barrier. Y runs its recursion and hands (Abar_i, Vbar_i, ybar_i)
 // through an LDS ring to the third wavefront (A for FD, a wavefront of its
-// own for ID), which forms q_bar, qd_bar and qdd_bar link by link; X runs the
-// wrench sweep (ID) and the inertia-parameter cotangents.
+// own for ID), which forms q_bar, qd_bar and qdd_bar link by link. For ID, X
+// runs the wrench sweep and a fourth wavefront the inertia-parameter
+// cotangents; for FD, X runs the cotangents.
 template <class T, int OP, int PI, bool SHARED, int OVERLAP>
 __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
                                                    const int32_t* __restrict__ order, const T* __restrict__ table,
@@ -703,7 +704,8 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
     }
     __syncthreads();
   }
-  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw) or the outputs (kCut), 3 = P_b (kAw)
+  // wave-uniform: 0 = X, 1 = Y, 2 = A (kAw) or the outputs (kCut), 3 = P_b (kAw) or, for ID with
+  // kCut, the inertia-parameter cotangents
   const int role = threadIdx.x / 64;
   const int lane = (int)(threadIdx.x % 64);
   const int lane_index = blockIdx.x * 64 + lane;
@@ -770,14 +772,16 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   if (!active) return;
   if (kCut) {
     const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>();
-    if (role == 0) {
-      if (kOv) vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
+    // the inertia-parameter cotangents: X's for FD, a fourth wavefront's for ID (beside X's wrench sweep)
+    if ((role == 0 && kAw) || role == 3) {
       if (PI != kPiNone) {
         PiSink<T, PI> sink;
         sink.out = (PI == kPiLanes) ? pi_out + lane_index : pi_out + link0 * 10;
         sink.stride = (PI == kPiLanes) ? n_states : 1;
         vjp_inertia_pass(n, tab, xs, scr, sink);
       }
+    } else if (role == 0) {
+      vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
     } else if (role == 1) {
       vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane});
     } else {
@@ -1382,7 +1386,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   const size_t lds2 = lds1 + (size_t)kPoseSlots * kBackWords * 64 * sizeof(T);  // and the cut sweep's ring
   const int ovl = lds2 <= max_lds_bytes() ? 2 : (lds1 <= max_lds_bytes() ? 1 : 0);
   const size_t lds = ovl == 2 ? lds2 : lds1;
-  const unsigned vjp_block = (OP == kVjpFD && ovl >= 1) ? 256 : (ovl == 2 ? 192 : 128);
+  const unsigned vjp_block = ((OP == kVjpFD && ovl >= 1) || ovl == 2) ? 256 : 128;
 #define PDYN_LAUNCH_VJP_SPLIT(PI, SH, OV, PIOUT)                                                              \
   do {                                                                                                        \
     if (OV && lds > 65536 &&                                                                                  \
