@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   // kOv: ring, then F [n_max][6][64]; kAw: U_i, 1/D_i [n_max][kAbiWords][64], then P_b's ring
   // [kPoseSlots][kPoseWordsB][64]; then (kCut) the (Abar, Vbar, ybar) ring [kPoseSlots][kBackWords][64]
   extern __shared__ __align__(16) unsigned char lds_vjp[];
-  __shared__ int ready, used, fprog, aprog, bready, bused, pready, pused;
+  __shared__ int ready, used, fprog, aprog, bready, bused, pready, pused, qready, qused;
   if (kOv || kAw) {
     if (threadIdx.x == 0) {
       ready = 0;
@@ -701,6 +701,8 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
       bused = 0;
       pready = 0;
       pused = 0;
+      qready = 0;
+      qused = 0;
     }
     __syncthreads();
   }
@@ -740,9 +742,9 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
                    (kOv ? ((long)kPoseSlots * kPoseWordsF + (long)n_max * 6) * 64
                         : (long)n_max * kAbiWords * 64 + (long)kPoseSlots * kPoseWordsB * 64);
   if (kAw && role == 3) {
-    // ends here; the workgroup barrier waits only for wavefronts still running
     if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{pring, &pready, &pused, lane});
-    return;
+    // without the cut sweep it ends here; the workgroup barrier waits only for wavefronts still running
+    if (!kCut) return;
   }
   if (kAw && role == 2) {
     if (active)
@@ -772,6 +774,12 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   if (!active) return;
   if (kCut) {
     const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>();
+    // FD: P_b forms the transforms of Y's recursion again, tip to base, through its ring (A took every
+    // entry of the first round before the barrier)
+    if (kAw && role == 3) {
+      split_pose_bwd_sc(n, tab, qs, RingPutB<T>{pring, &qready, &qused, lane});
+      return;
+    }
     // the inertia-parameter cotangents: X's for FD, a fourth wavefront's for ID (beside X's wrench sweep)
     if ((role == 0 && kAw) || role == 3) {
       if (PI != kPiNone) {
@@ -783,7 +791,11 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
     } else if (role == 0) {
       vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
     } else if (role == 1) {
-      vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane});
+      if (kAw)
+        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane},
+                           RingGetB<T>{pring, &qready, lane}, LdsProgress{&qused});
+      else
+        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane});
     } else {
       PiSink<T, kPiNone> sink;  // the inertia cotangents are X's
       const RingGetBack<T> get{bring, &bready, &bused, lane};

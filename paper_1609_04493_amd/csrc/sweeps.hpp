@@ -1329,9 +1329,15 @@ PD_HD void vjp_back_pass(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, SP
 // need as in vjp_back_pass), and hands the inertia-parameter cotangents to
 // sink (a sink that drops them leaves them to vjp_inertia_pass). Together they
 // do the arithmetic of vjp_back_pass and vjp_inertia_pass.
-template <class T, class Put, class Tab = const T*>
+// Where vjp_back_recursion gets link i's transform: formed from the stored
+// (sin, cos) by default; a caller may hand in get(k) (the k-th link from the
+// tip, as split_pose_bwd_sc forms it) and release(m) (the first m are used).
+struct FormStoredPose {};
+template <class T, class Put, class Get = FormStoredPose, class Release = NoHandoff, class Tab = const T*>
 PD_HD void vjp_back_recursion(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, const Scratch<T>& xs,
-                              const Scratch<T>& scr, const Put& put) {
+                              const Scratch<T>& scr, const Put& put, const Get& get = Get(),
+                              const Release& release = Release()) {
+  constexpr bool kForm = std::is_same<Get, FormStoredPose>::value;
   struct In {
     Sp<T> Fb, V;
     T sn, cs, q, qd;
@@ -1339,7 +1345,12 @@ PD_HD void vjp_back_recursion(int n, Tab table, SPtr<const T> q, SPtr<const T> q
   Sp<T> Ac = sp_zero<T>(), yc = sp_zero<T>();
   pipelined(
       n, n - 1, -1,
-      [&](int i) { return In{xs.get(i, 0), scr.get(i, 6), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i], qd[i]}; },
+      [&](int i) {
+        if constexpr (kForm)
+          return In{xs.get(i, 0), scr.get(i, 6), scr.at(i, kVjpSC), scr.at(i, kVjpSC + 1), q[i], qd[i]};
+        else
+          return In{xs.get(i, 0), scr.get(i, 6), T(0), T(0), T(0), qd[i]};
+      },
       [&](int i, const In& x) {
         const Link<T> L = link_at(table, i);
         const Sp<T> Ab = mul(L.J, x.Fb) + Ac;
@@ -1347,9 +1358,30 @@ PD_HD void vjp_back_recursion(int n, Tab table, SPtr<const T> q, SPtr<const T> q
         const Sp<T> Sqd = x.qd * L.S;
         const Sp<T> yb = Vb - adT_wrench(Sqd, Ab);
         put(n - 1 - i, Ab, Vb, yb);
-        const Pose<T> g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        Pose<T> g;
+        if constexpr (kForm) {
+          g = joint_transform_sc(L, x.q, x.sn, x.cs);
+        } else {
+          g = get(n - 1 - i);
+          release(n - i);
+        }
         Ac = XT_wrench(g, Ab);
         yc = XT_wrench(g, yb);
+      });
+}
+
+// The transforms of vjp_back_recursion formed by another wavefront, tip to
+// base: the k-th link from the tip to put(k, pose), from the same (sin, cos)
+// as the Newton-Euler pass stored, so the same bits.
+template <class T, class Put, class Tab = const T*>
+PD_HD void split_pose_bwd_sc(int n, Tab table, SPtr<const T> q, const Put& put) {
+  pipelined(
+      n, n - 1, -1, [&](int i) { return q[i]; },
+      [&](int i, T qi) {
+        const Link<T> L = link_at(table, i);
+        T sn, cs;
+        joint_sincos(L, qi, &sn, &cs);
+        put(n - 1 - i, joint_transform_sc(L, qi, sn, cs));
       });
 }
 template <class T, class Get, class Need, class Sink, class Tab = const T*>

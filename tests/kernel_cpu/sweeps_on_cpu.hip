@@ -212,11 +212,18 @@ static int run_vjp(int op, int n_states, int n_chains, int n_max, const int32_t*
       if (op == 6 || op == 7) {
         // the recursion hands (Abar, Vbar, ybar) of each link through an array (an LDS ring in the kernel)
         std::vector<Sp<T>> hand((size_t)n * 3);
-        vjp_back_recursion(n, tab, io.q, io.qd, xs, scr, [&](int k, const Sp<T>& a, const Sp<T>& v, const Sp<T>& y) {
+        auto put = [&](int k, const Sp<T>& a, const Sp<T>& v, const Sp<T>& y) {
           hand[3 * (size_t)k] = a;
           hand[3 * (size_t)k + 1] = v;
           hand[3 * (size_t)k + 2] = y;
-        });
+        };
+        if (op == 7) {  // FD: the recursion's transforms formed by another wavefront, as in the kernel
+          std::vector<Pose<T>> gb((size_t)n);
+          split_pose_bwd_sc(n, tab, io.q, [&](int k, const Pose<T>& g) { gb[(size_t)k] = g; });
+          vjp_back_recursion(n, tab, io.q, io.qd, xs, scr, put, [&](int k) { return gb[(size_t)k]; }, NoHandoff());
+        } else {
+          vjp_back_recursion(n, tab, io.q, io.qd, xs, scr, put);
+        }
         vjp_back_outputs(n, tab, io.qd, io.qdd, xs, scr, io.q_bar, io.qd_bar, qddb, scr, NoHandoff(),
                          [&](int k, Sp<T>* a, Sp<T>* v, Sp<T>* y) {
                            *a = hand[3 * (size_t)k];
