@@ -3,11 +3,18 @@
 // Kernel map (one lane = one state; consecutive lanes = consecutive states):
 //   k_link_table       per link: the derived 32-word record (rotation of M_i
 //                      from its quaternion, twist norms, h = m c, I_O) -- a map.
+//   k_link_table_ilv   the same records for one chain per state, interleaved
+//                      over the lanes of each wavefront.
 //   k_dynamics         per state: the sweeps of sweeps.hpp (ID, FD or both).
-//   k_dynamics_split   per 64 states, 2-3 wavefronts: the articulated-inertia
-//                      pass beside the Newton-Euler passes (FD, ID+FD).
+//   k_dynamics_split   per 64 states, 3-5 wavefronts with LDS hand-offs: the
+//                      transform producers, the articulated-inertia pass, the
+//                      bias passes and (ID+FD) the inverse dynamics.
+//   k_id_split         per 64 states, 2 wavefronts: transforms, Newton-Euler.
 //   k_vjp              per state: the adjoint sweeps (ID or FD vector-Jacobian
 //                      product), inertia cotangents summed per wave.
+//   k_vjp_split        per 64 states, 2-4 wavefronts: the adjoints cut into
+//                      passes (cotangent / solve, Newton-Euler, articulated
+//                      inertia, adjoint recursion, outputs) with LDS hand-offs.
 //   k_reduce_lanes     per (link, parameter): sum over states of the per-lane
 //                      inertia cotangents (fixed order).
 //   k_rollout          per state: T steps of forward dynamics + semi-implicit
