@@ -10,8 +10,8 @@ derived link tables of the (fixed) model are prepared once before timing.
 Prints ONE JSON line. ``value`` is ID+FD evaluations per second (one eval =
 one ID and one FD of one state). Extra keys: the separate-call ("plain") form,
 per-output errors against the FP64 oracle on a sample, the roofline of the
-dominant kernel (HIP-event timing, algorithmic flops per link stated in
-the design doc), and the oracle timed on the host cores.
+dominant kernel (HIP-event timing, algorithmic flops per link as counted
+below), and the oracle timed on the host cores.
 """
 
 from __future__ import annotations
@@ -29,8 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dynamics evals/s (ID+FD, ±grad) at 32 links FP32 vs plain, at stated error"
 N_LINKS, N_STATES = 32, 16384
-# Algorithmic flops per link (structured spatial algebra, counted once per link;
-# derivation in the design doc): ID 433, FD 1045, ID+FD sharing transforms and velocities 1212,
+# Algorithmic flops per link (structured spatial algebra, counted once per link,
+# an FMA as 2): transform 110 (Rodrigues + composition with M_i, sincos as 2),
+# V 54, ID acceleration 90, bias acceleration 48, ID wrench Fhat 120, bias Fhat 48,
+# wrench recursion 48 and torque 11 each, articulated inertia 489, z-hat/c-hat 67,
+# lambda/qdd 67. ID 433, FD 1045, ID+FD sharing transforms and velocities 1212,
 # ID adjoint 1076, FD adjoint 1699.
 FLOPS_PER_LINK = {"id": 433, "fd": 1045, "id_fd": 1212, "id_vjp": 1076, "fd_vjp": 1699}
 BYTES_PER_LINK = {"id": 16, "fd": 16, "id_fd": 24}  # joint inputs + outputs, FP32
@@ -220,8 +223,8 @@ def bench_rollout_100(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); how the batch would shard "
+              "over several GPUs is described with the design, not run here.", file=sys.stderr)
         return 2
     import torch
     from paper_1609_04493_amd import api, synth
