@@ -333,3 +333,22 @@ int cpu_rollout_f32(int with_grad, int n_states, int n, const float* pl, const f
 }
 }
 
+
+// The lane-interleaved record reader of one-chain-per-state models: record i
+// of lane `lane` read from `ilv` (one wavefront's block, laid out by the
+// caller) into out[32], as Link fields in record-word order.
+template <class T> static void read_ilv(const T* ilv, int lane, int i, T* out) {
+  const Link<T> L = link_at(IlvRec<T>{ilv + lane * IlvRec<T>::V}, i);
+  for (int k = 0; k < 9; ++k) out[k] = L.RM.m[k];
+  out[9] = L.pM.x; out[10] = L.pM.y; out[11] = L.pM.z;
+  out[12] = L.S.a.x; out[13] = L.S.a.y; out[14] = L.S.a.z;
+  out[15] = L.S.b.x; out[16] = L.S.b.y; out[17] = L.S.b.z;
+  out[18] = L.k; out[19] = L.ik; out[20] = L.ik2; out[21] = L.pc;
+  out[22] = L.J.m; out[23] = L.J.h.x; out[24] = L.J.h.y; out[25] = L.J.h.z;
+  out[26] = L.J.Io.xx; out[27] = L.J.Io.yy; out[28] = L.J.Io.zz;
+  out[29] = L.J.Io.xy; out[30] = L.J.Io.xz; out[31] = L.J.Io.yz;
+}
+extern "C" {
+void cpu_read_ilv_f32(const float* ilv, int lane, int i, float* out) { read_ilv(ilv, lane, i, out); }
+void cpu_read_ilv_f64(const double* ilv, int lane, int i, double* out) { read_ilv(ilv, lane, i, out); }
+}

@@ -305,3 +305,23 @@ def test_fp64_rollout_sweeps_match_oracle(cpu_lib):
         pref += gpi
     assert np.linalg.norm(pb - pref) <= 1e-12 * np.linalg.norm(pref)
 
+
+
+def test_interleaved_record_reader(cpu_lib):
+    """One chain per state: a wavefront's link records interleaved over its 64 lanes in 16-byte pieces (word w
+    of record i of lane l at i*32*64 + (w // V)*64*V + l*V + w % V, V = 16 / itemsize) read back exactly."""
+    rng = np.random.default_rng(3)
+    for dt, fn in ((np.float32, cpu_lib.cpu_read_ilv_f32), (np.float64, cpu_lib.cpu_read_ilv_f64)):
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        fn.restype = None
+        n, V = 5, 16 // np.dtype(dt).itemsize
+        rec = rng.standard_normal((n, 64, 32)).astype(dt)  # [record][lane][word]
+        ilv = np.zeros(n * 32 * 64, dt)
+        for i in range(n):
+            for l in range(64):
+                for w in range(32):
+                    ilv[i * 32 * 64 + (w // V) * 64 * V + l * V + w % V] = rec[i, l, w]
+        out = np.zeros(32, dt)
+        for i, l in ((0, 0), (2, 17), (4, 63), (3, 40)):
+            fn(_p(ilv), l, i, _p(out))
+            assert np.array_equal(out, rec[i, l]), (dt, i, l)
