@@ -150,7 +150,7 @@ def bench_uneven(args, dev):
     model.use_order = False
     ms_plain_launch = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
     best, timings = autotune.tune(api.OP_ID_FD, model, call, model.n_chains)
-    autotune.apply(best, api.OP_ID_FD, model)
+    autotune.apply(best, api.OP_ID_FD, model, model.n_chains)
     ms_eager = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
@@ -193,6 +193,13 @@ def bench_fd_grad_50(args, dev):
                               "state_jacobians_per_s": 8192 / (ms_jac * 1e-3)}}
 
 
+def final_position_loss_grad(q, qd, q_bar, qd_bar):
+    """Gradient of the rollout workload's loss L = ||q_T||^2: (2 q_T, 0)."""
+    import torch
+    torch.mul(q, 2.0, out=q_bar)
+    qd_bar.zero_()
+
+
 def bench_rollout_100(args, dev):
     """100-link chain, 65536 states, 100 Euler steps: gradient of ||q_T||^2, checkpoint every 10 steps."""
     import torch
@@ -206,12 +213,12 @@ def bench_rollout_100(args, dev):
     q0, qd0 = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd))
     reps = max(1, min(3, args.steps))
     stream = torch.cuda.current_stream(dev)
-    fused = rollout.FusedRolloutGrad(model, q0, qd0, tau, dt, 10)
+    fused = rollout.FusedRolloutGrad(model, q0, qd0, tau, dt, 10, loss_grad=final_position_loss_grad)
     ms_fused = time_steps(fused, reps, 1, stream)
-    plain = rollout.PlainRolloutGrad(model, q0, qd0, tau, dt, 10)
+    plain = rollout.PlainRolloutGrad(model, q0, qd0, tau, dt, 10, loss_grad=final_position_loss_grad)
     ms_plain = time_steps(plain, reps, 1, stream)
     del plain
-    graphed = rollout.GraphedRolloutGrad(model, q0, qd0, tau, dt, 10)
+    graphed = rollout.GraphedRolloutGrad(model, q0, qd0, tau, dt, 10, loss_grad=final_position_loss_grad)
     ms_graph = time_steps(graphed, reps, 1, stream)
     return {"workload": "100-link chain, 65536 states, 100 semi-implicit Euler steps (dt 1e-3), gradient of "
                         "||q_T||^2 w.r.t. q0, qd0, every tau_t and the inertia parameters, checkpoints every 10",

@@ -78,6 +78,20 @@ typedef struct pdyn_model {
    * records interleaved over its lanes), so a prepared model keeps the order
    * it was prepared with; a new order takes effect when it is prepared again. */
   const int32_t* order;
+  /* Host copies of link_ptr and order, with the same contents. Required when
+   * n_chains > 1 (link_ptr_host) and when order is set (order_host); ignored
+   * otherwise. The library checks them on the host before any device work --
+   * in pdyn_model_prepare, and in every call that is given no prepared tables
+   * -- and returns PDYN_EINVAL unless link_ptr_host[0] == 0, every chain has
+   * 1 .. n_links_max links, link_ptr_host[n_chains] == n_links_total and
+   * order_host is a permutation of 0 .. n_chains-1. The device copies are
+   * read only by the table derivation, which clamps every chain to
+   * n_links_max links inside 0 .. n_links_total and every order entry to a
+   * valid chain, so device copies that differ from the checked host copies
+   * give wrong results for the chains concerned but no access outside the
+   * caller's arrays. The library keeps neither pointer after a call. */
+  const int32_t* link_ptr_host;
+  const int32_t* order_host;
 } pdyn_model;
 
 /*
@@ -130,15 +144,21 @@ typedef struct pdyn_batch {
 } pdyn_batch;
 
 /* Status word. The first 256 bytes of every workspace hold a 32-bit word into
- * which the kernels OR these bits when a numerical fault occurs (the call
- * itself still returns PDYN_OK; faulty values propagate as NaN/inf):
+ * which the kernels OR these bits when a fault occurs (the call itself still
+ * returns PDYN_OK; faulty values propagate as NaN/inf):
  *   PDYN_STATUS_NONFINITE  an output (tau, qdd, q_bar, u = tau_bar) is not finite;
  *   PDYN_STATUS_PIVOT      an articulated-body pivot D_i = S_i^T Jhat_i S_i (Sec. II-B,
  *                          eq. (7)) is not positive: the inertia parameters are not
- *                          physical for this configuration.
+ *                          physical for this configuration;
+ *   PDYN_STATUS_WAIT       a wavefront of a multi-wavefront kernel gave up waiting for
+ *                          another wavefront of its workgroup after its spin bound
+ *                          (~30 ms): the hand-off it waited for never came, and the
+ *                          outputs of that workgroup's states are not to be trusted.
+ *                          A correct kernel never sets it.
  * A new workspace must start with this word zero; pdyn_read_status clears it. */
 #define PDYN_STATUS_NONFINITE 1u
 #define PDYN_STATUS_PIVOT 2u
+#define PDYN_STATUS_WAIT 4u
 
 /* Operation selector for pdyn_workspace_bytes. */
 enum {
@@ -172,6 +192,31 @@ int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared
 
 /* Longest chain the kernels accept. */
 int pdyn_max_links(void);
+
+/*
+ * Installs a launch tuning table (host text, NUL-terminated), as written by the
+ * project's autotuner:
+ *   {"entries": [{"op": 2, "scalar": 4, "shared": 0, "n_max": 100, "n_states": 4096,
+ *                 "block": 0, "max_blocks": 0, "variant": 2}, ...]}
+ * op is a PDYN_OP_* value, scalar 4 or 8, shared 1 for a shared chain and 0
+ * for one chain per state; block, max_blocks and variant follow the rules of
+ * pdyn_batch's launch fields. A later call that leaves all three launch fields
+ * of its batch at 0 takes them from the entry of its operation, scalar size
+ * and model kind whose n_max and n_states are nearest in log scale, provided
+ * both lie within a factor of 2; without such an entry the library defaults
+ * apply. Every variant gives the same results to rounding, so a table changes
+ * speed only. NULL or "" removes the table. Returns PDYN_EINVAL (and keeps the
+ * previous table) for text outside this form or an invalid value. Thread-safe;
+ * calls already running keep the table they started with.
+ */
+int pdyn_load_tuning(const char* json);
+
+/* The launch fields (block_threads, max_blocks, variant; host outputs) that a
+ * call of operation op with this model and batch would run with: the batch's
+ * own if any is non-zero, else the installed tuning table's entry for it, else
+ * zeros (the library defaults). Host only: no device work. */
+int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes,
+                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant);
 
 /* Human-readable text for a status code (static storage). */
 const char* pdyn_strerror(int status);
@@ -287,6 +332,38 @@ int pdyn_rollout_vjp_f64(const pdyn_model* model, const pdyn_batch* batch, int s
                          const double* tau_seq, const double* ckpt_q, const double* ckpt_qd, const double* qT_bar,
                          const double* qdT_bar, double* q0_bar, double* qd0_bar, double* tau_bar_seq,
                          double* inertia_bar, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * One step of the rollouts' integrator (semi-implicit Euler, the plain
+ * per-step form of pdyn_rollout), in place over n joint values:
+ *   qd <- qd + dt qdd,  then  q <- q + dt qd  (with the updated qd).
+ * n == 0 is a no-op; PDYN_EINVAL for n < 0, a NaN dt or a null array.
+ */
+int pdyn_euler_step(int64_t n, double dt, float* q, float* qd, const float* qdd, void* stream);
+int pdyn_euler_step_f64(int64_t n, double dt, double* q, double* qd, const double* qdd, void* stream);
+
+/*
+ * Adjoint of pdyn_euler_step, for a reverse pass over the steps that
+ * alternates it with pdyn_aba_fd_vjp. On entry (q_bar, qd_bar) are the
+ * cotangents of the state after the step, (q_{t+1}, qd_{t+1}); they are updated
+ * in place (an explicit exception to "outputs are overwritten"):
+ *  1. if q_bar_fd is not NULL (then qd_bar_fd must not be either), the
+ *     forward-dynamics adjoint of the later step is added first:
+ *     q_bar += q_bar_fd, qd_bar += qd_bar_fd; if pi_bar_fd is not NULL,
+ *     pi_bar[0 .. n_pi) += pi_bar_fd (inertia cotangents summed over steps);
+ *  2. if qdd_bar is not NULL, the step's own adjoint:
+ *     qd_bar <- qd_bar + dt q_bar (the cotangent of qd_t through the update),
+ *     qdd_bar = dt qd_bar (the cotangent of qdd_t = FD(q_t, qd_t, tau_t), to be
+ *     passed to pdyn_aba_fd_vjp); q_bar passes through unchanged.
+ * Calling it with qdd_bar == NULL after the first step's forward-dynamics
+ * adjoint leaves (q_bar, qd_bar) = dL/d(q_0, qd_0).
+ */
+int pdyn_euler_step_vjp(int64_t n, double dt, float* q_bar, float* qd_bar, const float* q_bar_fd,
+                        const float* qd_bar_fd, float* qdd_bar, int64_t n_pi, float* pi_bar, const float* pi_bar_fd,
+                        void* stream);
+int pdyn_euler_step_vjp_f64(int64_t n, double dt, double* q_bar, double* qd_bar, const double* q_bar_fd,
+                            const double* qd_bar_fd, double* qdd_bar, int64_t n_pi, double* pi_bar,
+                            const double* pi_bar_fd, void* stream);
 
 /* Workspace bytes of pdyn_rollout (with_grad = 0) or pdyn_rollout_vjp (1). */
 size_t pdyn_rollout_workspace_bytes(int with_grad, const pdyn_model* model, const pdyn_batch* batch, int ckpt_every,

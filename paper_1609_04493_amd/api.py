@@ -29,7 +29,8 @@ class PdynError(RuntimeError):
 class _Model(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_links_max", ctypes.c_int32), ("n_links_total", ctypes.c_int64),
                 ("link_ptr", ctypes.c_void_p), ("placement", ctypes.c_void_p), ("twist", ctypes.c_void_p),
-                ("inertia", ctypes.c_void_p), ("prepared", ctypes.c_void_p), ("order", ctypes.c_void_p)]
+                ("inertia", ctypes.c_void_p), ("prepared", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("link_ptr_host", ctypes.c_void_p), ("order_host", ctypes.c_void_p)]
 
 
 class _Batch(ctypes.Structure):
@@ -68,6 +69,11 @@ def lib():
             L.pdyn_strerror.argtypes = [ctypes.c_int]
             L.pdyn_strerror.restype = ctypes.c_char_p
             L.pdyn_max_links.restype = ctypes.c_int
+            L.pdyn_launch_choice.argtypes = [ctypes.c_int, ctypes.POINTER(_Model), ctypes.POINTER(_Batch),
+                                             ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 3
+            L.pdyn_launch_choice.restype = ctypes.c_int
+            L.pdyn_load_tuning.argtypes = [ctypes.c_char_p]
+            L.pdyn_load_tuning.restype = ctypes.c_int
             L.pdyn_model_prepared_bytes.argtypes = [ctypes.POINTER(_Model), ctypes.c_int]
             L.pdyn_model_prepared_bytes.restype = ctypes.c_size_t
             L.pdyn_model_prepare.argtypes = [ctypes.POINTER(_Model), ctypes.c_int, vp, ctypes.c_size_t, vp]
@@ -83,6 +89,13 @@ def lib():
             L.pdyn_rollout_workspace_bytes.restype = ctypes.c_size_t
             L.pdyn_read_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
             L.pdyn_read_status.restype = ctypes.c_int
+            i64 = ctypes.c_int64
+            for name in ("pdyn_euler_step", "pdyn_euler_step_f64"):
+                getattr(L, name).argtypes = [i64, cd, vp, vp, vp, vp]
+                getattr(L, name).restype = ci
+            for name in ("pdyn_euler_step_vjp", "pdyn_euler_step_vjp_f64"):
+                getattr(L, name).argtypes = [i64, cd, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+                getattr(L, name).restype = ci
             _lib = L
     return _lib
 
@@ -90,6 +103,7 @@ def lib():
 # status bits of a workspace (see Workspace.read_status)
 STATUS_NONFINITE = 1
 STATUS_PIVOT = 2
+STATUS_WAIT = 4
 
 
 def read_status(device=None, workspace=None) -> int:
@@ -118,7 +132,7 @@ class Model:
         self.placement = t(chains.placement)
         self.twist = t(chains.twist)
         self.inertia = t(chains.inertia)
-        lp = np.asarray(chains.link_ptr, dtype=np.int32)
+        lp = np.ascontiguousarray(chains.link_ptr, dtype=np.int32)
         self.n_chains = len(lp) - 1
         self.lengths = np.diff(lp)
         self.n_links_max = int(self.lengths.max())
@@ -126,7 +140,8 @@ class Model:
         self.link_ptr_host = lp
         self.link_ptr = torch.as_tensor(lp).to(self.device) if self.n_chains > 1 else None
         # longest chains first (stable): wavefronts of similar lengths, longest work dispatched first
-        self.order_host = np.argsort(-self.lengths, kind="stable").astype(np.int32) if self.n_chains > 1 else None
+        self.order_host = (np.ascontiguousarray(np.argsort(-self.lengths, kind="stable"), dtype=np.int32)
+                           if self.n_chains > 1 else None)
         self.order = torch.as_tensor(self.order_host).to(self.device) if self.n_chains > 1 else None
         self.use_order = True
         self.prepared = None
@@ -138,11 +153,15 @@ class Model:
         if with_prepared and self.prepared is not None and self._prepared_order != self.use_order:
             self.prepare()  # the tables of one chain per state are laid out for the lane order
         prep = self.prepared if with_prepared else None
-        order = self.order if (self.use_order and self.order is not None) else None
+        use_order = self.use_order and self.order is not None
+        order = self.order if use_order else None
+        per_chain = self.n_chains > 1
         return _Model(self.n_chains, self.n_links_max, self.n_links_total,
                       0 if self.link_ptr is None else self.link_ptr.data_ptr(),
                       self.placement.data_ptr(), self.twist.data_ptr(), self.inertia.data_ptr(),
-                      0 if prep is None else prep.data_ptr(), 0 if order is None else order.data_ptr())
+                      0 if prep is None else prep.data_ptr(), 0 if order is None else order.data_ptr(),
+                      self.link_ptr_host.ctypes.data if per_chain else 0,
+                      self.order_host.ctypes.data if use_order else 0)
 
     @property
     def scalar_bytes(self) -> int:
@@ -379,3 +398,31 @@ def rollout_vjp(model: Model, tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, dt, ckp
     _rollout_call("pdyn_rollout_vjp", 1, model, n_states, steps, dt, ckpt_every,
                   (tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0b, qd0b, tb, pib), base_vel, base_acc, workspace)
     return q0b, qd0b, tb, pib
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def euler_step(q, qd, qdd, dt):
+    """In place: qd += dt qdd, then q += dt qd (pdyn_euler_step)."""
+    for a in (q, qd, qdd):
+        if a.dtype != q.dtype or a.device != q.device or not a.is_contiguous() or a.numel() != q.numel():
+            raise PdynError("euler_step: q, qd, qdd must be contiguous, same size, dtype and device")
+    name = "pdyn_euler_step" + ("_f64" if q.dtype == torch.float64 else "")
+    stream = torch.cuda.current_stream(q.device).cuda_stream
+    _check(getattr(lib(), name)(q.numel(), float(dt), q.data_ptr(), qd.data_ptr(), qdd.data_ptr(), stream), name)
+
+
+def euler_step_vjp(q_bar, qd_bar, dt, qdd_bar=None, q_bar_fd=None, qd_bar_fd=None, pi_bar=None, pi_bar_fd=None):
+    """Adjoint of euler_step, updating (q_bar, qd_bar) in place (pdyn_euler_step_vjp): first adds the later
+    step's forward-dynamics cotangents (and pi_bar += pi_bar_fd), then, if qdd_bar is given, writes the
+    cotangent of this step's qdd into it."""
+    for a in (qd_bar, qdd_bar, q_bar_fd, qd_bar_fd):
+        if a is not None and (a.dtype != q_bar.dtype or a.numel() != q_bar.numel() or not a.is_contiguous()):
+            raise PdynError("euler_step_vjp: joint arrays must be contiguous, same size and dtype")
+    n_pi = 0 if pi_bar is None else pi_bar.numel()
+    name = "pdyn_euler_step_vjp" + ("_f64" if q_bar.dtype == torch.float64 else "")
+    stream = torch.cuda.current_stream(q_bar.device).cuda_stream
+    _check(getattr(lib(), name)(q_bar.numel(), float(dt), q_bar.data_ptr(), qd_bar.data_ptr(), _ptr(q_bar_fd),
+                                _ptr(qd_bar_fd), _ptr(qdd_bar), n_pi, _ptr(pi_bar), _ptr(pi_bar_fd), stream), name)

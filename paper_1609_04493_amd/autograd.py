@@ -10,23 +10,35 @@ one the model was prepared with.
 
 from __future__ import annotations
 
+import copy
+
 import torch
 
 from . import api
 
 
-def _use_inertia(model: api.Model, inertia: torch.Tensor):
-    if inertia.data_ptr() != model.inertia.data_ptr():
+def _use_inertia(model: api.Model, inertia: torch.Tensor) -> api.Model:
+    """Prepare the model's tables for these inertia values and return a snapshot for the backward pass.
+
+    The tables are derived again whenever the tensor differs from the one they were derived from, by
+    address or by version: an in-place update (an optimizer step on a learned inertia) keeps the address
+    but bumps the version counter, which a detached view shares. The snapshot keeps this forward's
+    tables, so a later forward that prepares the model again cannot change what this backward uses.
+    """
+    key = (inertia.data_ptr(), inertia._version)
+    if getattr(model, "_inertia_key", None) != key or model.prepared is None:
         model.inertia = inertia.detach().contiguous()
         model.prepare()
+        model._inertia_key = key
+    return copy.copy(model)
 
 
 class InverseDynamics(torch.autograd.Function):
     @staticmethod
     def forward(ctx, model, q, qd, qdd, inertia, base_vel=api.ZERO6, base_acc=api.GRAVITY_ACC):
-        _use_inertia(model, inertia)
-        tau = api.rnea_id(model, q, qd, qdd, base_vel, base_acc)
-        ctx.model, ctx.base = model, (base_vel, base_acc)
+        snap = _use_inertia(model, inertia)
+        tau = api.rnea_id(snap, q, qd, qdd, base_vel, base_acc)
+        ctx.model, ctx.base = snap, (base_vel, base_acc)
         ctx.save_for_backward(q, qd, qdd)
         return tau
 
@@ -42,9 +54,9 @@ class InverseDynamics(torch.autograd.Function):
 class ForwardDynamics(torch.autograd.Function):
     @staticmethod
     def forward(ctx, model, q, qd, tau, inertia, base_vel=api.ZERO6, base_acc=api.GRAVITY_ACC):
-        _use_inertia(model, inertia)
-        qdd = api.aba_fd(model, q, qd, tau, base_vel, base_acc)
-        ctx.model, ctx.base = model, (base_vel, base_acc)
+        snap = _use_inertia(model, inertia)
+        qdd = api.aba_fd(snap, q, qd, tau, base_vel, base_acc)
+        ctx.model, ctx.base = snap, (base_vel, base_acc)
         ctx.save_for_backward(q, qd, qdd)
         return qdd
 

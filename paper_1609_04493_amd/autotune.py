@@ -6,8 +6,11 @@ persistent), the kernel variant for forward dynamics (one wavefront per 64
 states, or the role split across wavefronts) and, for one chain per state,
 the chain order (natural, or longest first), with HIP events, and keeps the
 fastest. Results are recorded in a
-JSON table keyed by (operation, precision, model kind, links, states), which
-``apply`` installs into the binding so that later calls use them.
+JSON table keyed by (operation, precision, model kind, links, states).
+``apply`` installs the winner into libpdyn's own tuning table
+(pdyn_load_tuning), which every later call of that operation on a model of
+that kind and size consults when its batch leaves the launch fields at 0; the
+chain order is a property of the model and is set on it.
 """
 
 from __future__ import annotations
@@ -84,6 +87,30 @@ def record(path: str, op: int, model: api.Model, n_states: int, best: dict):
         json.dump(table, f, indent=1, sort_keys=True)
 
 
-def apply(best: dict, op: int, model: api.Model):
-    api.set_launch(op, best["block_threads"], best["max_blocks"], best.get("variant", 0))
+# entries installed in the library, keyed like the JSON table
+_installed = {}
+
+
+def library_entry(op: int, model: api.Model, n_states: int, best: dict) -> dict:
+    return {"op": int(op), "scalar": model.scalar_bytes, "shared": int(model.n_chains == 1),
+            "n_max": int(model.n_links_max), "n_states": int(n_states), "block": int(best["block_threads"]),
+            "max_blocks": int(best["max_blocks"]), "variant": int(best.get("variant", 0))}
+
+
+def install(entries) -> None:
+    """Load tuning entries (dicts of library_entry's form) into libpdyn (pdyn_load_tuning)."""
+    text = json.dumps({"entries": list(entries)}).encode()
+    api._check(api.lib().pdyn_load_tuning(text), "pdyn_load_tuning")
+
+
+def apply(best: dict, op: int, model: api.Model, n_states: int):
+    """Make `best` the launch of `op` for models like `model` with about `n_states` states."""
+    api._launch_override.pop(op, None)  # an explicit override would hide the table
+    _installed[key_of(op, model, n_states)] = library_entry(op, model, n_states, best)
+    install(_installed.values())
     model.use_order = bool(best.get("order", True))
+
+
+def clear():
+    _installed.clear()
+    install(())

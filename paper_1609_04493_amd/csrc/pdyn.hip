@@ -23,8 +23,14 @@
 //                      the checkpoints (recompute k steps, then k reverse steps).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/pdyn.h"
 #include "sweeps.hpp"
@@ -36,7 +42,8 @@ constexpr int kMaxLinks = 1 << 16;
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
 constexpr size_t kStatusBytes = 256;  // status word at the start of every workspace (padded for alignment)
-static_assert(kStatusNonFinite == PDYN_STATUS_NONFINITE && kStatusPivot == PDYN_STATUS_PIVOT,
+static_assert(kStatusNonFinite == PDYN_STATUS_NONFINITE && kStatusPivot == PDYN_STATUS_PIVOT &&
+                  kStatusWait == PDYN_STATUS_WAIT,
               "status bits of the kernels and of the C ABI");
 // Default kernel variant: the role split (2) for the adjoints; for forward
 // dynamics and ID+FD the role split while a one-wavefront launch would leave
@@ -67,17 +74,46 @@ template <class T> struct BoundaryArgs {
   T V0[6], dV0[6];
 };
 
+// One chain per state: the chain that lane index j runs (state s, its first
+// link, its link count), written by the table derivation from link_ptr and
+// order and clamped there, so that every kernel stays inside its tables and the
+// caller's arrays whatever the device copies of link_ptr and order hold.
+struct LaneChain {
+  int32_t s, link0, n, pad;
+};
+
+// The chain of lane index j, clamped: an order entry outside 0 .. n_chains-1
+// becomes chain 0 with no links; a chain starts inside 0 .. n_links_total and
+// has at most n_max links, none past n_links_total.
+__device__ __forceinline__ LaneChain clamp_chain(int64_t j, int n_chains, int n_max, int64_t n_links_total,
+                                                 const int32_t* __restrict__ link_ptr,
+                                                 const int32_t* __restrict__ order) {
+  LaneChain lc{0, 0, 0, 0};
+  const int c = order ? order[j] : (int)j;
+  if (c < 0 || c >= n_chains) return lc;
+  int64_t l0 = link_ptr[c], l1 = link_ptr[c + 1];
+  l0 = l0 < 0 ? 0 : (l0 > n_links_total ? n_links_total : l0);
+  l1 = l1 > n_links_total ? n_links_total : l1;
+  int64_t len = l1 - l0;
+  len = len < 0 ? 0 : (len > n_max ? n_max : len);
+  lc.s = c;
+  lc.link0 = (int32_t)l0;
+  lc.n = (int32_t)len;
+  return lc;
+}
+
 // One chain per state: the same records interleaved over the 64 lanes of each
 // wavefront (the layout of IlvRec), n_max records per group of 64 lane
 // indices; lane index j runs chain order[j] (chain j without an order), and
-// order_out[j] records that chain for the kernels. Records past a chain's end
+// lanes_out[j] records that chain for the kernels. Records past a chain's end
 // and lanes past the last chain hold zeros. One thread per (group, record, lane).
 template <class T>
-__global__ void __launch_bounds__(256) k_link_table_ilv(int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
+__global__ void __launch_bounds__(256) k_link_table_ilv(int n_chains, int n_max, int64_t n_links_total,
+                                                        const int32_t* __restrict__ link_ptr,
                                                         const int32_t* __restrict__ order,
                                                         const T* __restrict__ placement, const T* __restrict__ twist,
                                                         const T* __restrict__ inertia, T* __restrict__ table,
-                                                        double* __restrict__ wtable, int32_t* __restrict__ order_out) {
+                                                        double* __restrict__ wtable, LaneChain* __restrict__ lanes_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = (int)(t % 64);
   const int64_t slot = t / 64;  // group * n_max + record
@@ -87,11 +123,11 @@ __global__ void __launch_bounds__(256) k_link_table_ilv(int n_chains, int n_max,
   double rec[kLinkWords];
   bool live = false;
   if (j < n_chains) {
-    const int c = order ? order[j] : (int)j;
-    const int64_t l0 = link_ptr[c];
-    if (i == 0) order_out[j] = c;
-    if (i < link_ptr[c + 1] - l0) {
-      make_link_record(placement + 7 * (l0 + i), twist + 6 * (l0 + i), inertia + 10 * (l0 + i), rec);
+    const LaneChain lc = clamp_chain(j, n_chains, n_max, n_links_total, link_ptr, order);
+    if (i == 0) lanes_out[j] = lc;
+    if (i < lc.n) {
+      const int64_t l = (int64_t)lc.link0 + i;
+      make_link_record(placement + 7 * l, twist + 6 * l, inertia + 10 * l, rec);
       live = true;
     }
   }
@@ -109,9 +145,29 @@ __global__ void __launch_bounds__(256) k_link_table_ilv(int n_chains, int n_max,
   }
 }
 
-// Lane -> state: lane_index (0 .. n_states-1, possibly through `order`).
-__device__ __forceinline__ int state_of(int lane_index, const int32_t* __restrict__ order) {
-  return order ? order[lane_index] : lane_index;
+struct ChainOf {
+  int s, n;
+  int64_t link0, dof0;
+};
+// The state a lane index runs and its chain. SHARED (one chain for every
+// state) is a compile-time flag so that n stays wave-uniform and the link
+// records load through the scalar unit; otherwise the clamped lane map.
+template <bool SHARED>
+__device__ __forceinline__ ChainOf chain_of(int lane_index, int n_max, const LaneChain* __restrict__ lanes) {
+  ChainOf c;
+  if (SHARED) {
+    c.s = lane_index;
+    c.n = n_max;
+    c.link0 = 0;
+    c.dof0 = (int64_t)lane_index * n_max;
+  } else {
+    const LaneChain lc = lanes[lane_index];
+    c.s = lc.s;
+    c.n = lc.n;
+    c.link0 = lc.link0;
+    c.dof0 = lc.link0;
+  }
+  return c;
 }
 
 // The link records a lane reads: the shared chain's, back to back (a
@@ -129,9 +185,8 @@ __device__ __forceinline__ auto rec_view(const T* table, int lane_index, int n_m
 // SHARED: one chain shared by every state, known at compile time, so that the
 // link records are read with wave-uniform (scalar) loads.
 template <class T, int MODE, bool SHARED, int SWEEPS = kAllSweeps>
-__global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chains, int n_max,
-                                                        const int32_t* __restrict__ link_ptr,
-                                                        const int32_t* __restrict__ order,
+__global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_max,
+                                                        const LaneChain* __restrict__ lanes,
                                                         const T* __restrict__ table,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
@@ -141,18 +196,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
   for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {  // persistent when gridDim.x < n_work
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
     if (lane_index >= n_states) continue;
-    const int s = SHARED ? lane_index : state_of(lane_index, order);
-    int n;
-    int64_t link0, dof0;
-    if (SHARED) {
-      n = n_max;
-      link0 = 0;
-      dof0 = (int64_t)s * n_max;
-    } else {
-      link0 = link_ptr[s];
-      n = link_ptr[s + 1] - (int)link0;
-      dof0 = link0;
-    }
+    const ChainOf ch = chain_of<SHARED>(lane_index, n_max, lanes);
+    const int s = ch.s, n = ch.n;
+    const int64_t dof0 = ch.dof0;
     JointIO<T> io;
     io.q = q + dof0;
     io.qd = qd + dof0;
@@ -176,27 +222,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_dynamics(int n_states, int n_chai
                                                                   rec_view<SHARED>(wtable, lane_index, n_max), io, bd, scr,
                                                                   StoreQdd<T>{io.qdd_out});
   }
-}
-
-struct ChainOf {
-  int n;
-  int64_t link0, dof0;
-};
-// SHARED (one chain for every state) is a compile-time flag so that n stays
-// wave-uniform and the link records load through the scalar unit.
-template <bool SHARED>
-__device__ __forceinline__ ChainOf chain_of(int s, int n_max, const int32_t* link_ptr) {
-  ChainOf c;
-  if (SHARED) {
-    c.n = n_max;
-    c.link0 = 0;
-    c.dof0 = (int64_t)s * n_max;
-  } else {
-    c.link0 = link_ptr[s];
-    c.n = link_ptr[s + 1] - (int)c.link0;
-    c.dof0 = c.link0;
-  }
-  return c;
 }
 
 template <class T>
@@ -232,19 +257,17 @@ struct LdsProgress {
 // Waits until *p >= k. Progress words only grow, so the last value read is
 // kept: a wait it already covers returns without touching LDS (the acquire
 // that read it orders everything released up to it).
+// A wait that reaches its spin bound ORs PDYN_STATUS_WAIT into the call's
+// status word (see bounded_wait), so a broken hand-off never passes silently.
 struct LdsWait {
   int* p;
+  unsigned* status = nullptr;
   mutable int seen = 0;
   __device__ void operator()(int k) const {
     if (k <= seen) return;
-    for (int spin = 0; spin < kSpinLimit; ++spin) {
-      const int v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (v >= k) {
-        seen = v;
-        return;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
+    const int v = bounded_wait([&] { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); },
+                               [] { __builtin_amdgcn_s_sleep(1); }, k, kSpinLimit, status);
+    if (v >= k) seen = v;
   }
 };
 
@@ -279,7 +302,8 @@ template <class T> struct RingPutF {  // base-to-tip entries
   int* used_b;   // entries taken by B1
   int* used_id;  // entries taken by the inverse dynamics (null without it)
   int lane;
-  LdsWait wait_b{used_b}, wait_id{used_id};
+  unsigned* status;
+  LdsWait wait_b{used_b, status}, wait_id{used_id, status};
   __device__ void operator()(int i, const Pose<T>& g, T sn, T cs) const {
     wait_b(i - kPoseSlots + 1);
     if (used_id) wait_id(i - kPoseSlots + 1);
@@ -296,7 +320,8 @@ template <class T> struct RingTakeF {
   int* ready;
   int* used;
   int lane;
-  LdsWait wait{ready};
+  unsigned* status;
+  LdsWait wait{ready, status};
   __device__ void operator()(int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) const {
     wait(i + 1);
     const T* r = ring + (long)(i % kPoseSlots) * kPoseWordsF * 64 + lane;
@@ -313,7 +338,8 @@ template <class T> struct RingTakeF2 {
   int* ready;  // [2]
   int* used;
   int lane;
-  LdsWait wait0{ready}, wait1{ready + 1};
+  unsigned* status;
+  LdsWait wait0{ready, status}, wait1{ready + 1, status};
   __device__ void operator()(int i, const Link<T>&, T, Pose<T>* g, T* sn, T* cs) const {
     if (i & 1)
       wait1(i + 1);
@@ -334,7 +360,8 @@ template <class T> struct RingPutBack {
   int* ready;
   int* used;
   int lane;
-  LdsWait wait{used};
+  unsigned* status;
+  LdsWait wait{used, status};
   __device__ void operator()(int k, const Sp<T>& a, const Sp<T>& v, const Sp<T>& y) const {
     wait(k - kPoseSlots + 1);
     T* w = ring + (long)(k % kPoseSlots) * kBackWords * 64 + lane;
@@ -356,7 +383,8 @@ template <class T> struct RingGetBack {
   int* ready;
   int* used;
   int lane;
-  LdsWait wait{ready};
+  unsigned* status;
+  LdsWait wait{ready, status};
   __device__ void operator()(int k, Sp<T>* a, Sp<T>* v, Sp<T>* y) const {
     wait(k + 1);
     const T* r = ring + (long)(k % kPoseSlots) * kBackWords * 64 + lane;
@@ -379,7 +407,8 @@ template <class T> struct RingPutB {  // tip-to-base entries for pass A
   int* ready;
   int* used;
   int lane;
-  LdsWait wait{used};
+  unsigned* status;
+  LdsWait wait{used, status};
   __device__ void operator()(int k, const Pose<T>& g) const {
     wait(k - kPoseSlots + 1);
     put_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane, g);
@@ -390,7 +419,8 @@ template <class T> struct RingGetB {
   const T* ring;
   int* ready;
   int lane;
-  LdsWait wait{ready};
+  unsigned* status;
+  LdsWait wait{ready, status};
   __device__ Pose<T> operator()(int k) const {
     wait(k + 1);
     return get_pose(ring + (long)(k % kPoseSlots) * kPoseWordsB * 64 + lane);
@@ -398,8 +428,7 @@ template <class T> struct RingGetB {
 };
 
 template <class T, int MODE, bool SHARED, int LDSMODE>
-__global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
-                                                        const int32_t* __restrict__ order,
+__global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max, const LaneChain* __restrict__ lanes,
                                                         const T* __restrict__ table,
                                                         const double* __restrict__ wtable, const T* q, const T* qd,
                                                         const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out,
@@ -439,16 +468,12 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   const bool active = lane_index < n_states;
   // with a shared chain n stays uniform, so link records load through the scalar unit
   int s = 0, n = SHARED ? n_max : 0;
-  int64_t link0 = 0, dof0 = 0;
+  int64_t dof0 = 0;
   if (active) {
-    s = SHARED ? lane_index : state_of(lane_index, order);
-    if (SHARED) {
-      dof0 = (int64_t)s * n_max;
-    } else {
-      link0 = link_ptr[s];
-      n = link_ptr[s + 1] - (int)link0;
-      dof0 = link0;
-    }
+    const ChainOf ch = chain_of<SHARED>(lane_index, n_max, lanes);
+    s = ch.s;
+    n = ch.n;
+    dof0 = ch.dof0;
   }
   // links of the wavefront's longest chain: the last value of its progress words
   int n_wave = n;
@@ -474,19 +499,19 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   // P_b (idle by then) the odd ones.
   if (kRings && role == 2) {
     if (active) {
-      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_f, &used_b, kWithID ? &used_id : nullptr, lane});
-      LdsWait{&used_b}(n_wave);
-      if (kWithID) LdsWait{&used_id}(n_wave);
-      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[0], &used_l, nullptr, lane}, 0, 2);
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_f, &used_b, kWithID ? &used_id : nullptr, lane, status});
+      LdsWait{&used_b, status}(n_wave);
+      if (kWithID) LdsWait{&used_id, status}(n_wave);
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[0], &used_l, nullptr, lane, status}, 0, 2);
     }
     return;
   }
   if (kRings && role == 3) {
     if (active) {
-      split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane});
-      LdsWait{&used_b}(n_wave);
-      if (kWithID) LdsWait{&used_id}(n_wave);
-      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[1], &used_l, nullptr, lane}, 1, 2);
+      split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{ring_b, &ready_b, &used_a, lane, status});
+      LdsWait{&used_b, status}(n_wave);
+      if (kWithID) LdsWait{&used_id, status}(n_wave);
+      split_pose_fwd(n, tab, qs, RingPutF<T>{ring_f, &ready_l[1], &used_l, nullptr, lane, status}, 1, 2);
     }
     return;
   }
@@ -497,7 +522,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
       const Scratch<T> idscr{scr_id + lane_index, (long)n_states, ScratchWords<kModeID>::value, status};
       if (kRings)
         dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, idscr, StoreQdd<T>{SPtr<T>()},
-                                       RingTakeF<T>{ring_f, &ready_f, &used_id, lane});
+                                       RingTakeF<T>{ring_f, &ready_f, &used_id, lane, status});
       else
         dynamics_one_state<T, kModeID, StoreQdd<T>, FormPose<T>, kAllSweeps, !SHARED>(n, tab, wtab, io, bd, idscr,
                                                                                     StoreQdd<T>{SPtr<T>()});
@@ -507,7 +532,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   if (active) {
     if (role == 0) {
       if (kRings)
-        split_abi_from_poses(n, tab, abi, RingGetB<T>{ring_b, &ready_b, lane}, LdsProgress{&used_a},
+        split_abi_from_poses(n, tab, abi, RingGetB<T>{ring_b, &ready_b, lane, status}, LdsProgress{&used_a},
                              LdsProgress{&progress});
       else if (OVERLAP)
         split_abi_pass<T, LdsProgress, !SHARED>(n, tab, wtab, qs, abi, LdsProgress{&progress});
@@ -515,7 +540,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
         split_abi_pass<T, NoHandoff, !SHARED>(n, tab, wtab, qs, abi);
     } else {
       if (kRings)
-        split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane});
+        split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane, status});
       else
         split_bias_forward<T, FormPose<T>, !SHARED>(n, tab, qs, qds, bd, bias);
     }
@@ -524,16 +549,16 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   if (active && role == 1) {
     if (kRings)
       split_bias_backward<T, LdsWait, !SHARED, true>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias,
-                                                     abi, LdsWait{&progress});
+                                                     abi, LdsWait{&progress, status});
     else if (OVERLAP)
       split_bias_backward<T, LdsWait, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi,
-                                               LdsWait{&progress});
+                                               LdsWait{&progress, status});
     else
       split_bias_backward<T, NoHandoff, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi);
     if (kRings) {
       // pass C runs out of LDS alone: qdd_i goes to word 0 of link i's entry (read by then), then out
       split_lambda<T, StashQdd<T>, !SHARED, true>(n, tab, qs, bias, abi, StashQdd<T>{abi},
-                                                 RingTakeF2<T>{ring_f, ready_l, &used_l, lane});
+                                                 RingTakeF2<T>{ring_f, ready_l, &used_l, lane, status});
       T* const out = qdd_out + dof0;
       for (int i = 0; i < n; ++i) out[i] = abi.at(i, 0);
     } else
@@ -546,8 +571,8 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
 // ring to wavefront 0, which runs the two Newton-Euler sweeps without forming
 // any. P_f waits only for free slots and wavefront 0 only for entries.
 template <class T, bool SHARED>
-__global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
-                                                  const int32_t* __restrict__ order, const T* __restrict__ table,
+__global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                  const T* __restrict__ table,
                                                   const double* __restrict__ wtable, const T* q, const T* qd,
                                                   const T* qdd_in, T* tau_out, const T* __restrict__ tip,
                                                   BoundaryArgs<T> ba, T* scratch, unsigned* status) {
@@ -563,22 +588,18 @@ __global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const
   const int lane_index = blockIdx.x * 64 + lane;
   const bool active = lane_index < n_states;
   int s = 0, n = SHARED ? n_max : 0;
-  int64_t link0 = 0, dof0 = 0;
+  int64_t dof0 = 0;
   if (active) {
-    s = SHARED ? lane_index : state_of(lane_index, order);
-    if (SHARED) {
-      dof0 = (int64_t)s * n_max;
-    } else {
-      link0 = link_ptr[s];
-      n = link_ptr[s + 1] - (int)link0;
-      dof0 = link0;
-    }
+    const ChainOf ch = chain_of<SHARED>(lane_index, n_max, lanes);
+    s = ch.s;
+    n = ch.n;
+    dof0 = ch.dof0;
   }
   const auto tab = rec_view<SHARED>(table, lane_index, n_max);
   const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
   const SPtr<const T> qs(q + dof0);
   if (role == 1) {
-    if (active) split_pose_fwd(n, tab, qs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
+    if (active) split_pose_fwd(n, tab, qs, RingPutF<T>{ring, &ready, &used, nullptr, lane, status});
     return;
   }
   if (!active) return;
@@ -591,7 +612,7 @@ __global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const
                 SPtr<T>()};
   const Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeID>::value, status};
   dynamics_one_state<T, kModeID>(n, tab, wtab, io, bd, scr, StoreQdd<T>{SPtr<T>()},
-                                 RingTakeF<T>{ring, &ready, &used, lane});
+                                 RingTakeF<T>{ring, &ready, &used, lane, status});
 }
 
 // ---- adjoints ------------------------------------------------------------------
@@ -621,16 +642,16 @@ template <class T, int PI> struct PiSink {
 
 // Scratch of the adjoints: [n_max][kVjpWords][n_states].
 template <class T, int OP, int PI, bool SHARED>
-__global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int n_max, const int32_t* __restrict__ link_ptr,
-                                                const int32_t* __restrict__ order, const T* __restrict__ table,
+__global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                const T* __restrict__ table,
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
                                                 const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
                                                 T* tau_bar, T* pi_out, const T* __restrict__ tip, BoundaryArgs<T> ba,
                                                 T* scratch, unsigned* status) {
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
-  const int s = state_of(lane_index, order);
-  const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
+  const ChainOf c = chain_of<SHARED>(lane_index, n_max, lanes);
+  const int s = c.s;
   VjpIO<T> io;
   io.q = q + c.dof0;
   io.qd = qd + c.dof0;
@@ -684,8 +705,8 @@ __global__ void __launch_bounds__(kBlock) k_vjp(int n_states, int n_chains, int 
 // runs the wrench sweep and a fourth wavefront the inertia-parameter
 // cotangents; for FD, X runs the cotangents.
 template <class T, int OP, int PI, bool SHARED, int OVERLAP>
-__global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, const int32_t* __restrict__ link_ptr,
-                                                   const int32_t* __restrict__ order, const T* __restrict__ table,
+__global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                   const T* __restrict__ table,
                                                    const double* __restrict__ wtable, const T* q, const T* qd,
                                                    const T* qdd, const T* bar_in, T* q_bar, T* qd_bar, T* qdd_bar,
                                                    T* tau_bar, T* pi_out, const T* __restrict__ tip,
@@ -722,14 +743,11 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   int s = 0, n = SHARED ? n_max : 0;
   int64_t link0 = 0, dof0 = 0;
   if (active) {
-    s = SHARED ? lane_index : state_of(lane_index, order);
-    if (SHARED) {
-      dof0 = (int64_t)s * n_max;
-    } else {
-      link0 = link_ptr[s];
-      n = link_ptr[s + 1] - (int)link0;
-      dof0 = link0;
-    }
+    const ChainOf ch = chain_of<SHARED>(lane_index, n_max, lanes);
+    s = ch.s;
+    n = ch.n;
+    link0 = ch.link0;
+    dof0 = ch.dof0;
   }
   const auto tab = rec_view<SHARED>(table, lane_index, n_max);
   const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
@@ -749,13 +767,13 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
                    (kOv ? ((long)kPoseSlots * kPoseWordsF + (long)n_max * 6) * 64
                         : (long)n_max * kAbiWords * 64 + (long)kPoseSlots * kPoseWordsB * 64);
   if (kAw && role == 3) {
-    if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{pring, &pready, &pused, lane});
+    if (active) split_pose_bwd(n, tab, wtab, qs, RingPutB<T>{pring, &pready, &pused, lane, status});
     // without the cut sweep it ends here; the workgroup barrier waits only for wavefronts still running
     if (!kCut) return;
   }
   if (kAw && role == 2) {
     if (active)
-      split_abi_from_poses(n, tab, abi, RingGetB<T>{pring, &pready, lane}, LdsProgress{&pused},
+      split_abi_from_poses(n, tab, abi, RingGetB<T>{pring, &pready, lane, status}, LdsProgress{&pused},
                            LdsProgress{&aprog});
     // without the cut sweep it ends here
     if (!kCut) return;
@@ -763,16 +781,16 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   if (active && role < 2) {
     if (role == 0) {
       if (kOv)
-        vjp_fbar_pass(n, tab, qs, bar, T(1), xs, RingPutF<T>{ring, &ready, &used, nullptr, lane});
+        vjp_fbar_pass(n, tab, qs, bar, T(1), xs, RingPutF<T>{ring, &ready, &used, nullptr, lane, status});
       else if (OP == kVjpID)
         vjp_fbar_pass(n, tab, qs, bar, T(1), xs);
       else if (kAw)
-        fdvjp_solve_with_abi(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs, abi, LdsWait{&aprog});
+        fdvjp_solve_with_abi(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs, abi, LdsWait{&aprog, status});
       else
         fdvjp_solve_pass(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + dof0), xs);
     } else {
       if (kOv)
-        vjp_ne_forward(n, tab, qs, qds, qdds, bd, scr, RingTakeF<T>{ring, &ready, &used, lane});
+        vjp_ne_forward(n, tab, qs, qds, qdds, bd, scr, RingTakeF<T>{ring, &ready, &used, lane, status});
       else
         vjp_newton_euler_pass(n, tab, wtab, qs, qds, qdds, bd, scr);
     }
@@ -784,7 +802,7 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
     // FD: P_b forms the transforms of Y's recursion again, tip to base, through its ring (A took every
     // entry of the first round before the barrier)
     if (kAw && role == 3) {
-      split_pose_bwd_sc(n, tab, qs, RingPutB<T>{pring, &qready, &qused, lane});
+      split_pose_bwd_sc(n, tab, qs, RingPutB<T>{pring, &qready, &qused, lane, status});
       return;
     }
     // the inertia-parameter cotangents: X's for FD, a fourth wavefront's for ID (beside X's wrench sweep)
@@ -799,16 +817,16 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
       vjp_wrench_pass(n, wtab, qs, bd, scr, fl, LdsProgress{&fprog});
     } else if (role == 1) {
       if (kAw)
-        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane},
-                           RingGetB<T>{pring, &qready, lane}, LdsProgress{&qused});
+        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane, status},
+                           RingGetB<T>{pring, &qready, lane, status}, LdsProgress{&qused});
       else
-        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane});
+        vjp_back_recursion(n, tab, qs, qds, xs, scr, RingPutBack<T>{bring, &bready, &bused, lane, status});
     } else {
       PiSink<T, kPiNone> sink;  // the inertia cotangents are X's
-      const RingGetBack<T> get{bring, &bready, &bused, lane};
+      const RingGetBack<T> get{bring, &bready, &bused, lane, status};
       if (kOv)
         vjp_back_outputs(n, tab, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, fl,
-                         LdsWait{&fprog}, get, sink);
+                         LdsWait{&fprog, status}, get, sink);
       else
         vjp_back_outputs(n, tab, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, scr,
                          NoHandoff(), get, sink);
@@ -827,7 +845,7 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
     const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + dof0) : SPtr<T>();
     if (kOv)
       vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, fl,
-                    LdsWait{&fprog});
+                    LdsWait{&fprog, status});
     else
       vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + dof0), SPtr<T>(qd_bar + dof0), qddb, scr);
   }
@@ -884,9 +902,8 @@ struct NoSink {
 
 // Forward rollout, one lane per state, all steps in one launch.
 template <class T, bool SHARED>
-__global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chains, int n_max,
-                                                       const int32_t* __restrict__ link_ptr,
-                                                       const int32_t* __restrict__ order, const T* __restrict__ table,
+__global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                       const T* __restrict__ table,
                                                        const double* __restrict__ wtable, int steps, T dt, int every,
                                                        const T* tau_seq, T* q, T* qd, T* ckpt_q, T* ckpt_qd, long dofs,
                                                        BoundaryArgs<T> ba, T* scratch, unsigned* status) {
@@ -894,8 +911,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
   for (long wb = blockIdx.x; wb < n_work; wb += gridDim.x) {
     const int lane_index = (int)(wb * blockDim.x) + (int)threadIdx.x;
     if (lane_index >= n_states) continue;
-    const int s = state_of(lane_index, order);
-    const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
+    const ChainOf c = chain_of<SHARED>(lane_index, n_max, lanes);
     Scratch<T> scr{scratch + lane_index, (long)n_states, ScratchWords<kModeFD>::value, status};
     rollout_one_state(c.n, rec_view<SHARED>(table, lane_index, n_max), rec_view<SHARED>(wtable, lane_index, n_max), steps, dt, every,
                       SPtr<T>(q + c.dof0), SPtr<T>(qd + c.dof0), DevRows<T>{tau_seq + c.dof0, dofs},
@@ -908,9 +924,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_rollout(int n_states, int n_chain
 // [(3 every + 6) n_max][n_states]; pi accumulators [n_max][10][n_states]
 // (shared chain; zeroed here).
 template <class T, int PI, bool SHARED>
-__global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chains, int n_max,
-                                                        const int32_t* __restrict__ link_ptr,
-                                                        const int32_t* __restrict__ order, const T* __restrict__ table,
+__global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                        const T* __restrict__ table,
                                                         const double* __restrict__ wtable, int steps, T dt, int every,
                                                         const T* tau_seq, const T* ckpt_q, const T* ckpt_qd,
                                                         const T* qT_bar, const T* qdT_bar, T* q0_bar, T* qd0_bar,
@@ -918,8 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
                                                         T* scratch, T* rows_ws, T* pi_acc, unsigned* status) {
   const int lane_index = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane_index >= n_states) return;
-  const int s = state_of(lane_index, order);
-  const ChainOf c = chain_of<SHARED>(s, n_max, link_ptr);
+  const ChainOf c = chain_of<SHARED>(lane_index, n_max, lanes);
   // working rows, lane-interleaved: element i of row r at rows_ws[(r n_max + i) n_states + lane]
   const long S = n_states;
   T* const rb = rows_ws + lane_index;
@@ -954,6 +968,46 @@ __global__ void __launch_bounds__(kBlock) k_rollout_vjp(int n_states, int n_chai
   }
 }
 
+// One semi-implicit Euler step in place, n joint values (one thread each,
+// grid-stride): qd <- qd + dt qdd, then q <- q + dt qd with the new qd.
+template <class T>
+__global__ void __launch_bounds__(256) k_euler_step(int64_t n, T dt, T* __restrict__ q, T* __restrict__ qd,
+                                                    const T* __restrict__ qdd) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = qd[i] + dt * qdd[i];
+    qd[i] = v;
+    q[i] = q[i] + dt * v;
+  }
+}
+
+// Adjoint of k_euler_step for a reverse pass that alternates with the
+// forward-dynamics adjoint: first the forward-dynamics cotangents of the later
+// step are added (qb += qbf, qdb += qdbf, pib += pibf, each if given), then the
+// step's own adjoint: qdb <- qdb + dt qb (the cotangent of qd before the step),
+// qddb = dt qdb (the cotangent of qdd). qb passes through unchanged.
+template <class T>
+__global__ void __launch_bounds__(256) k_euler_step_vjp(int64_t n, T dt, T* __restrict__ qb, T* __restrict__ qdb,
+                                                        const T* __restrict__ qbf, const T* __restrict__ qdbf,
+                                                        T* __restrict__ qddb, int64_t n_pi, T* __restrict__ pib,
+                                                        const T* __restrict__ pibf) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    T a = qb[i], b = qdb[i];
+    if (qbf) {
+      a += qbf[i];
+      b += qdbf[i];
+      qb[i] = a;
+    }
+    if (qddb) {
+      b += dt * a;
+      qddb[i] = dt * b;
+    }
+    qdb[i] = b;
+  }
+  if (pibf)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pi; i += stride) pib[i] += pibf[i];
+}
+
 // ---- host side ------------------------------------------------------------------
 
 struct Layout {
@@ -973,6 +1027,30 @@ int scratch_words(int op) {
 
 bool is_vjp(int op) { return op == PDYN_OP_RNEA_ID_VJP || op == PDYN_OP_ABA_FD_VJP; }
 
+// The host copies of the CSR offsets and of the lane order (pdyn_model): first
+// offset 0, every chain 1 .. n_links_max links, last offset n_links_total, and
+// the order a permutation. Runs before any device work.
+int check_host_csr(const pdyn_model* m) {
+  if (m->n_chains == 1) return PDYN_OK;
+  const int32_t* lp = m->link_ptr_host;
+  if (!lp || lp[0] != 0) return PDYN_EINVAL;
+  for (int32_t c = 0; c < m->n_chains; ++c) {
+    const int64_t len = (int64_t)lp[c + 1] - lp[c];
+    if (len < 1 || len > m->n_links_max) return PDYN_EINVAL;
+  }
+  if ((int64_t)lp[m->n_chains] != m->n_links_total) return PDYN_EINVAL;
+  if (m->order) {
+    if (!m->order_host) return PDYN_EINVAL;
+    std::vector<unsigned char> seen((size_t)m->n_chains, 0);
+    for (int32_t j = 0; j < m->n_chains; ++j) {
+      const int32_t c = m->order_host[j];
+      if (c < 0 || c >= m->n_chains || seen[(size_t)c]) return PDYN_EINVAL;
+      seen[(size_t)c] = 1;
+    }
+  }
+  return PDYN_OK;
+}
+
 int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (!m || !b) return PDYN_EINVAL;
   if (m->n_chains < 1 || m->n_links_max < 1 || m->n_links_total < 1 || b->n_states < 0) return PDYN_EINVAL;
@@ -987,6 +1065,8 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   } else {
     if (m->n_chains != b->n_states || !m->link_ptr) return PDYN_EINVAL;
     if (m->n_links_total > INT32_MAX) return PDYN_EUNSUPPORTED;
+    // a call without prepared tables derives them from link_ptr and order: check their host copies
+    if (!m->prepared) return check_host_csr(m);
   }
   return PDYN_OK;
 }
@@ -994,26 +1074,26 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
 // The derived tables: records in the scalar type, then the same in double.
 // One shared chain: [n][32] each. One chain per state: interleaved over the
 // lanes of each wavefront, n_max records per group of 64 lane indices
-// ([group][n_max][32][64] each, see k_link_table_ilv), then the lane -> chain
-// map [n_chains] that the kernels use with these tables.
+// ([group][n_max][32][64] each, see k_link_table_ilv), then the clamped lane
+// map [n_chains] (LaneChain) that the kernels use with these tables.
 size_t ilv_slots(const pdyn_model* m) { return ((size_t)m->n_chains + 63) / 64 * (size_t)m->n_links_max; }
-size_t tables_bytes(const pdyn_model* m, size_t scalar, size_t* wtable_off, size_t* order_off = nullptr) {
+size_t tables_bytes(const pdyn_model* m, size_t scalar, size_t* wtable_off, size_t* lanes_off = nullptr) {
   const size_t recs = m->n_chains == 1 ? (size_t)m->n_links_total : ilv_slots(m) * 64;
   const size_t t = align_up(recs * kLinkWords * scalar);
   const size_t w = align_up(recs * kLinkWords * sizeof(double));
   if (wtable_off) *wtable_off = t;
-  if (order_off) *order_off = t + w;
-  return t + w + (m->n_chains == 1 ? 0 : align_up((size_t)m->n_chains * sizeof(int32_t)));
+  if (lanes_off) *lanes_off = t + w;
+  return t + w + (m->n_chains == 1 ? 0 : align_up((size_t)m->n_chains * sizeof(LaneChain)));
 }
 
-// Lane -> state map of the kernels: none with a shared chain; with one chain
+// Lane -> chain map of the kernels: none with a shared chain; with one chain
 // per state, the copy that the table derivation wrote beside the tables it
 // built (so that the tables and the map always agree).
-const int32_t* lane_order(const pdyn_model* m, const char* tbase, size_t scalar) {
+const LaneChain* lane_map(const pdyn_model* m, const char* tbase, size_t scalar) {
   if (m->n_chains == 1) return nullptr;
-  size_t woff, ooff;
-  tables_bytes(m, scalar, &woff, &ooff);
-  return reinterpret_cast<const int32_t*>(tbase + ooff);
+  size_t woff, loff;
+  tables_bytes(m, scalar, &woff, &loff);
+  return reinterpret_cast<const LaneChain*>(tbase + loff);
 }
 
 int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, Layout* L) {
@@ -1049,6 +1129,126 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// ---- launch tuning table (pdyn_load_tuning) ----------------------------------------
+//
+// Entries written by the autotuner: for an operation, scalar size, model kind
+// (shared chain or one chain per state), a link count and a batch size, the
+// launch fields of pdyn_batch to use when a call leaves all of them at 0. A
+// call takes the entry of its operation, scalar size and kind whose link count
+// and batch size are nearest in log scale, if both lie within a factor of 2.
+struct TuneEntry {
+  int op, scalar, shared, n_max, n_states, block, max_blocks, variant;
+};
+
+std::mutex g_tune_mutex;
+std::shared_ptr<const std::vector<TuneEntry>> g_tune;
+
+// A minimal reader for the one document shape pdyn_load_tuning accepts:
+// {"entries": [{"key": integer, ...}, ...]} (whitespace anywhere; nothing else).
+struct JsonReader {
+  const char* p;
+  void ws() {
+    while (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r') ++p;
+  }
+  bool lit(char c) {
+    ws();
+    if (*p != c) return false;
+    ++p;
+    return true;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (*p != '"') return false;
+    const char* q = ++p;
+    while (*p && *p != '"' && *p != '\\') ++p;
+    if (*p != '"') return false;
+    out->assign(q, p);
+    ++p;
+    return true;
+  }
+  bool integer(long* out) {
+    ws();
+    char* end = nullptr;
+    const long v = std::strtol(p, &end, 10);
+    if (end == p) return false;
+    p = end;
+    *out = v;
+    return true;
+  }
+};
+
+bool valid_launch(int block, int max_blocks, int variant) {
+  return block >= 0 && block % 64 == 0 && block <= kMaxBlock && max_blocks >= 0 && variant >= 0 && variant <= 3;
+}
+
+int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
+  JsonReader r{text};
+  std::string key;
+  if (!r.lit('{') || !r.str(&key) || key != "entries" || !r.lit(':') || !r.lit('[')) return PDYN_EINVAL;
+  if (!r.lit(']')) {
+    do {
+      if (!r.lit('{')) return PDYN_EINVAL;
+      TuneEntry e{-1, 0, -1, 0, -1, 0, 0, 0};
+      do {
+        long v;
+        if (!r.str(&key) || !r.lit(':') || !r.integer(&v) || v < INT32_MIN || v > INT32_MAX) return PDYN_EINVAL;
+        const int iv = (int)v;
+        if (key == "op") e.op = iv;
+        else if (key == "scalar") e.scalar = iv;
+        else if (key == "shared") e.shared = iv;
+        else if (key == "n_max") e.n_max = iv;
+        else if (key == "n_states") e.n_states = iv;
+        else if (key == "block") e.block = iv;
+        else if (key == "max_blocks") e.max_blocks = iv;
+        else if (key == "variant") e.variant = iv;
+        else return PDYN_EINVAL;
+      } while (r.lit(','));
+      if (!r.lit('}')) return PDYN_EINVAL;
+      if (e.op < PDYN_OP_RNEA_ID || e.op > PDYN_OP_ABA_FD_VJP || (e.scalar != 4 && e.scalar != 8) ||
+          (e.shared != 0 && e.shared != 1) || e.n_max < 1 || e.n_states < 0 ||
+          !valid_launch(e.block, e.max_blocks, e.variant))
+        return PDYN_EINVAL;
+      out->push_back(e);
+    } while (r.lit(','));
+    if (!r.lit(']')) return PDYN_EINVAL;
+  }
+  if (!r.lit('}')) return PDYN_EINVAL;
+  r.ws();
+  return *r.p == '\0' ? PDYN_OK : PDYN_EINVAL;
+}
+
+// The batch a call runs with: the caller's, or, when it leaves every launch
+// field at 0, the tuning table's nearest entry for this call (if any).
+pdyn_batch tuned_batch(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar) {
+  pdyn_batch r = *b;
+  if (b->block_threads || b->max_blocks || b->variant) return r;
+  std::shared_ptr<const std::vector<TuneEntry>> tab;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    tab = g_tune;
+  }
+  if (!tab) return r;
+  const int shared = m->n_chains == 1 ? 1 : 0;
+  const TuneEntry* best = nullptr;
+  double best_d = 0;
+  for (const TuneEntry& e : *tab) {
+    if (e.op != op || e.scalar != (int)scalar || e.shared != shared) continue;
+    const double dn = std::fabs(std::log2((double)m->n_links_max / e.n_max));
+    const double db = std::fabs(std::log2(((double)b->n_states + 1) / ((double)e.n_states + 1)));
+    if (dn > 1.0 || db > 1.0) continue;
+    if (!best || dn + db < best_d) {
+      best = &e;
+      best_d = dn + db;
+    }
+  }
+  if (best) {
+    r.block_threads = best->block;
+    r.max_blocks = best->max_blocks;
+    r.variant = best->variant;
+  }
+  return r;
+}
+
 // Workgroup size and count of the tunable kernels (validated in check_model_batch).
 void launch_shape(const pdyn_batch* b, unsigned* grid, unsigned* block) {
   const unsigned bt = b->block_threads > 0 ? (unsigned)b->block_threads : (unsigned)kBlock;
@@ -1082,9 +1282,10 @@ int launch_link_table(const pdyn_model* m, char* dst, hipStream_t s) {
     const size_t threads = ilv_slots(m) * 64;
     if ((threads + 255) / 256 > 0x7fffffffu) return PDYN_EUNSUPPORTED;
     hipLaunchKernelGGL(k_link_table_ilv<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m->n_chains,
-                       m->n_links_max, m->link_ptr, m->order, static_cast<const T*>(m->placement),
-                       static_cast<const T*>(m->twist), static_cast<const T*>(m->inertia), reinterpret_cast<T*>(dst),
-                       reinterpret_cast<double*>(dst + woff), reinterpret_cast<int32_t*>(dst + ooff));
+                       m->n_links_max, (int64_t)m->n_links_total, m->link_ptr, m->order,
+                       static_cast<const T*>(m->placement), static_cast<const T*>(m->twist),
+                       static_cast<const T*>(m->inertia), reinterpret_cast<T*>(dst),
+                       reinterpret_cast<double*>(dst + woff), reinterpret_cast<LaneChain*>(dst + ooff));
   }
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
@@ -1127,6 +1328,8 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
                  const T* tau_in, T* tau_out, T* qdd_out, void* ws, size_t ws_bytes, void* stream) {
   int st = check_model_batch(m, b);
   if (st) return st;
+  const pdyn_batch bt = tuned_batch(op, m, b, sizeof(T));
+  b = &bt;
   if (b->n_states == 0) return PDYN_OK;  // empty batch: nothing to do
   if (MODE & kModeID) {
     if ((st = check_ptrs<T>({q, qd, qdd_in, tau_out}))) return st;
@@ -1148,7 +1351,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   char* base = static_cast<char*>(ws) + kStatusBytes;
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
-  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
+  const LaneChain* const lanes = lane_map(m, tbase, sizeof(T));
   const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
   const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
   if (!m->prepared) {
@@ -1160,12 +1363,12 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   if (MODE == kModeID && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     if (m->n_chains == 1)
-      hipLaunchKernelGGL((k_id_split<T, true>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
-                         ord, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+      hipLaunchKernelGGL((k_id_split<T, true>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, lanes,
+                         table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
                          scratch, status);
     else
-      hipLaunchKernelGGL((k_id_split<T, false>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, m->link_ptr,
-                         ord, table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
+      hipLaunchKernelGGL((k_id_split<T, false>), dim3(g), dim3(128), 0, s, b->n_states, m->n_links_max, lanes,
+                         table, wtable, q, qd, qdd_in, tau_out, static_cast<const T*>(b->tip_wrench), ba,
                          scratch, status);
     if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
     return PDYN_OK;
@@ -1192,7 +1395,7 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)                  \
       return PDYN_ELAUNCH;                                                                                        \
     hipLaunchKernelGGL((k_dynamics_split<T, MODE, SH, LM>), dim3(g), dim3(blk), lds, s, b->n_states,              \
-                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
+                       m->n_links_max, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out,      \
                        qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi, status);     \
   } while (0)
     if (shared) {
@@ -1213,8 +1416,8 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   if (variant == 3) {
     // the plain form: one launch per sweep, per-link intermediates in the (HBM) scratch between them
 #define PDYN_LAUNCH_SWEEP(SH, SW)                                                                                 \
-  hipLaunchKernelGGL((k_dynamics<T, MODE, SH, SW>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,       \
-                     m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, \
+  hipLaunchKernelGGL((k_dynamics<T, MODE, SH, SW>), dim3(grid), dim3(block), 0, s, b->n_states,       \
+                     m->n_links_max, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, \
                      static_cast<const T*>(b->tip_wrench), ba, scratch, status)
     if (m->n_chains == 1) {
       PDYN_LAUNCH_SWEEP(true, kSweep1);
@@ -1230,12 +1433,12 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     return PDYN_OK;
   }
   if (m->n_chains == 1)
-    hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
-                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+    hipLaunchKernelGGL((k_dynamics<T, MODE, true>), dim3(grid), dim3(block), 0, s, b->n_states,
+                       m->n_links_max, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                        static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   else
-    hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains,
-                       m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
+    hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states,
+                       m->n_links_max, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                        static_cast<const T*>(b->tip_wrench), ba, scratch, status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
@@ -1289,7 +1492,7 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
-  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
+  const LaneChain* const lanes = lane_map(m, tbase, sizeof(T));
   if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
@@ -1297,8 +1500,8 @@ int run_rollout(const pdyn_model* m, const pdyn_batch* b, int steps, double dt, 
   unsigned grid, block;
   launch_shape(b, &grid, &block);
 #define PDYN_LAUNCH_ROLLOUT(SH)                                                                                  \
-  hipLaunchKernelGGL((k_rollout<T, SH>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_chains, m->n_links_max,   \
-                     m->link_ptr, ord, reinterpret_cast<const T*>(tbase),                                    \
+  hipLaunchKernelGGL((k_rollout<T, SH>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_links_max, lanes,         \
+                     reinterpret_cast<const T*>(tbase),                                    \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, q, qd, ckpt_q,   \
                      ckpt_qd, dofs, ba, reinterpret_cast<T*>(base + so), status)
   if (m->n_chains == 1)
@@ -1329,7 +1532,7 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
-  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
+  const LaneChain* const lanes = lane_map(m, tbase, sizeof(T));
   if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
@@ -1337,8 +1540,8 @@ int run_rollout_vjp(const pdyn_model* m, const pdyn_batch* b, int steps, double 
   const unsigned grid = (unsigned)((b->n_states + kBlock - 1) / kBlock);
   T* acc = reinterpret_cast<T*>(base + ao);
 #define PDYN_LAUNCH_RVJP(PI, SH)                                                                                 \
-  hipLaunchKernelGGL((k_rollout_vjp<T, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,          \
-                     m->n_links_max, m->link_ptr, ord, reinterpret_cast<const T*>(tbase),                   \
+  hipLaunchKernelGGL((k_rollout_vjp<T, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states,          \
+                     m->n_links_max, lanes, reinterpret_cast<const T*>(tbase),                   \
                      reinterpret_cast<const double*>(tbase + woff), steps, (T)dt, every, tau_seq, ckpt_q,          \
                      ckpt_qd, qT_bar, qdT_bar, q0_bar, qd0_bar, tau_bar_seq, inertia_bar, dofs, ba,               \
                      reinterpret_cast<T*>(base + so), reinterpret_cast<T*>(base + ro), acc, status)
@@ -1364,6 +1567,8 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   const int op = (OP == kVjpID) ? PDYN_OP_RNEA_ID_VJP : PDYN_OP_ABA_FD_VJP;
   int st = check_model_batch(m, b);
   if (st) return st;
+  const pdyn_batch bt = tuned_batch(op, m, b, sizeof(T));
+  b = &bt;
   if (b->n_states == 0) return PDYN_OK;
   if ((st = check_ptrs<T>({q, qd, qdd, bar_in, q_bar, qd_bar, out3}))) return st;
   if ((st = check_ptrs<T>({m->placement, m->twist, m->inertia}))) return st;
@@ -1382,7 +1587,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   T* partials = reinterpret_cast<T*>(base + L.partial_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
-  const int32_t* const ord = lane_order(m, tbase, sizeof(T));
+  const LaneChain* const lanes = lane_map(m, tbase, sizeof(T));
   const T* table = reinterpret_cast<const T*>(tbase + L.table_off);
   const double* wtable = reinterpret_cast<const double*>(tbase + L.wtable_off);
   if (!m->prepared) {
@@ -1413,7 +1618,7 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)              \
       return PDYN_ELAUNCH;                                                                                    \
     hipLaunchKernelGGL((k_vjp_split<T, OP, PI, SH, OV>), dim3(grid64), dim3(OV ? vjp_block : 128), OV ? lds : 0, s, \
-                       b->n_states, m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in,   \
+                       b->n_states, m->n_links_max, lanes, table, wtable, q, qd, qdd, bar_in,   \
                        q_bar, qd_bar, qdd_bar, tau_bar, PIOUT, tip, ba, scratch, xscratch, status);           \
   } while (0)
 #define PDYN_LAUNCH_VJP(PI, SH, PIOUT)                                                                        \
@@ -1425,8 +1630,8 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
     else if (split)                                                                                           \
       PDYN_LAUNCH_VJP_SPLIT(PI, SH, 0, PIOUT);                                                                \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states, m->n_chains,    \
-                         m->n_links_max, m->link_ptr, ord, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
+      hipLaunchKernelGGL((k_vjp<T, OP, PI, SH>), dim3(grid), dim3(kBlock), 0, s, b->n_states,    \
+                         m->n_links_max, lanes, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, \
                          qdd_bar, tau_bar, PIOUT, tip, ba, scratch, status);                                  \
   } while (0)
   if (!inertia_bar) {
@@ -1445,6 +1650,40 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
 #undef PDYN_LAUNCH_VJP_SPLIT
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
+}
+
+// Grid of the elementwise kernels: one thread per element, at most 8192 workgroups (grid-stride beyond).
+unsigned elementwise_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+template <class T>
+int run_euler_step(int64_t n, double dt, T* q, T* qd, const T* qdd, void* stream) {
+  if (n < 0 || !(dt == dt)) return PDYN_EINVAL;
+  if (n == 0) return PDYN_OK;
+  int st = check_ptrs<T>({q, qd, qdd});
+  if (st) return st;
+  hipLaunchKernelGGL(k_euler_step<T>, dim3(elementwise_grid(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
+                     (T)dt, q, qd, qdd);
+  return hipGetLastError() == hipSuccess ? PDYN_OK : PDYN_ELAUNCH;
+}
+
+template <class T>
+int run_euler_step_vjp(int64_t n, double dt, T* qb, T* qdb, const T* qbf, const T* qdbf, T* qddb, int64_t n_pi, T* pib,
+                       const T* pibf, void* stream) {
+  if (n < 0 || n_pi < 0 || !(dt == dt)) return PDYN_EINVAL;
+  if ((qbf == nullptr) != (qdbf == nullptr)) return PDYN_EINVAL;
+  if (pibf && !pib) return PDYN_EINVAL;
+  int st = check_ptrs<T>({qb, qdb});
+  if (n > 0 && st) return st;
+  for (const void* p : {(const void*)qbf, (const void*)qdbf, (const void*)qddb, (const void*)pib, (const void*)pibf})
+    if (p && !aligned(p, sizeof(T))) return PDYN_EALIGN;
+  const int64_t m = n > n_pi || !pibf ? n : n_pi;
+  if (m == 0) return PDYN_OK;
+  hipLaunchKernelGGL(k_euler_step_vjp<T>, dim3(elementwise_grid(m)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     n, (T)dt, qb, qdb, qbf, qdbf, qddb, n_pi, pib, pibf);
+  return hipGetLastError() == hipSuccess ? PDYN_OK : PDYN_ELAUNCH;
 }
 
 }  // namespace
@@ -1486,6 +1725,11 @@ int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared
   if (!model || model->n_chains < 1 || model->n_links_total < 1 || !prepared) return PDYN_EINVAL;
   if (!model->placement || !model->twist || !model->inertia) return PDYN_EINVAL;
   if (model->n_chains > 1 && !model->link_ptr) return PDYN_EINVAL;
+  if (model->n_links_max < 1) return PDYN_EINVAL;
+  if (model->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
+  if (model->n_chains == 1 ? model->n_links_total != model->n_links_max : model->n_links_total > INT32_MAX)
+    return model->n_chains == 1 ? PDYN_EINVAL : PDYN_EUNSUPPORTED;
+  if (check_host_csr(model)) return PDYN_EINVAL;
   if (!aligned(prepared, kAlign) || (model->order && !aligned(model->order, sizeof(int32_t)))) return PDYN_EALIGN;
   size_t a = (size_t)scalar_bytes;
   if (!aligned(model->placement, a) || !aligned(model->twist, a) || !aligned(model->inertia, a)) return PDYN_EALIGN;
@@ -1496,6 +1740,33 @@ int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared
 }
 
 int pdyn_max_links(void) { return kMaxLinks; }
+
+int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes,
+                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant) {
+  if (scalar_bytes != 4 && scalar_bytes != 8) return PDYN_EINVAL;
+  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP || !block_threads || !max_blocks || !variant)
+    return PDYN_EINVAL;
+  const int st = check_model_batch(model, batch);
+  if (st) return st;
+  const pdyn_batch b = tuned_batch(op, model, batch, (size_t)scalar_bytes);
+  *block_threads = b.block_threads;
+  *max_blocks = b.max_blocks;
+  *variant = b.variant;
+  return PDYN_OK;
+}
+
+int pdyn_load_tuning(const char* json) {
+  std::shared_ptr<const std::vector<TuneEntry>> tab;
+  if (json && *json) {
+    auto v = std::make_shared<std::vector<TuneEntry>>();
+    const int st = parse_tuning(json, v.get());
+    if (st) return st;
+    tab = v;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune = tab;
+  return PDYN_OK;
+}
 
 const char* pdyn_strerror(int status) {
   switch (status) {
@@ -1585,6 +1856,25 @@ int pdyn_rollout_vjp_f64(const pdyn_model* m, const pdyn_batch* b, int steps, do
                          double* inertia_bar, void* ws, size_t ws_bytes, void* stream) {
   return run_rollout_vjp<double>(m, b, steps, dt, ckpt_every, tau_seq, ckpt_q, ckpt_qd, qT_bar, qdT_bar, q0_bar,
                                  qd0_bar, tau_bar_seq, inertia_bar, ws, ws_bytes, stream);
+}
+
+int pdyn_euler_step(int64_t n, double dt, float* q, float* qd, const float* qdd, void* stream) {
+  return run_euler_step<float>(n, dt, q, qd, qdd, stream);
+}
+int pdyn_euler_step_f64(int64_t n, double dt, double* q, double* qd, const double* qdd, void* stream) {
+  return run_euler_step<double>(n, dt, q, qd, qdd, stream);
+}
+int pdyn_euler_step_vjp(int64_t n, double dt, float* q_bar, float* qd_bar, const float* q_bar_fd,
+                        const float* qd_bar_fd, float* qdd_bar, int64_t n_pi, float* pi_bar, const float* pi_bar_fd,
+                        void* stream) {
+  return run_euler_step_vjp<float>(n, dt, q_bar, qd_bar, q_bar_fd, qd_bar_fd, qdd_bar, n_pi, pi_bar, pi_bar_fd,
+                                   stream);
+}
+int pdyn_euler_step_vjp_f64(int64_t n, double dt, double* q_bar, double* qd_bar, const double* q_bar_fd,
+                            const double* qd_bar_fd, double* qdd_bar, int64_t n_pi, double* pi_bar,
+                            const double* pi_bar_fd, void* stream) {
+  return run_euler_step_vjp<double>(n, dt, q_bar, qd_bar, q_bar_fd, qd_bar_fd, qdd_bar, n_pi, pi_bar, pi_bar_fd,
+                                    stream);
 }
 
 }  // extern "C"

@@ -208,6 +208,24 @@ template <int MODE> struct ScratchWords {
 // (non-physical inertia parameters).
 constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusPivot = 2u;
+// A wavefront gave up waiting for a hand-off from another wavefront of its
+// workgroup (PDYN_STATUS_WAIT).
+constexpr unsigned kStatusWait = 4u;
+
+// Polls poll() until it returns at least k, calling pause() between polls, at
+// most `limit` times. Returns the last value read; if that is still below k
+// the wait has given up, and kStatusWait is ORed into *status (if given), so
+// that the caller's results are marked untrustworthy instead of silently wrong.
+template <class Poll, class Pause>
+PD_HD int bounded_wait(const Poll& poll, const Pause& pause, int k, int limit, unsigned* status) {
+  int v = poll();
+  for (int spin = 0; v < k && spin < limit; ++spin) {
+    pause();
+    v = poll();
+  }
+  if (v < k && status) __hip_atomic_fetch_or(status, kStatusWait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
 
 // Strided view of the per-link scratch of one state. It also carries the
 // call's status word (null: faults are not reported).

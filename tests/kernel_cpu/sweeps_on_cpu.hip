@@ -352,3 +352,19 @@ extern "C" {
 void cpu_read_ilv_f32(const float* ilv, int lane, int i, float* out) { read_ilv(ilv, lane, i, out); }
 void cpu_read_ilv_f64(const double* ilv, int lane, int i, double* out) { read_ilv(ilv, lane, i, out); }
 }
+
+// The kernels' bounded wait (bounded_wait) driven from the host: a progress
+// word that reaches `reach` after `after` polls (never, if after < 0), waited
+// for up to `k` with `limit` polls. Returns the last value read; *status gets
+// the give-up bit exactly when the wait ends below k.
+extern "C" int cpu_bounded_wait(int k, int reach, int after, int limit, unsigned* status, int* polls) {
+  int calls = 0;
+  const int v = bounded_wait(
+      [&] {
+        ++calls;
+        return (after >= 0 && calls > after) ? reach : 0;
+      },
+      [] {}, k, limit, status);
+  *polls = calls;
+  return v;
+}

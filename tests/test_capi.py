@@ -166,3 +166,155 @@ def test_workspace_holds_the_status_word():
     b = api._batch_struct(1, api.ZERO6, api.GRAVITY_ACC, None)
     for op in range(5):
         assert L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), 4) >= 256 + 256
+
+
+def _chain_model(lp_host, order_host=None, n_links_max=None, with_order=False):
+    """A two-or-more-chain model whose device pointers are host addresses: only host-side checks may touch it."""
+    lp_host = np.ascontiguousarray(lp_host, np.int32)
+    n_chains = len(lp_host) - 1
+    L = int(max(lp_host[-1], 1))
+    nmax = n_links_max if n_links_max is not None else int(max(np.diff(lp_host).max(), 1))
+    arrays = [np.zeros((L, k), np.float32) for k in (7, 6, 10)]
+    dev_lp = lp_host.copy()
+    order = None if order_host is None else np.ascontiguousarray(order_host, np.int32)
+    m = api._Model(n_chains, nmax, L, dev_lp.ctypes.data, *(a.ctypes.data for a in arrays), 0,
+                   0 if not with_order else order.ctypes.data,
+                   lp_host.ctypes.data, 0 if order is None else order.ctypes.data)
+    return m, (lp_host, dev_lp, order, arrays)
+
+
+def _csr_accepted(m):
+    """Host validation of a one-chain-per-state model, without launching anything: the workspace query
+    returns 0 exactly when the model/batch checks fail, and pdyn_model_prepare fails before any launch."""
+    L = api.lib()
+    b = api._batch_struct(m.n_chains, api.ZERO6, api.GRAVITY_ACC, None)
+    return L.pdyn_workspace_bytes(2, ctypes.byref(m), ctypes.byref(b), 4) > 0
+
+
+def test_bad_csr_is_rejected_on_the_host():
+    L = api.lib()
+    good, keep = _chain_model([0, 3, 5, 9])
+    assert _csr_accepted(good)
+    cases = {
+        "first offset not 0": [1, 3, 5, 9],
+        "empty chain": [0, 3, 3, 9],
+        "decreasing offsets": [0, 5, 3, 9],
+        "last offset is not n_links_total": [0, 3, 5, 8],
+    }
+    for what, lp in cases.items():
+        m, k = _chain_model(lp, n_links_max=4)
+        m.n_links_total = 9
+        assert not _csr_accepted(m), what
+    # a chain longer than n_links_max
+    m, k = _chain_model([0, 3, 5, 9], n_links_max=3)
+    assert not _csr_accepted(m)
+    # the host copy is required
+    m, k = _chain_model([0, 3, 5, 9])
+    m.link_ptr_host = 0
+    assert not _csr_accepted(m)
+    # the same checks guard pdyn_model_prepare and the operations themselves, before any launch
+    m, k = _chain_model([0, 3, 3, 9], n_links_max=4)
+    m.n_links_total = 9
+    buf = np.zeros(1 << 22, np.uint8)
+    p = buf.ctypes.data + ((-buf.ctypes.data) % 256)
+    assert L.pdyn_model_prepare(ctypes.byref(m), 4, p, (1 << 22) - 256, None) == -1
+    x = np.zeros(9, np.float32)
+    b = api._batch_struct(3, api.ZERO6, api.GRAVITY_ACC, None)
+    px = x.ctypes.data
+    assert L.pdyn_rnea_id(ctypes.byref(m), ctypes.byref(b), px, px, px, px, p, (1 << 22) - 256, None) == -1
+    assert L.pdyn_aba_fd_vjp(ctypes.byref(m), ctypes.byref(b), px, px, px, px, px, px, px, 0, p,
+                             (1 << 22) - 256, None) == -1
+
+
+def test_bad_order_is_rejected_on_the_host():
+    good, keep = _chain_model([0, 3, 5, 9], order_host=[2, 0, 1], with_order=True)
+    assert _csr_accepted(good)
+    for what, order in {"duplicate": [0, 0, 1], "out of range": [0, 1, 3], "negative": [-1, 0, 1]}.items():
+        m, k = _chain_model([0, 3, 5, 9], order_host=order, with_order=True)
+        assert not _csr_accepted(m), what
+    # a device order without its host copy
+    m, k = _chain_model([0, 3, 5, 9], order_host=[2, 0, 1], with_order=True)
+    m.order_host = 0
+    assert not _csr_accepted(m)
+
+
+def test_prepared_model_skips_the_per_call_csr_check():
+    """With prepared tables the per-call check reads no host CSR (the tables carry the clamped lane map)."""
+    m, keep = _chain_model([0, 3, 5, 9])
+    m.link_ptr_host = 0
+    assert not _csr_accepted(m)
+    m.prepared = 256  # any aligned non-null pointer: only the workspace size is queried
+    assert _csr_accepted(m)
+
+
+def test_euler_step_validation():
+    """pdyn_euler_step / _vjp: argument checks on the host, before any launch; n == 0 queues nothing."""
+    L = api.lib()
+    x = np.zeros(8, np.float32)
+    p = x.ctypes.data
+    assert L.pdyn_euler_step(0, 1e-3, p, p, p, None) == 0
+    assert L.pdyn_euler_step(-1, 1e-3, p, p, p, None) == -1
+    assert L.pdyn_euler_step(8, float("nan"), p, p, p, None) == -1
+    assert L.pdyn_euler_step(8, 1e-3, p, None, p, None) == -1
+    assert L.pdyn_euler_step(8, 1e-3, p, p + 2, p, None) == -2
+    f = L.pdyn_euler_step_vjp
+    assert f(0, 1e-3, p, p, None, None, None, 0, None, None, None) == 0
+    assert f(8, 1e-3, p, p, p, None, p, 0, None, None, None) == -1   # q_bar_fd without qd_bar_fd
+    assert f(8, 1e-3, p, p, None, None, p, 10, None, p, None) == -1  # pi_bar_fd without pi_bar
+    assert f(8, 1e-3, None, p, None, None, p, 0, None, None, None) == -1
+    assert f(8, 1e-3, p, p, None, None, p + 1, 0, None, None, None) == -2
+    assert f(-2, 1e-3, p, p, None, None, p, 0, None, None, None) == -1
+
+
+def test_load_tuning_parses_and_rejects():
+    """pdyn_load_tuning: the autotuner's table form is accepted; malformed text or out-of-range values are
+    rejected (PDYN_EINVAL) without replacing the installed table; NULL clears it."""
+    L = api.lib()
+    good = (b'{"entries": [{"op": 2, "scalar": 4, "shared": 0, "n_max": 100, "n_states": 4096, '
+            b'"block": 0, "max_blocks": 0, "variant": 2},\n {"op": 0, "scalar": 8, "shared": 1, "n_max": 7, '
+            b'"n_states": 64, "block": 128, "max_blocks": 256, "variant": 1}]}')
+    assert L.pdyn_load_tuning(good) == 0
+    assert L.pdyn_load_tuning(b'{"entries": []}') == 0
+    bad = [b'{"entries": [{"op": 9, "scalar": 4, "shared": 0, "n_max": 1, "n_states": 1}]}',
+           b'{"entries": [{"op": 0, "scalar": 2, "shared": 0, "n_max": 1, "n_states": 1}]}',
+           b'{"entries": [{"op": 0, "scalar": 4, "shared": 0, "n_max": 1, "n_states": 1, "block": 100}]}',
+           b'{"entries": [{"op": 0, "scalar": 4, "shared": 0, "n_max": 1, "n_states": 1, "variant": 7}]}',
+           b'{"entries": [{"op": 0, "scalar": 4, "shared": 0, "n_max": 0, "n_states": 1}]}',
+           b'{"entries": [{"op": 0, "scalar": 4, "shared": 0, "n_max": 1, "n_states": 1, "colour": 3}]}',
+           b'{"entries": [{"op": 0, "scalar": 4}', b'{"rows": []}', b'{"entries": []} trailing', b'[]']
+    for text in bad:
+        assert L.pdyn_load_tuning(text) == -1, text
+    assert L.pdyn_load_tuning(None) == 0
+    assert L.pdyn_load_tuning(b"") == 0
+
+
+def test_tuning_table_decides_the_launch():
+    """After pdyn_load_tuning, a call that leaves its launch fields at 0 takes the nearest entry of its
+    operation, precision and model kind within a factor of 2 in links and states (pdyn_launch_choice)."""
+    L = api.lib()
+    m, keep = _fake_model(n=32)
+
+    def choice(op, n_states, scalar=4, fields=(0, 0, 0)):
+        b = api._batch_struct(n_states, api.ZERO6, api.GRAVITY_ACC, None)
+        b.block_threads, b.max_blocks, b.variant = fields
+        out = [ctypes.c_int32(-9) for _ in range(3)]
+        assert L.pdyn_launch_choice(op, ctypes.byref(m), ctypes.byref(b), scalar, *map(ctypes.byref, out)) == 0
+        return tuple(o.value for o in out)
+
+    text = (b'{"entries": [{"op": 2, "scalar": 4, "shared": 1, "n_max": 32, "n_states": 16384, "block": 0, '
+            b'"max_blocks": 0, "variant": 1}, {"op": 2, "scalar": 4, "shared": 1, "n_max": 32, "n_states": 1024, '
+            b'"block": 128, "max_blocks": 64, "variant": 3}, {"op": 1, "scalar": 8, "shared": 1, "n_max": 40, '
+            b'"n_states": 100, "block": 64, "max_blocks": 0, "variant": 2}]}')
+    try:
+        assert choice(2, 16384) == (0, 0, 0)  # no table yet: library defaults
+        assert L.pdyn_load_tuning(text) == 0
+        assert choice(2, 20000) == (0, 0, 1)
+        assert choice(2, 1500) == (128, 64, 3)
+        assert choice(2, 100) == (0, 0, 0)  # no entry within a factor of 2 in states
+        assert choice(2, 16384, scalar=8) == (0, 0, 0)  # other precision
+        assert choice(0, 16384) == (0, 0, 0)  # other operation
+        assert choice(1, 100, scalar=8) == (64, 0, 2)  # 32 vs 40 links: within a factor of 2
+        assert choice(2, 16384, fields=(64, 0, 0)) == (64, 0, 0)  # explicit launch fields win
+    finally:
+        assert L.pdyn_load_tuning(None) == 0
+    assert choice(2, 20000) == (0, 0, 0)

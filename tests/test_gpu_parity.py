@@ -368,3 +368,4 @@ def test_role_split_lds_modes(device, n, B, dtype):
     finally:
         for op in (api.OP_ABA_FD, api.OP_ID_FD):
             api.set_launch(op, 0, 0, 0)
+

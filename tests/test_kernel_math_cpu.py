@@ -325,3 +325,25 @@ def test_interleaved_record_reader(cpu_lib):
         for i, l in ((0, 0), (2, 17), (4, 63), (3, 40)):
             fn(_p(ilv), l, i, _p(out))
             assert np.array_equal(out, rec[i, l]), (dt, i, l)
+
+
+def test_bounded_wait_reports_a_give_up(cpu_lib):
+    """The wavefront hand-off wait of the role-split kernels: a wait that is satisfied leaves the status word
+    alone; one that reaches its spin bound ORs PDYN_STATUS_WAIT (4) into it and returns the value it last read."""
+    fn = cpu_lib.cpu_bounded_wait
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32),
+                   ctypes.POINTER(ctypes.c_int)]
+    fn.restype = ctypes.c_int
+    st, polls = ctypes.c_uint32(1), ctypes.c_int(0)
+    assert fn(5, 7, 3, 100, ctypes.byref(st), ctypes.byref(polls)) == 7
+    assert st.value == 1 and polls.value == 4  # satisfied on the 4th poll; the other bits are kept
+    assert fn(5, 7, -1, 50, ctypes.byref(st), ctypes.byref(polls)) == 0
+    assert st.value == 1 | 4 and polls.value == 51  # gave up after the first poll and 50 more
+    st.value = 0
+    assert fn(5, 4, 0, 10, ctypes.byref(st), ctypes.byref(polls)) == 4  # progress stalls below k
+    assert st.value == 4
+    st.value = 0
+    assert fn(0, 0, -1, 10, ctypes.byref(st), ctypes.byref(polls)) == 0 and st.value == 0  # nothing to wait for
+    assert polls.value == 1
+    from paper_1609_04493_amd import api
+    assert api.STATUS_WAIT == 4
