@@ -137,10 +137,20 @@ typedef struct pdyn_batch {
    * tip-to-base adjoint sweep run side by side. 3 (forward operations; the
    * adjoints take it as 1) = the plain form: the sweeps of variant 1 as
    * separate launches, one per recursion sweep, with the per-link
-   * intermediates in the workspace (HBM) between them. block_threads and
-   * max_blocks apply to variants 1 and 3. Every variant gives the same
+   * intermediates in the workspace (HBM) between them. 4 (inverse dynamics;
+   * the adjoints take it as 1) = the paper's serial-parallel hybrid: each
+   * chain is cut into `segments` consecutive segments handled by as many
+   * lanes; every lane folds its segment's scan operands (eqs. (12)-(13) for
+   * the velocities and accelerations, eq. (16) for the wrenches), the lanes of
+   * a chain combine their aggregates with an inclusive scan across lanes, and
+   * each lane then runs its segment from the value at its start. block_threads
+   * and max_blocks apply to variants 1 and 3. Every variant gives the same
    * results to rounding. */
   int32_t variant;
+  /* Variant 4 only: segments (lanes) per chain, a power of two 1 .. 64;
+   * 0 = library default (the largest power of two, at most 64, that leaves at
+   * least 8 links per segment). */
+  int32_t segments;
 } pdyn_batch;
 
 /* Status word. The first 256 bytes of every workspace hold a 32-bit word into
@@ -197,10 +207,11 @@ int pdyn_max_links(void);
  * Installs a launch tuning table (host text, NUL-terminated), as written by the
  * project's autotuner:
  *   {"entries": [{"op": 2, "scalar": 4, "shared": 0, "n_max": 100, "n_states": 4096,
- *                 "block": 0, "max_blocks": 0, "variant": 2}, ...]}
+ *                 "block": 0, "max_blocks": 0, "variant": 2, "segments": 0}, ...]}
  * op is a PDYN_OP_* value, scalar 4 or 8, shared 1 for a shared chain and 0
- * for one chain per state; block, max_blocks and variant follow the rules of
- * pdyn_batch's launch fields. A later call that leaves all three launch fields
+ * for one chain per state; block, max_blocks, variant and segments (optional,
+ * 0 by default) follow the rules of pdyn_batch's launch fields. A later call
+ * that leaves all four launch fields
  * of its batch at 0 takes them from the entry of its operation, scalar size
  * and model kind whose n_max and n_states are nearest in log scale, provided
  * both lie within a factor of 2; without such an entry the library defaults
@@ -211,12 +222,13 @@ int pdyn_max_links(void);
  */
 int pdyn_load_tuning(const char* json);
 
-/* The launch fields (block_threads, max_blocks, variant; host outputs) that a
- * call of operation op with this model and batch would run with: the batch's
- * own if any is non-zero, else the installed tuning table's entry for it, else
- * zeros (the library defaults). Host only: no device work. */
+/* The launch fields (block_threads, max_blocks, variant, segments; host
+ * outputs) that a call of operation op with this model and batch would run
+ * with: the batch's own if any is non-zero, else the installed tuning table's
+ * entry for it, else zeros (the library defaults). For variant 4, segments is
+ * the resolved lane count per chain. Host only: no device work. */
 int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes,
-                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant);
+                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant, int32_t* segments);
 
 /* Human-readable text for a status code (static storage). */
 const char* pdyn_strerror(int status);

@@ -36,7 +36,7 @@ class _Model(ctypes.Structure):
 class _Batch(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int32), ("base_vel", ctypes.c_double * 6), ("base_acc", ctypes.c_double * 6),
                 ("tip_wrench", ctypes.c_void_p), ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
-                ("variant", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("segments", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,7 +70,7 @@ def lib():
             L.pdyn_strerror.restype = ctypes.c_char_p
             L.pdyn_max_links.restype = ctypes.c_int
             L.pdyn_launch_choice.argtypes = [ctypes.c_int, ctypes.POINTER(_Model), ctypes.POINTER(_Batch),
-                                             ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 3
+                                             ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4
             L.pdyn_launch_choice.restype = ctypes.c_int
             L.pdyn_load_tuning.argtypes = [ctypes.c_char_p]
             L.pdyn_load_tuning.restype = ctypes.c_int
@@ -193,18 +193,19 @@ class Model:
         return (n_states, self.n_links_max) if self.n_chains == 1 else (self.n_links_total,)
 
 
-# Launch shape per call: (block_threads, max_blocks, variant); 0 = library default. Set by the autotuner.
+# Explicit launch fields per operation: (block_threads, max_blocks, variant, segments); 0 = library default
+# (or the library's tuning table, see autotune.apply).
 _launch_override = {}
 
 
-def set_launch(op: int, block_threads: int = 0, max_blocks: int = 0, variant: int = 0):
-    _launch_override[op] = (int(block_threads), int(max_blocks), int(variant))
+def set_launch(op: int, block_threads: int = 0, max_blocks: int = 0, variant: int = 0, segments: int = 0):
+    _launch_override[op] = (int(block_threads), int(max_blocks), int(variant), int(segments))
 
 
 def _batch_struct(n_states, base_vel, base_acc, tip, op=None):
     b = _Batch()
     b.n_states = n_states
-    b.block_threads, b.max_blocks, b.variant = _launch_override.get(op, (0, 0, 0))
+    b.block_threads, b.max_blocks, b.variant, b.segments = _launch_override.get(op, (0, 0, 0, 0))
     for k in range(6):
         b.base_vel[k] = float(base_vel[k])
         b.base_acc[k] = float(base_acc[k])

@@ -94,7 +94,8 @@ _installed = {}
 def library_entry(op: int, model: api.Model, n_states: int, best: dict) -> dict:
     return {"op": int(op), "scalar": model.scalar_bytes, "shared": int(model.n_chains == 1),
             "n_max": int(model.n_links_max), "n_states": int(n_states), "block": int(best["block_threads"]),
-            "max_blocks": int(best["max_blocks"]), "variant": int(best.get("variant", 0))}
+            "max_blocks": int(best["max_blocks"]), "variant": int(best.get("variant", 0)),
+            "segments": int(best.get("segments", 0))}
 
 
 def install(entries) -> None:

@@ -34,6 +34,7 @@
 
 #include "../../include/pdyn.h"
 #include "sweeps.hpp"
+#include "team.hpp"
 
 namespace pdyn {
 namespace {
@@ -615,6 +616,98 @@ __global__ void __launch_bounds__(128) k_id_split(int n_states, int n_max, const
                                  RingTakeF<T>{ring, &ready, &used, lane, status});
 }
 
+// ---- team kernels: P lanes per chain, segmented scans (team.hpp) ---------------------
+//
+// Lane index L runs member k = L % P of team j = L / P; team j takes state j
+// (in lane order) and member k the k-th segment of its chain. The cross-lane
+// scans below move an operand between the lanes of a team word by word with
+// wave shuffles (ds_bpermute), log2(P) steps (Kogge-Stone).
+
+template <int P, class Op> __device__ __forceinline__ Op team_shfl_up(const Op& x, int d) {
+  static_assert(sizeof(Op) % 4 == 0, "operands are made of 32-bit words");
+  constexpr int W = sizeof(Op) / 4;
+  unsigned w[W];
+  __builtin_memcpy(w, &x, sizeof(Op));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = (unsigned)__shfl_up((int)w[i], (unsigned)d, P);
+  Op r;
+  __builtin_memcpy(&r, w, sizeof(Op));
+  return r;
+}
+template <int P, class Op> __device__ __forceinline__ Op team_shfl_down(const Op& x, int d) {
+  constexpr int W = sizeof(Op) / 4;
+  unsigned w[W];
+  __builtin_memcpy(w, &x, sizeof(Op));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = (unsigned)__shfl_down((int)w[i], (unsigned)d, P);
+  Op r;
+  __builtin_memcpy(&r, w, sizeof(Op));
+  return r;
+}
+// Exclusive prefix over the team, later (+) earlier: member k gets the
+// composite of members 0 .. k-1 (member 0: `id`). Every lane of the wave must
+// take part.
+template <int P, class Op, class Comb>
+__device__ __forceinline__ Op team_prefix_exclusive(Op x, int k, const Op& id, const Comb& comb) {
+#pragma unroll
+  for (int d = 1; d < P; d <<= 1) {
+    const Op y = team_shfl_up<P>(x, d);
+    if (k >= d) x = comb(x, y);
+  }
+  const Op e = team_shfl_up<P>(x, 1);
+  return k == 0 ? id : e;
+}
+// Exclusive suffix over the team, earlier (x) later: member k gets the
+// composite of members k+1 .. P-1 (the last member: `id`).
+template <int P, class Op, class Comb>
+__device__ __forceinline__ Op team_suffix_exclusive(Op x, int k, const Op& id, const Comb& comb) {
+#pragma unroll
+  for (int d = 1; d < P; d <<= 1) {
+    const Op y = team_shfl_down<P>(x, d);
+    if (k + d < P) x = comb(x, y);
+  }
+  const Op e = team_shfl_down<P>(x, 1);
+  return k == P - 1 ? id : e;
+}
+
+// Inverse dynamics by the two segmented scans (variant 4). Scratch: per lane,
+// the slots of its segment, [slot][kTeamIdWords][n_lanes].
+template <class T, int P, bool SHARED>
+__global__ void __launch_bounds__(256) k_id_team(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                 const T* __restrict__ table, const double* __restrict__ wtable,
+                                                 const T* q, const T* qd, const T* qdd_in, T* tau_out,
+                                                 const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
+                                                 long n_lanes, unsigned* status) {
+  const long L = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = (int)(L / P), k = (int)(L % P);
+  const bool active = j < n_states;
+  ChainOf ch{0, 0, 0, 0};
+  if (active) ch = chain_of<SHARED>(j, n_max, lanes);
+  const Seg sg = segment_of(ch.n, P, k);
+  const auto tab = rec_view<SHARED>(table, j, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, j, n_max);
+  const SPtr<const T> qs(q + ch.dof0), qds(qd + ch.dof0), qdds(qdd_in + ch.dof0);
+  Boundary<T> bd = boundary_of(ba);
+  if (active && tip) {
+    const T* t = tip + 6 * (int64_t)ch.s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  }
+  const Scratch<T> scr{scratch + L, n_lanes, kTeamIdWords, status};
+  const FwdOp<T> agg = team_fwd_aggregate(sg, tab, qs, qds, qdds, bd);
+  const FwdOp<T> pre = team_prefix_exclusive<P>(agg, k, fwd_identity<T>(),
+                                                [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); });
+  Sp<T> dV = bd.dV0, V = bd.V0;
+  if (k > 0) {
+    dV = pre.x1;
+    V = pre.x2;
+  }
+  team_fwd_apply(sg, tab, qs, qds, qdds, dV, V, scr);
+  const BwdOp<double> bag = team_bwd_aggregate(sg, wtab, qs, scr);
+  const BwdOp<double> suf = team_suffix_exclusive<P>(
+      bag, k, bwd_identity<double>(), [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); });
+  team_bwd_apply(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<T>(tau_out + ch.dof0));
+}
+
 // ---- adjoints ------------------------------------------------------------------
 //
 // One lane per state as above. With a shared chain each lane writes its
@@ -1058,7 +1151,8 @@ int check_model_batch(const pdyn_model* m, const pdyn_batch* b) {
   if (m->n_links_max > kMaxLinks) return PDYN_EUNSUPPORTED;
   if (b->block_threads < 0 || b->block_threads % 64 != 0 || b->block_threads > kMaxBlock) return PDYN_EINVAL;
   if (b->max_blocks < 0) return PDYN_EINVAL;
-  if (b->variant < 0 || b->variant > 3) return PDYN_EINVAL;
+  if (b->variant < 0 || b->variant > 4) return PDYN_EINVAL;
+  if (b->segments < 0 || b->segments > 64 || (b->segments & (b->segments - 1))) return PDYN_EINVAL;
   if (m->order && (m->n_chains == 1 || (uintptr_t)m->order % sizeof(int32_t) != 0)) return PDYN_EINVAL;
   if (m->n_chains == 1) {
     if (m->n_links_total != m->n_links_max) return PDYN_EINVAL;
@@ -1096,6 +1190,16 @@ const LaneChain* lane_map(const pdyn_model* m, const char* tbase, size_t scalar)
   return reinterpret_cast<const LaneChain*>(tbase + loff);
 }
 
+// Lanes per chain of the team kernels (variant 4): the batch's `segments`, or
+// by default the largest power of two up to 64 that leaves at least 8 links
+// per segment (at least 1 lane).
+int team_lanes(const pdyn_model* m, const pdyn_batch* b) {
+  if (b->segments > 0) return b->segments;
+  int P = 1;
+  while (P < 64 && m->n_links_max >= 16 * P) P *= 2;
+  return P;
+}
+
 int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, Layout* L) {
   int words = scratch_words(op);
   if (words < 0) return PDYN_EINVAL;
@@ -1106,6 +1210,11 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
   L->scratch_off = m->prepared ? 0 : tb;
   const size_t nm = (size_t)m->n_links_max;
   L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
+  if (b->variant == 4) {  // the team kernels: their own per-segment slots, one column per lane
+    const size_t P = (size_t)team_lanes(m, b);
+    const size_t need = align_up((nm + P - 1) / P * (size_t)kTeamIdWords * (size_t)b->n_states * P * scalar);
+    if (need > L->scratch_bytes) L->scratch_bytes = need;
+  }
   if (op == PDYN_OP_ABA_FD || op == PDYN_OP_ID_FD) {  // room for the role-split variant too
     const size_t need = align_up(nm * (size_t)ScratchWords<kModeID>::value * (size_t)b->n_states * scalar) +
                         align_up(nm * (size_t)kBiasWords * (size_t)b->n_states * scalar) +
@@ -1137,7 +1246,7 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // call takes the entry of its operation, scalar size and kind whose link count
 // and batch size are nearest in log scale, if both lie within a factor of 2.
 struct TuneEntry {
-  int op, scalar, shared, n_max, n_states, block, max_blocks, variant;
+  int op, scalar, shared, n_max, n_states, block, max_blocks, variant, segments;
 };
 
 std::mutex g_tune_mutex;
@@ -1177,8 +1286,9 @@ struct JsonReader {
   }
 };
 
-bool valid_launch(int block, int max_blocks, int variant) {
-  return block >= 0 && block % 64 == 0 && block <= kMaxBlock && max_blocks >= 0 && variant >= 0 && variant <= 3;
+bool valid_launch(int block, int max_blocks, int variant, int segments) {
+  return block >= 0 && block % 64 == 0 && block <= kMaxBlock && max_blocks >= 0 && variant >= 0 && variant <= 4 &&
+         segments >= 0 && segments <= 64 && (segments & (segments - 1)) == 0;
 }
 
 int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
@@ -1188,7 +1298,7 @@ int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
   if (!r.lit(']')) {
     do {
       if (!r.lit('{')) return PDYN_EINVAL;
-      TuneEntry e{-1, 0, -1, 0, -1, 0, 0, 0};
+      TuneEntry e{-1, 0, -1, 0, -1, 0, 0, 0, 0};
       do {
         long v;
         if (!r.str(&key) || !r.lit(':') || !r.integer(&v) || v < INT32_MIN || v > INT32_MAX) return PDYN_EINVAL;
@@ -1201,12 +1311,13 @@ int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
         else if (key == "block") e.block = iv;
         else if (key == "max_blocks") e.max_blocks = iv;
         else if (key == "variant") e.variant = iv;
+        else if (key == "segments") e.segments = iv;
         else return PDYN_EINVAL;
       } while (r.lit(','));
       if (!r.lit('}')) return PDYN_EINVAL;
       if (e.op < PDYN_OP_RNEA_ID || e.op > PDYN_OP_ABA_FD_VJP || (e.scalar != 4 && e.scalar != 8) ||
           (e.shared != 0 && e.shared != 1) || e.n_max < 1 || e.n_states < 0 ||
-          !valid_launch(e.block, e.max_blocks, e.variant))
+          !valid_launch(e.block, e.max_blocks, e.variant, e.segments))
         return PDYN_EINVAL;
       out->push_back(e);
     } while (r.lit(','));
@@ -1221,7 +1332,7 @@ int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
 // field at 0, the tuning table's nearest entry for this call (if any).
 pdyn_batch tuned_batch(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar) {
   pdyn_batch r = *b;
-  if (b->block_threads || b->max_blocks || b->variant) return r;
+  if (b->block_threads || b->max_blocks || b->variant || b->segments) return r;
   std::shared_ptr<const std::vector<TuneEntry>> tab;
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -1245,6 +1356,7 @@ pdyn_batch tuned_batch(int op, const pdyn_model* m, const pdyn_batch* b, size_t 
     r.block_threads = best->block;
     r.max_blocks = best->max_blocks;
     r.variant = best->variant;
+    r.segments = best->segments;
   }
   return r;
 }
@@ -1305,7 +1417,7 @@ int cu_count() {
 }
 
 int pick_variant(const pdyn_batch* b, bool forward) {
-  if (b->variant) return (!forward && b->variant == 3) ? 1 : b->variant;
+  if (b->variant) return (!forward && b->variant >= 3) ? 1 : b->variant;
   if (!forward) return 2;
   return (int64_t)b->n_states <= (int64_t)128 * cu_count() ? 2 : 1;
 }
@@ -1360,6 +1472,34 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   const int variant = pick_variant(b, true);
+  if (MODE == kModeID && variant == 4) {
+    const int P = team_lanes(m, b);
+    const long n_lanes = (long)b->n_states * P;
+    const unsigned g = (unsigned)((n_lanes + 255) / 256);
+    const T* tip = static_cast<const T*>(b->tip_wrench);
+#define PDYN_LAUNCH_TEAM_ID(PP)                                                                                \
+  do {                                                                                                         \
+    if (m->n_chains == 1)                                                                                      \
+      hipLaunchKernelGGL((k_id_team<T, PP, true>), dim3(g), dim3(256), 0, s, b->n_states, m->n_links_max, lanes, \
+                         table, wtable, q, qd, qdd_in, tau_out, tip, ba, scratch, n_lanes, status);              \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_id_team<T, PP, false>), dim3(g), dim3(256), 0, s, b->n_states, m->n_links_max,      \
+                         lanes, table, wtable, q, qd, qdd_in, tau_out, tip, ba, scratch, n_lanes, status);       \
+  } while (0)
+    switch (P) {
+      case 1: PDYN_LAUNCH_TEAM_ID(1); break;
+      case 2: PDYN_LAUNCH_TEAM_ID(2); break;
+      case 4: PDYN_LAUNCH_TEAM_ID(4); break;
+      case 8: PDYN_LAUNCH_TEAM_ID(8); break;
+      case 16: PDYN_LAUNCH_TEAM_ID(16); break;
+      case 32: PDYN_LAUNCH_TEAM_ID(32); break;
+      default: PDYN_LAUNCH_TEAM_ID(64); break;
+    }
+#undef PDYN_LAUNCH_TEAM_ID
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
+  if ((MODE & kModeFD) && variant == 4) return PDYN_EUNSUPPORTED;  // the team kernels do inverse dynamics only
   if (MODE == kModeID && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     if (m->n_chains == 1)
@@ -1708,8 +1848,10 @@ int pdyn_read_status(void* ws, void* stream, uint32_t* bits) {
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
   if (check_model_batch(model, batch)) return 0;
+  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP) return 0;
+  const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
-  if (layout_for(op, model, batch, (size_t)scalar_bytes, &L)) return 0;
+  if (layout_for(op, model, &bt, (size_t)scalar_bytes, &L)) return 0;
   return L.total;
 }
 
@@ -1742,9 +1884,9 @@ int pdyn_model_prepare(const pdyn_model* model, int scalar_bytes, void* prepared
 int pdyn_max_links(void) { return kMaxLinks; }
 
 int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes,
-                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant) {
+                       int32_t* block_threads, int32_t* max_blocks, int32_t* variant, int32_t* segments) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return PDYN_EINVAL;
-  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP || !block_threads || !max_blocks || !variant)
+  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP || !block_threads || !max_blocks || !variant || !segments)
     return PDYN_EINVAL;
   const int st = check_model_batch(model, batch);
   if (st) return st;
@@ -1752,6 +1894,7 @@ int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch,
   *block_threads = b.block_threads;
   *max_blocks = b.max_blocks;
   *variant = b.variant;
+  *segments = b.variant == 4 ? team_lanes(model, &b) : b.segments;
   return PDYN_OK;
 }
 

@@ -1,0 +1,193 @@
+// The serial-parallel hybrid of the paper's scans (abstract; Sec. III-A to
+// III-C): a chain is cut into P consecutive segments, one per lane of a
+// "team" of P lanes. Each lane folds its segment's scan operands into one
+// aggregate (serial within a segment), the team combines the aggregates with
+// an inclusive scan across its lanes (parallel across segments), and each
+// lane then runs its segment again from the value the scan gives at its
+// start. P = 1 is the plain serial recursion, P = n one link per lane.
+//
+// Two scans make inverse dynamics (eq. (3)), as in Sec. III-B and III-C:
+//
+// * the forward scan of (dV, V), eq. (1), whose operands form the group
+//   SE(3) x se(3)^2 of eqs. (12)-(13). An operand (F, x1, x2) maps the pair at
+//   the frame before a segment to the pair at its last link,
+//     V' = X_F V + x2,   dV' = X_F dV + x1 - ad_{x2} X_F V,   X_F = Ad_{F^-1},
+//   with F = f_{a-1,a} ... f_{b-2,b-1} the composed link transform. Composing
+//   a later operand with an earlier one follows eq. (13) with the later one on
+//   the left (the recursion x_i = A_i x_{i-1} needs P_i = A_i ... A_0);
+// * the backward scan of the wrenches, eq. (2) with the 8x8 operand of
+//   eq. (16) kept in structured form. With W_i = X_i^T F_i (the wrench of
+//   link i in its parent's frame), F_i = Fhat_i + W_{i+1} and a segment maps
+//   the W entering at its tip end to the W leaving at its base end,
+//     W_a = X_G^T W_b + beta,   G = f_{a-1,a} ... f_{b-2,b-1};
+//   composing an earlier segment with a later one gives
+//     (G_e G_l, X_{G_e}^T beta_l + beta_e).
+//
+// The functions here are the per-lane pieces; the cross-lane scan that
+// connects them (team_scan_* in the kernels, a loop in the host build) only
+// calls the combines below, so the host build reproduces the kernels'
+// arithmetic.
+#pragma once
+
+#include "sweeps.hpp"
+
+namespace pdyn {
+
+// Links [a, b) of an n-link chain that member k of a team of P lanes owns:
+// consecutive segments of ceil(n / P) links; the last ones may be short or
+// empty (then a = b and the member's operands are identities).
+struct Seg {
+  int a, b;
+};
+PD_HD Seg segment_of(int n, int P, int k) {
+  const int len = (n + P - 1) / P;
+  int a = k * len;
+  if (a > n) a = n;
+  int b = a + len;
+  if (b > n) b = n;
+  return {a, b};
+}
+
+template <class T> PD_HD Pose<T> pose_identity() {
+  Pose<T> g;
+  g.R = {{T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)}};
+  g.p = v3(T(0), T(0), T(0));
+  return g;
+}
+// g1 g2 = (R1 R2, R1 p2 + p1): frame of g2's target expressed through g1.
+template <class T> PD_HD Pose<T> compose(const Pose<T>& g1, const Pose<T>& g2) {
+  Pose<T> g;
+  g.R = mul(g1.R, g2.R);
+  g.p = mul(g1.R, g2.p) + g1.p;
+  return g;
+}
+
+// ---- forward operand, eqs. (12)-(13) ----------------------------------------------
+
+template <class T> struct FwdOp {
+  Pose<T> F;
+  Sp<T> x1, x2;  // the dV and V parts
+};
+template <class T> PD_HD FwdOp<T> fwd_identity() { return {pose_identity<T>(), sp_zero<T>(), sp_zero<T>()}; }
+// later (+) earlier, eq. (13) with the later operand on the left.
+template <class T> PD_HD FwdOp<T> fwd_combine(const FwdOp<T>& later, const FwdOp<T>& earlier) {
+  FwdOp<T> r;
+  r.F = compose(earlier.F, later.F);
+  const Sp<T> y2 = X_twist(later.F, earlier.x2);
+  r.x2 = y2 + later.x2;
+  r.x1 = X_twist(later.F, earlier.x1) + later.x1 - ad_twist(later.x2, y2);
+  return r;
+}
+// The operand applied to (dV, V).
+template <class T> PD_HD void fwd_apply(const FwdOp<T>& op, Sp<T>* dV, Sp<T>* V) {
+  const Sp<T> XV = X_twist(op.F, *V);
+  *V = XV + op.x2;
+  *dV = X_twist(op.F, *dV) + op.x1 - ad_twist(op.x2, XV);
+}
+
+// ---- backward operand, eq. (16) ------------------------------------------------------
+
+template <class W> struct BwdOp {
+  Pose<W> G;
+  Sp<W> beta;
+};
+template <class W> PD_HD BwdOp<W> bwd_identity() { return {pose_identity<W>(), sp_zero<W>()}; }
+// earlier (x) later: the earlier (base-side) segment on the left.
+template <class W> PD_HD BwdOp<W> bwd_combine(const BwdOp<W>& earlier, const BwdOp<W>& later) {
+  return {compose(earlier.G, later.G), XT_wrench(earlier.G, later.beta) + earlier.beta};
+}
+template <class W> PD_HD Sp<W> bwd_apply(const BwdOp<W>& op, const Sp<W>& Wb) { return XT_wrench(op.G, Wb) + op.beta; }
+
+// ---- per-lane passes of inverse dynamics ---------------------------------------------
+//
+// Scratch per link of the segment (slot i - a): Fhat_i (6), sin, cos of the
+// joint angle (formed once, in pass 2, and reused by the backward passes).
+constexpr int kTeamIdWords = 8;
+
+// Pass 1: the segment's forward operand. The member that owns link 0 starts
+// from the base values (dV_0, V_0) instead of zero, so its x1, x2 are the true
+// values at its last link; the others start from zero, so x1, x2 are the
+// response of the recursion to a zero start. Either way the aggregate composes
+// correctly with earlier segments (the base enters through the first member).
+template <class T, class Tab>
+PD_HD FwdOp<T> team_fwd_aggregate(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
+                                  const Boundary<T>& bd) {
+  FwdOp<T> op = fwd_identity<T>();
+  if (sg.a == 0) {
+    op.x1 = bd.dV0;
+    op.x2 = bd.V0;
+  }
+  for (int i = sg.a; i < sg.b; ++i) {
+    const Link<T> L = link_at(tab, i);
+    const T qi = q[i];
+    T sn, cs;
+    joint_sincos(L, qi, &sn, &cs);
+    const Pose<T> g = joint_transform_sc(L, qi, sn, cs);
+    const Sp<T> XV = X_twist(g, op.x2);
+    const Sp<T> Sqd = qd[i] * L.S;
+    const T a = qdd ? qdd[i] : T(0);
+    op.x1 = X_twist(g, op.x1) + a * L.S - ad_twist(Sqd, XV);
+    op.x2 = XV + Sqd;
+    op.F = compose(op.F, g);
+  }
+  return op;
+}
+
+// Pass 2: the recursion over the segment again, from the true (dV, V) at its
+// start (the exclusive prefix of the team's aggregates; the base values for
+// the first member), forming the bias wrench Fhat_i = J dV_i - ad^T_{V_i}(J V_i)
+// of every link into scratch.
+template <class T, class Tab>
+PD_HD void team_fwd_apply(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd, Sp<T> dV, Sp<T> V,
+                          const Scratch<T>& scr) {
+  for (int i = sg.a; i < sg.b; ++i) {
+    const int s = i - sg.a;
+    const Link<T> L = link_at(tab, i);
+    const T qi = q[i];
+    T sn, cs;
+    joint_sincos(L, qi, &sn, &cs);
+    const Pose<T> g = joint_transform_sc(L, qi, sn, cs);
+    const Sp<T> XV = X_twist(g, V);
+    const Sp<T> Sqd = qd[i] * L.S;
+    const T a = qdd ? qdd[i] : T(0);
+    V = XV + Sqd;
+    dV = X_twist(g, dV) + a * L.S - ad_twist(Sqd, XV);
+    scr.put(s, 0, mul(L.J, dV) - adT_wrench(V, mul(L.J, V)));
+    scr.at(s, 6) = sn;
+    scr.at(s, 7) = cs;
+  }
+}
+
+// Pass 3: the segment's backward operand, tip to base within the segment from
+// a zero wrench, in double with each link transform formed in double from the
+// stored (sin, cos) (as the serial wrench sweep does).
+template <class T, class WTab>
+PD_HD BwdOp<double> team_bwd_aggregate(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr) {
+  BwdOp<double> op = bwd_identity<double>();
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const int s = i - sg.a;
+    const Link<double> Lw = link_at(wtab, i);
+    const Pose<double> g = joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7));
+    op.beta = XT_wrench(g, op.beta + cast_sp<double>(scr.get(s, 0)));
+    op.G = compose(g, op.G);
+  }
+  return op;
+}
+
+// Pass 4: the wrench recursion over the segment from the true W at its tip
+// end (the exclusive suffix of the team's aggregates applied to the tip
+// wrench), with tau_i = S_i^T F_i (eq. (2)).
+template <class T, class WTab>
+PD_HD void team_bwd_apply(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, Sp<double> W, SPtr<T> tau) {
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const int s = i - sg.a;
+    const Link<double> Lw = link_at(wtab, i);
+    const Sp<double> F = cast_sp<double>(scr.get(s, 0)) + W;
+    const T t = (T)dot(Lw.S, F);
+    tau[i] = t;
+    scr.check_finite(t);
+    W = XT_wrench(joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7)), F);
+  }
+}
+
+}  // namespace pdyn

@@ -138,8 +138,13 @@ def test_launch_shape_and_order_validation():
     assert _call_id(m, b, (p, p, p, p)) == -1
     b.block_threads, b.max_blocks = 64, -3
     assert _call_id(m, b, (p, p, p, p)) == -1
-    b.max_blocks, b.variant = 0, 4  # no such kernel variant
+    b.max_blocks, b.variant = 0, 5  # no such kernel variant
     assert _call_id(m, b, (p, p, p, p)) == -1
+    b.variant, b.segments = 4, 3  # segments must be a power of two
+    assert _call_id(m, b, (p, p, p, p)) == -1
+    b.segments = 128
+    assert _call_id(m, b, (p, p, p, p)) == -1
+    b.variant, b.segments = 0, 0
     order = np.arange(8, dtype=np.int32)
     m.order = order.ctypes.data  # an order with a shared chain is meaningless
     b2 = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)
@@ -297,9 +302,10 @@ def test_tuning_table_decides_the_launch():
     def choice(op, n_states, scalar=4, fields=(0, 0, 0)):
         b = api._batch_struct(n_states, api.ZERO6, api.GRAVITY_ACC, None)
         b.block_threads, b.max_blocks, b.variant = fields
-        out = [ctypes.c_int32(-9) for _ in range(3)]
+        out = [ctypes.c_int32(-9) for _ in range(4)]
         assert L.pdyn_launch_choice(op, ctypes.byref(m), ctypes.byref(b), scalar, *map(ctypes.byref, out)) == 0
-        return tuple(o.value for o in out)
+        assert out[3].value == 0
+        return tuple(o.value for o in out[:3])
 
     text = (b'{"entries": [{"op": 2, "scalar": 4, "shared": 1, "n_max": 32, "n_states": 16384, "block": 0, '
             b'"max_blocks": 0, "variant": 1}, {"op": 2, "scalar": 4, "shared": 1, "n_max": 32, "n_states": 1024, '
@@ -318,3 +324,21 @@ def test_tuning_table_decides_the_launch():
     finally:
         assert L.pdyn_load_tuning(None) == 0
     assert choice(2, 20000) == (0, 0, 0)
+
+
+def test_team_segments_resolve():
+    """Variant 4 (segmented scans): the lane count per chain is the batch's, or by default the largest power of
+    two up to 64 leaving at least 8 links per segment; its workspace holds one slot per link of a segment."""
+    L = api.lib()
+    for n, P in ((7, 1), (16, 2), (32, 4), (100, 8), (1000, 64)):
+        m, keep = _fake_model(n=n)
+        b = api._batch_struct(100, api.ZERO6, api.GRAVITY_ACC, None)
+        b.variant = 4
+        out = [ctypes.c_int32(-9) for _ in range(4)]
+        assert L.pdyn_launch_choice(0, ctypes.byref(m), ctypes.byref(b), 4, *map(ctypes.byref, out)) == 0
+        assert out[2].value == 4 and out[3].value == P, (n, out[3].value)
+        b.segments = 16
+        assert L.pdyn_launch_choice(0, ctypes.byref(m), ctypes.byref(b), 4, *map(ctypes.byref, out)) == 0
+        assert out[3].value == 16
+        ws = L.pdyn_workspace_bytes(0, ctypes.byref(m), ctypes.byref(b), 4)
+        assert ws >= -(-n // 16) * 8 * 100 * 16 * 4
