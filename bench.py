@@ -84,6 +84,63 @@ def parse():
     return p.parse_args()
 
 
+PEAKS_LIB = os.path.join(ROOT, "paper_1609_04493_amd", "libpdyn_peaks.so")
+
+
+def time_windows(fn, stream, min_ms=10.0, windows=11, warmup=3):
+    """Median time per call over `windows` back-to-back windows of at least `min_ms` each (HIP events on
+    `stream`), after `warmup` calls; the repetitions per window are calibrated first."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+
+    def window(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    reps = 1
+    while True:
+        t = window(reps)
+        if t >= min_ms:
+            break
+        reps = max(reps + 1, int(reps * 1.25 * min_ms / max(t, 1e-3)))
+    per = sorted(window(reps) / reps for _ in range(windows))
+    return {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1], "windows": windows,
+            "calls_per_window": reps}
+
+
+def measured_peaks(dev, stream):
+    """The chip's FP32 / FP64 vector FMA rate and HBM copy bandwidth, measured now (libpdyn_peaks)."""
+    import ctypes
+    import torch
+    L = ctypes.CDLL(PEAKS_LIB)
+    L.peaks_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.peaks_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    chains, blocks, iters = L.peaks_fma_chains(), 8192, 512
+    out = {}
+    for dp, name in ((0, "fp32_fma_tflops"), (1, "fp64_fma_tflops")):
+        w = time_windows(lambda: L.peaks_fma(dp, blocks, iters, sink.data_ptr(), stream.cuda_stream), stream)
+        out[name] = blocks * 256 * iters * chains * 2 / (w["median_ms"] * 1e-3) / 1e12
+    nbytes = 1 << 30  # 1 GiB each way: far beyond the 256 MB last-level cache
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    w = time_windows(lambda: L.peaks_copy(src.data_ptr(), dst.data_ptr(), nbytes, 256 * 16, stream.cuda_stream),
+                     stream)
+    out["hbm_copy_gbs"] = 2 * nbytes / (w["median_ms"] * 1e-3) / 1e9
+    out["how"] = (f"FMA chains: {blocks} x 256 threads, {chains} independent chains of {iters} FMAs each, all "
+                  "operands in vector registers, no packed FP32; copy: 1 GiB read + 1 GiB written by a grid-stride "
+                  "16-byte copy; median of 11 windows of >= 10 ms")
+    del src, dst
+    return out
+
+
 def time_steps(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -151,17 +208,73 @@ def bench_uneven(args, dev):
     ms_plain_launch = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
     best, timings = autotune.tune(api.OP_ID_FD, model, call, model.n_chains)
     autotune.apply(best, api.OP_ID_FD, model, model.n_chains)
+    idfd_by_variant = {}
+    for r in timings:
+        k = f"variant_{r['variant']}" + (f"_segments_{r['segments']}" if r["variant"] == 4 else "")
+        idfd_by_variant[k] = min(idfd_by_variant.get(k, 1e30), r["ms"] * 1e3)
     ms_eager = time_steps(call, args.steps, args.warmup, torch.cuda.current_stream(dev))
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         call()
     ms_graph = time_steps(g.replay, args.steps, args.warmup, torch.cuda.current_stream(dev))
     api.set_launch(api.OP_ID_FD, 0, 0)
-    return {"workload": "4096 chains, links uniform in [10, 100] (%d joints), one state each, fused ID+FD" % ch.n_links_total,
+    # inverse dynamics alone: the tuner also chooses the segmented scans and their segment count
+    call_id = lambda: api.rnea_id(model, q, qd, qdd, out=out[0], workspace=ws)
+    best_id, timings_id = autotune.tune(api.OP_RNEA_ID, model, call_id, model.n_chains)
+    autotune.apply(best_id, api.OP_RNEA_ID, model, model.n_chains)
+    ms_id = time_windows(call_id, torch.cuda.current_stream(dev))["median_ms"]
+    by_variant = {}
+    for r in timings_id:
+        k = f"variant_{r['variant']}" + (f"_segments_{r['segments']}" if r["variant"] == 4 else "")
+        by_variant[k] = min(by_variant.get(k, 1e30), r["ms"] * 1e3)
+    autotune.clear()
+    model.use_order = True
+    id_alone = {"tuned": best_id, "us_tuned": ms_id * 1e3, "evals_per_s": model.n_chains / (ms_id * 1e-3),
+                "joint_evals_per_s": ch.n_links_total / (ms_id * 1e-3), "best_us_by_variant": by_variant}
+    print(f"uneven ID alone: {id_alone}", file=sys.stderr, flush=True)
+    return {"inverse_dynamics_alone": id_alone,
+            "workload": "4096 chains, links uniform in [10, 100] (%d joints), one state each, fused ID+FD" % ch.n_links_total,
             "evals_per_s_graph": model.n_chains / (ms_graph * 1e-3),
             "joint_evals_per_s_graph": ch.n_links_total / (ms_graph * 1e-3),
             "ms_graph": ms_graph, "ms_eager_tuned": ms_eager, "ms_default_launch_natural_order": ms_plain_launch,
-            "tuned": best, "candidates": len(timings), "longest_chain": int(ch.lengths().max())}
+            "tuned": best, "candidates": len(timings), "best_us_by_variant": idfd_by_variant,
+            "longest_chain": int(ch.lengths().max())}
+
+
+def bench_jsiia(args, dev):
+    """Forward dynamics two ways on 16384 states of one chain, at 10 and 32 links: the articulated-body
+    recursions (pdyn_aba_fd) and the joint-space inertia with its Cholesky factor (pdyn_jsiia_fd)."""
+    import torch
+    import oracle
+    from paper_1609_04493_amd import api, synth
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    for n in (10, 32):
+        B = N_STATES
+        ch = synth.make_chains([n], synth.config_seed(2))
+        st = synth.make_states((B, n), synth.config_seed(2))
+        model = api.Model(ch, dev, torch.float32)
+        q, qd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.tau))
+        o1, o2 = torch.empty_like(q), torch.empty_like(q)
+        M = torch.empty((B, n, n), dtype=torch.float32, device=dev)
+        ws = api.Workspace()
+        ms_aba = time_windows(lambda: api.aba_fd(model, q, qd, tau, out=o1, workspace=ws), stream)["median_ms"]
+        ms_j = time_windows(lambda: api.jsiia_fd(model, q, qd, tau, out=o2, workspace=ws), stream)["median_ms"]
+        ms_m = time_windows(lambda: api.mass_matrix(model, q, out=M, workspace=ws), stream)["median_ms"]
+        torch.cuda.synchronize()
+        idx = np.random.default_rng(4).choice(B, 256, replace=False)
+        cr, sr = ch.rounded(), st.rounded()
+        ref = oracle.aba(cr, sr.q[idx], sr.qd[idx], sr.tau[idx], threads=len(os.sched_getaffinity(0)))
+        rows[f"{n}_links"] = {
+            "states": B, "aba_us": ms_aba * 1e3, "jsiia_us": ms_j * 1e3, "mass_matrix_us": ms_m * 1e3,
+            "aba_evals_per_s": B / (ms_aba * 1e-3), "jsiia_evals_per_s": B / (ms_j * 1e-3),
+            "jsiia_over_aba_time": ms_j / ms_aba,
+            "max_rel_err_vs_oracle_256_states": {"aba": float(rel_rows(o1.cpu().numpy()[idx], ref).max()),
+                                                 "jsiia": float(rel_rows(o2.cpu().numpy()[idx], ref).max())}}
+        print(f"jsiia vs aba, {n} links: {rows[f'{n}_links']}", file=sys.stderr, flush=True)
+    rows["note"] = ("JSIIA computes in double after the joint angles' (sin, cos): forming and factoring M "
+                    "amplify rounding by its condition number; the articulated-body path stays FP32 in bulk")
+    return rows
 
 
 def bench_fd_grad_50(args, dev):
@@ -268,6 +381,8 @@ def main():
     torch.cuda.synchronize()
     ms_fused = time_steps(fused, args.steps, args.warmup, stream)
     print(f"fused ID+FD: {ms_fused * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    win_fused = time_windows(fused, stream)
+    print(f"fused ID+FD, median of windows: {win_fused}", file=sys.stderr, flush=True)
     variants = {}
     for v in (1, 2):
         api.set_launch(api.OP_ID_FD, 0, 0, v)
@@ -315,7 +430,7 @@ def main():
     ms_fdv = time_steps(lambda: api.aba_fd_vjp(model, q, qd, qdd_out, qdd_bar, out=gfd, workspace=ws), args.steps,
                         args.warmup, stream)
     vjp_variants = {}
-    for v in (1, 2):
+    for v in (1, 2, 3):
         api.set_launch(api.OP_RNEA_ID_VJP, 0, 0, v)
         api.set_launch(api.OP_ABA_FD_VJP, 0, 0, v)
         vjp_variants[str(v)] = {
@@ -326,6 +441,16 @@ def main():
         print(f"adjoint variant {v}: {vjp_variants[str(v)]}", file=sys.stderr, flush=True)
     api.set_launch(api.OP_RNEA_ID_VJP, 0, 0, 0)
     api.set_launch(api.OP_ABA_FD_VJP, 0, 0, 0)
+    # the same step in the plain form: every forward sweep and every adjoint pass its own launch,
+    # intermediates in HBM
+    for op in (api.OP_ID_FD, api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):
+        api.set_launch(op, 0, 0, 3)
+    ms_grad_plain = time_steps(with_grad, args.steps, args.warmup, stream)
+    for op in (api.OP_ID_FD, api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):
+        api.set_launch(op, 0, 0, 0)
+    print(f"ID+FD with both adjoints, plain form: {ms_grad_plain * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    peaks = measured_peaks(dev, stream)
+    print(f"measured peaks: {peaks}", file=sys.stderr, flush=True)
 
     # cold inputs: rotate 64 copies of the inputs (512 MiB) so that every step reads them from HBM
     n_cold = 64
@@ -396,7 +521,18 @@ def main():
                      "frac": achieved / PEAK_VALU_FLOPS, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC)", "algorithmic_bytes": 24 * links,
                      "kernel": "k_dynamics_split<float, ID+FD>", "flops_per_link": FLOPS_PER_LINK["id_fd"],
-                     "links_per_launch": links, "frac_vs_packed_fp32_peak": achieved / 157.3e12},
+                     "flops_per_link_note": "ID 433 + FD 1045 counted step by step, less the transform, V, J V, "
+                                            "ad^T and Coriolis terms the fused kernel forms once: 1212; an estimate "
+                                            "that counts them twice gives about 1500 (x 1.24)",
+                     "links_per_launch": links,
+                     "peak_note": "78.6 = 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, the unpacked FP32 and the "
+                                  "FP64 vector rate; the published 157.3 TFLOP/s FP32 vector figure needs packed "
+                                  "FP32, which this code does not use",
+                     "frac_vs_published_fp32_vector_157": achieved / 157.3e12,
+                     "frac_vs_measured_fp32_fma": achieved / (peaks["fp32_fma_tflops"] * 1e12),
+                     "median_of_windows": dict(win_fused, achieved_tflops=FLOPS_PER_LINK["id_fd"] * links
+                                               / (win_fused["median_ms"] * 1e-3) / 1e12)},
+        "measured_peaks": peaks,
         "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
                             "2": dict(variants[2], form="role split across wavefronts with LDS hand-offs"),
                             "3": dict(per_sweep, form="plain: one launch per recursion sweep, HBM intermediates")},
@@ -417,14 +553,17 @@ def main():
                  "value": N_STATES / (ms_grad * 1e-3), "unit": "evals/s", "ms_per_step": ms_grad,
                  "roofline_frac": (FLOPS_PER_LINK["id_fd"] + FLOPS_PER_LINK["id_vjp"] + FLOPS_PER_LINK["fd_vjp"])
                  * links / (ms_grad * 1e-3) / PEAK_VALU_FLOPS,
-                 "max_rel_err_vs_oracle_4_states": gerr},
+                 "max_rel_err_vs_oracle_4_states": gerr,
+                 "plain": {"form": "the same step with every forward sweep and every adjoint pass its own launch, "
+                                   "intermediates in HBM", "ms_per_step": ms_grad_plain,
+                           "value": N_STATES / (ms_grad_plain * 1e-3), "fused_over_plain": ms_grad_plain / ms_grad}},
         "error_vs_fp64_oracle": {"sample_states": len(idx), "tau": err_stats(et), "qdd": err_stats(eq),
                                  "metric": "per-state ||x - x*|| / ||x*||"},
     }
     if not args.no_other_workloads:
         others = {}
-        for name, fn in (("uneven_4096_chains", bench_uneven), ("fd_grad_50_links", bench_fd_grad_50),
-                         ("rollout_grad_100_links", bench_rollout_100)):
+        for name, fn in (("uneven_4096_chains", bench_uneven), ("jsiia_vs_aba", bench_jsiia),
+                         ("fd_grad_50_links", bench_fd_grad_50), ("rollout_grad_100_links", bench_rollout_100)):
             others[name] = fn(args, dev)
             print(f"{name}: {json.dumps(others[name])}", file=sys.stderr, flush=True)
         out["other_workloads"] = others

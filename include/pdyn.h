@@ -134,22 +134,28 @@ typedef struct pdyn_batch {
    * wavefront per 64 states; 2 = role split -- one wavefront runs the
    * cotangent recursions (for FD first the articulated-body solve), another
    * the Newton-Euler sweeps, then the inertia-parameter terms and the
-   * tip-to-base adjoint sweep run side by side. 3 (forward operations; the
-   * adjoints take it as 1) = the plain form: the sweeps of variant 1 as
-   * separate launches, one per recursion sweep, with the per-link
-   * intermediates in the workspace (HBM) between them. 4 (inverse dynamics;
-   * the adjoints take it as 1) = the paper's serial-parallel hybrid: each
-   * chain is cut into `segments` consecutive segments handled by as many
+   * tip-to-base adjoint sweep run side by side. 3 = the plain form: for the
+   * forward operations the sweeps of variant 1 as separate launches, one per
+   * recursion sweep; for the adjoints the passes of the role split (cotangent
+   * recursion or articulated-body solve, Newton-Euler sweep, wrench sweep,
+   * inertia-parameter terms, tip-to-base adjoint sweep) as separate launches;
+   * either way with the per-link intermediates in the workspace (HBM) between
+   * them. 4 (the adjoints take it as 1) = the paper's serial-parallel hybrid:
+   * each chain is cut into `segments` consecutive segments handled by as many
    * lanes; every lane folds its segment's scan operands (eqs. (12)-(13) for
    * the velocities and accelerations, eq. (16) for the wrenches), the lanes of
    * a chain combine their aggregates with an inclusive scan across lanes, and
-   * each lane then runs its segment from the value at its start. block_threads
-   * and max_blocks apply to variants 1 and 3. Every variant gives the same
-   * results to rounding. */
+   * each lane then runs its segment from the value at its start. Forward
+   * dynamics and ID+FD take the bias forces (and the inverse dynamics) this
+   * way, while one wavefront runs the articulated-body recursion (7), which is
+   * not a linear recursion, serially per chain beside them, and another the
+   * two recursions of eq. (8) behind it. block_threads and max_blocks apply to
+   * variants 1 and 3. Every variant gives the same results to rounding. */
   int32_t variant;
-  /* Variant 4 only: segments (lanes) per chain, a power of two 1 .. 64;
-   * 0 = library default (the largest power of two, at most 64, that leaves at
-   * least 8 links per segment). */
+  /* Variant 4 only: segments (lanes) per chain, a power of two 1 .. 64 for
+   * inverse dynamics, 1 .. 16 for forward dynamics and ID+FD (PDYN_EUNSUPPORTED
+   * above); 0 = library default (the largest power of two within that bound
+   * that leaves at least 8 links per segment). */
   int32_t segments;
 } pdyn_batch;
 
@@ -176,7 +182,9 @@ enum {
   PDYN_OP_ABA_FD = 1,
   PDYN_OP_ID_FD = 2,
   PDYN_OP_RNEA_ID_VJP = 3,
-  PDYN_OP_ABA_FD_VJP = 4
+  PDYN_OP_ABA_FD_VJP = 4,
+  PDYN_OP_JSIIA_FD = 5,
+  PDYN_OP_MASS_MATRIX = 6
 };
 
 /* Bytes of device workspace that operation op needs for this model and batch
@@ -275,6 +283,40 @@ int pdyn_id_fd(const pdyn_model* model, const pdyn_batch* batch, const float* q,
 int pdyn_id_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
                    const double* qdd_in, const double* tau_in, double* tau_out, double* qdd_out,
                    void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Joint-space inertia M(q) of eq. (17), the matrix with tau = M(q) qdd + tau_bias
+ * (eqs. (5)-(6)): M[s] is written whole (both triangles), [n_states][n][n]
+ * row-major. Column j of M is the inverse dynamics of a unit acceleration of
+ * joint j with no velocity, base motion or gravity (eq. (17)); the kernel
+ * forms it from the composite bodies of the chain, n(n+1)/2 wrench transforms
+ * per state, computed in double whatever the scalar type of q and M.
+ * Shared chain only (model->n_chains == 1; PDYN_EUNSUPPORTED otherwise).
+ * block_threads and max_blocks of the batch apply; variant and segments are
+ * ignored. Workspace: pdyn_workspace_bytes(PDYN_OP_MASS_MATRIX, ...).
+ */
+int pdyn_mass_matrix(const pdyn_model* model, const pdyn_batch* batch, const float* q, float* M, void* workspace,
+                     size_t workspace_bytes, void* stream);
+int pdyn_mass_matrix_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, double* M,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Forward dynamics by the joint-space inertia inversion algorithm (JSIIA,
+ * Sec. II-B, eq. (6)): qdd = M(q)^-1 (tau - tau_bias) with
+ * tau_bias = ID(q, qd, 0, V_0, dV_0, F_{n+1}) (eq. (5)), M(q) as for
+ * pdyn_mass_matrix, factored as L L^T (Cholesky) and solved by two triangular
+ * substitutions. Same arguments and results as pdyn_aba_fd (the two differ by
+ * rounding only). All arithmetic after the joint angles' (sin, cos) runs in
+ * double: forming and factoring M amplify rounding by its condition number.
+ * A pivot of the factorisation that is not positive sets PDYN_STATUS_PIVOT.
+ * Shared chain only (PDYN_EUNSUPPORTED otherwise); launch fields as for
+ * pdyn_mass_matrix. Workspace: pdyn_workspace_bytes(PDYN_OP_JSIIA_FD, ...),
+ * (13 n + max(6 n, n (n + 1) / 2)) doubles per state plus the tables.
+ */
+int pdyn_jsiia_fd(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                  const float* tau, float* qdd, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_jsiia_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                      const double* tau, double* qdd, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Adjoint of the inverse dynamics (vector-Jacobian product). Gradients of the

@@ -30,13 +30,16 @@ _i32 = ctypes.POINTER(ctypes.c_int32)
 
 
 def lib():
+    """The C++ oracle (oracle/liboracle.so, built on first use). PDYN_ORACLE_LIB names another build of the
+    same source instead (the sanitizer test runs the oracle built with AddressSanitizer and UBSan)."""
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB_PATH):
+            path = os.environ.get("PDYN_ORACLE_LIB") or _LIB_PATH
+            if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
                 from . import build_oracle
                 build_oracle.build()
-            _lib = ctypes.CDLL(_LIB_PATH)
+            _lib = ctypes.CDLL(path)
             _declare(_lib)
     return _lib
 

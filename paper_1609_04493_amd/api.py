@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdyn.so")
 
-OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP = 0, 1, 2, 3, 4
+OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP, OP_JSIIA_FD, OP_MASS_MATRIX = 0, 1, 2, 3, 4, 5, 6
 GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
 ZERO6 = (0.0,) * 6
 
@@ -46,6 +46,7 @@ _lib_lock = threading.Lock()
 _ENTRY_ARITY = {
     "pdyn_rnea_id": 4, "pdyn_aba_fd": 4, "pdyn_id_fd": 6,
     "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 8,
+    "pdyn_jsiia_fd": 4, "pdyn_mass_matrix": 2,
 }
 
 
@@ -313,6 +314,25 @@ def id_fd(model: Model, q, qd, qdd_in, tau_in, base_vel=ZERO6, base_acc=GRAVITY_
     _call("pdyn_id_fd", OP_ID_FD, model, n_states, (q, qd, qdd_in, tau_in, tau_out, qdd_out),
           base_vel, base_acc, tip, workspace)
     return tau_out, qdd_out
+
+
+def jsiia_fd(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None, workspace=None):
+    """qdd = M(q)^-1 (tau - tau_bias) by the joint-space inertia and its Cholesky factor (eq. (6)); shared chain."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, tau, tip))
+    qdd = torch.empty_like(q) if out is None else out
+    _call("pdyn_jsiia_fd", OP_JSIIA_FD, model, n_states, (q, qd, tau, qdd), base_vel, base_acc, tip, workspace)
+    return qdd
+
+
+def mass_matrix(model: Model, q, out=None, workspace=None):
+    """M(q) of eq. (17) for every state of a shared chain: [B, n, n]."""
+    n_states = _n_states(model, q)
+    _prep(model, (q,))
+    n = model.n_links_max
+    M = torch.empty((n_states, n, n), dtype=model.dtype, device=model.device) if out is None else out
+    _call("pdyn_mass_matrix", OP_MASS_MATRIX, model, n_states, (q, M), ZERO6, ZERO6, None, workspace)
+    return M
 
 
 def _inertia_bar_like(model):

@@ -2,8 +2,9 @@
 
 For one operation on one model/batch, times every candidate launch shape
 (threads per workgroup, workgroup cap -- a cap below the work makes the launch
-persistent), the kernel variant for forward dynamics (one wavefront per 64
-states, or the role split across wavefronts) and, for one chain per state,
+persistent), the kernel variant (one wavefront per 64 states, the role split
+across wavefronts, or the segmented scans with 1 to 32 lanes, i.e. segments,
+per chain -- at most 16 for forward dynamics) and, for one chain per state,
 the chain order (natural, or longest first), with HIP events, and keeps the
 fastest. Results are recorded in a
 JSON table keyed by (operation, precision, model kind, links, states).
@@ -25,6 +26,7 @@ from . import api
 
 BLOCKS = (64, 128, 256)
 CAPS = (0, 256, 512, 1024)
+SEGMENTS = (1, 2, 4, 8, 16, 32)  # lanes per chain of the segmented-scan variant (4)
 
 
 def key_of(op: int, model: api.Model, n_states: int) -> str:
@@ -52,7 +54,8 @@ def tune(op: int, model: api.Model, call, n_states: int, reps: int = 20):
     timings = []
     saved = api._launch_override.get(op)
     saved_order = model.use_order
-    variants = (1, 2) if op in (api.OP_ABA_FD, api.OP_ID_FD) else (1,)
+    variants = (1, 2, 4) if op in (api.OP_RNEA_ID, api.OP_ABA_FD, api.OP_ID_FD) else (1,)
+    max_segments = 64 if op == api.OP_RNEA_ID else 16  # forward dynamics: at most 16 lanes per chain
     try:
         for bt, cap, use_order in itertools.product(BLOCKS, CAPS, orders):
             if cap and cap * bt >= n_states:
@@ -67,6 +70,14 @@ def tune(op: int, model: api.Model, call, n_states: int, reps: int = 20):
                 model.use_order = use_order
                 timings.append({"block_threads": 0, "max_blocks": 0, "order": use_order, "variant": 2,
                                 "ms": _time(call, reps)})
+        if 4 in variants:  # segmented scans: P lanes per chain, each folding about n / P links
+            for P, use_order in itertools.product(SEGMENTS, orders):
+                if P > max_segments or (P > 1 and model.n_links_max < 2 * P):
+                    continue  # segments of fewer than two links
+                api.set_launch(op, 0, 0, 4, P)
+                model.use_order = use_order
+                timings.append({"block_threads": 0, "max_blocks": 0, "order": use_order, "variant": 4,
+                                "segments": P, "ms": _time(call, reps)})
     finally:
         model.use_order = saved_order
         if saved is None:

@@ -30,16 +30,26 @@ def sources():
     return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-shared", "-o", tmp, *sources()]
+PEAKS_LIB = os.path.join(HERE, "libpdyn_peaks.so")
+PEAKS_SRC = os.path.join(CSRC, "peaks", "peaks.hip")
+
+
+def _hipcc_shared(out: str, srcs, verbose: bool):
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, "-shared", "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libpdyn.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """libpdyn.so (the dynamics library), then libpdyn_peaks.so (the measured roofline denominators)."""
+    _hipcc_shared(LIB, sources(), verbose)
+    _hipcc_shared(PEAKS_LIB, [PEAKS_SRC], verbose)
     return LIB
 
 

@@ -21,6 +21,9 @@
 //                      Euler in one launch, (q, qd) checkpoints every k steps.
 //   k_rollout_vjp      per state: the rollout adjoint, segment by segment from
 //                      the checkpoints (recompute k steps, then k reverse steps).
+//   k_id_team          per chain, P lanes: inverse dynamics by segmented scans.
+//   k_jsiia            per state: M(q) by composite bodies, and forward
+//                      dynamics by its Cholesky factorisation (jsiia.hpp).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,6 +36,7 @@
 #include <vector>
 
 #include "../../include/pdyn.h"
+#include "jsiia.hpp"
 #include "sweeps.hpp"
 #include "team.hpp"
 
@@ -40,6 +44,7 @@ namespace pdyn {
 namespace {
 
 constexpr int kMaxLinks = 1 << 16;
+constexpr int kMaxFdSegments = 16;  // team forward dynamics: 16 chains x 16 lanes + 2 wavefronts per workgroup
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
 constexpr size_t kStatusBytes = 256;  // status word at the start of every workspace (padded for alignment)
@@ -708,6 +713,141 @@ __global__ void __launch_bounds__(256) k_id_team(int n_states, int n_max, const 
   team_bwd_apply(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<T>(tau_out + ch.dof0));
 }
 
+// ---- joint-space inertia (jsiia.hpp) -----------------------------------------------
+//
+// One lane per state of a shared chain, grid-stride. FD: qdd = M^-1 (tau - tau_bias);
+// otherwise M(q) only, written whole to M ([n_states][n][n]). Working storage:
+// [jsiia_words(n)][n_states] doubles (consecutive lanes, consecutive words).
+template <class T, bool FD>
+__global__ void __launch_bounds__(256) k_jsiia(int n_states, int n, const T* __restrict__ table,
+                                               const double* __restrict__ wtable, const T* q, const T* qd,
+                                               const T* tau, T* qdd, T* M, const T* __restrict__ tip,
+                                               BoundaryArgs<T> ba, double* work, unsigned* status) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_states; s += stride) {
+    Boundary<T> bd = boundary_of(ba);
+    if (tip) {
+      const T* t = tip + 6 * (int64_t)s;
+      bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+    }
+    const JsiiaWork<SPtr<double>> ws{SPtr<double>(work + s, (long)n_states), n};
+    const int64_t row = (int64_t)s * n;
+    T* const Ms = M ? M + row * n : nullptr;
+    auto mout = [&](int i, int k, double v) {
+      if (!FD) Ms[(int64_t)i * n + k] = (T)v;
+    };
+    jsiia_mass_matrix<T, FD>(n, table, wtable, SPtr<const T>(q + row), SPtr<const T>(FD ? qd + row : nullptr),
+                             SPtr<const T>(FD ? tau + row : nullptr), bd, ws, mout);
+    if (FD) {
+      unsigned bits = 0;
+      const bool ok = jsiia_solve<T>(n, ws, [&](int i, double v) {
+        const T x = (T)v;
+        qdd[row + i] = x;
+        if (!__builtin_isfinite(x)) bits |= kStatusNonFinite;
+      });
+      if (!ok) bits |= kStatusPivot;
+      if (bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Forward dynamics (and ID+FD) by the team scans (variant 4). A workgroup takes
+// kTeamChains chains (in lane order) and has three kinds of wavefronts:
+//  * team wavefronts, P lanes per chain (team.hpp): the bias forces by the two
+//    segmented scans, leaving tau-hat = tau - tau_bias per link (double) and
+//    the (sin, cos) of every joint angle; for ID+FD also the inverse dynamics;
+//    then each adds one to `p1done` (release) and ends;
+//  * A, one lane per chain: the articulated-body recursion (7), serial, from
+//    the start, publishing its progress in `aprog` after every link;
+//  * Z, one lane per chain: once every team wavefront is done, z-hat / c-hat
+//    tip to base, each link as soon as A has it, then lambda / qdd base to tip.
+// No workgroup barrier follows the first: waits are one-directional (Z waits
+// for the others), so every wave runs to its end.
+constexpr int kTeamChains = 16;
+
+template <class T, int MODE, int P, bool SHARED>
+__global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                  const T* __restrict__ table, const double* __restrict__ wtable,
+                                                  const T* q, const T* qd, const T* qdd_in, const T* tau_in,
+                                                  T* tau_out, T* qdd_out, const T* __restrict__ tip,
+                                                  BoundaryArgs<T> ba, T* scr_id, T* scr_bias, T* scr_abi,
+                                                  T* scr_chat, double* tauhat, long n_lanes, unsigned* status) {
+  constexpr int kLanes = kTeamChains * P;
+  constexpr int kTeamWaves = (kLanes + 63) / 64;
+  __shared__ int p1done, aprog;
+  if (threadIdx.x == 0) {
+    p1done = 0;
+    aprog = 0;
+  }
+  __syncthreads();
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  Boundary<T> bd = boundary_of(ba);
+  if (wave < kTeamWaves) {
+    const int t = (int)threadIdx.x;
+    const int k = t % P;
+    const long j = (long)blockIdx.x * kTeamChains + t / P;
+    const bool active = t < kLanes && j < n_states;
+    const int jj = active ? (int)j : 0;
+    ChainOf ch{0, 0, 0, 0};
+    if (active) ch = chain_of<SHARED>(jj, n_max, lanes);
+    const Seg sg = segment_of(ch.n, P, k);
+    const auto tab = rec_view<SHARED>(table, jj, n_max);
+    const auto wtab = rec_view<SHARED>(wtable, jj, n_max);
+    const SPtr<const T> qs(q + ch.dof0), qds(qd + ch.dof0);
+    if (active && tip) {
+      const T* tp = tip + 6 * (int64_t)ch.s;
+      bd.Ftip = {v3(tp[0], tp[1], tp[2]), v3(tp[3], tp[4], tp[5])};
+    }
+    const long L = j * P + k;
+    const auto fcomb = [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); };
+    const auto bcomb = [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); };
+    // the bias forces: qdd = 0
+    {
+      const Scratch<T> scr{scr_bias + L, n_lanes, kTeamIdWords, status};
+      const FwdOp<T> pre =
+          team_prefix_exclusive<P>(team_fwd_aggregate(sg, tab, qs, qds, SPtr<const T>(), bd), k, fwd_identity<T>(), fcomb);
+      team_fwd_apply(sg, tab, qs, qds, SPtr<const T>(), k > 0 ? pre.x1 : bd.dV0, k > 0 ? pre.x2 : bd.V0, scr);
+      const BwdOp<double> suf =
+          team_suffix_exclusive<P>(team_bwd_aggregate(sg, wtab, qs, scr), k, bwd_identity<double>(), bcomb);
+      team_bwd_apply_hat(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<const T>(tau_in + ch.dof0),
+                         [&](int i, double v) { tauhat[(long)i * n_states + j] = v; });
+    }
+    if (MODE & kModeID) {
+      const Scratch<T> scr{scr_id + L, n_lanes, kTeamIdWords, status};
+      const SPtr<const T> qdds(qdd_in + ch.dof0);
+      const FwdOp<T> pre =
+          team_prefix_exclusive<P>(team_fwd_aggregate(sg, tab, qs, qds, qdds, bd), k, fwd_identity<T>(), fcomb);
+      team_fwd_apply(sg, tab, qs, qds, qdds, k > 0 ? pre.x1 : bd.dV0, k > 0 ? pre.x2 : bd.V0, scr);
+      const BwdOp<double> suf =
+          team_suffix_exclusive<P>(team_bwd_aggregate(sg, wtab, qs, scr), k, bwd_identity<double>(), bcomb);
+      team_bwd_apply(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<T>(tau_out + ch.dof0));
+    }
+    if (lane == 0) __hip_atomic_fetch_add(&p1done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return;
+  }
+  const int role = wave - kTeamWaves;  // 0: articulated-body pass; 1: z-hat, then lambda
+  const long j = (long)blockIdx.x * kTeamChains + lane;
+  const bool active = lane < kTeamChains && j < n_states;
+  const int jj = active ? (int)j : 0;
+  ChainOf ch{0, 0, 0, 0};
+  if (active) ch = chain_of<SHARED>(jj, n_max, lanes);
+  const auto tab = rec_view<SHARED>(table, jj, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, jj, n_max);
+  const SPtr<const T> qs(q + ch.dof0);
+  const Scratch<T> abi{scr_abi + jj, (long)n_states, kAbiWords, status};
+  if (role == 0) {
+    if (active) split_abi_pass(ch.n, tab, wtab, qs, abi, LdsProgress{&aprog});
+    return;
+  }
+  LdsWait{&p1done, status}(kTeamWaves);
+  if (!active) return;
+  const TeamSlots<T> sc{scr_bias, n_lanes, j * P, (ch.n + P - 1) / P, kTeamIdWords};
+  const Scratch<T> chat{scr_chat + jj, (long)n_states, 1, status};
+  team_zhat_pass(ch.n, wtab, qs, abi, [&](int i) { return tauhat[(long)i * n_states + j]; }, sc, chat,
+                 LdsWait{&aprog, status});
+  team_lambda_pass(ch.n, tab, qs, abi, chat, sc, chat, [&](int i, T v) { qdd_out[ch.dof0 + i] = v; });
+}
+
 // ---- adjoints ------------------------------------------------------------------
 //
 // One lane per state as above. With a shared chain each lane writes its
@@ -944,6 +1084,56 @@ __global__ void __launch_bounds__(256) k_vjp_split(int n_states, int n_max, cons
   }
 }
 
+// The plain form of the adjoints (variant 3): the passes of k_vjp_split at its
+// lowest LDS level, each as its own launch of one wavefront per 64 states, with
+// every per-link intermediate in the workspace (HBM) between launches:
+//   PASS 0  the cotangent recursion F-bar (ID), or the articulated-body solve
+//           u = M^-1 qdd_bar and F-bar (FD);
+//   PASS 1  Newton-Euler sweep 1 (V, A, Fhat);   PASS 2  the wrench sweep (F);
+//   PASS 3  the inertia-parameter cotangents;    PASS 4  the tip-to-base adjoint sweep.
+enum : int { kVjpPassX = 0, kVjpPassNeFwd = 1, kVjpPassWrench = 2, kVjpPassInertia = 3, kVjpPassBack = 4 };
+
+template <class T, int OP, int PI, bool SHARED, int PASS>
+__global__ void __launch_bounds__(64) k_vjp_pass(int n_states, int n_max, const LaneChain* __restrict__ lanes,
+                                                 const T* __restrict__ table, const double* __restrict__ wtable,
+                                                 const T* q, const T* qd, const T* qdd, const T* bar_in, T* q_bar,
+                                                 T* qd_bar, T* qdd_bar, T* tau_bar, T* pi_out,
+                                                 const T* __restrict__ tip, BoundaryArgs<T> ba, T* scratch,
+                                                 T* xscratch, unsigned* status) {
+  const int lane_index = blockIdx.x * 64 + (int)threadIdx.x;
+  if (lane_index >= n_states) return;
+  const ChainOf ch = chain_of<SHARED>(lane_index, n_max, lanes);
+  const int n = ch.n;
+  const auto tab = rec_view<SHARED>(table, lane_index, n_max);
+  const auto wtab = rec_view<SHARED>(wtable, lane_index, n_max);
+  Boundary<T> bd = boundary_of(ba);
+  if (tip) {
+    const T* t = tip + 6 * (int64_t)ch.s;
+    bd.Ftip = {v3(t[0], t[1], t[2]), v3(t[3], t[4], t[5])};
+  }
+  const Scratch<T> scr{scratch + lane_index, (long)n_states, kVjpWords, status};
+  const Scratch<T> xs{xscratch + lane_index, (long)n_states, kVjpXWords, status};
+  const SPtr<const T> qs(q + ch.dof0), qds(qd + ch.dof0), qdds(qdd + ch.dof0), bar(bar_in + ch.dof0);
+  if (PASS == kVjpPassX) {
+    if (OP == kVjpID)
+      vjp_fbar_pass(n, tab, qs, bar, T(1), xs);
+    else
+      fdvjp_solve_pass(n, tab, wtab, qs, bar, SPtr<T>(tau_bar + ch.dof0), xs);
+  } else if (PASS == kVjpPassNeFwd) {
+    vjp_ne_forward(n, tab, qs, qds, qdds, bd, scr);
+  } else if (PASS == kVjpPassWrench) {
+    vjp_wrench_pass(n, wtab, qs, bd, scr, scr);
+  } else if (PASS == kVjpPassInertia) {
+    PiSink<T, PI> sink;
+    sink.out = (PI == kPiLanes) ? pi_out + lane_index : pi_out + ch.link0 * 10;
+    sink.stride = (PI == kPiLanes) ? n_states : 1;
+    vjp_inertia_pass(n, tab, xs, scr, sink);
+  } else {
+    const SPtr<T> qddb = OP == kVjpID ? SPtr<T>(qdd_bar + ch.dof0) : SPtr<T>();
+    vjp_back_pass(n, tab, qs, qds, qdds, xs, scr, SPtr<T>(q_bar + ch.dof0), SPtr<T>(qd_bar + ch.dof0), qddb, scr);
+  }
+}
+
 // out[i] = sum over j < n_in of in[i * n_in + j], one workgroup per output, fixed
 // order (strided partial sums in double, then a fixed tree), so deterministic.
 template <class T>
@@ -1114,11 +1304,14 @@ int scratch_words(int op) {
     case PDYN_OP_ID_FD: return ScratchWords<kModeIDFD>::value;
     case PDYN_OP_RNEA_ID_VJP:
     case PDYN_OP_ABA_FD_VJP: return kVjpWords;
+    case PDYN_OP_JSIIA_FD:
+    case PDYN_OP_MASS_MATRIX: return 0;  // their own layout, jsiia_words doubles per state
     default: return -1;
   }
 }
 
 bool is_vjp(int op) { return op == PDYN_OP_RNEA_ID_VJP || op == PDYN_OP_ABA_FD_VJP; }
+bool is_jsiia(int op) { return op == PDYN_OP_JSIIA_FD || op == PDYN_OP_MASS_MATRIX; }
 
 // The host copies of the CSR offsets and of the lane order (pdyn_model): first
 // offset 0, every chain 1 .. n_links_max links, last offset n_links_total, and
@@ -1193,11 +1386,31 @@ const LaneChain* lane_map(const pdyn_model* m, const char* tbase, size_t scalar)
 // Lanes per chain of the team kernels (variant 4): the batch's `segments`, or
 // by default the largest power of two up to 64 that leaves at least 8 links
 // per segment (at least 1 lane).
-int team_lanes(const pdyn_model* m, const pdyn_batch* b) {
+int team_lanes(const pdyn_model* m, const pdyn_batch* b, int op = PDYN_OP_RNEA_ID) {
   if (b->segments > 0) return b->segments;
+  const int cap = (op == PDYN_OP_ABA_FD || op == PDYN_OP_ID_FD) ? kMaxFdSegments : 64;
   int P = 1;
-  while (P < 64 && m->n_links_max >= 16 * P) P *= 2;
+  while (P < cap && m->n_links_max >= 16 * P) P *= 2;
   return P;
+}
+
+// Scratch of the team forward-dynamics kernel, in this order: the team slots of
+// the inverse dynamics (ID+FD only) and of the bias forces ([len][8][n_states * P]
+// each), the articulated terms [n][7][n_states], c-hat [n][n_states], and
+// tau-hat [n][n_states] in double.
+struct FdTeamLayout {
+  size_t id_off, bias_off, abi_off, chat_off, hat_off, total;
+};
+FdTeamLayout fd_team_layout(int op, size_t nm, size_t B, size_t P, size_t scalar) {
+  FdTeamLayout t;
+  const size_t team = align_up((nm + P - 1) / P * (size_t)kTeamIdWords * B * P * scalar);
+  t.id_off = 0;
+  t.bias_off = op == PDYN_OP_ID_FD ? team : 0;
+  t.abi_off = t.bias_off + team;
+  t.chat_off = t.abi_off + align_up(nm * (size_t)kAbiWords * B * scalar);
+  t.hat_off = t.chat_off + align_up(nm * B * scalar);
+  t.total = t.hat_off + align_up(nm * B * sizeof(double));
+  return t;
 }
 
 int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, Layout* L) {
@@ -1211,10 +1424,12 @@ int layout_for(int op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, 
   const size_t nm = (size_t)m->n_links_max;
   L->scratch_bytes = align_up(nm * (size_t)words * (size_t)b->n_states * scalar);
   if (b->variant == 4) {  // the team kernels: their own per-segment slots, one column per lane
-    const size_t P = (size_t)team_lanes(m, b);
-    const size_t need = align_up((nm + P - 1) / P * (size_t)kTeamIdWords * (size_t)b->n_states * P * scalar);
+    const size_t P = (size_t)team_lanes(m, b, op);
+    size_t need = align_up((nm + P - 1) / P * (size_t)kTeamIdWords * (size_t)b->n_states * P * scalar);
+    if (op == PDYN_OP_ABA_FD || op == PDYN_OP_ID_FD) need = fd_team_layout(op, nm, b->n_states, P, scalar).total;
     if (need > L->scratch_bytes) L->scratch_bytes = need;
   }
+  if (is_jsiia(op)) L->scratch_bytes = align_up((size_t)jsiia_words((int)nm) * (size_t)b->n_states * sizeof(double));
   if (op == PDYN_OP_ABA_FD || op == PDYN_OP_ID_FD) {  // room for the role-split variant too
     const size_t need = align_up(nm * (size_t)ScratchWords<kModeID>::value * (size_t)b->n_states * scalar) +
                         align_up(nm * (size_t)kBiasWords * (size_t)b->n_states * scalar) +
@@ -1315,7 +1530,7 @@ int parse_tuning(const char* text, std::vector<TuneEntry>* out) {
         else return PDYN_EINVAL;
       } while (r.lit(','));
       if (!r.lit('}')) return PDYN_EINVAL;
-      if (e.op < PDYN_OP_RNEA_ID || e.op > PDYN_OP_ABA_FD_VJP || (e.scalar != 4 && e.scalar != 8) ||
+      if (e.op < PDYN_OP_RNEA_ID || e.op > PDYN_OP_MASS_MATRIX || (e.scalar != 4 && e.scalar != 8) ||
           (e.shared != 0 && e.shared != 1) || e.n_max < 1 || e.n_states < 0 ||
           !valid_launch(e.block, e.max_blocks, e.variant, e.segments))
         return PDYN_EINVAL;
@@ -1417,7 +1632,7 @@ int cu_count() {
 }
 
 int pick_variant(const pdyn_batch* b, bool forward) {
-  if (b->variant) return (!forward && b->variant >= 3) ? 1 : b->variant;
+  if (b->variant) return (!forward && b->variant == 4) ? 1 : b->variant;
   if (!forward) return 2;
   return (int64_t)b->n_states <= (int64_t)128 * cu_count() ? 2 : 1;
 }
@@ -1435,9 +1650,23 @@ size_t max_lds_bytes() {
   return (size_t)cached[dev] - 1024;  // room for the kernel's static LDS
 }
 
+// One word of device memory: zero it (out == nullptr) or copy it to *out.
+__global__ void __launch_bounds__(64) k_status_word(unsigned* word, uint32_t* out) {
+  if (threadIdx.x != 0) return;
+  if (out) *out = *word;
+  else *word = 0u;
+}
+
+template <class T, int MODE>
+int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, const T* q, const T* qd,
+                    const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out, char* ws, hipStream_t s);
+
+// clear_status: zero the workspace's status word before the first kernel;
+// status_out (device, or nullptr): receives the status word after the last.
 template <class T, int MODE>
 int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* qdd_in,
-                 const T* tau_in, T* tau_out, T* qdd_out, void* ws, size_t ws_bytes, void* stream) {
+                 const T* tau_in, T* tau_out, T* qdd_out, void* ws, size_t ws_bytes, void* stream,
+                 bool clear_status = false, uint32_t* status_out = nullptr) {
   int st = check_model_batch(m, b);
   if (st) return st;
   const pdyn_batch bt = tuned_batch(op, m, b, sizeof(T));
@@ -1457,10 +1686,29 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
   Layout L;
   if ((st = layout_for(op, m, b, sizeof(T), &L))) return st;
   if (ws_bytes < L.total) return PDYN_EWORKSPACE;
+  if ((MODE & kModeFD) && pick_variant(b, true) == 4 && b->segments > kMaxFdSegments) return PDYN_EUNSUPPORTED;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned* status = static_cast<unsigned*>(ws);  // the first kStatusBytes of every workspace
-  char* base = static_cast<char*>(ws) + kStatusBytes;
+  if (clear_status) {
+    hipLaunchKernelGGL(k_status_word, dim3(1), dim3(64), 0, s, status, nullptr);
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  }
+  st = launch_dynamics<T, MODE>(m, b, L, q, qd, qdd_in, tau_in, tau_out, qdd_out, static_cast<char*>(ws), s);
+  if (st == PDYN_OK && status_out) {
+    hipLaunchKernelGGL(k_status_word, dim3(1), dim3(64), 0, s, status, status_out);
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  }
+  return st;
+}
+
+// The kernels of one call of run_dynamics, after its checks.
+template <class T, int MODE>
+int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, const T* q, const T* qd,
+                    const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out, char* ws, hipStream_t s) {
+  int st = PDYN_OK;
+  unsigned* status = reinterpret_cast<unsigned*>(ws);
+  char* base = ws + kStatusBytes;
   T* scratch = reinterpret_cast<T*>(base + L.scratch_off);
   const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
   const LaneChain* const lanes = lane_map(m, tbase, sizeof(T));
@@ -1499,7 +1747,41 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
     return PDYN_OK;
   }
-  if ((MODE & kModeFD) && variant == 4) return PDYN_EUNSUPPORTED;  // the team kernels do inverse dynamics only
+  if ((MODE & kModeFD) && variant == 4) {
+    const int P = team_lanes(m, b, MODE == kModeIDFD ? PDYN_OP_ID_FD : PDYN_OP_ABA_FD);
+    const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
+    const FdTeamLayout t = fd_team_layout(MODE == kModeIDFD ? PDYN_OP_ID_FD : PDYN_OP_ABA_FD, nm, B, (size_t)P, sizeof(T));
+    char* sc = reinterpret_cast<char*>(scratch);
+    const long n_lanes = (long)b->n_states * P;
+    const unsigned g = (unsigned)((b->n_states + kTeamChains - 1) / kTeamChains);
+    const T* tip = static_cast<const T*>(b->tip_wrench);
+#define PDYN_LAUNCH_TEAM_FD(PP)                                                                                  \
+  do {                                                                                                           \
+    constexpr unsigned blk = 64u * ((kTeamChains * PP + 63) / 64 + 2);                                           \
+    if (m->n_chains == 1)                                                                                        \
+      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, true>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,  \
+                         lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,                 \
+                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off),            \
+                         reinterpret_cast<T*>(sc + t.abi_off), reinterpret_cast<T*>(sc + t.chat_off),           \
+                         reinterpret_cast<double*>(sc + t.hat_off), n_lanes, status);                            \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, false>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max, \
+                         lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,                 \
+                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off),            \
+                         reinterpret_cast<T*>(sc + t.abi_off), reinterpret_cast<T*>(sc + t.chat_off),           \
+                         reinterpret_cast<double*>(sc + t.hat_off), n_lanes, status);                            \
+  } while (0)
+    switch (P) {
+      case 1: PDYN_LAUNCH_TEAM_FD(1); break;
+      case 2: PDYN_LAUNCH_TEAM_FD(2); break;
+      case 4: PDYN_LAUNCH_TEAM_FD(4); break;
+      case 8: PDYN_LAUNCH_TEAM_FD(8); break;
+      default: PDYN_LAUNCH_TEAM_FD(16); break;
+    }
+#undef PDYN_LAUNCH_TEAM_FD
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
   if (MODE == kModeID && variant == 2) {
     const unsigned g = (unsigned)((b->n_states + 63) / 64);
     if (m->n_chains == 1)
@@ -1580,6 +1862,46 @@ int run_dynamics(int op, const pdyn_model* m, const pdyn_batch* b, const T* q, c
     hipLaunchKernelGGL((k_dynamics<T, MODE, false>), dim3(grid), dim3(block), 0, s, b->n_states,
                        m->n_links_max, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out,
                        static_cast<const T*>(b->tip_wrench), ba, scratch, status);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+// Forward dynamics by JSIIA (FD) or the joint-space inertia alone, shared chain only.
+template <class T, bool FD>
+int run_jsiia(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* tau, T* out, void* ws,
+              size_t ws_bytes, void* stream) {
+  const int op = FD ? PDYN_OP_JSIIA_FD : PDYN_OP_MASS_MATRIX;
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
+  const pdyn_batch bt = tuned_batch(op, m, b, sizeof(T));
+  b = &bt;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, out}))) return st;
+  if (FD && (st = check_ptrs<T>({qd, tau}))) return st;
+  if ((st = check_ptrs<T>({m->placement, m->twist, m->inertia}))) return st;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  Layout L;
+  if ((st = layout_for(op, m, b, sizeof(T), &L))) return st;
+  if (ws_bytes < L.total) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned* status = static_cast<unsigned*>(ws);
+  char* base = static_cast<char*>(ws) + kStatusBytes;
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  unsigned grid, block;
+  launch_shape(b, &grid, &block);
+  hipLaunchKernelGGL((k_jsiia<T, FD>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_links_max,
+                     reinterpret_cast<const T*>(tbase + L.table_off),
+                     reinterpret_cast<const double*>(tbase + L.wtable_off), q, FD ? qd : nullptr,
+                     FD ? tau : nullptr, FD ? out : nullptr, FD ? nullptr : out,
+                     static_cast<const T*>(b->tip_wrench), ba, reinterpret_cast<double*>(base + L.scratch_off),
+                     status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -1739,9 +2061,40 @@ int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, c
   T* qdd_bar = (OP == kVjpID) ? out3 : nullptr;
   T* tau_bar = (OP == kVjpFD) ? out3 : nullptr;
   const T* tip = static_cast<const T*>(b->tip_wrench);
-  const bool split = pick_variant(b, false) == 2;
+  const int vjp_variant = pick_variant(b, false);
+  const bool split = vjp_variant == 2;
   const unsigned grid64 = (unsigned)((b->n_states + 63) / 64);
   T* xscratch = reinterpret_cast<T*>(base + L.xscratch_off);
+  if (vjp_variant == 3) {  // the plain form: one launch per pass
+#define PDYN_LAUNCH_VJP_PASS(PI, SH, PASS, PIOUT)                                                              \
+  hipLaunchKernelGGL((k_vjp_pass<T, OP, PI, SH, PASS>), dim3(grid64), dim3(64), 0, s, b->n_states,              \
+                     m->n_links_max, lanes, table, wtable, q, qd, qdd, bar_in, q_bar, qd_bar, qdd_bar, tau_bar, \
+                     PIOUT, tip, ba, scratch, xscratch, status)
+#define PDYN_LAUNCH_VJP_PASSES(PI, SH, PIOUT)                                                                  \
+  do {                                                                                                         \
+    PDYN_LAUNCH_VJP_PASS(PI, SH, kVjpPassX, PIOUT);                                                            \
+    PDYN_LAUNCH_VJP_PASS(PI, SH, kVjpPassNeFwd, PIOUT);                                                        \
+    PDYN_LAUNCH_VJP_PASS(PI, SH, kVjpPassWrench, PIOUT);                                                       \
+    if (PI != kPiNone) PDYN_LAUNCH_VJP_PASS(PI, SH, kVjpPassInertia, PIOUT);                                   \
+    PDYN_LAUNCH_VJP_PASS(PI, SH, kVjpPassBack, PIOUT);                                                         \
+  } while (0)
+    if (!inertia_bar) {
+      if (m->n_chains == 1)
+        PDYN_LAUNCH_VJP_PASSES(kPiNone, true, static_cast<T*>(nullptr));
+      else
+        PDYN_LAUNCH_VJP_PASSES(kPiNone, false, static_cast<T*>(nullptr));
+    } else if (m->n_chains == 1) {
+      PDYN_LAUNCH_VJP_PASSES(kPiLanes, true, partials);
+      hipLaunchKernelGGL(k_reduce_lanes<T>, dim3(m->n_links_max * 10), dim3(256), 0, s, b->n_states, partials,
+                         inertia_bar);
+    } else {
+      PDYN_LAUNCH_VJP_PASSES(kPiDirect, false, inertia_bar);
+    }
+#undef PDYN_LAUNCH_VJP_PASSES
+#undef PDYN_LAUNCH_VJP_PASS
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    return PDYN_OK;
+  }
   // ID adjoint: the wrenches of every link in LDS, after the transform ring; FD adjoint: the
   // articulated terms of every link (third wavefront)
   const size_t lds1 = OP == kVjpID
@@ -1848,7 +2201,7 @@ int pdyn_read_status(void* ws, void* stream, uint32_t* bits) {
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
   if (check_model_batch(model, batch)) return 0;
-  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP) return 0;
+  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX) return 0;
   const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
   if (layout_for(op, model, &bt, (size_t)scalar_bytes, &L)) return 0;
@@ -1886,7 +2239,7 @@ int pdyn_max_links(void) { return kMaxLinks; }
 int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes,
                        int32_t* block_threads, int32_t* max_blocks, int32_t* variant, int32_t* segments) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return PDYN_EINVAL;
-  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_ABA_FD_VJP || !block_threads || !max_blocks || !variant || !segments)
+  if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX || !block_threads || !max_blocks || !variant || !segments)
     return PDYN_EINVAL;
   const int st = check_model_batch(model, batch);
   if (st) return st;
@@ -1894,7 +2247,7 @@ int pdyn_launch_choice(int op, const pdyn_model* model, const pdyn_batch* batch,
   *block_threads = b.block_threads;
   *max_blocks = b.max_blocks;
   *variant = b.variant;
-  *segments = b.variant == 4 ? team_lanes(model, &b) : b.segments;
+  *segments = b.variant == 4 ? team_lanes(model, &b, op) : b.segments;
   return PDYN_OK;
 }
 
@@ -1946,6 +2299,23 @@ int pdyn_id_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const f
 int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd_in,
                    const double* tau_in, double* tau_out, double* qdd_out, void* ws, size_t ws_bytes, void* stream) {
   return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+
+int pdyn_mass_matrix(const pdyn_model* m, const pdyn_batch* b, const float* q, float* M, void* ws, size_t ws_bytes,
+                     void* stream) {
+  return run_jsiia<float, false>(m, b, q, nullptr, nullptr, M, ws, ws_bytes, stream);
+}
+int pdyn_mass_matrix_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, double* M, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return run_jsiia<double, false>(m, b, q, nullptr, nullptr, M, ws, ws_bytes, stream);
+}
+int pdyn_jsiia_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* tau,
+                  float* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_jsiia<float, true>(m, b, q, qd, tau, qdd, ws, ws_bytes, stream);
+}
+int pdyn_jsiia_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                      const double* tau, double* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_jsiia<double, true>(m, b, q, qd, tau, qdd, ws, ws_bytes, stream);
 }
 
 int pdyn_rnea_id_vjp(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* qdd,

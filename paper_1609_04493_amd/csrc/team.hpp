@@ -190,4 +190,77 @@ PD_HD void team_bwd_apply(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& 
   }
 }
 
+// ---- forward dynamics with the team scans (Sec. II-B, III-E) ------------------------
+//
+// The linear recursions that do not depend on the articulated-body inertia run
+// as the team scans above: the bias forces tau_bias = ID(q, qd, 0) (eq. (5))
+// with the bias wrench scan in double, giving tau-hat = tau - tau_bias per
+// link. The articulated-body recursion (7) is not a linear recursion and stays
+// serial, one lane per chain (split_abi_pass), as do the two recursions of
+// eq. (8) that follow it: z-hat / c-hat tip to base, behind the articulated
+// pass link by link, and lambda / qdd base to tip.
+
+// Pass 4 of the bias forces: the wrench recursion over the segment from the
+// true W at its tip end, writing tau-hat_i = tau_i - S_i^T F_i (double).
+template <class T, class WTab, class Hat>
+PD_HD void team_bwd_apply_hat(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, Sp<double> W,
+                              SPtr<const T> tau, const Hat& hat) {
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const int s = i - sg.a;
+    const Link<double> Lw = link_at(wtab, i);
+    const Sp<double> F = cast_sp<double>(scr.get(s, 0)) + W;
+    hat(i, (double)tau[i] - dot(Lw.S, F));
+    W = XT_wrench(joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7)), F);
+  }
+}
+
+// Link i's slot in the team scratch of its chain: member i / len, slot i % len
+// ([slot][words][n_lanes], the team's first lane at team0).
+template <class T> struct TeamSlots {
+  T* base;
+  long n_lanes;
+  long team0;
+  int len, words;
+  PD_HD T& at(int i, int comp) const {
+    const int k = i / len;
+    return base[((long)(i - k * len) * words + comp) * n_lanes + team0 + k];
+  }
+};
+
+// z-hat / c-hat, tip to base (eq. (8), scan operand eq. (18) with reading R3):
+// z-hat_{n} = 0 at the tip; c-hat_i = (tau-hat_i - S_i^T z-hat_i) / D_i;
+// z-hat_{i-1} = X_i^T (z-hat_i + U_i c-hat_i), in double. need(k) is called
+// before the k-th link from the tip reads the articulated terms U_i, 1/D_i.
+template <class T, class WTab, class Hat, class SC, class Need>
+PD_HD void team_zhat_pass(int n, WTab wtab, SPtr<const T> q, const Scratch<T>& abi, const Hat& tauhat, const SC& sc,
+                          const Scratch<T>& chat_out, const Need& need) {
+  Sp<double> z = sp_zero<double>();
+  for (int i = n - 1; i >= 0; --i) {
+    need(n - i);
+    const Link<double> Lw = link_at(wtab, i);
+    const Sp<double> U = cast_sp<double>(abi.get(i, 0));
+    const double invD = (double)abi.at(i, 6);
+    const double c = (tauhat(i) - dot(Lw.S, z)) * invD;
+    chat_out.at(i, 0) = (T)c;
+    if (i > 0) z = XT_wrench(joint_transform_wide_sc(Lw, q[i], sc.at(i, 6), sc.at(i, 7)), z + c * U);
+  }
+}
+
+// lambda / qdd, base to tip (eq. (8), scan operand eq. (19), lambda_0 = 0):
+// a'_i = X_i lambda_{i-1}; qdd_i = c-hat_i - U_i^T a'_i / D_i; lambda_i = a'_i + S_i qdd_i.
+template <class T, class Tab, class SC, class Out>
+PD_HD void team_lambda_pass(int n, Tab tab, SPtr<const T> q, const Scratch<T>& abi, const Scratch<T>& chat,
+                            const SC& sc, const Scratch<T>& flags, const Out& out) {
+  Sp<T> lam = sp_zero<T>();
+  for (int i = 0; i < n; ++i) {
+    const Link<T> L = link_at(tab, i);
+    const Pose<T> g = joint_transform_sc(L, q[i], sc.at(i, 6), sc.at(i, 7));
+    const Sp<T> a = X_twist(g, lam);
+    const T qdd = chat.at(i, 0) - dot(abi.get(i, 0), a) * abi.at(i, 6);
+    lam = a + qdd * L.S;
+    flags.check_finite(qdd);
+    out(i, qdd);
+  }
+}
+
 }  // namespace pdyn

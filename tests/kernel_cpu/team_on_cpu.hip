@@ -81,7 +81,80 @@ static int run_team_id(int P, int n_states, int n_chains, int n_max, const int32
   return 0;
 }
 
+// Forward dynamics as k_fd_team runs it, one state at a time: the bias forces by
+// the team scans (tau-hat per link), the articulated-body pass, then z-hat / c-hat
+// and lambda / qdd; the z-hat and lambda passes read the (sin, cos) through the
+// team-slot view of the kernel (one team, so the team's first lane is 0).
+template <class T>
+static int run_team_fd(int P, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
+                       const T* twist, const T* inertia, const T* q, const T* qd, const T* tau, T* qdd,
+                       const T* tip, const T* V0, const T* dV0) {
+  const int64_t L = (n_chains == 1) ? n_max : link_ptr[n_chains];
+  std::vector<T> table((size_t)L * kLinkWords);
+  std::vector<double> wtable((size_t)L * kLinkWords);
+  for (int64_t i = 0; i < L; ++i) {
+    make_link_record(placement + 7 * i, twist + 6 * i, inertia + 10 * i, &wtable[i * kLinkWords]);
+    for (int k = 0; k < kLinkWords; ++k) table[i * kLinkWords + k] = (T)wtable[i * kLinkWords + k];
+  }
+  Boundary<T> bd;
+  bd.V0 = {v3(V0[0], V0[1], V0[2]), v3(V0[3], V0[4], V0[5])};
+  bd.dV0 = {v3(dV0[0], dV0[1], dV0[2]), v3(dV0[3], dV0[4], dV0[5])};
+  int faults = 0;
+  for (int s = 0; s < n_states; ++s) {
+    int n;
+    int64_t link0, dof0;
+    if (n_chains == 1) { n = n_max; link0 = 0; dof0 = (int64_t)s * n_max; }
+    else { link0 = link_ptr[s]; n = link_ptr[s + 1] - (int)link0; dof0 = link0; }
+    bd.Ftip = tip ? Sp<T>{v3(tip[6 * s], tip[6 * s + 1], tip[6 * s + 2]), v3(tip[6 * s + 3], tip[6 * s + 4], tip[6 * s + 5])}
+                  : sp_zero<T>();
+    const T* tab = table.data() + link0 * kLinkWords;
+    const double* wtab = wtable.data() + link0 * kLinkWords;
+    const SPtr<const T> qs(q + dof0), qds(qd + dof0), taus(tau + dof0);
+    const int slots = (n + P - 1) / P;
+    std::vector<T> scratch((size_t)P * (slots > 0 ? slots : 1) * kTeamIdWords, T(-7777));  // poisoned
+    auto scr = [&](int k) { return Scratch<T>{scratch.data() + k, (long)P, kTeamIdWords}; };
+    std::vector<double> hat((size_t)n, -7777.0);
+    std::vector<Seg> seg(P);
+    std::vector<FwdOp<T>> agg(P);
+    for (int k = 0; k < P; ++k) {
+      seg[k] = segment_of(n, P, k);
+      agg[k] = team_fwd_aggregate(seg[k], tab, qs, qds, SPtr<const T>(), bd);
+    }
+    const auto pre = prefix_exclusive(agg, fwd_identity<T>(), [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); });
+    std::vector<BwdOp<double>> bag(P);
+    for (int k = 0; k < P; ++k) {
+      team_fwd_apply(seg[k], tab, qs, qds, SPtr<const T>(), k > 0 ? pre[k].x1 : bd.dV0, k > 0 ? pre[k].x2 : bd.V0,
+                     scr(k));
+      bag[k] = team_bwd_aggregate(seg[k], wtab, qs, scr(k));
+    }
+    const auto suf = suffix_exclusive(bag, bwd_identity<double>(), [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); });
+    for (int k = 0; k < P; ++k)
+      team_bwd_apply_hat(seg[k], wtab, qs, scr(k), bwd_apply(suf[k], cast_sp<double>(bd.Ftip)), taus,
+                         [&](int i, double v) { hat[(size_t)i] = v; });
+    unsigned status = 0;
+    std::vector<T> abi_mem((size_t)(n > 0 ? n : 1) * kAbiWords, T(-7777)), chat_mem((size_t)(n > 0 ? n : 1), T(-7777));
+    const Scratch<T> abi{abi_mem.data(), 1L, kAbiWords, &status};
+    const Scratch<T> chat{chat_mem.data(), 1L, 1, &status};
+    split_abi_pass(n, tab, wtab, qs, abi);
+    const TeamSlots<T> sc{scratch.data(), (long)P, 0L, slots, kTeamIdWords};
+    team_zhat_pass(n, wtab, qs, abi, [&](int i) { return hat[(size_t)i]; }, sc, chat, NoHandoff());
+    team_lambda_pass(n, tab, qs, abi, chat, sc, chat, [&](int i, T v) { qdd[dof0 + i] = v; });
+    if (status) ++faults;
+  }
+  return faults;
+}
+
 extern "C" {
+int cpu_team_fd_f64(int P, int n_states, int n_chains, int n_max, const int32_t* lp, const double* pl,
+                    const double* tw, const double* in, const double* q, const double* qd, const double* tau,
+                    double* qdd, const double* tip, const double* V0, const double* dV0) {
+  return run_team_fd<double>(P, n_states, n_chains, n_max, lp, pl, tw, in, q, qd, tau, qdd, tip, V0, dV0);
+}
+int cpu_team_fd_f32(int P, int n_states, int n_chains, int n_max, const int32_t* lp, const float* pl,
+                    const float* tw, const float* in, const float* q, const float* qd, const float* tau, float* qdd,
+                    const float* tip, const float* V0, const float* dV0) {
+  return run_team_fd<float>(P, n_states, n_chains, n_max, lp, pl, tw, in, q, qd, tau, qdd, tip, V0, dV0);
+}
 int cpu_team_id_f64(int P, int n_states, int n_chains, int n_max, const int32_t* lp, const double* pl,
                     const double* tw, const double* in, const double* q, const double* qd, const double* qdd,
                     double* tau, const double* tip, const double* V0, const double* dV0) {

@@ -342,3 +342,46 @@ def test_team_segments_resolve():
         assert out[3].value == 16
         ws = L.pdyn_workspace_bytes(0, ctypes.byref(m), ctypes.byref(b), 4)
         assert ws >= -(-n // 16) * 8 * 100 * 16 * 4
+
+
+def test_team_fd_segments_resolve():
+    """Forward dynamics and ID+FD with variant 4: at most 16 lanes per chain by default, and a workspace with
+    the team slots of the bias forces (and, for ID+FD, of the inverse dynamics), the articulated terms, c-hat
+    and tau-hat."""
+    L = api.lib()
+    for op in (1, 2):
+        for n, P in ((7, 1), (32, 4), (100, 8), (1000, 16)):
+            m, keep = _fake_model(n=n)
+            b = api._batch_struct(100, api.ZERO6, api.GRAVITY_ACC, None)
+            b.variant = 4
+            out = [ctypes.c_int32(-9) for _ in range(4)]
+            assert L.pdyn_launch_choice(op, ctypes.byref(m), ctypes.byref(b), 4, *map(ctypes.byref, out)) == 0
+            assert out[3].value == P, (op, n, out[3].value)
+            ws = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), 4)
+            team = -(-n // P) * 8 * 100 * P * 4
+            assert ws >= (2 if op == 2 else 1) * team + n * 100 * (7 * 4 + 4 + 8)
+
+
+def test_jsiia_host_rules():
+    """The joint-space inertia entry points: shared chains only, null and misaligned pointers, workspace size."""
+    L = api.lib()
+    fn = L.pdyn_jsiia_fd
+    fn.argtypes = [ctypes.POINTER(api._Model), ctypes.POINTER(api._Batch)] + [ctypes.c_void_p] * 5 + \
+        [ctypes.c_size_t, ctypes.c_void_p]
+    m, keep = _fake_model(n=6)
+    b = api._batch_struct(8, api.ZERO6, api.GRAVITY_ACC, None)
+    x = np.zeros(48, np.float32)
+    p = x.ctypes.data
+    ws = np.zeros((1 << 20) + 512, np.uint8)
+    w = ws.ctypes.data + ((-ws.ctypes.data) % 256)
+    need = L.pdyn_workspace_bytes(5, ctypes.byref(m), ctypes.byref(b), 4)
+    assert need >= 8 * (13 * 6 + 21) * 8
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, 0, p, w, 1 << 20, None) == -1
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p + 2, p, p, w, 1 << 20, None) == -2
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need - 1, None) == -3
+    lp = np.array([0, 3, 6], np.int32)
+    m2, keep2 = _fake_model(n=6, n_chains=2, link_ptr=lp)
+    m2.n_links_max = 3
+    m2.link_ptr_host = lp.ctypes.data
+    b2 = api._batch_struct(2, api.ZERO6, api.GRAVITY_ACC, None)
+    assert fn(ctypes.byref(m2), ctypes.byref(b2), p, p, p, p, w, 1 << 20, None) == -5

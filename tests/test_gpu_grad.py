@@ -199,9 +199,10 @@ def test_inertia_gradient_is_deterministic(device):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_adjoint_variants(device, variant):
-    """Both adjoint kernels (one wavefront per 64 states; role split) against the oracle: FP64 with base motion
+    """Every adjoint variant (one wavefront per 64 states; role split; plain, one launch per pass) against the
+    oracle: FP64 with base motion
     and tip wrenches on ragged chains, and the FP32 32-link FD adjoint on sampled states of a full batch."""
     print(f"case: adjoint variant {variant}", flush=True)
     for op in (api.OP_RNEA_ID_VJP, api.OP_ABA_FD_VJP):

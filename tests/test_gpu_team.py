@@ -100,3 +100,100 @@ def test_fp32_team_id_32_links_full_batch(device, P):
     ref = oracle.rnea(cr, sr.q[idx], sr.qd[idx], sr.qdd[idx], threads=THREADS)
     assert rel_rows(tau[idx], ref).max() <= TOL32
     assert rel_rows(tau, fold).max() <= 2 * TOL32
+
+
+@pytest.mark.parametrize("P", [1, 2, 4, 8, 16])
+def test_fp64_team_fd_and_id_fd_every_segment_count(device, P):
+    """FP64 forward dynamics and fused ID+FD with the bias forces by team scans and the serial articulated-body
+    recursions beside them: ragged chains of 1..40 links (with base motion and tip wrenches) and a shared
+    13-link chain (prepared and not), equal to the oracle to rounding."""
+    print(f"case: fp64 team FD P={P}", flush=True)
+    with_team(api.OP_ABA_FD, P)
+    with_team(api.OP_ID_FD, P)
+    ch = synth.make_chains([13, 1, 40, 7, 22, 3, 16, 9], 43)
+    st = synth.make_states((ch.n_links_total,), 43)
+    rng = np.random.default_rng(43)
+    tip = rng.standard_normal((ch.n_chains, 6))
+    V0, dV0 = rng.standard_normal(6), rng.standard_normal(6)
+    ref_q = oracle.aba(ch, st.q, st.qd, st.tau, V0=V0, dV0=dV0, Ftip=tip)
+    ref_t = oracle.rnea(ch, st.q, st.qd, st.qdd, V0=V0, dV0=dV0, Ftip=tip)
+    for prepare in (True, False):
+        model = api.Model(ch, device, torch.float64, prepare=prepare)
+        d = lambda a: to_dev(a, device, torch.float64)
+        kw = dict(base_vel=tuple(V0), base_acc=tuple(dV0), tip=d(tip))
+        q1 = api.aba_fd(model, d(st.q), d(st.qd), d(st.tau), **kw).cpu().numpy()
+        t2, q2 = (x.cpu().numpy() for x in api.id_fd(model, d(st.q), d(st.qd), d(st.qdd), d(st.tau), **kw))
+        assert api.read_status(device) == 0
+        assert rel_ragged(q1, ref_q, ch.link_ptr).max() <= 1e-11
+        assert rel_ragged(q2, ref_q, ch.link_ptr).max() <= 1e-11
+        assert rel_ragged(t2, ref_t, ch.link_ptr).max() <= 1e-12
+    ch1 = synth.make_chains([13], 44)
+    st1 = synth.make_states((67, 13), 44)
+    m1 = api.Model(ch1, device, torch.float64)
+    d = lambda a: to_dev(a, device, torch.float64)
+    q1 = api.aba_fd(m1, d(st1.q), d(st1.qd), d(st1.tau)).cpu().numpy()
+    assert rel_rows(q1, oracle.aba(ch1, st1.q, st1.qd, st1.tau)).max() <= 1e-11
+
+
+@pytest.mark.parametrize("P", [4, 8, 16])
+def test_fp32_team_id_fd_uneven_4096(device, P):
+    """The uneven batch (4096 chains of 10..100 links, one state each), fused ID+FD by the team kernel: every
+    output against the oracle (tau within 1e-4; qdd within 1e-4 up to 32 links, bounded by the conditioning of
+    M above), and against the role-split kernel's outputs."""
+    print(f"case: fp32 team ID+FD uneven 4096 P={P}", flush=True)
+    ch, st = synth.workload_uneven()
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: to_dev(a, device, torch.float32)
+    q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+    api.set_launch(api.OP_ID_FD, 0, 0, 2)
+    t_ref, q_ref = (x.cpu().numpy() for x in api.id_fd(model, q, qd, qdd, tau))
+    with_team(api.OP_ID_FD, P)
+    t4, q4 = (x.cpu().numpy() for x in api.id_fd(model, q, qd, qdd, tau))
+    assert api.read_status(device) == 0
+    cr, sr = ch.rounded(), st.rounded()
+    rt = oracle.rnea(cr, sr.q, sr.qd, sr.qdd, threads=THREADS)
+    rq = oracle.aba(cr, sr.q, sr.qd, sr.tau, threads=THREADS)
+    lens = ch.lengths()
+    et, eq = rel_ragged(t4, rt, ch.link_ptr), rel_ragged(q4, rq, ch.link_ptr)
+    print(f"team ID+FD P={P}: tau max {et.max():.2e}, qdd max {eq.max():.2e} (<=32 links {eq[lens <= 32].max():.2e})",
+          flush=True)
+    assert et.max() <= TOL32
+    assert eq[lens <= 32].max() <= TOL32
+    assert eq.max() <= 1e-2
+    # the two kernels differ by rounding only
+    assert rel_ragged(q4, q_ref.astype(np.float64), ch.link_ptr)[lens <= 32].max() <= 2 * TOL32
+
+
+def test_team_id_fd_in_a_captured_graph(device):
+    """The team ID+FD kernel on the uneven batch captured once in a HIP graph; every replay equals the eager call."""
+    print("case: team ID+FD graph capture", flush=True)
+    ch, st = synth.workload_uneven(1024, 10, 100)
+    model = api.Model(ch, device, torch.float32)
+    d = lambda a: to_dev(a, device, torch.float32)
+    q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+    with_team(api.OP_ID_FD, 8)
+    out = (torch.empty_like(q), torch.empty_like(q))
+    ws = api.Workspace()
+    api.id_fd(model, q, qd, qdd, tau, out=out, workspace=ws)  # sizes the workspace outside capture
+    eager = [x.clone() for x in out]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.id_fd(model, q, qd, qdd, tau, out=out, workspace=ws)
+    for rep in range(3):
+        out[0].fill_(float("nan"))
+        out[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], eager[0]) and torch.equal(out[1], eager[1]), f"replay {rep}"
+        api.rnea_id(model, q, qd, qdd)  # eager work between replays
+
+
+def test_team_fd_segment_bound(device):
+    print("case: team FD segment bound", flush=True)
+    ch, st = synth.workload_uneven(64, 10, 20)
+    model = api.Model(ch, device, torch.float32)
+    x = to_dev(st.q, device, torch.float32)
+    with_team(api.OP_ABA_FD, 32)
+    with pytest.raises(api.PdynError, match="unsupported"):
+        api.aba_fd(model, x, x, x)

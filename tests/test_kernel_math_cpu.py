@@ -28,7 +28,9 @@ ABI_U_ONLY = 32  # flag: the articulated hand-off holds U_i only; B2 forms 1/D_i
 def cpu_lib(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("kcpu") / "libsweeps_cpu.so")
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-host-only", "-o", out, SRC], check=True)
+    extra = os.environ.get("PDYN_HOST_BUILD_FLAGS", "").split()  # set by the sanitizer run (test_sanitized_cpu)
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-host-only", *extra, "-o", out, SRC],
+                   check=True)
     lib = ctypes.CDLL(out)
     for f in (lib.cpu_dynamics_f32, lib.cpu_dynamics_f64):
         f.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 13
