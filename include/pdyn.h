@@ -319,6 +319,30 @@ int pdyn_jsiia_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const do
                       const double* tau, double* qdd, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * pdyn_id_fd without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the call allocates nothing, on the device or through
+ * any library routine. Its scratch is a static device array of
+ * PDYN_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends; the caller still passes inputs and outputs.
+ *
+ * Same arguments, results and rules as pdyn_id_fd (the same kernels run), except:
+ *  - PDYN_EWORKSPACE when pdyn_workspace_bytes(PDYN_OP_ID_FD, model, batch, 4)
+ *    exceeds PDYN_NOALLOC_SCRATCH_BYTES (64 MiB: e.g. 32 links x 16384 states
+ *    with prepared tables needs 50 MiB), checked before any device work;
+ *  - the call zeroes the array's status word first; status_out (device, one
+ *    32-bit word, or NULL) then receives the PDYN_STATUS_* bits of this call.
+ *    For an empty batch nothing is queued and *status_out is not written.
+ * All calls on one device share that device's array: calls that overlap in
+ * time on one device (several host threads, or several streams) race and give
+ * undefined results. Serialise them, e.g. on one stream.
+ */
+#define PDYN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pdyn_id_fd_noalloc(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                       const float* qdd_in, const float* tau_in, float* tau_out, float* qdd_out, uint32_t* status_out,
+                       void* stream);
+
+/*
  * Adjoint of the inverse dynamics (vector-Jacobian product). Gradients of the
  * dynamics are the paper's stated future work (Sec. VI); this is reverse-mode
  * differentiation of the recursions (1)-(2):

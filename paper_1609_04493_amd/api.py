@@ -88,6 +88,8 @@ def lib():
                 getattr(L, name).restype = ci
             L.pdyn_rollout_workspace_bytes.argtypes = [ci, ctypes.POINTER(_Model), ctypes.POINTER(_Batch), ci, ci]
             L.pdyn_rollout_workspace_bytes.restype = ctypes.c_size_t
+            L.pdyn_id_fd_noalloc.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Batch)] + [vp] * 7 + [vp]
+            L.pdyn_id_fd_noalloc.restype = ctypes.c_int
             L.pdyn_read_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
             L.pdyn_read_status.restype = ctypes.c_int
             i64 = ctypes.c_int64
@@ -333,6 +335,27 @@ def mass_matrix(model: Model, q, out=None, workspace=None):
     M = torch.empty((n_states, n, n), dtype=model.dtype, device=model.device) if out is None else out
     _call("pdyn_mass_matrix", OP_MASS_MATRIX, model, n_states, (q, M), ZERO6, ZERO6, None, workspace)
     return M
+
+
+def id_fd_noalloc(model: Model, q, qd, qdd_in, tau_in, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None,
+                  status_out=None):
+    """id_fd through pdyn_id_fd_noalloc: no workspace, the library's static device scratch instead.
+
+    status_out: an int32 tensor of one element on the model's device that receives the call's status bits,
+    or None."""
+    if model.dtype != torch.float32:
+        raise PdynError("id_fd_noalloc: FP32 only")
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd_in, tau_in, tip))
+    tau_out, qdd_out = (torch.empty_like(q), torch.empty_like(q)) if out is None else out
+    m = model.c_struct()
+    b = _batch_struct(n_states, base_vel, base_acc, tip, OP_ID_FD)
+    stream = torch.cuda.current_stream(model.device).cuda_stream
+    st = lib().pdyn_id_fd_noalloc(ctypes.byref(m), ctypes.byref(b), q.data_ptr(), qd.data_ptr(), qdd_in.data_ptr(),
+                                  tau_in.data_ptr(), tau_out.data_ptr(), qdd_out.data_ptr(),
+                                  None if status_out is None else status_out.data_ptr(), stream)
+    _check(st, "pdyn_id_fd_noalloc")
+    return tau_out, qdd_out
 
 
 def _inertia_bar_like(model):

@@ -2179,6 +2179,35 @@ int run_euler_step_vjp(int64_t n, double dt, T* qb, T* qdb, const T* qbf, const 
   return hipGetLastError() == hipSuccess ? PDYN_OK : PDYN_ELAUNCH;
 }
 
+// ---- the allocation-free entry point (pdyn_id_fd_noalloc) -----------------------------
+//
+// Its workspace is this file-scope array instead of caller memory: every device
+// the library runs on holds one copy of it until the process ends. In host code
+// the name is only a host-side handle of the symbol; its device address comes
+// from hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever handed to kernels.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static_assert(kNoAllocBytes == PDYN_NOALLOC_SCRATCH_BYTES, "static scratch size of the C ABI");
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kMaxDevices];
+
+// Device address of noalloc_scratch on the current device.
+int noalloc_scratch_ptr(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PDYN_ELAUNCH;
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return PDYN_ELAUNCH;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return PDYN_OK;
+}
+
 }  // namespace
 }  // namespace pdyn
 
@@ -2299,6 +2328,25 @@ int pdyn_id_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const f
 int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd_in,
                    const double* tau_in, double* tau_out, double* qdd_out, void* ws, size_t ws_bytes, void* stream) {
   return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+
+int pdyn_id_fd_noalloc(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
+                       const float* qdd_in, const float* tau_in, float* tau_out, float* qdd_out, uint32_t* status_out,
+                       void* stream) {
+  // every check that needs no device comes first, so a rejected call queues nothing
+  const size_t need = pdyn_workspace_bytes(PDYN_OP_ID_FD, m, b, 4);
+  if (need == 0) {
+    const int st = check_model_batch(m, b);
+    return st ? st : PDYN_EINVAL;
+  }
+  if (need > kNoAllocBytes) return PDYN_EWORKSPACE;
+  if (status_out && !aligned(status_out, sizeof(uint32_t))) return PDYN_EALIGN;
+  if (b->n_states == 0) return PDYN_OK;
+  void* ws = nullptr;
+  const int st = noalloc_scratch_ptr(&ws);
+  if (st) return st;
+  return run_dynamics<float, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws,
+                                        kNoAllocBytes, stream, true, status_out);
 }
 
 int pdyn_mass_matrix(const pdyn_model* m, const pdyn_batch* b, const float* q, float* M, void* ws, size_t ws_bytes,

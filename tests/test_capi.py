@@ -385,3 +385,22 @@ def test_jsiia_host_rules():
     m2.link_ptr_host = lp.ctypes.data
     b2 = api._batch_struct(2, api.ZERO6, api.GRAVITY_ACC, None)
     assert fn(ctypes.byref(m2), ctypes.byref(b2), p, p, p, p, w, 1 << 20, None) == -5
+
+
+def test_noalloc_rejects_before_device_work():
+    """pdyn_id_fd_noalloc: invalid arguments and batches beyond its static scratch fail on the host."""
+    L = api.lib()
+    assert L.pdyn_id_fd_noalloc(None, None, 0, 0, 0, 0, 0, 0, None, None) == -1
+    m, keep = _fake_model(n=32)
+    m.prepared = 1 << 12  # any aligned value: no device work is queued on these paths
+    x = np.zeros(8, np.float32)
+    p = x.ctypes.data
+    big = api._batch_struct(40000, api.ZERO6, api.GRAVITY_ACC, None)  # ~122 MiB of scratch > 64 MiB
+    assert L.pdyn_workspace_bytes(2, ctypes.byref(m), ctypes.byref(big), 4) > (64 << 20)
+    assert L.pdyn_id_fd_noalloc(ctypes.byref(m), ctypes.byref(big), p, p, p, p, p, p, None, None) == -3
+    bneg = api._batch_struct(-1, api.ZERO6, api.GRAVITY_ACC, None)
+    assert L.pdyn_id_fd_noalloc(ctypes.byref(m), ctypes.byref(bneg), p, p, p, p, p, p, None, None) == -1
+    ok = api._batch_struct(16, api.ZERO6, api.GRAVITY_ACC, None)
+    assert L.pdyn_id_fd_noalloc(ctypes.byref(m), ctypes.byref(ok), p, p, p, p, p, p, p + 1, None) == -2
+    empty = api._batch_struct(0, api.ZERO6, api.GRAVITY_ACC, None)
+    assert L.pdyn_id_fd_noalloc(ctypes.byref(m), ctypes.byref(empty), p, p, p, p, p, p, None, None) == 0
