@@ -27,6 +27,15 @@ Operands (1-based links, n links):
        as the inverse.)
   (19) ABIA forward, 8x8, on (lambda_{i-1}, qdd_{i-1}, 1) -> (lambda_i, qdd_i, 1):
        A_i = [[Y_{i-1,i}^T, 0, S_i chat_i], [-Pi_{i-1,i}^T, 0, chat_i], [0, 0, 1]], i = 1..n.
+  (20) the bias-wrench scan of (16) and the ABIA backward scan of (18) as one, 15x15, on
+       (F_i, tauhat_{i+1}, zhat_{i+1}, chat_{i+2}, 1) -> (F_{i-1}, tauhat_i, zhat_i, chat_{i+1}, 1):
+       A_i = [[X_i^T, 0, 0, 0, Fhat_{i-1}], [-S_i^T, 0, 0, 0, tau_i],
+              [0, Pi_{i,i+1}, Y_{i,i+1}, 0, 0], [0, Omega_{i+1}^-1, -Omega_{i+1}^-1 S_{i+1}^T, 0, 0],
+              [0, 0, 0, 0, 1]],
+       F and Fhat the bias wrenches (qdd = 0), Omega read as the inverse (as in (18)). In scan order
+       A_{n+1}, A_n, ..., A_0 from (F_{n+1}, 0, 0, 0, 1) = (tip wrench, 0, 0, 0, 1), with the padding
+       X_{n+1} = I, S_{n+1} = 0, tau_{n+1} = 0 and Pi_{n,n+1} = Y_{n,n+1} = Omega_{n+1}^-1 = 0 (no
+       child of link n), Fhat_0 = 0, S_0 = 0 and tau_0 = 0 (no joint 0).
 """
 
 from __future__ import annotations
@@ -196,6 +205,32 @@ def lambda_operands(ch, at):
         A[:6, 7] = ch.twist[i - 1] * at["chat"][i]
         A[6, :6] = -at["Pi"][i]
         A[6, 7] = at["chat"][i]
+        ops.append(A)
+    return ops
+
+
+def merged_backward_operands(ch, bt, at, tau):
+    """Eq. (20) operands in scan order A_{n+1}, A_n, ..., A_0; bt is the trace of the bias forces
+    (rnea_trace with qdd = 0), at the ABIA trace at the same state, tau the joint torques."""
+    n = len(at["qdd"]) - 1
+    ops = []
+    for i in range(n + 1, -1, -1):
+        A = np.zeros((15, 15))
+        A[14, 14] = 1.0
+        if i == n + 1:
+            A[:6, :6] = np.eye(6)                     # X_{n+1} = I: F_n = F_tip + Fhat_n
+        elif i >= 1:
+            A[:6, :6] = Ad(*inv_pose(bt["R"][i], bt["p"][i])).T
+            A[6, :6] = -ch.twist[i - 1]
+            A[6, 14] = tau[i - 1]
+        if 1 <= i - 1 <= n:
+            A[:6, 14] = bt["Fhat"][i - 1]
+        if 0 <= i <= n - 1:                           # link i + 1 exists
+            Om = at["Omega"][i + 1]
+            A[7:13, 6] = at["Pi"][i + 1]
+            A[7:13, 7:13] = at["Y"][i + 1]
+            A[13, 6] = 1.0 / Om
+            A[13, 7:13] = -ch.twist[i] / Om
         ops.append(A)
     return ops
 

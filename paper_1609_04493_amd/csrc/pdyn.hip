@@ -260,6 +260,20 @@ struct LdsProgress {
   int* p;
   __device__ void operator()(int k) const { __hip_atomic_store(p, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 };
+// The same for a hand-off whose data this wavefront wrote to LDS only: the
+// progress word is stored after this wavefront's LDS operations have completed
+// (s_waitcnt lgkmcnt(0); a wavefront's LDS operations complete in order, so the
+// entries are in LDS before the word changes), without the release store's wait
+// for outstanding vector-memory loads, which would expose the latency of the
+// next link's prefetched inputs at every link.
+struct LdsPublish {
+  int* p;
+  __device__ void operator()(int k) const {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no compiler reordering of the LDS writes past this point
+    __builtin_amdgcn_s_waitcnt(0xC07F);       // gfx9 encoding: lgkmcnt(0), vmcnt and expcnt not waited for
+    __hip_atomic_store(p, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
 // Waits until *p >= k. Progress words only grow, so the last value read is
 // kept: a wait it already covers returns without touching LDS (the acquire
 // that read it orders everything released up to it).
@@ -718,7 +732,7 @@ __global__ void __launch_bounds__(256) k_id_team(int n_states, int n_max, const 
 // One lane per state of a shared chain, grid-stride. FD: qdd = M^-1 (tau - tau_bias);
 // otherwise M(q) only, written whole to M ([n_states][n][n]). Working storage:
 // [jsiia_words(n)][n_states] doubles (consecutive lanes, consecutive words).
-template <class T, bool FD>
+template <class T, bool FD, bool SOLVE = true>
 __global__ void __launch_bounds__(256) k_jsiia(int n_states, int n, const T* __restrict__ table,
                                                const double* __restrict__ wtable, const T* q, const T* qd,
                                                const T* tau, T* qdd, T* M, const T* __restrict__ tip,
@@ -738,7 +752,7 @@ __global__ void __launch_bounds__(256) k_jsiia(int n_states, int n, const T* __r
     };
     jsiia_mass_matrix<T, FD>(n, table, wtable, SPtr<const T>(q + row), SPtr<const T>(FD ? qd + row : nullptr),
                              SPtr<const T>(FD ? tau + row : nullptr), bd, ws, mout);
-    if (FD) {
+    if (FD && SOLVE) {
       unsigned bits = 0;
       const bool ok = jsiia_solve<T>(n, ws, [&](int i, double v) {
         const T x = (T)v;
@@ -751,42 +765,117 @@ __global__ void __launch_bounds__(256) k_jsiia(int n_states, int n, const T* __r
   }
 }
 
+// The factorisation and solves of JSIIA for n <= NT links (NT a power of two up
+// to 32; longer chains keep the per-lane solve of k_jsiia): a team of NT lanes per state, lane i holding row i of M (the packed
+// lower triangle that k_jsiia left in `work`) in registers. Right-looking
+// Cholesky: at step j lane j's diagonal becomes L_jj, the lanes below scale
+// their entry of column j, and every entry of the trailing rows takes its
+// update from column j, whose entries reach the other lanes by wave shuffles.
+// Then L y = tau-hat with y_k broadcast the same way, and L^T qdd = y with the
+// columns of L read from LDS, where each lane leaves its row. Double throughout.
+template <class T, int NT>
+__global__ void __launch_bounds__(256) k_jsiia_chol(int n_states, int n, const double* __restrict__ work, T* qdd,
+                                                    unsigned* status) {
+  extern __shared__ __align__(16) unsigned char lds_chol[];
+  const long L = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long s = L / NT;
+  const int i = (int)(L % NT);
+  const bool active = s < n_states;
+  const bool row = active && i < n;
+  double* const Ls = reinterpret_cast<double*>(lds_chol) + (long)(threadIdx.x / NT) * NT * NT;
+  const long area = 13L * n;  // jsiia.hpp: poses (12 n), tau-hat (n), then the packed triangle
+  const long stride = n_states;
+  const double* const w = work + (active ? s : 0);
+  double r[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) r[k] = (row && k <= i) ? w[(area + (long)i * (i + 1) / 2 + k) * stride] : 0.0;
+  double b = row ? w[(12L * n + i) * stride] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    if (j < n) {
+      const double d = __shfl(r[j], j, NT);
+      if (i == j && !(d > 0.0)) ok = false;
+      const double ljj = sqrt(d);
+      if (i == j) r[j] = ljj;
+      else if (i > j) r[j] = r[j] / ljj;
+#pragma unroll
+      for (int k = j + 1; k < NT; ++k) {
+        if (k < n) {
+          const double lkj = __shfl(r[j], k, NT);
+          if (i >= k) r[k] -= r[j] * lkj;
+        }
+      }
+    }
+  }
+  // L y = tau-hat: lane k finishes y_k, then every lane below takes its term
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    if (k < n) {
+      if (i == k) b = b / r[k];
+      const double yk = __shfl(b, k, NT);
+      if (i > k) b -= r[k] * yk;
+    }
+  }
+  // L^T qdd = y: column k of L is row k's entries, read from LDS
+#pragma unroll
+  for (int k = 0; k < NT; ++k) Ls[(long)i * NT + k] = r[k];
+  __syncthreads();
+  for (int k = n - 1; k >= 0; --k) {
+    if (i == k) b = b / Ls[(long)k * NT + k];
+    const double xk = __shfl(b, k, NT);
+    if (i < k) b -= Ls[(long)k * NT + i] * xk;
+  }
+  if (row) {
+    const T x = (T)b;
+    qdd[s * n + i] = x;
+    unsigned bits = 0;
+    if (!__builtin_isfinite(x)) bits |= kStatusNonFinite;
+    if (!ok) bits |= kStatusPivot;
+    if (bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Forward dynamics (and ID+FD) by the team scans (variant 4). A workgroup takes
-// kTeamChains chains (in lane order) and has three kinds of wavefronts:
-//  * team wavefronts, P lanes per chain (team.hpp): the bias forces by the two
-//    segmented scans, leaving tau-hat = tau - tau_bias per link (double) and
-//    the (sin, cos) of every joint angle; for ID+FD also the inverse dynamics;
-//    then each adds one to `p1done` (release) and ends;
+// C chains (in lane order; C chosen on the host so that their per-link values
+// fit in LDS, at most kTeamChains) and has three kinds of wavefronts:
+//  * team wavefronts, P lanes per chain (team.hpp): first every link transform
+//    of their segments into LDS (then one add to `pdone`); then the bias forces
+//    by the two segmented scans, leaving tau-hat = tau - tau_bias per link in
+//    LDS (then one add to `p1done`); for ID+FD then the inverse dynamics;
 //  * A, one lane per chain: the articulated-body recursion (7), serial, from
-//    the start, publishing its progress in `aprog` after every link;
-//  * Z, one lane per chain: once every team wavefront is done, z-hat / c-hat
-//    tip to base, each link as soon as A has it, then lambda / qdd base to tip.
-// No workgroup barrier follows the first: waits are one-directional (Z waits
-// for the others), so every wave runs to its end.
+//    the transforms in LDS, publishing its progress in `aprog` after each link;
+//  * Z, one lane per chain: once the team is done, z-hat / c-hat tip to base,
+//    each link as soon as A has it, then lambda / qdd base to tip, all out of
+//    LDS; qdd is written out at the end.
+// No workgroup barrier follows the first: waits are one-directional (A waits
+// for the team, Z for the team and A), so every wavefront runs to its end.
 constexpr int kTeamChains = 16;
 
 template <class T, int MODE, int P, bool SHARED>
-__global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, const LaneChain* __restrict__ lanes,
-                                                  const T* __restrict__ table, const double* __restrict__ wtable,
-                                                  const T* q, const T* qd, const T* qdd_in, const T* tau_in,
-                                                  T* tau_out, T* qdd_out, const T* __restrict__ tip,
-                                                  BoundaryArgs<T> ba, T* scr_id, T* scr_bias, T* scr_abi,
-                                                  T* scr_chat, double* tauhat, long n_lanes, unsigned* status) {
-  constexpr int kLanes = kTeamChains * P;
-  constexpr int kTeamWaves = (kLanes + 63) / 64;
-  __shared__ int p1done, aprog;
+__global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, int C, const LaneChain* __restrict__ lanes,
+                                                 const T* __restrict__ table, const double* __restrict__ wtable,
+                                                 const T* q, const T* qd, const T* qdd_in, const T* tau_in,
+                                                 T* tau_out, T* qdd_out, const T* __restrict__ tip,
+                                                 BoundaryArgs<T> ba, T* scr_id, T* scr_bias, long n_lanes,
+                                                 unsigned* status) {
+  extern __shared__ __align__(16) unsigned char lds_team[];
+  __shared__ int pdone, p1done, aprog;
   if (threadIdx.x == 0) {
+    pdone = 0;
     p1done = 0;
     aprog = 0;
   }
   __syncthreads();
+  const int team_lanes = C * P;
+  const int team_waves = (team_lanes + 63) / 64;
   const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
   Boundary<T> bd = boundary_of(ba);
-  if (wave < kTeamWaves) {
+  if (wave < team_waves) {
     const int t = (int)threadIdx.x;
-    const int k = t % P;
-    const long j = (long)blockIdx.x * kTeamChains + t / P;
-    const bool active = t < kLanes && j < n_states;
+    const int k = t % P, c = t / P;
+    const long j = (long)blockIdx.x * C + c;
+    const bool active = t < team_lanes && j < n_states;
     const int jj = active ? (int)j : 0;
     ChainOf ch{0, 0, 0, 0};
     if (active) ch = chain_of<SHARED>(jj, n_max, lanes);
@@ -794,6 +883,9 @@ __global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, const 
     const auto tab = rec_view<SHARED>(table, jj, n_max);
     const auto wtab = rec_view<SHARED>(wtable, jj, n_max);
     const SPtr<const T> qs(q + ch.dof0), qds(qd + ch.dof0);
+    const TeamChainLds<T> cl = TeamChainLds<T>::at(lds_team, n_max, C, active ? c : 0);
+    team_pose_pass(sg, tab, wtab, qs, cl);
+    if (lane == 0) __hip_atomic_fetch_add(&pdone, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (active && tip) {
       const T* tp = tip + 6 * (int64_t)ch.s;
       bd.Ftip = {v3(tp[0], tp[1], tp[2]), v3(tp[3], tp[4], tp[5])};
@@ -810,8 +902,9 @@ __global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, const 
       const BwdOp<double> suf =
           team_suffix_exclusive<P>(team_bwd_aggregate(sg, wtab, qs, scr), k, bwd_identity<double>(), bcomb);
       team_bwd_apply_hat(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<const T>(tau_in + ch.dof0),
-                         [&](int i, double v) { tauhat[(long)i * n_states + j] = v; });
+                         [&](int i, double v) { cl.put_hat(i, v); });
     }
+    if (lane == 0) __hip_atomic_fetch_add(&p1done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (MODE & kModeID) {
       const Scratch<T> scr{scr_id + L, n_lanes, kTeamIdWords, status};
       const SPtr<const T> qdds(qdd_in + ch.dof0);
@@ -822,30 +915,33 @@ __global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, const 
           team_suffix_exclusive<P>(team_bwd_aggregate(sg, wtab, qs, scr), k, bwd_identity<double>(), bcomb);
       team_bwd_apply(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<T>(tau_out + ch.dof0));
     }
-    if (lane == 0) __hip_atomic_fetch_add(&p1done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     return;
   }
-  const int role = wave - kTeamWaves;  // 0: articulated-body pass; 1: z-hat, then lambda
-  const long j = (long)blockIdx.x * kTeamChains + lane;
-  const bool active = lane < kTeamChains && j < n_states;
+  const int role = wave - team_waves;  // 0: articulated-body pass; 1: z-hat, then lambda
+  const long j = (long)blockIdx.x * C + lane;
+  const bool active = lane < C && j < n_states;
   const int jj = active ? (int)j : 0;
   ChainOf ch{0, 0, 0, 0};
   if (active) ch = chain_of<SHARED>(jj, n_max, lanes);
   const auto tab = rec_view<SHARED>(table, jj, n_max);
   const auto wtab = rec_view<SHARED>(wtable, jj, n_max);
-  const SPtr<const T> qs(q + ch.dof0);
-  const Scratch<T> abi{scr_abi + jj, (long)n_states, kAbiWords, status};
+  const TeamChainLds<T> cl = TeamChainLds<T>::at(lds_team, n_max, C, active ? lane : 0);
   if (role == 0) {
-    if (active) split_abi_pass(ch.n, tab, wtab, qs, abi, LdsProgress{&aprog});
+    LdsWait{&pdone, status}(team_waves);
+    if (active) {
+      const int n = ch.n;
+      const auto get = [&](int k) { return cl.pose(n - 1 - k); };  // the k-th transform from the tip
+      split_abi_from_poses<T, decltype(get), NoHandoff, LdsPublish, decltype(tab), !SHARED>(
+          n, tab, cl.abi(status), get, NoHandoff(), LdsPublish{&aprog});
+    }
     return;
   }
-  LdsWait{&p1done, status}(kTeamWaves);
+  LdsWait{&p1done, status}(team_waves);
   if (!active) return;
-  const TeamSlots<T> sc{scr_bias, n_lanes, j * P, (ch.n + P - 1) / P, kTeamIdWords};
-  const Scratch<T> chat{scr_chat + jj, (long)n_states, 1, status};
-  team_zhat_pass(ch.n, wtab, qs, abi, [&](int i) { return tauhat[(long)i * n_states + j]; }, sc, chat,
-                 LdsWait{&aprog, status});
-  team_lambda_pass(ch.n, tab, qs, abi, chat, sc, chat, [&](int i, T v) { qdd_out[ch.dof0 + i] = v; });
+  team_zhat_pass(ch.n, wtab, SPtr<const T>(q + ch.dof0), cl, LdsWait{&aprog, status});
+  team_lambda_pass(ch.n, tab, cl, Scratch<T>{nullptr, 0L, 0, status});
+  T* const out = qdd_out + ch.dof0;
+  for (int i = 0; i < ch.n; ++i) out[i] = cl.chat(i);
 }
 
 // ---- adjoints ------------------------------------------------------------------
@@ -1394,22 +1490,18 @@ int team_lanes(const pdyn_model* m, const pdyn_batch* b, int op = PDYN_OP_RNEA_I
   return P;
 }
 
-// Scratch of the team forward-dynamics kernel, in this order: the team slots of
-// the inverse dynamics (ID+FD only) and of the bias forces ([len][8][n_states * P]
-// each), the articulated terms [n][7][n_states], c-hat [n][n_states], and
-// tau-hat [n][n_states] in double.
+// Global scratch of the team forward-dynamics kernel: the team slots of the
+// inverse dynamics (ID+FD only), then of the bias forces, [len][8][n_states * P]
+// each. The per-chain values of the serial passes live in LDS.
 struct FdTeamLayout {
-  size_t id_off, bias_off, abi_off, chat_off, hat_off, total;
+  size_t id_off, bias_off, total;
 };
 FdTeamLayout fd_team_layout(int op, size_t nm, size_t B, size_t P, size_t scalar) {
   FdTeamLayout t;
   const size_t team = align_up((nm + P - 1) / P * (size_t)kTeamIdWords * B * P * scalar);
   t.id_off = 0;
   t.bias_off = op == PDYN_OP_ID_FD ? team : 0;
-  t.abi_off = t.bias_off + team;
-  t.chat_off = t.abi_off + align_up(nm * (size_t)kAbiWords * B * scalar);
-  t.hat_off = t.chat_off + align_up(nm * B * scalar);
-  t.total = t.hat_off + align_up(nm * B * sizeof(double));
+  t.total = t.bias_off + team;
   return t;
 }
 
@@ -1657,6 +1749,17 @@ __global__ void __launch_bounds__(64) k_status_word(unsigned* word, uint32_t* ou
   else *word = 0u;
 }
 
+// Chains per workgroup of the team forward-dynamics kernel: the most (up to
+// kTeamChains, a power of two) whose per-link values fit in LDS; 0 if not even one.
+int fd_team_chains(int n_max, size_t scalar) {
+  const size_t cap = max_lds_bytes();
+  for (int C = kTeamChains; C >= 1; C /= 2) {
+    const size_t bytes = scalar == 4 ? TeamChainLds<float>::bytes(n_max, C) : TeamChainLds<double>::bytes(n_max, C);
+    if (bytes <= cap) return C;
+  }
+  return 0;
+}
+
 template <class T, int MODE>
 int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, const T* q, const T* qd,
                     const T* qdd_in, const T* tau_in, T* tau_out, T* qdd_out, char* ws, hipStream_t s);
@@ -1751,25 +1854,30 @@ int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, c
     const int P = team_lanes(m, b, MODE == kModeIDFD ? PDYN_OP_ID_FD : PDYN_OP_ABA_FD);
     const size_t nm = (size_t)m->n_links_max, B = (size_t)b->n_states;
     const FdTeamLayout t = fd_team_layout(MODE == kModeIDFD ? PDYN_OP_ID_FD : PDYN_OP_ABA_FD, nm, B, (size_t)P, sizeof(T));
+    const int C = fd_team_chains(m->n_links_max, sizeof(T));
+    if (C < 1) return PDYN_EUNSUPPORTED;
+    const size_t lds = TeamChainLds<T>::bytes(m->n_links_max, C);
     char* sc = reinterpret_cast<char*>(scratch);
     const long n_lanes = (long)b->n_states * P;
-    const unsigned g = (unsigned)((b->n_states + kTeamChains - 1) / kTeamChains);
+    const unsigned g = (unsigned)((b->n_states + C - 1) / C);
+    const unsigned blk = 64u * (unsigned)((C * P + 63) / 64 + 2);
     const T* tip = static_cast<const T*>(b->tip_wrench);
-#define PDYN_LAUNCH_TEAM_FD(PP)                                                                                  \
-  do {                                                                                                           \
-    constexpr unsigned blk = 64u * ((kTeamChains * PP + 63) / 64 + 2);                                           \
-    if (m->n_chains == 1)                                                                                        \
-      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, true>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max,  \
-                         lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,                 \
-                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off),            \
-                         reinterpret_cast<T*>(sc + t.abi_off), reinterpret_cast<T*>(sc + t.chat_off),           \
-                         reinterpret_cast<double*>(sc + t.hat_off), n_lanes, status);                            \
-    else                                                                                                         \
-      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, false>), dim3(g), dim3(blk), 0, s, b->n_states, m->n_links_max, \
-                         lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,                 \
-                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off),            \
-                         reinterpret_cast<T*>(sc + t.abi_off), reinterpret_cast<T*>(sc + t.chat_off),           \
-                         reinterpret_cast<double*>(sc + t.hat_off), n_lanes, status);                            \
+#define PDYN_LAUNCH_TEAM_FD(PP)                                                                                   \
+  do {                                                                                                            \
+    const void* fn = m->n_chains == 1 ? reinterpret_cast<const void*>(&k_fd_team<T, MODE, PP, true>)              \
+                                      : reinterpret_cast<const void*>(&k_fd_team<T, MODE, PP, false>);            \
+    if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) \
+      return PDYN_ELAUNCH;                                                                                        \
+    if (m->n_chains == 1)                                                                                         \
+      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, true>), dim3(g), dim3(blk), lds, s, b->n_states, m->n_links_max, \
+                         C, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,               \
+                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off), n_lanes,    \
+                         status);                                                                                 \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_fd_team<T, MODE, PP, false>), dim3(g), dim3(blk), lds, s, b->n_states, m->n_links_max, \
+                         C, lanes, table, wtable, q, qd, qdd_in, tau_in, tau_out, qdd_out, tip, ba,               \
+                         reinterpret_cast<T*>(sc + t.id_off), reinterpret_cast<T*>(sc + t.bias_off), n_lanes,    \
+                         status);                                                                                 \
   } while (0)
     switch (P) {
       case 1: PDYN_LAUNCH_TEAM_FD(1); break;
@@ -1896,12 +2004,38 @@ int run_jsiia(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd,
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   unsigned grid, block;
   launch_shape(b, &grid, &block);
-  hipLaunchKernelGGL((k_jsiia<T, FD>), dim3(grid), dim3(block), 0, s, b->n_states, m->n_links_max,
-                     reinterpret_cast<const T*>(tbase + L.table_off),
-                     reinterpret_cast<const double*>(tbase + L.wtable_off), q, FD ? qd : nullptr,
-                     FD ? tau : nullptr, FD ? out : nullptr, FD ? nullptr : out,
-                     static_cast<const T*>(b->tip_wrench), ba, reinterpret_cast<double*>(base + L.scratch_off),
-                     status);
+  double* const work = reinterpret_cast<double*>(base + L.scratch_off);
+  const int n = m->n_links_max;
+  // forward dynamics up to 32 links: M and tau-hat here, the solve by a team of lanes per state
+  const bool team = FD && n <= 32;
+#define PDYN_LAUNCH_JSIIA(SOLVE)                                                                                   \
+  hipLaunchKernelGGL((k_jsiia<T, FD, SOLVE>), dim3(grid), dim3(block), 0, s, b->n_states, n,                       \
+                     reinterpret_cast<const T*>(tbase + L.table_off),                                              \
+                     reinterpret_cast<const double*>(tbase + L.wtable_off), q, FD ? qd : nullptr,                  \
+                     FD ? tau : nullptr, FD ? out : nullptr, FD ? nullptr : out,                                   \
+                     static_cast<const T*>(b->tip_wrench), ba, work, status)
+  if (team) PDYN_LAUNCH_JSIIA(false);
+  else PDYN_LAUNCH_JSIIA(true);
+#undef PDYN_LAUNCH_JSIIA
+  if (team) {
+    const int NT = n <= 8 ? 8 : (n <= 16 ? 16 : 32);
+    const long lanes_total = (long)b->n_states * NT;
+    const unsigned g = (unsigned)((lanes_total + 255) / 256);
+    const size_t lds = (size_t)(256 / NT) * NT * NT * sizeof(double);
+#define PDYN_LAUNCH_CHOL(NN)                                                                                       \
+  do {                                                                                                             \
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jsiia_chol<T, NN>),                    \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)    \
+      return PDYN_ELAUNCH;                                                                                         \
+    hipLaunchKernelGGL((k_jsiia_chol<T, NN>), dim3(g), dim3(256), lds, s, b->n_states, n, work, out, status);      \
+  } while (0)
+    switch (NT) {
+      case 8: PDYN_LAUNCH_CHOL(8); break;
+      case 16: PDYN_LAUNCH_CHOL(16); break;
+      default: PDYN_LAUNCH_CHOL(32); break;
+    }
+#undef PDYN_LAUNCH_CHOL
+  }
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }

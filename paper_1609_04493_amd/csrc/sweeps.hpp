@@ -625,15 +625,28 @@ PD_HD void split_pose_bwd(int n, Tab table, WTab wtable, SPtr<const T> q, const 
 // Pass A with the transforms handed in: get(k) is the transform of the k-th
 // link from the tip, as pass A forms it; release(m) reports that the first m
 // of them are used; done(k) as in pass A.
-template <class T, class Get, class Release, class Done, class Tab = const T*>
+// PF: the next link's record is loaded with its transform, one link ahead (for
+// records that come through vector loads, one chain per lane).
+template <class T, class Get, class Release, class Done, class Tab = const T*, bool PF = false>
 PD_HD void split_abi_from_poses(int n, Tab table, const Scratch<T>& abi, const Get& get,
                                 const Release& release, const Done& done) {
+  struct In {
+    Pose<T> gc;
+    Link<T> L;
+  };
   Sym6<T> JA;
   // load(i): the transform of link i's child (link i + 1), none at the tip
   pipelined(
-      n, n - 1, -1, [&](int i) { return i < n - 1 ? get(n - 2 - i) : Pose<T>(); },
-      [&](int i, const Pose<T>& gc) {
-        const Link<T> L = link_at(table, i);
+      n, n - 1, -1,
+      [&](int i) {
+        In x;
+        x.gc = i < n - 1 ? get(n - 2 - i) : Pose<T>();
+        if constexpr (PF) x.L = link_at(table, i);
+        return x;
+      },
+      [&](int i, const In& x) {
+        const Pose<T>& gc = x.gc;
+        const Link<T> L = PF ? x.L : link_at(table, i);
         Sym6<T> Jh = sym6_from_inertia(L.J);
         if (i < n - 1) {
           const Sym6<T> P = congruence_to_parent(gc, JA);

@@ -196,12 +196,35 @@ PD_HD void team_bwd_apply(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& 
 // as the team scans above: the bias forces tau_bias = ID(q, qd, 0) (eq. (5))
 // with the bias wrench scan in double, giving tau-hat = tau - tau_bias per
 // link. The articulated-body recursion (7) is not a linear recursion and stays
-// serial, one lane per chain (split_abi_pass), as do the two recursions of
-// eq. (8) that follow it: z-hat / c-hat tip to base, behind the articulated
-// pass link by link, and lambda / qdd base to tip.
+// serial, one lane per chain, as do the two recursions of eq. (8) that follow
+// it: z-hat / c-hat tip to base, behind the articulated pass link by link,
+// and lambda / qdd base to tip. The team first forms every link transform in
+// parallel (each lane its segment), so that the serial passes form none.
+//
+// The serial passes read and write the per-chain values through `Chain`
+// objects (LDS views in the kernel, arrays in the host build) with:
+//   pose(i) / put_pose(i, g)   f_{i-1,i} formed in double and rounded to T
+//   sc(i, &s, &c) / put_sc     the (sin, cos) of the joint angle, in T
+//   hat(i) / put_hat(i, v)     tau-hat_i, in double
+//   U(i), invD(i)              the articulated terms (written by the A pass)
+//   chat(i) / put_chat(i, v)   c-hat_i, in T; the lambda pass overwrites it with qdd_i
+
+// Pass 0: the transforms of the segment's links (double from the T (sin, cos),
+// rounded to T, as the articulated-body pass uses them) and their (sin, cos).
+template <class T, class Tab, class WTab, class Chain>
+PD_HD void team_pose_pass(Seg sg, Tab tab, WTab wtab, SPtr<const T> q, const Chain& ch) {
+  for (int i = sg.a; i < sg.b; ++i) {
+    const Link<T> L = link_at(tab, i);
+    const Link<double> Lw = link_at(wtab, i);
+    T sn, cs;
+    joint_sincos(L, q[i], &sn, &cs);
+    ch.put_pose(i, cast_pose<T>(joint_transform_wide_sc(Lw, q[i], sn, cs)));
+    ch.put_sc(i, sn, cs);
+  }
+}
 
 // Pass 4 of the bias forces: the wrench recursion over the segment from the
-// true W at its tip end, writing tau-hat_i = tau_i - S_i^T F_i (double).
+// true W at its tip end, handing tau-hat_i = tau_i - S_i^T F_i (double) to hat.
 template <class T, class WTab, class Hat>
 PD_HD void team_bwd_apply_hat(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, Sp<double> W,
                               SPtr<const T> tau, const Hat& hat) {
@@ -214,53 +237,109 @@ PD_HD void team_bwd_apply_hat(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<
   }
 }
 
-// Link i's slot in the team scratch of its chain: member i / len, slot i % len
-// ([slot][words][n_lanes], the team's first lane at team0).
-template <class T> struct TeamSlots {
-  T* base;
-  long n_lanes;
-  long team0;
-  int len, words;
-  PD_HD T& at(int i, int comp) const {
-    const int k = i / len;
-    return base[((long)(i - k * len) * words + comp) * n_lanes + team0 + k];
-  }
-};
-
 // z-hat / c-hat, tip to base (eq. (8), scan operand eq. (18) with reading R3):
 // z-hat_{n} = 0 at the tip; c-hat_i = (tau-hat_i - S_i^T z-hat_i) / D_i;
-// z-hat_{i-1} = X_i^T (z-hat_i + U_i c-hat_i), in double. need(k) is called
-// before the k-th link from the tip reads the articulated terms U_i, 1/D_i.
-template <class T, class WTab, class Hat, class SC, class Need>
-PD_HD void team_zhat_pass(int n, WTab wtab, SPtr<const T> q, const Scratch<T>& abi, const Hat& tauhat, const SC& sc,
-                          const Scratch<T>& chat_out, const Need& need) {
+// z-hat_{i-1} = X_i^T (z-hat_i + U_i c-hat_i), in double, X_i formed in double
+// from the stored (sin, cos). need(k) is called before the k-th link from the
+// tip reads the articulated terms. The next link's record and angle load while
+// the current link computes.
+template <class T, class WTab, class Chain, class Need>
+PD_HD void team_zhat_pass(int n, WTab wtab, SPtr<const T> q, const Chain& ch, const Need& need) {
+  struct In {
+    T q;
+    Link<double> Lw;
+  };
   Sp<double> z = sp_zero<double>();
-  for (int i = n - 1; i >= 0; --i) {
-    need(n - i);
-    const Link<double> Lw = link_at(wtab, i);
-    const Sp<double> U = cast_sp<double>(abi.get(i, 0));
-    const double invD = (double)abi.at(i, 6);
-    const double c = (tauhat(i) - dot(Lw.S, z)) * invD;
-    chat_out.at(i, 0) = (T)c;
-    if (i > 0) z = XT_wrench(joint_transform_wide_sc(Lw, q[i], sc.at(i, 6), sc.at(i, 7)), z + c * U);
-  }
+  pipelined(
+      n, n - 1, -1, [&](int i) { return In{q[i], link_at(wtab, i)}; },
+      [&](int i, const In& x) {
+        need(n - i);
+        const double invD = (double)ch.invD(i);
+        const double c = (ch.hat(i) - dot(x.Lw.S, z)) * invD;
+        ch.put_chat(i, (T)c);
+        if (i > 0) {
+          T sn, cs;
+          ch.sc(i, &sn, &cs);
+          z = XT_wrench(joint_transform_wide_sc(x.Lw, x.q, sn, cs), z + c * cast_sp<double>(ch.U(i)));
+        }
+      });
 }
 
 // lambda / qdd, base to tip (eq. (8), scan operand eq. (19), lambda_0 = 0):
 // a'_i = X_i lambda_{i-1}; qdd_i = c-hat_i - U_i^T a'_i / D_i; lambda_i = a'_i + S_i qdd_i.
-template <class T, class Tab, class SC, class Out>
-PD_HD void team_lambda_pass(int n, Tab tab, SPtr<const T> q, const Scratch<T>& abi, const Scratch<T>& chat,
-                            const SC& sc, const Scratch<T>& flags, const Out& out) {
+// qdd_i replaces c-hat_i in the chain's storage (written out after the pass).
+template <class T, class Tab, class Chain>
+PD_HD void team_lambda_pass(int n, Tab tab, const Chain& ch, const Scratch<T>& flags) {
   Sp<T> lam = sp_zero<T>();
-  for (int i = 0; i < n; ++i) {
-    const Link<T> L = link_at(tab, i);
-    const Pose<T> g = joint_transform_sc(L, q[i], sc.at(i, 6), sc.at(i, 7));
-    const Sp<T> a = X_twist(g, lam);
-    const T qdd = chat.at(i, 0) - dot(abi.get(i, 0), a) * abi.at(i, 6);
-    lam = a + qdd * L.S;
-    flags.check_finite(qdd);
-    out(i, qdd);
-  }
+  pipelined(
+      n, 0, 1, [&](int i) { return link_at(tab, i).S; },
+      [&](int i, const Sp<T>& S) {
+        const Sp<T> a = X_twist(ch.pose(i), lam);
+        const T qdd = ch.chat(i) - dot(ch.U(i), a) * ch.invD(i);
+        lam = a + qdd * S;
+        flags.check_finite(qdd);
+        ch.put_chat(i, qdd);
+      });
 }
+
+// Per-chain storage of the serial passes, [link][word][C] for the C chains of a
+// workgroup (the chain's column c): tau-hat in double, then in T the transform
+// (12 words), (sin, cos), U_i and 1/D_i (7), c-hat.
+template <class T> struct TeamChainLds {
+  static constexpr int kPoseW = 12, kScW = 2;
+  double* hat_base;
+  T* pose_base;
+  T* sc_base;
+  T* abi_base;
+  T* chat_base;
+  int C, c;
+  PD_HD static size_t bytes(int n_max, int C) {
+    return (size_t)n_max * C * (sizeof(double) + (size_t)(kPoseW + kScW + kAbiWords + 1) * sizeof(T));
+  }
+  PD_HD static TeamChainLds at(unsigned char* base, int n_max, int C, int c) {
+    TeamChainLds v;
+    v.hat_base = reinterpret_cast<double*>(base);
+    v.pose_base = reinterpret_cast<T*>(base + (size_t)n_max * C * sizeof(double));
+    v.sc_base = v.pose_base + (size_t)n_max * kPoseW * C;
+    v.abi_base = v.sc_base + (size_t)n_max * kScW * C;
+    v.chat_base = v.abi_base + (size_t)n_max * kAbiWords * C;
+    v.C = C;
+    v.c = c;
+    return v;
+  }
+  PD_HD T* w(T* b, int words, int i, int k) const { return b + ((long)i * words + k) * C + c; }
+  PD_HD void put_pose(int i, const Pose<T>& g) const {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) *w(pose_base, kPoseW, i, k) = g.R.m[k];
+    *w(pose_base, kPoseW, i, 9) = g.p.x;
+    *w(pose_base, kPoseW, i, 10) = g.p.y;
+    *w(pose_base, kPoseW, i, 11) = g.p.z;
+  }
+  PD_HD Pose<T> pose(int i) const {
+    Pose<T> g;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g.R.m[k] = *w(pose_base, kPoseW, i, k);
+    g.p = v3(*w(pose_base, kPoseW, i, 9), *w(pose_base, kPoseW, i, 10), *w(pose_base, kPoseW, i, 11));
+    return g;
+  }
+  PD_HD void put_sc(int i, T s, T c_) const {
+    *w(sc_base, kScW, i, 0) = s;
+    *w(sc_base, kScW, i, 1) = c_;
+  }
+  PD_HD void sc(int i, T* s, T* c_) const {
+    *s = *w(sc_base, kScW, i, 0);
+    *c_ = *w(sc_base, kScW, i, 1);
+  }
+  PD_HD void put_hat(int i, double v) const { hat_base[(long)i * C + c] = v; }
+  PD_HD double hat(int i) const { return hat_base[(long)i * C + c]; }
+  PD_HD Scratch<T> abi(unsigned* status) const { return Scratch<T>{abi_base + c, (long)C, kAbiWords, status}; }
+  PD_HD Sp<T> U(int i) const {
+    return {v3(*w(abi_base, kAbiWords, i, 0), *w(abi_base, kAbiWords, i, 1), *w(abi_base, kAbiWords, i, 2)),
+            v3(*w(abi_base, kAbiWords, i, 3), *w(abi_base, kAbiWords, i, 4), *w(abi_base, kAbiWords, i, 5))};
+  }
+  PD_HD T invD(int i) const { return *w(abi_base, kAbiWords, i, 6); }
+  PD_HD void put_chat(int i, T v) const { chat_base[(long)i * C + c] = v; }
+  PD_HD T chat(int i) const { return chat_base[(long)i * C + c]; }
+};
 
 }  // namespace pdyn

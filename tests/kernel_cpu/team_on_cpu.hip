@@ -81,10 +81,11 @@ static int run_team_id(int P, int n_states, int n_chains, int n_max, const int32
   return 0;
 }
 
-// Forward dynamics as k_fd_team runs it, one state at a time: the bias forces by
-// the team scans (tau-hat per link), the articulated-body pass, then z-hat / c-hat
-// and lambda / qdd; the z-hat and lambda passes read the (sin, cos) through the
-// team-slot view of the kernel (one team, so the team's first lane is 0).
+// Forward dynamics as k_fd_team runs it, one state at a time, with the kernel's
+// per-chain storage (TeamChainLds, here one chain in a host buffer): the team's
+// transforms and (sin, cos), the bias forces by the team scans (tau-hat per
+// link), the articulated-body pass from the stored transforms, then z-hat /
+// c-hat and lambda / qdd.
 template <class T>
 static int run_team_fd(int P, int n_states, int n_chains, int n_max, const int32_t* link_ptr, const T* placement,
                        const T* twist, const T* inertia, const T* q, const T* qd, const T* tau, T* qdd,
@@ -113,13 +114,15 @@ static int run_team_fd(int P, int n_states, int n_chains, int n_max, const int32
     const int slots = (n + P - 1) / P;
     std::vector<T> scratch((size_t)P * (slots > 0 ? slots : 1) * kTeamIdWords, T(-7777));  // poisoned
     auto scr = [&](int k) { return Scratch<T>{scratch.data() + k, (long)P, kTeamIdWords}; };
-    std::vector<double> hat((size_t)n, -7777.0);
+    std::vector<unsigned char> store(TeamChainLds<T>::bytes(n > 0 ? n : 1, 1) + 16, 0xA5);  // poisoned
+    const TeamChainLds<T> cl = TeamChainLds<T>::at(store.data(), n > 0 ? n : 1, 1, 0);
     std::vector<Seg> seg(P);
-    std::vector<FwdOp<T>> agg(P);
     for (int k = 0; k < P; ++k) {
       seg[k] = segment_of(n, P, k);
-      agg[k] = team_fwd_aggregate(seg[k], tab, qs, qds, SPtr<const T>(), bd);
+      team_pose_pass(seg[k], tab, wtab, qs, cl);
     }
+    std::vector<FwdOp<T>> agg(P);
+    for (int k = 0; k < P; ++k) agg[k] = team_fwd_aggregate(seg[k], tab, qs, qds, SPtr<const T>(), bd);
     const auto pre = prefix_exclusive(agg, fwd_identity<T>(), [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); });
     std::vector<BwdOp<double>> bag(P);
     for (int k = 0; k < P; ++k) {
@@ -130,15 +133,14 @@ static int run_team_fd(int P, int n_states, int n_chains, int n_max, const int32
     const auto suf = suffix_exclusive(bag, bwd_identity<double>(), [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); });
     for (int k = 0; k < P; ++k)
       team_bwd_apply_hat(seg[k], wtab, qs, scr(k), bwd_apply(suf[k], cast_sp<double>(bd.Ftip)), taus,
-                         [&](int i, double v) { hat[(size_t)i] = v; });
+                         [&](int i, double v) { cl.put_hat(i, v); });
     unsigned status = 0;
-    std::vector<T> abi_mem((size_t)(n > 0 ? n : 1) * kAbiWords, T(-7777)), chat_mem((size_t)(n > 0 ? n : 1), T(-7777));
-    const Scratch<T> abi{abi_mem.data(), 1L, kAbiWords, &status};
-    const Scratch<T> chat{chat_mem.data(), 1L, 1, &status};
-    split_abi_pass(n, tab, wtab, qs, abi);
-    const TeamSlots<T> sc{scratch.data(), (long)P, 0L, slots, kTeamIdWords};
-    team_zhat_pass(n, wtab, qs, abi, [&](int i) { return hat[(size_t)i]; }, sc, chat, NoHandoff());
-    team_lambda_pass(n, tab, qs, abi, chat, sc, chat, [&](int i, T v) { qdd[dof0 + i] = v; });
+    const auto get = [&](int k) { return cl.pose(n - 1 - k); };
+    split_abi_from_poses<T, decltype(get), NoHandoff, NoHandoff, const T*, true>(n, tab, cl.abi(&status), get,
+                                                                               NoHandoff(), NoHandoff());
+    team_zhat_pass(n, wtab, qs, cl, NoHandoff());
+    team_lambda_pass(n, tab, cl, Scratch<T>{nullptr, 0L, 0, &status});
+    for (int i = 0; i < n; ++i) qdd[dof0 + i] = cl.chat(i);
     if (status) ++faults;
   }
   return faults;

@@ -77,6 +77,29 @@ def test_abia_forward_scan(n, how):
         assert abs(y[6] - at["qdd"][i]) <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_merged_backward_scan(n, how):
+    """Eq. (20): one backward scan of the bias wrench, tau-hat, z-hat and c-hat. After A_{n+1} .. A_i applied
+    to (F_tip, 0, 0, 0, 1) the state is (F_{i-1}, tauhat_i, zhat_i, chat_{i+1}), equal to the serial bias
+    forces (qdd = 0) and to the serial ABIA intermediates."""
+    ch, q, qd, _, tau, V0, dV0, Ft = _setup(n, 500 + n)
+    bt = oracle.rnea_trace(ch, q, qd, np.zeros(n), V0, dV0, Ft)
+    at = oracle.aba_trace(ch, q, qd, tau, V0, dV0, Ft)
+    P = sf.prefix(sf.merged_backward_operands(ch, bt, at, tau), how, np.random.default_rng(n))
+    x = np.concatenate([Ft, np.zeros(8), [1.0]])
+    scale = 1 + np.abs(bt["F"]).max() + np.abs(at["zhat"]).max() + np.abs(at["chat"]).max() + np.abs(tau).max()
+    for k, i in enumerate(range(n + 1, -1, -1)):
+        y = P[k] @ x
+        if 1 <= i - 1 <= n:
+            assert np.abs(y[:6] - bt["F"][i - 1]).max() <= 1e-11 * scale
+        if 1 <= i <= n:
+            assert abs(y[6] - at["tauhat"][i]) <= 1e-11 * scale
+            assert np.abs(y[7:13] - at["zhat"][i]).max() <= 1e-11 * scale
+        if 1 <= i + 1 <= n:
+            assert abs(y[13] - at["chat"][i + 1]) <= 1e-11 * scale
+
+
 def test_omega_not_inverted_breaks_the_backward_scan():
     """The printed Omega_{i+1} (not its inverse) in (18) does not reproduce (8): the reading matters."""
     n = 5
