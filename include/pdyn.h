@@ -184,7 +184,9 @@ enum {
   PDYN_OP_RNEA_ID_VJP = 3,
   PDYN_OP_ABA_FD_VJP = 4,
   PDYN_OP_JSIIA_FD = 5,
-  PDYN_OP_MASS_MATRIX = 6
+  PDYN_OP_MASS_MATRIX = 6,
+  PDYN_OP_RNEA_ID_JACOBIAN = 7,
+  PDYN_OP_ABA_FD_JACOBIAN = 8
 };
 
 /* Bytes of device workspace that operation op needs for this model and batch
@@ -317,6 +319,36 @@ int pdyn_jsiia_fd(const pdyn_model* model, const pdyn_batch* batch, const float*
                   const float* tau, float* qdd, void* workspace, size_t workspace_bytes, void* stream);
 int pdyn_jsiia_fd_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
                       const double* tau, double* qdd, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Full Jacobians of the dynamics of a shared chain (model->n_chains == 1;
+ * PDYN_EUNSUPPORTED otherwise), the paper's stated future work (Sec. VI), each
+ * [n_states][n][n] row-major with J[s][i][k] = d y_i / d x_k for state s:
+ *   pdyn_rnea_id_jacobian: y = tau = ID(q, qd, qdd, ...) (eq. (3)); J_q, J_qd and
+ *     J_qdd = d tau / d qdd = M(q), the joint-space inertia of eq. (17);
+ *   pdyn_aba_fd_jacobian: y = qdd = FD(q, qd, tau, ...) (eq. (4)), taken at the
+ *     forward output `qdd` (pass pdyn_aba_fd's result); J_q, J_qd and
+ *     J_tau = d qdd / d tau = M(q)^-1.
+ * Row i of each is the adjoint (pdyn_rnea_id_vjp / pdyn_aba_fd_vjp) with the
+ * one-hot cotangent e_i: the call expands chunks of states into n rows each in
+ * its workspace and runs the adjoint kernels over them, so J is exactly what n
+ * adjoint calls with e_0 .. e_{n-1} would give. Workspace:
+ * pdyn_workspace_bytes(PDYN_OP_RNEA_ID_JACOBIAN or PDYN_OP_ABA_FD_JACOBIAN, ...)
+ * (at most 2^17 expanded rows per chunk); the batch's launch fields apply to
+ * the adjoint launches, and its status word is the adjoint's.
+ */
+int pdyn_rnea_id_jacobian(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                          const float* qdd, float* J_q, float* J_qd, float* J_qdd, void* workspace,
+                          size_t workspace_bytes, void* stream);
+int pdyn_rnea_id_jacobian_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                              const double* qdd, double* J_q, double* J_qd, double* J_qdd, void* workspace,
+                              size_t workspace_bytes, void* stream);
+int pdyn_aba_fd_jacobian(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                         const float* qdd, float* J_q, float* J_qd, float* J_tau, void* workspace,
+                         size_t workspace_bytes, void* stream);
+int pdyn_aba_fd_jacobian_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                             const double* qdd, double* J_q, double* J_qd, double* J_tau, void* workspace,
+                             size_t workspace_bytes, void* stream);
 
 /*
  * pdyn_id_fd without a workspace argument, for callers that cannot allocate

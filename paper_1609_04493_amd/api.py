@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdyn.so")
 
 OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP, OP_JSIIA_FD, OP_MASS_MATRIX = 0, 1, 2, 3, 4, 5, 6
+OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN = 7, 8
 GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
 ZERO6 = (0.0,) * 6
 
@@ -47,6 +48,7 @@ _ENTRY_ARITY = {
     "pdyn_rnea_id": 4, "pdyn_aba_fd": 4, "pdyn_id_fd": 6,
     "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 8,
     "pdyn_jsiia_fd": 4, "pdyn_mass_matrix": 2,
+    "pdyn_rnea_id_jacobian": 6, "pdyn_aba_fd_jacobian": 6,
 }
 
 
@@ -325,6 +327,32 @@ def jsiia_fd(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip
     qdd = torch.empty_like(q) if out is None else out
     _call("pdyn_jsiia_fd", OP_JSIIA_FD, model, n_states, (q, qd, tau, qdd), base_vel, base_acc, tip, workspace)
     return qdd
+
+
+def _jacobian(name, op, model, q, qd, x3, base_vel, base_acc, tip, out, workspace):
+    n_states = _n_states(model, q)
+    if model.n_chains != 1:
+        raise PdynError(f"{name}: Jacobians need one chain shared by the batch")
+    _prep(model, (q, qd, x3, tip))
+    n = model.n_links_max
+    if out is None:
+        out = tuple(torch.empty((n_states, n, n), dtype=model.dtype, device=model.device) for _ in range(3))
+    _call(name, op, model, n_states, (q, qd, x3) + tuple(out), base_vel, base_acc, tip, workspace)
+    return out
+
+
+def rnea_id_jacobian(model: Model, q, qd, qdd, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None,
+                     workspace=None):
+    """(dtau/dq, dtau/dqd, dtau/dqdd = M), each [B, n, n], by pdyn_rnea_id_jacobian."""
+    return _jacobian("pdyn_rnea_id_jacobian", OP_RNEA_ID_JACOBIAN, model, q, qd, qdd, base_vel, base_acc, tip, out,
+                     workspace)
+
+
+def aba_fd_jacobian(model: Model, q, qd, qdd, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None,
+                    workspace=None):
+    """(dqdd/dq, dqdd/dqd, dqdd/dtau = M^-1), each [B, n, n], at qdd = FD(q, qd, tau), by pdyn_aba_fd_jacobian."""
+    return _jacobian("pdyn_aba_fd_jacobian", OP_ABA_FD_JACOBIAN, model, q, qd, qdd, base_vel, base_acc, tip, out,
+                     workspace)
 
 
 def mass_matrix(model: Model, q, out=None, workspace=None):

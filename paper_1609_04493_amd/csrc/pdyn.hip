@@ -26,6 +26,7 @@
 //                      dynamics by its Cholesky factorisation (jsiia.hpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -840,14 +841,15 @@ __global__ void __launch_bounds__(256) k_jsiia_chol(int n_states, int n, const d
 // C chains (in lane order; C chosen on the host so that their per-link values
 // fit in LDS, at most kTeamChains) and has three kinds of wavefronts:
 //  * team wavefronts, P lanes per chain (team.hpp): first every link transform
-//    of their segments into LDS (then one add to `pdone`); then the bias forces
-//    by the two segmented scans, leaving tau-hat = tau - tau_bias per link in
-//    LDS (then one add to `p1done`); for ID+FD then the inverse dynamics;
+//    of their segments into LDS (then one add to `pdone`); then the velocities
+//    and bias accelerations by the segmented forward scan, leaving the bias
+//    wrench Fhat_i of every link in their global slots (then one add to
+//    `p1done`); for ID+FD then the inverse dynamics;
 //  * A, one lane per chain: the articulated-body recursion (7), serial, from
 //    the transforms in LDS, publishing its progress in `aprog` after each link;
-//  * Z, one lane per chain: once the team is done, z-hat / c-hat tip to base,
-//    each link as soon as A has it, then lambda / qdd base to tip, all out of
-//    LDS; qdd is written out at the end.
+//  * Z, one lane per chain: once the team's Fhat are in, the bias wrench and
+//    z-hat / c-hat tip to base as one recursion (folded eq. (20)), each link as
+//    soon as A has it, then lambda / qdd base to tip; qdd is written out at the end.
 // No workgroup barrier follows the first: waits are one-directional (A waits
 // for the team, Z for the team and A), so every wavefront runs to its end.
 constexpr int kTeamChains = 16;
@@ -893,16 +895,12 @@ __global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, int C,
     const long L = j * P + k;
     const auto fcomb = [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); };
     const auto bcomb = [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); };
-    // the bias forces: qdd = 0
+    // the bias forces (qdd = 0): the forward scan leaves Fhat_bias in the team slots for Z
     {
       const Scratch<T> scr{scr_bias + L, n_lanes, kTeamIdWords, status};
       const FwdOp<T> pre =
           team_prefix_exclusive<P>(team_fwd_aggregate(sg, tab, qs, qds, SPtr<const T>(), bd), k, fwd_identity<T>(), fcomb);
       team_fwd_apply(sg, tab, qs, qds, SPtr<const T>(), k > 0 ? pre.x1 : bd.dV0, k > 0 ? pre.x2 : bd.V0, scr);
-      const BwdOp<double> suf =
-          team_suffix_exclusive<P>(team_bwd_aggregate(sg, wtab, qs, scr), k, bwd_identity<double>(), bcomb);
-      team_bwd_apply_hat(sg, wtab, qs, scr, bwd_apply(suf, cast_sp<double>(bd.Ftip)), SPtr<const T>(tau_in + ch.dof0),
-                         [&](int i, double v) { cl.put_hat(i, v); });
     }
     if (lane == 0) __hip_atomic_fetch_add(&p1done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (MODE & kModeID) {
@@ -938,7 +936,21 @@ __global__ void __launch_bounds__(384) k_fd_team(int n_states, int n_max, int C,
   }
   LdsWait{&p1done, status}(team_waves);
   if (!active) return;
-  team_zhat_pass(ch.n, wtab, SPtr<const T>(q + ch.dof0), cl, LdsWait{&aprog, status});
+  Sp<double> Ftip = sp_zero<double>();
+  if (tip) {
+    const T* tp = tip + 6 * (int64_t)ch.s;
+    Ftip = {v3((double)tp[0], (double)tp[1], (double)tp[2]), v3((double)tp[3], (double)tp[4], (double)tp[5])};
+  }
+  // the team's slot of link i: member i / len, slot i % len, [slot][8][n_lanes] from the chain's first lane
+  const int len = (ch.n + P - 1) / P;
+  const long team0 = j * P;
+  const auto fhat = [&](int i) {
+    const int k = i / len;
+    const T* f = scr_bias + (long)(i - k * len) * kTeamIdWords * n_lanes + team0 + k;
+    return Sp<T>{v3(f[0], f[n_lanes], f[2 * n_lanes]), v3(f[3 * n_lanes], f[4 * n_lanes], f[5 * n_lanes])};
+  };
+  team_bias_zhat_pass(ch.n, wtab, SPtr<const T>(q + ch.dof0), SPtr<const T>(tau_in + ch.dof0), cl, fhat, Ftip,
+                      LdsWait{&aprog, status});
   team_lambda_pass(ch.n, tab, cl, Scratch<T>{nullptr, 0L, 0, status});
   T* const out = qdd_out + ch.dof0;
   for (int i = 0; i < ch.n; ++i) out[i] = cl.chat(i);
@@ -1385,6 +1397,31 @@ __global__ void __launch_bounds__(256) k_euler_step_vjp(int64_t n, T dt, T* __re
   }
   if (pibf)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pi; i += stride) pib[i] += pibf[i];
+}
+
+// ---- Jacobian mode -----------------------------------------------------------------
+//
+// Row j of the Jacobian of y = f(x) is the vector-Jacobian product with the
+// one-hot cotangent e_j. For a chunk of states of a shared chain, row
+// r = s n + j of the expanded batch is a copy of state s with cotangent e_j, so
+// the adjoint kernels, run over the expanded batch, write J[s][j][k] directly
+// ([states][n][n] row-major, like [rows][n]).
+template <class T>
+__global__ void __launch_bounds__(256) k_jac_expand(int64_t rows, int n, const T* q, const T* qd, const T* x3,
+                                                    const T* tip, T* eq, T* eqd, T* ex3, T* ebar, T* etip) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * n; e += stride) {
+    const int64_t r = e / n;
+    const int k = (int)(e % n);
+    const int64_t src = (r / n) * n + k;
+    eq[e] = q[src];
+    eqd[e] = qd[src];
+    ex3[e] = x3[src];
+    ebar[e] = (k == (int)(r % n)) ? T(1) : T(0);
+  }
+  if (tip)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * 6; e += stride)
+      etip[e] = tip[(e / 6) / n * 6 + e % 6];
 }
 
 // ---- host side ------------------------------------------------------------------
@@ -2040,6 +2077,84 @@ int run_jsiia(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd,
   return PDYN_OK;
 }
 
+// Jacobian mode: the workspace holds the adjoint's workspace for one chunk of
+// expanded rows (status word first), then the expanded q, qd, third input and
+// cotangents ([rows][n] each) and tip wrenches ([rows][6]).
+constexpr int64_t kJacRows = 1 << 17;  // rows (state x cotangent) per adjoint launch
+struct JacLayout {
+  int64_t chunk_states;
+  size_t vjp_bytes, q_off, qd_off, x3_off, bar_off, tip_off, total;
+};
+int jac_layout(int vjp_op, const pdyn_model* m, const pdyn_batch* b, size_t scalar, JacLayout* J) {
+  const int64_t n = m->n_links_max;
+  J->chunk_states = std::max<int64_t>(1, std::min<int64_t>(b->n_states, kJacRows / n));
+  pdyn_batch bc = *b;
+  const int64_t rows = J->chunk_states * n;
+  if (rows > INT32_MAX) return PDYN_EUNSUPPORTED;
+  bc.n_states = (int32_t)rows;
+  const pdyn_batch bt = tuned_batch(vjp_op, m, &bc, scalar);
+  Layout L;
+  const int st = layout_for(vjp_op, m, &bt, scalar, &L);
+  if (st) return st;
+  J->vjp_bytes = align_up(L.total);
+  const size_t arr = align_up((size_t)rows * (size_t)n * scalar);
+  J->q_off = J->vjp_bytes;
+  J->qd_off = J->q_off + arr;
+  J->x3_off = J->qd_off + arr;
+  J->bar_off = J->x3_off + arr;
+  J->tip_off = J->bar_off + arr;
+  J->total = J->tip_off + align_up((size_t)rows * 6 * scalar);
+  return PDYN_OK;
+}
+
+template <class T, int OP>
+int run_vjp(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* qdd, const T* bar_in,
+            T* q_bar, T* qd_bar, T* out3, T* inertia_bar, void* ws, size_t ws_bytes, void* stream);
+
+// Full Jacobians of a shared chain's ID (x3 = qdd; J3 = d tau / d qdd = M) or FD
+// (x3 = qdd from FD; J3 = d qdd / d tau = M^-1), [n_states][n][n] each.
+template <class T, int OP>
+int run_jacobian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* x3, T* J1, T* J2,
+                 T* J3, void* ws, size_t ws_bytes, void* stream) {
+  const int vjp_op = OP == kVjpID ? PDYN_OP_RNEA_ID_VJP : PDYN_OP_ABA_FD_VJP;
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, qd, x3, J1, J2, J3}))) return st;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  JacLayout jl;
+  if ((st = jac_layout(vjp_op, m, b, sizeof(T), &jl))) return st;
+  if (ws_bytes < jl.total) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* const base = static_cast<char*>(ws);
+  T* const eq = reinterpret_cast<T*>(base + jl.q_off);
+  T* const eqd = reinterpret_cast<T*>(base + jl.qd_off);
+  T* const ex3 = reinterpret_cast<T*>(base + jl.x3_off);
+  T* const ebar = reinterpret_cast<T*>(base + jl.bar_off);
+  T* const etip = reinterpret_cast<T*>(base + jl.tip_off);
+  const T* tip = static_cast<const T*>(b->tip_wrench);
+  const int64_t n = m->n_links_max;
+  for (int64_t s0 = 0; s0 < b->n_states; s0 += jl.chunk_states) {
+    const int64_t ms = std::min<int64_t>(jl.chunk_states, b->n_states - s0);
+    const int64_t rows = ms * n;
+    const int64_t blocks = std::min<int64_t>((rows * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_jac_expand<T>, dim3((unsigned)blocks), dim3(256), 0, s, rows, (int)n, q + s0 * n,
+                       qd + s0 * n, x3 + s0 * n, tip ? tip + s0 * 6 : nullptr, eq, eqd, ex3, ebar, etip);
+    if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+    pdyn_batch bc = *b;
+    bc.n_states = (int32_t)rows;
+    bc.tip_wrench = tip ? etip : nullptr;
+    const int64_t off = s0 * n * n;
+    if ((st = run_vjp<T, OP>(m, &bc, eq, eqd, ex3, ebar, J1 + off, J2 + off, J3 + off, nullptr, ws, jl.vjp_bytes,
+                             stream)))
+      return st;
+  }
+  return PDYN_OK;
+}
+
 size_t rollout_layout(int with_grad, const pdyn_model* m, const pdyn_batch* b, int every, size_t scalar,
                       size_t* scratch_off, size_t* rows_off, size_t* acc_off) {
   size_t woff;
@@ -2364,6 +2479,14 @@ int pdyn_read_status(void* ws, void* stream, uint32_t* bits) {
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
   if (check_model_batch(model, batch)) return 0;
+  if (op == PDYN_OP_RNEA_ID_JACOBIAN || op == PDYN_OP_ABA_FD_JACOBIAN) {
+    JacLayout jl;
+    if (model->n_chains != 1 ||
+        jac_layout(op == PDYN_OP_RNEA_ID_JACOBIAN ? PDYN_OP_RNEA_ID_VJP : PDYN_OP_ABA_FD_VJP, model, batch,
+                   (size_t)scalar_bytes, &jl))
+      return 0;
+    return jl.total;
+  }
   if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX) return 0;
   const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
@@ -2462,6 +2585,27 @@ int pdyn_id_fd(const pdyn_model* m, const pdyn_batch* b, const float* q, const f
 int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd, const double* qdd_in,
                    const double* tau_in, double* tau_out, double* qdd_out, void* ws, size_t ws_bytes, void* stream) {
   return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
+}
+
+int pdyn_rnea_id_jacobian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
+                          const float* qdd, float* J_q, float* J_qd, float* J_qdd, void* ws, size_t ws_bytes,
+                          void* stream) {
+  return run_jacobian<float, kVjpID>(m, b, q, qd, qdd, J_q, J_qd, J_qdd, ws, ws_bytes, stream);
+}
+int pdyn_rnea_id_jacobian_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                              const double* qdd, double* J_q, double* J_qd, double* J_qdd, void* ws, size_t ws_bytes,
+                              void* stream) {
+  return run_jacobian<double, kVjpID>(m, b, q, qd, qdd, J_q, J_qd, J_qdd, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_jacobian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
+                         const float* qdd, float* J_q, float* J_qd, float* J_tau, void* ws, size_t ws_bytes,
+                         void* stream) {
+  return run_jacobian<float, kVjpFD>(m, b, q, qd, qdd, J_q, J_qd, J_tau, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_jacobian_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                             const double* qdd, double* J_q, double* J_qd, double* J_tau, void* ws, size_t ws_bytes,
+                             void* stream) {
+  return run_jacobian<double, kVjpFD>(m, b, q, qd, qdd, J_q, J_qd, J_tau, ws, ws_bytes, stream);
 }
 
 int pdyn_id_fd_noalloc(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,

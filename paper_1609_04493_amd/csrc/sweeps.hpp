@@ -635,38 +635,41 @@ PD_HD void split_abi_from_poses(int n, Tab table, const Scratch<T>& abi, const G
     Link<T> L;
   };
   Sym6<T> JA;
-  // load(i): the transform of link i's child (link i + 1), none at the tip
-  pipelined(
-      n, n - 1, -1,
-      [&](int i) {
-        In x;
-        x.gc = i < n - 1 ? get(n - 2 - i) : Pose<T>();
-        if constexpr (PF) x.L = link_at(table, i);
-        return x;
-      },
-      [&](int i, const In& x) {
-        const Pose<T>& gc = x.gc;
-        const Link<T> L = PF ? x.L : link_at(table, i);
-        Sym6<T> Jh = sym6_from_inertia(L.J);
-        if (i < n - 1) {
-          const Sym6<T> P = congruence_to_parent(gc, JA);
-          Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
-          Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
+  // load(i): the transform of link i's child (link i + 1), none at the tip; with PF the record too,
+  // requested three links ahead (records that come from memory, not from a cache another pass warmed)
+  const auto load = [&](int i) {
+    In x;
+    x.gc = i < n - 1 ? get(n - 2 - i) : Pose<T>();
+    if constexpr (PF) x.L = link_at(table, i);
+    return x;
+  };
+  const auto body = [&](int i, const In& x) {
+    const Pose<T>& gc = x.gc;
+    const Link<T> L = PF ? x.L : link_at(table, i);
+    Sym6<T> Jh = sym6_from_inertia(L.J);
+    if (i < n - 1) {
+      const Sym6<T> P = congruence_to_parent(gc, JA);
+      Jh.A.xx += P.A.xx; Jh.A.yy += P.A.yy; Jh.A.zz += P.A.zz;
+      Jh.A.xy += P.A.xy; Jh.A.xz += P.A.xz; Jh.A.yz += P.A.yz;
 #pragma unroll
-          for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
-          Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
-          Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
-          release(n - 1 - i);  // transforms 0 .. n-2-i from the tip are used
-        }
-        const Sp<T> U = mul(Jh, L.S);
-        const T D = dot(L.S, U);
-        abi.check_pivot(D);
-        const T invD = T(1) / D;
-        JA = sym6_minus_outer(Jh, U, invD);
-        abi.put(i, 0, U);
-        if (abi.words > 6) abi.at(i, 6) = invD;
-        done(n - i);
-      });
+      for (int k = 0; k < 9; ++k) Jh.B.m[k] += P.B.m[k];
+      Jh.C.xx += P.C.xx; Jh.C.yy += P.C.yy; Jh.C.zz += P.C.zz;
+      Jh.C.xy += P.C.xy; Jh.C.xz += P.C.xz; Jh.C.yz += P.C.yz;
+      release(n - 1 - i);  // transforms 0 .. n-2-i from the tip are used
+    }
+    const Sp<T> U = mul(Jh, L.S);
+    const T D = dot(L.S, U);
+    abi.check_pivot(D);
+    const T invD = T(1) / D;
+    JA = sym6_minus_outer(Jh, U, invD);
+    abi.put(i, 0, U);
+    if (abi.words > 6) abi.at(i, 6) = invD;
+    done(n - i);
+  };
+  if constexpr (PF)
+    pipelined_ahead<4>(n, n - 1, -1, load, body);
+  else
+    pipelined(n, n - 1, -1, load, body);
 }
 
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).

@@ -109,6 +109,16 @@ constexpr int kTeamIdWords = 8;
 // values at its last link; the others start from zero, so x1, x2 are the
 // response of the recursion to a zero start. Either way the aggregate composes
 // correctly with earlier segments (the base enters through the first member).
+// The per-link inputs of the forward passes, loaded one link ahead (pipelined).
+template <class T> struct TeamFwdIn {
+  T q, qd, qdd;
+  Link<T> L;
+};
+template <class T, class Tab>
+PD_HD TeamFwdIn<T> team_fwd_load(Tab tab, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd, int i) {
+  return {q[i], qd[i], qdd ? qdd[i] : T(0), link_at(tab, i)};
+}
+
 template <class T, class Tab>
 PD_HD FwdOp<T> team_fwd_aggregate(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd,
                                   const Boundary<T>& bd) {
@@ -117,19 +127,18 @@ PD_HD FwdOp<T> team_fwd_aggregate(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T
     op.x1 = bd.dV0;
     op.x2 = bd.V0;
   }
-  for (int i = sg.a; i < sg.b; ++i) {
-    const Link<T> L = link_at(tab, i);
-    const T qi = q[i];
-    T sn, cs;
-    joint_sincos(L, qi, &sn, &cs);
-    const Pose<T> g = joint_transform_sc(L, qi, sn, cs);
-    const Sp<T> XV = X_twist(g, op.x2);
-    const Sp<T> Sqd = qd[i] * L.S;
-    const T a = qdd ? qdd[i] : T(0);
-    op.x1 = X_twist(g, op.x1) + a * L.S - ad_twist(Sqd, XV);
-    op.x2 = XV + Sqd;
-    op.F = compose(op.F, g);
-  }
+  pipelined(
+      sg.b - sg.a, sg.a, 1, [&](int i) { return team_fwd_load(tab, q, qd, qdd, i); },
+      [&](int, const TeamFwdIn<T>& x) {
+        T sn, cs;
+        joint_sincos(x.L, x.q, &sn, &cs);
+        const Pose<T> g = joint_transform_sc(x.L, x.q, sn, cs);
+        const Sp<T> XV = X_twist(g, op.x2);
+        const Sp<T> Sqd = x.qd * x.L.S;
+        op.x1 = X_twist(g, op.x1) + x.qdd * x.L.S - ad_twist(Sqd, XV);
+        op.x2 = XV + Sqd;
+        op.F = compose(op.F, g);
+      });
   return op;
 }
 
@@ -140,22 +149,34 @@ PD_HD FwdOp<T> team_fwd_aggregate(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T
 template <class T, class Tab>
 PD_HD void team_fwd_apply(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T> qd, SPtr<const T> qdd, Sp<T> dV, Sp<T> V,
                           const Scratch<T>& scr) {
-  for (int i = sg.a; i < sg.b; ++i) {
-    const int s = i - sg.a;
-    const Link<T> L = link_at(tab, i);
-    const T qi = q[i];
-    T sn, cs;
-    joint_sincos(L, qi, &sn, &cs);
-    const Pose<T> g = joint_transform_sc(L, qi, sn, cs);
-    const Sp<T> XV = X_twist(g, V);
-    const Sp<T> Sqd = qd[i] * L.S;
-    const T a = qdd ? qdd[i] : T(0);
-    V = XV + Sqd;
-    dV = X_twist(g, dV) + a * L.S - ad_twist(Sqd, XV);
-    scr.put(s, 0, mul(L.J, dV) - adT_wrench(V, mul(L.J, V)));
-    scr.at(s, 6) = sn;
-    scr.at(s, 7) = cs;
-  }
+  pipelined(
+      sg.b - sg.a, sg.a, 1, [&](int i) { return team_fwd_load(tab, q, qd, qdd, i); },
+      [&](int i, const TeamFwdIn<T>& x) {
+        const int s = i - sg.a;
+        T sn, cs;
+        joint_sincos(x.L, x.q, &sn, &cs);
+        const Pose<T> g = joint_transform_sc(x.L, x.q, sn, cs);
+        const Sp<T> XV = X_twist(g, V);
+        const Sp<T> Sqd = x.qd * x.L.S;
+        V = XV + Sqd;
+        dV = X_twist(g, dV) + x.qdd * x.L.S - ad_twist(Sqd, XV);
+        scr.put(s, 0, mul(x.L.J, dV) - adT_wrench(V, mul(x.L.J, V)));
+        scr.at(s, 6) = sn;
+        scr.at(s, 7) = cs;
+      });
+}
+
+// The per-link inputs of the backward passes: the double record, the angle and
+// what pass 2 left in the segment's slot.
+template <class T> struct TeamBwdIn {
+  T q, sn, cs;
+  Sp<T> fh;
+  Link<double> Lw;
+};
+template <class T, class WTab>
+PD_HD TeamBwdIn<T> team_bwd_load(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, int i) {
+  const int s = i - sg.a;
+  return {q[i], scr.at(s, 6), scr.at(s, 7), scr.get(s, 0), link_at(wtab, i)};
 }
 
 // Pass 3: the segment's backward operand, tip to base within the segment from
@@ -164,13 +185,13 @@ PD_HD void team_fwd_apply(Seg sg, Tab tab, SPtr<const T> q, SPtr<const T> qd, SP
 template <class T, class WTab>
 PD_HD BwdOp<double> team_bwd_aggregate(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr) {
   BwdOp<double> op = bwd_identity<double>();
-  for (int i = sg.b - 1; i >= sg.a; --i) {
-    const int s = i - sg.a;
-    const Link<double> Lw = link_at(wtab, i);
-    const Pose<double> g = joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7));
-    op.beta = XT_wrench(g, op.beta + cast_sp<double>(scr.get(s, 0)));
-    op.G = compose(g, op.G);
-  }
+  pipelined(
+      sg.b - sg.a, sg.b - 1, -1, [&](int i) { return team_bwd_load(sg, wtab, q, scr, i); },
+      [&](int, const TeamBwdIn<T>& x) {
+        const Pose<double> g = joint_transform_wide_sc(x.Lw, x.q, x.sn, x.cs);
+        op.beta = XT_wrench(g, op.beta + cast_sp<double>(x.fh));
+        op.G = compose(g, op.G);
+      });
   return op;
 }
 
@@ -179,33 +200,33 @@ PD_HD BwdOp<double> team_bwd_aggregate(Seg sg, WTab wtab, SPtr<const T> q, const
 // wrench), with tau_i = S_i^T F_i (eq. (2)).
 template <class T, class WTab>
 PD_HD void team_bwd_apply(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, Sp<double> W, SPtr<T> tau) {
-  for (int i = sg.b - 1; i >= sg.a; --i) {
-    const int s = i - sg.a;
-    const Link<double> Lw = link_at(wtab, i);
-    const Sp<double> F = cast_sp<double>(scr.get(s, 0)) + W;
-    const T t = (T)dot(Lw.S, F);
-    tau[i] = t;
-    scr.check_finite(t);
-    W = XT_wrench(joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7)), F);
-  }
+  pipelined(
+      sg.b - sg.a, sg.b - 1, -1, [&](int i) { return team_bwd_load(sg, wtab, q, scr, i); },
+      [&](int i, const TeamBwdIn<T>& x) {
+        const Sp<double> F = cast_sp<double>(x.fh) + W;
+        const T t = (T)dot(x.Lw.S, F);
+        tau[i] = t;
+        scr.check_finite(t);
+        W = XT_wrench(joint_transform_wide_sc(x.Lw, x.q, x.sn, x.cs), F);
+      });
 }
 
 // ---- forward dynamics with the team scans (Sec. II-B, III-E) ------------------------
 //
-// The linear recursions that do not depend on the articulated-body inertia run
-// as the team scans above: the bias forces tau_bias = ID(q, qd, 0) (eq. (5))
-// with the bias wrench scan in double, giving tau-hat = tau - tau_bias per
+// The linear recursion that does not depend on the articulated-body inertia
+// runs as the team scan above: the velocities and bias accelerations of
+// tau_bias = ID(q, qd, 0) (eq. (5)), giving the bias wrench Fhat_i of every
 // link. The articulated-body recursion (7) is not a linear recursion and stays
-// serial, one lane per chain, as do the two recursions of eq. (8) that follow
-// it: z-hat / c-hat tip to base, behind the articulated pass link by link,
-// and lambda / qdd base to tip. The team first forms every link transform in
-// parallel (each lane its segment), so that the serial passes form none.
+// serial, one lane per chain, as do the recursions that follow it: the bias
+// wrench and z-hat / c-hat tip to base as one recursion, behind the
+// articulated pass link by link, and lambda / qdd base to tip. The team first
+// forms every link transform in parallel (each lane its segment), so that the
+// serial passes form none.
 //
 // The serial passes read and write the per-chain values through `Chain`
 // objects (LDS views in the kernel, arrays in the host build) with:
 //   pose(i) / put_pose(i, g)   f_{i-1,i} formed in double and rounded to T
 //   sc(i, &s, &c) / put_sc     the (sin, cos) of the joint angle, in T
-//   hat(i) / put_hat(i, v)     tau-hat_i, in double
 //   U(i), invD(i)              the articulated terms (written by the A pass)
 //   chat(i) / put_chat(i, v)   c-hat_i, in T; the lambda pass overwrites it with qdd_i
 
@@ -213,55 +234,61 @@ PD_HD void team_bwd_apply(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& 
 // rounded to T, as the articulated-body pass uses them) and their (sin, cos).
 template <class T, class Tab, class WTab, class Chain>
 PD_HD void team_pose_pass(Seg sg, Tab tab, WTab wtab, SPtr<const T> q, const Chain& ch) {
-  for (int i = sg.a; i < sg.b; ++i) {
-    const Link<T> L = link_at(tab, i);
-    const Link<double> Lw = link_at(wtab, i);
-    T sn, cs;
-    joint_sincos(L, q[i], &sn, &cs);
-    ch.put_pose(i, cast_pose<T>(joint_transform_wide_sc(Lw, q[i], sn, cs)));
-    ch.put_sc(i, sn, cs);
-  }
-}
-
-// Pass 4 of the bias forces: the wrench recursion over the segment from the
-// true W at its tip end, handing tau-hat_i = tau_i - S_i^T F_i (double) to hat.
-template <class T, class WTab, class Hat>
-PD_HD void team_bwd_apply_hat(Seg sg, WTab wtab, SPtr<const T> q, const Scratch<T>& scr, Sp<double> W,
-                              SPtr<const T> tau, const Hat& hat) {
-  for (int i = sg.b - 1; i >= sg.a; --i) {
-    const int s = i - sg.a;
-    const Link<double> Lw = link_at(wtab, i);
-    const Sp<double> F = cast_sp<double>(scr.get(s, 0)) + W;
-    hat(i, (double)tau[i] - dot(Lw.S, F));
-    W = XT_wrench(joint_transform_wide_sc(Lw, q[i], scr.at(s, 6), scr.at(s, 7)), F);
-  }
-}
-
-// z-hat / c-hat, tip to base (eq. (8), scan operand eq. (18) with reading R3):
-// z-hat_{n} = 0 at the tip; c-hat_i = (tau-hat_i - S_i^T z-hat_i) / D_i;
-// z-hat_{i-1} = X_i^T (z-hat_i + U_i c-hat_i), in double, X_i formed in double
-// from the stored (sin, cos). need(k) is called before the k-th link from the
-// tip reads the articulated terms. The next link's record and angle load while
-// the current link computes.
-template <class T, class WTab, class Chain, class Need>
-PD_HD void team_zhat_pass(int n, WTab wtab, SPtr<const T> q, const Chain& ch, const Need& need) {
   struct In {
-    T q;
+    T q, k;
     Link<double> Lw;
   };
-  Sp<double> z = sp_zero<double>();
+  // the next link's angle and records load while the current one computes
   pipelined(
-      n, n - 1, -1, [&](int i) { return In{q[i], link_at(wtab, i)}; },
+      sg.b - sg.a, sg.a, 1, [&](int i) { return In{q[i], link_at(tab, i).k, link_at(wtab, i)}; },
       [&](int i, const In& x) {
+        T sn, cs;
+        sin_cos(x.k * x.q, &sn, &cs);  // as joint_sincos
+        ch.put_pose(i, cast_pose<T>(joint_transform_wide_sc(x.Lw, x.q, sn, cs)));
+        ch.put_sc(i, sn, cs);
+      });
+}
+
+// The bias wrench and z-hat / c-hat in one recursion, tip to base, in double:
+// eq. (20) carried folded, as the role-split kernel does. Both the bias wrench
+// F_i = X_{i+1}^T F_{i+1} + Fhat_i (eq. (2) with qdd = 0) and the articulated
+// bias z-hat_i = X_{i+1}^T (z-hat_{i+1} + U_{i+1} c-hat_{i+1}) (eq. (8), reading
+// R3) pass through X_{i+1}^T, so their sum P_i = F_i + z-hat_i + U_i c-hat_i is
+// one recursion: with W_i = X_{i+1}^T P_{i+1} + Fhat_i,
+//   c-hat_i = (tau_i - S_i^T W_i) / D_i     (= (tau-hat_i - S_i^T z-hat_i) / D_i),
+//   P_i = W_i + U_i c-hat_i,
+// started from P = F_{n+1} (the tip wrench, X_{n+1} = I). fhat(i) gives the
+// bias wrench Fhat_i of the team's forward scan; need(k) is called before the
+// k-th link from the tip reads the articulated terms. The next link's record,
+// angle, torque, (sin, cos) and Fhat load while the current one computes.
+template <class T, class WTab, class Chain, class Fhat, class Need>
+PD_HD void team_bias_zhat_pass(int n, WTab wtab, SPtr<const T> q, SPtr<const T> tau, const Chain& ch,
+                               const Fhat& fhat, const Sp<double>& Ftip, const Need& need) {
+  struct In {
+    T q, tau, sn, cs;
+    Sp<T> fh;
+    Link<double> Lw;
+  };
+  Sp<double> P = Ftip;
+  Pose<double> gcw;  // f_{i,i+1}, the child's transform in double
+  pipelined(
+      n, n - 1, -1,
+      [&](int i) {
+        In x;
+        x.q = q[i];
+        x.tau = tau[i];
+        ch.sc(i, &x.sn, &x.cs);
+        x.fh = fhat(i);
+        x.Lw = link_at(wtab, i);
+        return x;
+      },
+      [&](int i, const In& x) {
+        const Sp<double> W = (i < n - 1 ? XT_wrench(gcw, P) : P) + cast_sp<double>(x.fh);
         need(n - i);
-        const double invD = (double)ch.invD(i);
-        const double c = (ch.hat(i) - dot(x.Lw.S, z)) * invD;
+        const double c = ((double)x.tau - dot(x.Lw.S, W)) * (double)ch.invD(i);
         ch.put_chat(i, (T)c);
-        if (i > 0) {
-          T sn, cs;
-          ch.sc(i, &sn, &cs);
-          z = XT_wrench(joint_transform_wide_sc(x.Lw, x.q, sn, cs), z + c * cast_sp<double>(ch.U(i)));
-        }
+        P = W + c * cast_sp<double>(ch.U(i));
+        gcw = joint_transform_wide_sc(x.Lw, x.q, x.sn, x.cs);
       });
 }
 
@@ -270,13 +297,19 @@ PD_HD void team_zhat_pass(int n, WTab wtab, SPtr<const T> q, const Chain& ch, co
 // qdd_i replaces c-hat_i in the chain's storage (written out after the pass).
 template <class T, class Tab, class Chain>
 PD_HD void team_lambda_pass(int n, Tab tab, const Chain& ch, const Scratch<T>& flags) {
+  struct In {
+    Sp<T> S, U;
+    Pose<T> g;
+    T invD, chat;
+  };
   Sp<T> lam = sp_zero<T>();
+  // every input of the next link (its record and its stored values) loads while the current one computes
   pipelined(
-      n, 0, 1, [&](int i) { return link_at(tab, i).S; },
-      [&](int i, const Sp<T>& S) {
-        const Sp<T> a = X_twist(ch.pose(i), lam);
-        const T qdd = ch.chat(i) - dot(ch.U(i), a) * ch.invD(i);
-        lam = a + qdd * S;
+      n, 0, 1, [&](int i) { return In{link_at(tab, i).S, ch.U(i), ch.pose(i), ch.invD(i), ch.chat(i)}; },
+      [&](int i, const In& x) {
+        const Sp<T> a = X_twist(x.g, lam);
+        const T qdd = x.chat - dot(x.U, a) * x.invD;
+        lam = a + qdd * x.S;
         flags.check_finite(qdd);
         ch.put_chat(i, qdd);
       });
@@ -287,19 +320,17 @@ PD_HD void team_lambda_pass(int n, Tab tab, const Chain& ch, const Scratch<T>& f
 // (12 words), (sin, cos), U_i and 1/D_i (7), c-hat.
 template <class T> struct TeamChainLds {
   static constexpr int kPoseW = 12, kScW = 2;
-  double* hat_base;
   T* pose_base;
   T* sc_base;
   T* abi_base;
   T* chat_base;
   int C, c;
   PD_HD static size_t bytes(int n_max, int C) {
-    return (size_t)n_max * C * (sizeof(double) + (size_t)(kPoseW + kScW + kAbiWords + 1) * sizeof(T));
+    return (size_t)n_max * C * (size_t)(kPoseW + kScW + kAbiWords + 1) * sizeof(T);
   }
   PD_HD static TeamChainLds at(unsigned char* base, int n_max, int C, int c) {
     TeamChainLds v;
-    v.hat_base = reinterpret_cast<double*>(base);
-    v.pose_base = reinterpret_cast<T*>(base + (size_t)n_max * C * sizeof(double));
+    v.pose_base = reinterpret_cast<T*>(base);
     v.sc_base = v.pose_base + (size_t)n_max * kPoseW * C;
     v.abi_base = v.sc_base + (size_t)n_max * kScW * C;
     v.chat_base = v.abi_base + (size_t)n_max * kAbiWords * C;
@@ -330,8 +361,6 @@ template <class T> struct TeamChainLds {
     *s = *w(sc_base, kScW, i, 0);
     *c_ = *w(sc_base, kScW, i, 1);
   }
-  PD_HD void put_hat(int i, double v) const { hat_base[(long)i * C + c] = v; }
-  PD_HD double hat(int i) const { return hat_base[(long)i * C + c]; }
   PD_HD Scratch<T> abi(unsigned* status) const { return Scratch<T>{abi_base + c, (long)C, kAbiWords, status}; }
   PD_HD Sp<T> U(int i) const {
     return {v3(*w(abi_base, kAbiWords, i, 0), *w(abi_base, kAbiWords, i, 1), *w(abi_base, kAbiWords, i, 2)),

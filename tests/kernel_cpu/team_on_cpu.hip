@@ -124,21 +124,18 @@ static int run_team_fd(int P, int n_states, int n_chains, int n_max, const int32
     std::vector<FwdOp<T>> agg(P);
     for (int k = 0; k < P; ++k) agg[k] = team_fwd_aggregate(seg[k], tab, qs, qds, SPtr<const T>(), bd);
     const auto pre = prefix_exclusive(agg, fwd_identity<T>(), [](const FwdOp<T>& a, const FwdOp<T>& b) { return fwd_combine(a, b); });
-    std::vector<BwdOp<double>> bag(P);
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < P; ++k)
       team_fwd_apply(seg[k], tab, qs, qds, SPtr<const T>(), k > 0 ? pre[k].x1 : bd.dV0, k > 0 ? pre[k].x2 : bd.V0,
                      scr(k));
-      bag[k] = team_bwd_aggregate(seg[k], wtab, qs, scr(k));
-    }
-    const auto suf = suffix_exclusive(bag, bwd_identity<double>(), [](const BwdOp<double>& a, const BwdOp<double>& b) { return bwd_combine(a, b); });
-    for (int k = 0; k < P; ++k)
-      team_bwd_apply_hat(seg[k], wtab, qs, scr(k), bwd_apply(suf[k], cast_sp<double>(bd.Ftip)), taus,
-                         [&](int i, double v) { cl.put_hat(i, v); });
     unsigned status = 0;
     const auto get = [&](int k) { return cl.pose(n - 1 - k); };
     split_abi_from_poses<T, decltype(get), NoHandoff, NoHandoff, const T*, true>(n, tab, cl.abi(&status), get,
                                                                                NoHandoff(), NoHandoff());
-    team_zhat_pass(n, wtab, qs, cl, NoHandoff());
+    const auto fhat = [&](int i) {
+      const int len = slots, k = i / len;
+      return scr(k).get(i - k * len, 0);
+    };
+    team_bias_zhat_pass(n, wtab, qs, taus, cl, fhat, cast_sp<double>(bd.Ftip), NoHandoff());
     team_lambda_pass(n, tab, cl, Scratch<T>{nullptr, 0L, 0, &status});
     for (int i = 0; i < n; ++i) qdd[dof0 + i] = cl.chat(i);
     if (status) ++faults;

@@ -346,8 +346,8 @@ def test_team_segments_resolve():
 
 def test_team_fd_segments_resolve():
     """Forward dynamics and ID+FD with variant 4: at most 16 lanes per chain by default, and a workspace with
-    the team slots of the bias forces (and, for ID+FD, of the inverse dynamics), the articulated terms, c-hat
-    and tau-hat."""
+    the team slots of the bias forces (and, for ID+FD, of the inverse dynamics); the per-chain values of the
+    serial passes live in LDS."""
     L = api.lib()
     for op in (1, 2):
         for n, P in ((7, 1), (32, 4), (100, 8), (1000, 16)):
@@ -359,7 +359,7 @@ def test_team_fd_segments_resolve():
             assert out[3].value == P, (op, n, out[3].value)
             ws = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), 4)
             team = -(-n // P) * 8 * 100 * P * 4
-            assert ws >= (2 if op == 2 else 1) * team + n * 100 * (7 * 4 + 4 + 8)
+            assert ws >= (2 if op == 2 else 1) * team
 
 
 def test_jsiia_host_rules():
@@ -385,6 +385,33 @@ def test_jsiia_host_rules():
     m2.link_ptr_host = lp.ctypes.data
     b2 = api._batch_struct(2, api.ZERO6, api.GRAVITY_ACC, None)
     assert fn(ctypes.byref(m2), ctypes.byref(b2), p, p, p, p, w, 1 << 20, None) == -5
+
+
+def test_jacobian_host_rules():
+    """The Jacobian entry points: shared chains only, null pointers, workspace size, chunked workspace query."""
+    L = api.lib()
+    fn = L.pdyn_aba_fd_jacobian
+    m, keep = _fake_model(n=5)
+    b = api._batch_struct(100, api.ZERO6, api.GRAVITY_ACC, None)
+    x = np.zeros(8, np.float32)
+    p = x.ctypes.data
+    need = L.pdyn_workspace_bytes(8, ctypes.byref(m), ctypes.byref(b), 4)
+    vjp = L.pdyn_workspace_bytes(4, ctypes.byref(m), ctypes.byref(api._batch_struct(500, api.ZERO6,
+                                                                                      api.GRAVITY_ACC, None)), 4)
+    assert need >= vjp + 4 * 500 * 5 * 4 + 500 * 6 * 4  # the adjoint's workspace for 500 rows + expansions
+    ws = np.zeros(need + 512, np.uint8)
+    w = ws.ctypes.data + ((-ws.ctypes.data) % 256)
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, 0, p, p, p, w, need, None) == -1
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, p, p, w, need - 1, None) == -3
+    lp = np.array([0, 3, 6], np.int32)
+    m2, keep2 = _fake_model(n=6, n_chains=2, link_ptr=lp)
+    m2.n_links_max = 3
+    m2.link_ptr_host = lp.ctypes.data
+    b2 = api._batch_struct(2, api.ZERO6, api.GRAVITY_ACC, None)
+    assert fn(ctypes.byref(m2), ctypes.byref(b2), p, p, p, p, p, p, w, need, None) == -5
+    assert L.pdyn_workspace_bytes(7, ctypes.byref(m2), ctypes.byref(b2), 4) == 0
+    big = api._batch_struct(100000, api.ZERO6, api.GRAVITY_ACC, None)  # chunked: 2^17 / 5 states at a time
+    assert L.pdyn_workspace_bytes(8, ctypes.byref(m), ctypes.byref(big), 4) < 4 * (100000 * 25 * 4)
 
 
 def test_noalloc_rejects_before_device_work():

@@ -348,3 +348,34 @@ def test_autograd_sees_in_place_inertia_updates(device):
     ref = sum(grad.aba_vjp(ch, st.q[s], st.qd[s], st.tau[s], 2 * qdd1[s].detach().cpu().numpy())[3]
               for s in range(16))
     assert rel(g1, ref) <= 1e-10
+
+
+def test_jacobian_entry_points_equal_one_hot_adjoints(device):
+    """pdyn_rnea_id_jacobian / pdyn_aba_fd_jacobian: row i of each Jacobian equals the adjoint with cotangent
+    e_i (FP64, base motion and tip wrenches, a batch that spans several expansion chunks), and the FD tau-block
+    times the ID qdd-block is the identity (M^-1 M = I)."""
+    print("case: jacobian entry points, fp64", flush=True)
+    n, B = 9, 16000  # 2^17 / 9 = 14563 states per chunk: two chunks, the second ragged
+    ch = synth.make_chains([n], 91)
+    st = synth.make_states((B, n), 91)
+    rng = np.random.default_rng(91)
+    V0, dV0, tip = rng.standard_normal(6), rng.standard_normal(6), rng.standard_normal((B, 6))
+    model = api.Model(ch, device, torch.float64)
+    d = lambda a: dev_t(a, device, torch.float64)
+    kw = dict(base_vel=tuple(V0), base_acc=tuple(dV0), tip=d(tip))
+    q, qd, qdd, tau = d(st.q), d(st.qd), d(st.qdd), d(st.tau)
+    Jq, Jqd, M = api.rnea_id_jacobian(model, q, qd, qdd, **kw)
+    qddf = api.aba_fd(model, q, qd, tau, **kw)
+    Fq, Fqd, Minv = api.aba_fd_jacobian(model, q, qd, qddf, **kw)
+    for i in (0, 4, n - 1):
+        e = torch.zeros((B, n), dtype=torch.float64, device=device)
+        e[:, i] = 1.0
+        qb, qdb, qddb, _ = api.rnea_id_vjp(model, q, qd, qdd, e, want_inertia=False, **kw)
+        assert torch.equal(Jq[:, i, :], qb) and torch.equal(Jqd[:, i, :], qdb) and torch.equal(M[:, i, :], qddb)
+        fb, fdb, tb, _ = api.aba_fd_vjp(model, q, qd, qddf, e, want_inertia=False, **kw)
+        assert torch.equal(Fq[:, i, :], fb) and torch.equal(Fqd[:, i, :], fdb) and torch.equal(Minv[:, i, :], tb)
+    eye = torch.eye(n, dtype=torch.float64, device=device).expand(B, n, n)
+    assert (torch.bmm(Minv.contiguous(), M.contiguous()) - eye).abs().max().item() <= 1e-9
+    s = 15000  # a state of the second chunk against the oracle's eq. (17) matrix
+    ref = oracle.mass_matrix(ch, st.q[s])
+    assert np.abs(M[s].cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
