@@ -53,6 +53,8 @@ def _declare(L):
     L.or_mass_matrix_d.argtypes = [c_int, vp, vp, vp, vp, vp]
     for name in ("or_rollout_d", "or_rollout_z"):
         getattr(L, name).argtypes = [c_int, vp, vp, vp, c_int, c_double] + [vp] * 7
+    L.or_rnea_hessian_d.argtypes = [c_int] + [vp] * 9 + [c_int, vp]
+    L.or_rnea_hessian_d.restype = None
     L.or_rnea_trace_d.argtypes = [c_int] + [vp] * 15
     L.or_aba_trace_d.argtypes = [c_int] + [vp] * 18
     for name in ("or_rnea_batch_d", "or_aba_batch_d"):

@@ -10,6 +10,11 @@ adjoint kernels must reproduce are assembled column by column here:
   ID:  tau = ID(q, qd, qdd; pi)       VJP: (q_bar, qd_bar, qdd_bar, pi_bar) = J^T tau_bar
   FD:  qdd = FD(q, qd, tau; pi)       VJP: (q_bar, qd_bar, tau_bar, pi_bar) = J^T qdd_bar
 
+Second derivatives of the inverse dynamics use the multicomplex step
+(Lantoine, Russell & Dargent 2012; bicomplex arithmetic in multicomplex.hpp):
+the i1 i2 part of ID(x + i1 h e_j, y + i2 h e_k) / h^2 is d^2 tau / dx_j dy_k
+exactly to rounding.
+
 pi are the inertia parameters of every link, [n, 10] in the order
 (m, c_x, c_y, c_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz); an off-diagonal
 moment fills both symmetric slots of I_c, so its derivative covers both.
@@ -65,6 +70,25 @@ def rnea_jacobians(ch, q, qd, qdd, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
     Ftip is the wrench F_{n+1} on the last link (eq. (2)), held fixed."""
     f = lambda c, a, b, d: rnea1(c, a, b, d, V0, dV0, Ftip)
     return {k: _jac(f, (q, qd, qdd), w, ch) for k, w in (("q", 0), ("qd", 1), ("qdd", 2), ("pi", "pi"))}
+
+
+HESSIAN_BLOCKS = ("q_q", "q_qd", "qd_qd", "q_qdd")
+
+
+def rnea_hessian(ch, q, qd, qdd, block, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):
+    """One block of the second derivatives of tau = ID(q, qd, qdd) at one state, [n, n, n]:
+    H[i, j, k] = d^2 tau_i / (dx_j dy_k) with (x, y) named by block ("q_q", "q_qd", "qd_qd" or "q_qdd";
+    tau is linear in qdd, so no other block is nonzero). Ftip is held fixed."""
+    from . import _f64, _p, _single_chain, lib
+    n = _single_chain(ch)
+    b = HESSIAN_BLOCKS.index(block)
+    pl, tw, ine = (_f64(x) for x in (ch.placement, ch.twist, ch.inertia))
+    q, qd, qdd, V0, dV0 = (_f64(x) for x in (q, qd, qdd, V0, dV0))
+    Ft = None if Ftip is None else _f64(Ftip)
+    out = np.zeros((n, n, n))
+    lib().or_rnea_hessian_d(n, _p(pl), _p(tw), _p(ine), _p(q), _p(qd), _p(qdd), _p(V0), _p(dV0),
+                            None if Ft is None else _p(Ft), b, _p(out))
+    return out
 
 
 def aba_jacobians(ch, q, qd, tau, V0=ZERO6, dV0=GRAVITY_ACC, Ftip=None):

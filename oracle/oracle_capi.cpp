@@ -9,6 +9,7 @@
 // n_chains == 1 every state uses chain 0 and state s owns dofs [s n, (s+1) n);
 // with n_chains == n_states state s uses chain s and owns dofs
 // [link_ptr[s], link_ptr[s+1]). Ftip is [n_states][6] or NULL (zero).
+#include "multicomplex.hpp"
 #include "oracle.hpp"
 
 #include <complex>
@@ -98,6 +99,15 @@ void or_rollout_z(int n, const cplx* placement, const cplx* twist, const cplx* i
                   double dt, const cplx* q0, const cplx* qd0, const cplx* tau_seq, const cplx* V0,
                   const cplx* dV0, cplx* qT, cplx* qdT) {
   rollout(make_chain(n, placement, twist, inertia), steps, cplx(dt), q0, qd0, tau_seq, V0, dV0, qT, qdT);
+}
+
+// One block of the second derivatives of tau = ID(q, qd, qdd): H [n][n][n],
+// H[i][j][k] = d^2 tau_i / (dx_j dy_k) with (x, y) = (q, q), (q, qd), (qd, qd),
+// (q, qdd) for block 0..3 (multicomplex step, multicomplex.hpp).
+void or_rnea_hessian_d(int n, const double* placement, const double* twist, const double* inertia,
+                       const double* q, const double* qd, const double* qdd, const double* V0,
+                       const double* dV0, const double* Ftip, int block, double* H) {
+  rnea_hessian_block(make_chain(n, placement, twist, inertia), q, qd, qdd, V0, dV0, Ftip, block, H);
 }
 
 // Intermediates of one RNEA call. f: [n+1][12] (R row-major, p) with f[i] =

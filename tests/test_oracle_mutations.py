@@ -39,6 +39,13 @@ MUTANTS = {
         "v6_scale(Pi[i + 1], tauhat[i + 1]));", "v6_scale(Pi[i + 1], tauhat[i]));"),
     "explicit instead of semi-implicit Euler": ("oracle.hpp",
         "q[i] = q[i] + dt * qd[i];", "q[i] = q[i] + dt * (qd[i] - dt * qdd[i]);"),
+    "bicomplex product cross-term sign": ("multicomplex.hpp",
+        "x.a * y.b + x.b * y.a};", "x.a * y.b - x.b * y.a};"),
+    "bicomplex sine: sin instead of cos in the i2 part": ("multicomplex.hpp",
+        "return {std::sin(z.a) * std::cosh(z.b), std::cos(z.a) * std::sinh(z.b)};",
+        "return {std::sin(z.a) * std::cosh(z.b), std::sin(z.a) * std::sinh(z.b)};"),
+    "Hessian (q, qd) block seeds qdd": ("multicomplex.hpp",
+        "(block == 1 || block == 2) ? 1 : 2;", "(block == 2) ? 1 : 2;"),
     "gravity sign": ("__init__.py",
         "GRAVITY_ACC = np.array([0.0, 0.0, 9.81, 0.0, 0.0, 0.0])", "GRAVITY_ACC = np.array([0.0, 0.0, -9.81, 0.0, 0.0, 0.0])"),
 }
@@ -59,6 +66,7 @@ def test_pins_catch_mutant(name, tmp_path):
     path.write_text(src.replace(old, new))
     env = dict(os.environ, PYTHONPATH=f"{dst}{os.pathsep}{ROOT}")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
-                        "tests/test_oracle_pins.py", "tests/test_scan_form.py", "tests/test_oracle_grad.py"],
+                        "tests/test_oracle_pins.py", "tests/test_scan_form.py", "tests/test_oracle_grad.py",
+                        "tests/test_oracle_hessian.py"],
                        cwd=dst, env=env, capture_output=True, text=True, timeout=600)
     assert "failed" in r.stdout, f"no pin failed for mutant '{name}':\n{r.stdout[-2000:]}\n{r.stderr[-2000:]}"
