@@ -40,6 +40,16 @@ FLOPS_PER_LINK = {"id": 433, "fd": 1045, "id_fd": 1212, "id_vjp": 1076, "fd_vjp"
 # dynamics, and the bias wrench (48), torque (11), tau-hat (1) and z-hat / c-hat (67) of forward dynamics.
 FLOPS_PER_LINK_FP64 = {"id": 59, "fd": 127, "id_fd": 186}
 BYTES_PER_LINK = {"id": 16, "fd": 16, "id_fd": 24}  # joint inputs + outputs, FP32
+# One thread of the second-derivative kernel (one state, block, j, k) runs the
+# recursions on hyper-dual numbers; its additions and multiplications as written,
+# counted on a counting scalar by the host build of the same code, are
+# 2416 for one link and 4512 per further link (two sin/cos pairs per link aside).
+
+
+def hessian_thread_flops(n: int) -> int:
+    return 4512 * n - 2096
+
+
 PEAK_FP32_VECTOR = 157.3e12  # published MI355X FP32 vector rate
 PEAK_FP64_VECTOR = 78.6e12   # published MI355X FP64 vector rate (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
 PEAK_VALU_FLOPS = PEAK_FP32_VECTOR  # the denominator of the per-operation fractions
@@ -299,6 +309,36 @@ def bench_jsiia(args, dev):
         print(f"jsiia vs aba, {n} links: {rows[f'{n}_links']}", file=sys.stderr, flush=True)
     rows["note"] = ("JSIIA computes in double after the joint angles' (sin, cos): forming and factoring M "
                     "amplify rounding by its condition number; the articulated-body path stays FP32 in bulk")
+    return rows
+
+
+def bench_hessian(args, dev):
+    """All four second-derivative blocks of the inverse dynamics of the 32-link chain (1024 states) and of a
+    10-link chain (16384 states), FP32 and FP64, by pdyn_rnea_id_hessian."""
+    import torch
+    from paper_1609_04493_amd import api, synth
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    for n, B in ((32, 1024), (10, N_STATES)):
+        ch = synth.make_chains([n], synth.config_seed(2))
+        st = synth.make_states((B, n), synth.config_seed(2))
+        for dt, peak in ((torch.float32, PEAK_FP32_VECTOR), (torch.float64, PEAK_FP64_VECTOR)):
+            model = api.Model(ch, dev, dt)
+            q, qd, qdd = (torch.as_tensor(a, dtype=dt).to(dev) for a in (st.q, st.qd, st.qdd))
+            out = {b: torch.empty((B, n, n, n), dtype=dt, device=dev) for b in api.HESSIAN_BLOCKS}
+            ws = api.Workspace()
+            ms = time_windows(lambda: api.rnea_id_hessian(model, q, qd, qdd, out=out, workspace=ws), stream)["median_ms"]
+            threads = 4 * B * n * n
+            tflops = threads * hessian_thread_flops(n) / (ms * 1e-3) / 1e12
+            name = "f32" if dt == torch.float32 else "f64"
+            rows[f"{n}_links_{B}_states_{name}"] = {
+                "ms": ms, "state_hessians_per_s": B / (ms * 1e-3), "entries_per_s": 4 * B * n ** 3 / (ms * 1e-3),
+                "output_bytes": 4 * B * n ** 3 * out["q_q"].element_size(),
+                "achieved_tflops": tflops, "peak_tflops": peak / 1e12, "frac": tflops * 1e12 / peak}
+            del out
+        print(f"hessian, {n} links: {rows}", file=sys.stderr, flush=True)
+    rows["note"] = ("one thread per (state, block, j, k): forward and reversed-forward hyper-dual passes, "
+                    f"{hessian_thread_flops(32)} flops per thread at 32 links; bound by vector ALU")
     return rows
 
 
@@ -593,7 +633,8 @@ def main():
     if not args.no_other_workloads:
         others = {}
         for name, fn in (("uneven_4096_chains", bench_uneven), ("jsiia_vs_aba", bench_jsiia),
-                         ("fd_grad_50_links", bench_fd_grad_50), ("rollout_grad_100_links", bench_rollout_100)):
+                         ("fd_grad_50_links", bench_fd_grad_50), ("rollout_grad_100_links", bench_rollout_100),
+                         ("id_hessian", bench_hessian)):
             others[name] = fn(args, dev)
             print(f"{name}: {json.dumps(others[name])}", file=sys.stderr, flush=True)
         out["other_workloads"] = others

@@ -186,7 +186,8 @@ enum {
   PDYN_OP_JSIIA_FD = 5,
   PDYN_OP_MASS_MATRIX = 6,
   PDYN_OP_RNEA_ID_JACOBIAN = 7,
-  PDYN_OP_ABA_FD_JACOBIAN = 8
+  PDYN_OP_ABA_FD_JACOBIAN = 8,
+  PDYN_OP_RNEA_ID_HESSIAN = 9
 };
 
 /* Bytes of device workspace that operation op needs for this model and batch
@@ -349,6 +350,30 @@ int pdyn_aba_fd_jacobian(const pdyn_model* model, const pdyn_batch* batch, const
 int pdyn_aba_fd_jacobian_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
                              const double* qdd, double* J_q, double* J_qd, double* J_tau, void* workspace,
                              size_t workspace_bytes, void* stream);
+
+/*
+ * Second derivatives of the inverse dynamics tau = ID(q, qd, qdd, ...) (eqs.
+ * (1)-(3)) of a shared chain (model->n_chains == 1; PDYN_EUNSUPPORTED
+ * otherwise), the Hessians that Sec. VI names as future work. Four blocks,
+ * each [n_states][n][n][n] row-major:
+ *   H_qq[s][i][j][k]   = d^2 tau_i / dq_j dq_k     (symmetric in j, k)
+ *   H_qqd[s][i][j][k]  = d^2 tau_i / dq_j dqd_k
+ *   H_qdqd[s][i][j][k] = d^2 tau_i / dqd_j dqd_k   (symmetric in j, k; no qd or qdd dependence)
+ *   H_qqdd[s][i][j][k] = d^2 tau_i / dq_j dqdd_k = dM_ik / dq_j
+ * (tau is linear in qdd, so no other block is nonzero). Any output may be NULL
+ * and is then not computed; at least one must be given (PDYN_EINVAL). Base
+ * motion and the tip wrench (held fixed) come from the batch. Exact up to
+ * rounding: the recursions run on hyper-dual numbers, one thread per (state,
+ * block, j, k). A non-finite entry sets PDYN_STATUS_NONFINITE in the
+ * workspace's status word. Workspace: pdyn_workspace_bytes(PDYN_OP_RNEA_ID_HESSIAN,
+ * ...); the batch's launch fields are ignored.
+ */
+int pdyn_rnea_id_hessian(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                         const float* qdd, float* H_qq, float* H_qqd, float* H_qdqd, float* H_qqdd, void* workspace,
+                         size_t workspace_bytes, void* stream);
+int pdyn_rnea_id_hessian_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                             const double* qdd, double* H_qq, double* H_qqd, double* H_qdqd, double* H_qqdd,
+                             void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * pdyn_id_fd without a workspace argument, for callers that cannot allocate

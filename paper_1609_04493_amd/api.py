@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdyn.so")
 
 OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP, OP_JSIIA_FD, OP_MASS_MATRIX = 0, 1, 2, 3, 4, 5, 6
-OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN = 7, 8
+OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN, OP_RNEA_ID_HESSIAN = 7, 8, 9
 GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
 ZERO6 = (0.0,) * 6
 
@@ -49,6 +49,7 @@ _ENTRY_ARITY = {
     "pdyn_rnea_id_vjp": 8, "pdyn_aba_fd_vjp": 8,
     "pdyn_jsiia_fd": 4, "pdyn_mass_matrix": 2,
     "pdyn_rnea_id_jacobian": 6, "pdyn_aba_fd_jacobian": 6,
+    "pdyn_rnea_id_hessian": 7,
 }
 
 
@@ -353,6 +354,31 @@ def aba_fd_jacobian(model: Model, q, qd, qdd, base_vel=ZERO6, base_acc=GRAVITY_A
     """(dqdd/dq, dqdd/dqd, dqdd/dtau = M^-1), each [B, n, n], at qdd = FD(q, qd, tau), by pdyn_aba_fd_jacobian."""
     return _jacobian("pdyn_aba_fd_jacobian", OP_ABA_FD_JACOBIAN, model, q, qd, qdd, base_vel, base_acc, tip, out,
                      workspace)
+
+
+HESSIAN_BLOCKS = ("q_q", "q_qd", "qd_qd", "q_qdd")
+
+
+def rnea_id_hessian(model: Model, q, qd, qdd, blocks=HESSIAN_BLOCKS, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None,
+                    out=None, workspace=None):
+    """Second derivatives of tau = ID(q, qd, qdd) by pdyn_rnea_id_hessian: a dict block -> [B, n, n, n] with
+    H[s, i, j, k] = d^2 tau_i / dx_j dy_k for the requested blocks (x, y) in ("q_q", "q_qd", "qd_qd", "q_qdd");
+    `out` may give the tensors for some blocks."""
+    n_states = _n_states(model, q)
+    if model.n_chains != 1:
+        raise PdynError("pdyn_rnea_id_hessian: Hessians need one chain shared by the batch")
+    if not blocks or any(b not in HESSIAN_BLOCKS for b in blocks):
+        raise PdynError(f"pdyn_rnea_id_hessian: blocks must be a non-empty subset of {HESSIAN_BLOCKS}")
+    _prep(model, (q, qd, qdd, tip))
+    n = model.n_links_max
+    res = dict(out or {})
+    for b in blocks:
+        if b not in res:
+            res[b] = torch.empty((n_states, n, n, n), dtype=model.dtype, device=model.device)
+    ptrs = tuple(res.get(b) if b in blocks else None for b in HESSIAN_BLOCKS)
+    _call("pdyn_rnea_id_hessian", OP_RNEA_ID_HESSIAN, model, n_states, (q, qd, qdd) + ptrs, base_vel, base_acc, tip,
+          workspace)
+    return {b: res[b] for b in blocks}
 
 
 def mass_matrix(model: Model, q, out=None, workspace=None):

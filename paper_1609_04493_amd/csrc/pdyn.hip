@@ -37,6 +37,7 @@
 #include <vector>
 
 #include "../../include/pdyn.h"
+#include "hessian.hpp"
 #include "jsiia.hpp"
 #include "sweeps.hpp"
 #include "team.hpp"
@@ -2077,6 +2078,11 @@ int run_jsiia(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd,
   return PDYN_OK;
 }
 
+// Second-derivative mode: the status word, then the link tables unless the model is prepared.
+size_t hessian_ws_bytes(const pdyn_model* m, size_t scalar) {
+  return kStatusBytes + (m->prepared ? 0 : tables_bytes(m, scalar, nullptr));
+}
+
 // Jacobian mode: the workspace holds the adjoint's workspace for one chunk of
 // expanded rows (status word first), then the expanded q, qd, third input and
 // cotangents ([rows][n] each) and tip wrenches ([rows][6]).
@@ -2152,6 +2158,82 @@ int run_jacobian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* 
                              stream)))
       return st;
   }
+  return PDYN_OK;
+}
+
+// Second derivatives of a shared chain's inverse dynamics: one thread per
+// (state, requested block, j, k); the e1e2 parts of tau_0..tau_{n-1} go to
+// H_b[s][i][j][k], so for each i the threads of a wavefront (k fastest) write
+// consecutive words.
+template <class T> struct HessOut {
+  T* p[4];     // output of each requested block, in request order
+  int blk[4];  // its block code (0 (q,q), 1 (q,qd), 2 (qd,qd), 3 (q,qdd))
+  int nb;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_id_hessian(int64_t n_states, int n, const T* table, const T* q,
+                                                    const T* qd, const T* qdd, BoundaryArgs<T> ba, const T* tip,
+                                                    HessOut<T> ho, unsigned* status) {
+  const int64_t nn = (int64_t)n * n, per = (int64_t)ho.nb * nn, total = n_states * per;
+  const Sp<T> V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
+  const Sp<T> dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = t / per, r = t - s * per;
+    const int bi = (int)(r / nn), jk = (int)(r - (int64_t)bi * nn);
+    const int j = jk / n, k = jk - j * n;
+    Sp<T> F;
+    if (tip) {
+      const T* f = tip + 6 * s;
+      F = {v3(f[0], f[1], f[2]), v3(f[3], f[4], f[5])};
+    }
+    T* const H = ho.p[bi] + s * nn * n + jk;
+    bool finite = true;
+    id_hessian_one<T>(n, table, q + s * n, qd + s * n, qdd + s * n, V0, dV0, tip ? &F : nullptr, ho.blk[bi], j, k,
+                      [&](int i, T v) {
+                        H[(int64_t)i * nn] = v;
+                        finite = finite && isfinite(v);
+                      });
+    if (!finite) atomicOr(status, PDYN_STATUS_NONFINITE);
+  }
+}
+
+template <class T>
+int run_id_hessian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* qdd, T* H_qq,
+                   T* H_qqd, T* H_qdqd, T* H_qqdd, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
+  HessOut<T> ho{};
+  T* const outs[4] = {H_qq, H_qqd, H_qdqd, H_qqdd};
+  for (int k = 0; k < 4; ++k)
+    if (outs[k]) {
+      if (!aligned(outs[k], sizeof(T))) return PDYN_EALIGN;
+      ho.p[ho.nb] = outs[k];
+      ho.blk[ho.nb++] = k;
+    }
+  if (ho.nb == 0) return PDYN_EINVAL;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, qd, qdd, m->placement, m->twist, m->inertia}))) return st;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  if (ws_bytes < hessian_ws_bytes(m, sizeof(T))) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned* status = static_cast<unsigned*>(ws);
+  char* base = static_cast<char*>(ws) + kStatusBytes;
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const int64_t n = m->n_links_max;
+  const int64_t total = (int64_t)b->n_states * ho.nb * n * n;
+  const int64_t grid = std::min<int64_t>((total + 255) / 256, int64_t(1) << 16);
+  hipLaunchKernelGGL(k_id_hessian<T>, dim3((unsigned)grid), dim3(256), 0, s, (int64_t)b->n_states, (int)n,
+                     reinterpret_cast<const T*>(tbase), q, qd, qdd, ba, static_cast<const T*>(b->tip_wrench), ho,
+                     status);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
 
@@ -2487,6 +2569,7 @@ size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* b
       return 0;
     return jl.total;
   }
+  if (op == PDYN_OP_RNEA_ID_HESSIAN) return model->n_chains == 1 ? hessian_ws_bytes(model, (size_t)scalar_bytes) : 0;
   if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX) return 0;
   const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
@@ -2587,6 +2670,16 @@ int pdyn_id_fd_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, co
   return run_dynamics<double, kModeIDFD>(PDYN_OP_ID_FD, m, b, q, qd, qdd_in, tau_in, tau_out, qdd_out, ws, ws_bytes, stream);
 }
 
+int pdyn_rnea_id_hessian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
+                         const float* qdd, float* H_qq, float* H_qqd, float* H_qdqd, float* H_qqdd, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return run_id_hessian<float>(m, b, q, qd, qdd, H_qq, H_qqd, H_qdqd, H_qqdd, ws, ws_bytes, stream);
+}
+int pdyn_rnea_id_hessian_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                             const double* qdd, double* H_qq, double* H_qqd, double* H_qdqd, double* H_qqdd,
+                             void* ws, size_t ws_bytes, void* stream) {
+  return run_id_hessian<double>(m, b, q, qd, qdd, H_qq, H_qqd, H_qdqd, H_qqdd, ws, ws_bytes, stream);
+}
 int pdyn_rnea_id_jacobian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
                           const float* qdd, float* J_q, float* J_qd, float* J_qdd, void* ws, size_t ws_bytes,
                           void* stream) {

@@ -9,6 +9,9 @@ M(q) (eq. (17)).
 
 Shapes (shared chain, B states, n links): inputs [B, n]; each Jacobian
 [B, n, n] with J[b, j, k] = d y_j / d x_k for state b.
+
+Second derivatives of the inverse dynamics (pdyn_rnea_id_hessian) come as
+blocks [B, n, n, n], H[b, i, j, k] = d^2 tau_i / dx_j dy_k.
 """
 
 from __future__ import annotations
@@ -26,3 +29,9 @@ def fd_jacobians(model: api.Model, q, qd, tau, qdd=None, workspace=None, **kw):
 def id_jacobians(model: api.Model, q, qd, qdd, workspace=None, **kw):
     """(dtau/dq, dtau/dqd, dtau/dqdd = M), each [B, n, n], for tau = ID(q, qd, qdd)."""
     return api.rnea_id_jacobian(model, q, qd, qdd, workspace=workspace, **kw)
+
+
+def id_hessians(model: api.Model, q, qd, qdd, blocks=api.HESSIAN_BLOCKS, workspace=None, **kw):
+    """{block: [B, n, n, n]} second derivatives of tau = ID(q, qd, qdd) for blocks among
+    ("q_q", "q_qd", "qd_qd", "q_qdd"); d^2 tau / dqdd^2 and d^2 tau / dqd dqdd are zero."""
+    return api.rnea_id_hessian(model, q, qd, qdd, blocks=blocks, workspace=workspace, **kw)

@@ -19,7 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 SAN = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined", "-shared-libasan"]
 TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_grad.py", "tests/test_kernel_math_cpu.py",
-         "tests/test_team_cpu.py", "tests/test_jsiia_cpu.py"]
+         "tests/test_team_cpu.py", "tests/test_jsiia_cpu.py", "tests/test_oracle_hessian.py",
+         "tests/test_hessian_cpu.py"]
 
 
 def _runtime():
