@@ -27,6 +27,17 @@ Operands (1-based links, n links):
        as the inverse.)
   (19) ABIA forward, 8x8, on (lambda_{i-1}, qdd_{i-1}, 1) -> (lambda_i, qdd_i, 1):
        A_i = [[Y_{i-1,i}^T, 0, S_i chat_i], [-Pi_{i-1,i}^T, 0, chat_i], [0, 0, 1]], i = 1..n.
+  (15) forward velocity, acceleration and bias wrench as one, 28x28, on (dV, Q, V, Fhat, 1) with
+       Q = (w x v, w1^2, w1 w2, w1 w3, w2^2, w2 w3, w3^2) for V = (v, w). The paper gives only the
+       block pattern; the blocks follow from w_i = a + s_w u, v_i = b + s_v u (u = qd_i,
+       (b, a) = X_i V_{i-1}, S_i = (s_v, s_w)):
+         w_i w_i^T = R^T W R + u (a s_w^T + s_w a^T) + u^2 s_w s_w^T          (W = w_{i-1} w_{i-1}^T)
+         w_i x v_i = R^T (w x v) - R^T ((tr W) p - W p) + u (a x s_v + s_w x b) + u^2 s_w x s_v
+       (X_i = Ad_{f^-1}, f = f_{i-1,i} = (R, p)), and, with J = [[m I, -[h]], [[h], I_O]], h = m c,
+         Fhat = J dV - ad_V^T (J V) = J dV + G Q,
+         G Q = (m (w x v) - ((tr W) I - W) h,  h x (w x v) + w x (I_O w)),
+       so Fhat_i is linear in (dV_{i-1}, Q_{i-1}, V_{i-1}, 1) and no block reads Fhat_{i-1}.
+       A_0 starts the scan at (dV0, Q(V0), V0, 0, 1).
   (20) the bias-wrench scan of (16) and the ABIA backward scan of (18) as one, 15x15, on
        (F_i, tauhat_{i+1}, zhat_{i+1}, chat_{i+2}, 1) -> (F_{i-1}, tauhat_i, zhat_i, chat_{i+1}, 1):
        A_i = [[X_i^T, 0, 0, 0, Fhat_{i-1}], [-S_i^T, 0, 0, 0, tau_i],
@@ -205,6 +216,91 @@ def lambda_operands(ch, at):
         A[:6, 7] = ch.twist[i - 1] * at["chat"][i]
         A[6, :6] = -at["Pi"][i]
         A[6, 7] = at["chat"][i]
+        ops.append(A)
+    return ops
+
+
+_SYM = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def q_vector(V):
+    """Q = (w x v, the six products w_j w_k, j <= k) of a twist V = (v, w)."""
+    v, w = np.asarray(V[:3], float), np.asarray(V[3:], float)
+    return np.concatenate([np.cross(w, v), [w[a] * w[b] for a, b in _SYM]])
+
+
+def _W_of(Q):
+    W = np.zeros((3, 3))
+    for k, (a, b) in enumerate(_SYM):
+        W[a, b] = W[b, a] = Q[3 + k]
+    return W
+
+
+def _sym6(W):
+    return np.array([W[a, b] for a, b in _SYM])
+
+
+def spatial_inertia(pi):
+    """J = [[m I, -[h]], [[h], I_O]] with h = m c and I_O = I_c - m [c][c] (the oracle's eq. (1) inertia)."""
+    m, c = pi[0], np.asarray(pi[1:4], float)
+    Ic = np.array([[pi[4], pi[7], pi[8]], [pi[7], pi[5], pi[9]], [pi[8], pi[9], pi[6]]])
+    J = np.zeros((6, 6))
+    J[:3, :3] = m * np.eye(3)
+    J[:3, 3:] = -m * skew(c)
+    J[3:, :3] = m * skew(c)
+    J[3:, 3:] = Ic - m * skew(c) @ skew(c)
+    return J
+
+
+def _matrix_of(fun, dim_in):
+    """The matrix of a linear map given as a function, column by column."""
+    return np.stack([fun(e) for e in np.eye(dim_in)], axis=1)
+
+
+def merged_forward_operands(ch, rt, qd, qdd, V0, dV0):
+    """Eq. (15) operands A_0..A_n (28x28) from an RNEA trace (R, p of f_{i-1,i})."""
+    n = len(qd)
+    A0 = np.eye(28)
+    A0[:, 27] = np.concatenate([dV0, q_vector(V0), V0, np.zeros(6), [1.0]])
+    ops = [A0]
+    for i in range(1, n + 1):
+        R, p = rt["R"][i], rt["p"][i]
+        X = Ad(*inv_pose(R, p))
+        S = np.asarray(ch.twist[i - 1], float)
+        s_v, s_w = S[:3], S[3:]
+        u, ud = qd[i - 1], qdd[i - 1]
+        pi = np.asarray(ch.inertia[i - 1], float)
+        J = spatial_inertia(pi)
+        m, h, I_O = pi[0], pi[0] * pi[1:4], J[3:, 3:]
+
+        def q_from_q(Q):  # the Q_{i-1} -> Q_i part
+            c, W = Q[:3], _W_of(Q)
+            return np.concatenate([R.T @ c - R.T @ (np.trace(W) * p - W @ p), _sym6(R.T @ W @ R)])
+
+        def q_from_v(Vp):  # the V_{i-1} -> Q_i part (linear in V)
+            bv = X @ Vp
+            b, a = bv[:3], bv[3:]
+            return u * np.concatenate([np.cross(a, s_v) + np.cross(s_w, b),
+                                       _sym6(np.outer(a, s_w) + np.outer(s_w, a))])
+
+        def g_of(Q):  # -ad_V^T (J V) as a linear map of Q
+            c, W = Q[:3], _W_of(Q)
+            eps = np.zeros((3, 3, 3))
+            eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1.0
+            eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1.0
+            wIw = np.einsum("abc,cd,bd->a", eps, I_O, W)
+            return np.concatenate([m * c - (np.trace(W) * np.eye(3) - W) @ h, np.cross(h, c) + wIw])
+
+        AQQ, AQV, G = _matrix_of(q_from_q, 9), _matrix_of(q_from_v, 6), _matrix_of(g_of, 9)
+        cQ = u * u * np.concatenate([np.cross(s_w, s_v), _sym6(np.outer(s_w, s_w))])
+        AdV = -ad(S * u) @ X
+        A = np.zeros((28, 28))
+        A[0:6, 0:6], A[0:6, 15:21], A[0:6, 27] = X, AdV, S * ud
+        A[6:15, 6:15], A[6:15, 15:21], A[6:15, 27] = AQQ, AQV, cQ
+        A[15:21, 15:21], A[15:21, 27] = X, S * u
+        A[21:27, 0:6], A[21:27, 6:15] = J @ X, G @ AQQ
+        A[21:27, 15:21], A[21:27, 27] = J @ AdV + G @ AQV, J @ (S * ud) + G @ cQ
+        A[27, 27] = 1.0
         ops.append(A)
     return ops
 

@@ -46,6 +46,10 @@ MUTANTS = {
         "return {std::sin(z.a) * std::cosh(z.b), std::sin(z.a) * std::sinh(z.b)};"),
     "Hessian (q, qd) block seeds qdd": ("multicomplex.hpp",
         "(block == 1 || block == 2) ? 1 : 2;", "(block == 2) ? 1 : 2;"),
+    "eq. (15) operand: velocity cross term sign": ("scan_form.py",
+        "np.cross(a, s_v) + np.cross(s_w, b)", "np.cross(a, s_v) - np.cross(s_w, b)"),
+    "eq. (15) operand: gyroscopic moment drops w x (I_O w)": ("scan_form.py",
+        "np.cross(h, c) + wIw", "np.cross(h, c)"),
     "gravity sign": ("__init__.py",
         "GRAVITY_ACC = np.array([0.0, 0.0, 9.81, 0.0, 0.0, 0.0])", "GRAVITY_ACC = np.array([0.0, 0.0, -9.81, 0.0, 0.0, 0.0])"),
 }

@@ -78,6 +78,59 @@ def test_abia_forward_scan(n, how):
 
 
 @pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_merged_forward_scan(n, how):
+    """Eq. (15): the last column of A_i ... A_0 is (dV_i, Q_i, V_i, Fhat_i, 1), equal to the serial RNEA's
+    accelerations, velocities and bias wrenches, and Q_i to the nine products formed from V_i directly."""
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 150 + n)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    P = sf.prefix(sf.merged_forward_operands(ch, rt, qd, qdd, V0, dV0), how, np.random.default_rng(n))
+    for i in range(n + 1):
+        x = P[i][:, 27]
+        v, w = rt["V"][i][:3], rt["V"][i][3:]
+        Q = np.concatenate([np.cross(w, v), [w[0] * w[0], w[0] * w[1], w[0] * w[2], w[1] * w[1], w[1] * w[2],
+                                             w[2] * w[2]]])
+        scale = 1 + max(np.abs(rt["dV"][i]).max(), np.abs(Q).max(), np.abs(rt["Fhat"][i]).max())
+        assert np.abs(x[0:6] - rt["dV"][i]).max() <= 1e-12 * scale
+        assert np.abs(x[6:15] - Q).max() <= 1e-12 * scale
+        assert np.abs(x[15:21] - rt["V"][i]).max() <= 1e-12 * scale
+        if i >= 1:
+            assert np.abs(x[21:27] - rt["Fhat"][i]).max() <= 1e-12 * scale
+        assert x[27] == 1.0
+
+
+def test_merged_forward_block_pattern():
+    """Every operand of eq. (15) has the printed block pattern: (dV | Q, V | Fhat | 1) rows read
+    [* 0 * 0 *], [0 * * 0 *], [0 0 * 0 *], [* * * 0 *], [0 0 0 0 1]."""
+    n = 6
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 170)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    blocks = [slice(0, 6), slice(6, 15), slice(15, 21), slice(21, 27), slice(27, 28)]
+    zero = {(0, 1), (0, 3), (1, 0), (1, 3), (2, 0), (2, 1), (2, 3), (3, 3), (4, 0), (4, 1), (4, 2), (4, 3)}
+    for A in sf.merged_forward_operands(ch, rt, qd, qdd, V0, dV0)[1:]:
+        for r in range(5):
+            for c in range(5):
+                if (r, c) in zero:
+                    assert not A[blocks[r], blocks[c]].any(), (r, c)
+        assert A[27, 27] == 1.0
+
+
+@pytest.mark.parametrize("n", [1, 4, 8])
+def test_inverse_dynamics_by_the_two_merged_scans(n):
+    """Inverse dynamics from scans alone: Fhat_i read off the scan of eq. (15) feeds the wrench scan of
+    eq. (16), whose torques equal the serial RNEA's tau."""
+    ch, q, qd, qdd, _, V0, dV0, Ft = _setup(n, 180 + n)
+    rt = oracle.rnea_trace(ch, q, qd, qdd, V0, dV0, Ft)
+    P = sf.prefix(sf.merged_forward_operands(ch, rt, qd, qdd, V0, dV0), "blelloch")
+    scanned = dict(rt, Fhat=np.stack([np.zeros(6)] + [P[i][21:27, 27] for i in range(1, n + 1)]))
+    B = sf.prefix(sf.force_operands(ch, scanned), "hillis_steele")
+    x = np.concatenate([Ft, [0.0, 1.0]])
+    tau = [(B[k] @ x)[6] for k in range(1, n + 1)]  # tau_n .. tau_1
+    ref = oracle.rnea1(ch, q, qd, qdd, V0, dV0, Ft)
+    assert np.abs(np.array(tau[::-1]) - ref).max() <= 1e-11 * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
 @pytest.mark.parametrize("n", [1, 2, 5, 8])
 def test_merged_backward_scan(n, how):
     """Eq. (20): one backward scan of the bias wrench, tau-hat, z-hat and c-hat. After A_{n+1} .. A_i applied
