@@ -458,10 +458,12 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
                                                         T* scr_bias, T* scr_abi, unsigned* status) {
   // LDSMODE: 0 no LDS hand-off (barrier); 1 U_i, 1/D_i in LDS and the
   // transform wavefronts with their rings; 2 U_i alone in LDS (B2 forms 1/D_i,
-  // so that longer chains fit). LDS: [link][kAbiLds][64 lanes], then (mode 1)
-  // the two rings.
+  // so that longer chains fit); 3 as 1, and B1's bias wrenches handed to B2 in
+  // LDS too instead of through HBM. LDS: [link][kAbiLds][64 lanes], then (modes
+  // 1, 3) the two rings, then (mode 3) the bias wrenches [link][6][64].
   constexpr bool OVERLAP = LDSMODE != 0;
-  constexpr bool kRings = LDSMODE == 1;
+  constexpr bool kRings = LDSMODE == 1 || LDSMODE == 3;
+  constexpr bool kFhatLds = LDSMODE == 3;
   constexpr int kAbiLds = kRings ? kAbiWords : 6;
   extern __shared__ __align__(16) unsigned char lds_abi[];
   __shared__ int progress, ready_f, used_b, used_id, ready_b, used_a, ready_l[2], used_l;
@@ -516,6 +518,8 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   const SPtr<const T> qs(q + dof0), qds(qd + dof0);
   T* const ring_f = reinterpret_cast<T*>(lds_abi) + (long)n_max * kAbiLds * 64;
   T* const ring_b = ring_f + (long)kPoseSlots * kPoseWordsF * 64;
+  const Scratch<T> fhat_lds{ring_b + (long)kPoseSlots * kPoseWordsB * 64 + lane, 64L, 6, status};
+  const Scratch<T>* const fhat = kFhatLds ? &fhat_lds : nullptr;
   // Pass C takes the transforms again through the base-to-tip ring, once B1
   // and the inverse dynamics have taken every entry: P_f forms the even links,
   // P_b (idle by then) the odd ones.
@@ -562,7 +566,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
         split_abi_pass<T, NoHandoff, !SHARED>(n, tab, wtab, qs, abi);
     } else {
       if (kRings)
-        split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane, status});
+        split_bias_forward(n, tab, qs, qds, bd, bias, RingTakeF<T>{ring_f, &ready_f, &used_b, lane, status}, fhat);
       else
         split_bias_forward<T, FormPose<T>, !SHARED>(n, tab, qs, qds, bd, bias);
     }
@@ -571,7 +575,7 @@ __global__ void __launch_bounds__(320) k_dynamics_split(int n_states, int n_max,
   if (active && role == 1) {
     if (kRings)
       split_bias_backward<T, LdsWait, !SHARED, true>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias,
-                                                     abi, LdsWait{&progress, status});
+                                                     abi, LdsWait{&progress, status}, fhat);
     else if (OVERLAP)
       split_bias_backward<T, LdsWait, !SHARED>(n, tab, wtab, qs, SPtr<const T>(tau_in + dof0), bd, bias, abi,
                                                LdsWait{&progress, status});
@@ -1948,14 +1952,17 @@ int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, c
     T* scr_bias = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_id) +
                                        align_up(nm * ScratchWords<kModeID>::value * B * sizeof(T)));
     T* scr_abi = reinterpret_cast<T*>(reinterpret_cast<char*>(scr_bias) + align_up(nm * kBiasWords * B * sizeof(T)));
-    // LDS hand-off of U_i with the transform rings if they fit, else of U_i alone, else none
+    // LDS hand-off of U_i with the transform rings and the bias wrenches if they fit, else of U_i with
+    // the rings, else of U_i alone, else none
     const size_t lds_rings = (nm * kAbiWords + (size_t)kPoseSlots * (kPoseWordsF + kPoseWordsB)) * 64 * sizeof(T);
+    const size_t lds_fhat = lds_rings + nm * 6 * 64 * sizeof(T);
     const size_t lds_abi = nm * 6 * 64 * sizeof(T);
-    const int ldsmode = lds_rings <= max_lds_bytes() ? 1 : (lds_abi <= max_lds_bytes() ? 2 : 0);
-    const size_t lds = ldsmode == 1 ? lds_rings : (ldsmode == 2 ? lds_abi : 0);
+    const size_t cap = max_lds_bytes();
+    const int ldsmode = lds_fhat <= cap ? 3 : lds_rings <= cap ? 1 : (lds_abi <= cap ? 2 : 0);
+    const size_t lds = ldsmode == 3 ? lds_fhat : ldsmode == 1 ? lds_rings : (ldsmode == 2 ? lds_abi : 0);
     const bool shared = m->n_chains == 1;
     // wavefronts: A, B, [P_f and P_b with the rings], [ID for ID+FD]
-    const unsigned blk = 128 + (ldsmode == 1 ? 128 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
+    const unsigned blk = 128 + (ldsmode == 1 || ldsmode == 3 ? 128 : 0) + ((MODE == kModeIDFD) ? 64 : 0);
 #define PDYN_LAUNCH_SPLIT(SH, LM)                                                                                 \
   do {                                                                                                            \
     if (lds > 65536 &&                                                                                            \
@@ -1967,11 +1974,13 @@ int launch_dynamics(const pdyn_model* m, const pdyn_batch* b, const Layout& L, c
                        qdd_out, static_cast<const T*>(b->tip_wrench), ba, scr_id, scr_bias, scr_abi, status);     \
   } while (0)
     if (shared) {
-      if (ldsmode == 1) PDYN_LAUNCH_SPLIT(true, 1);
+      if (ldsmode == 3) PDYN_LAUNCH_SPLIT(true, 3);
+      else if (ldsmode == 1) PDYN_LAUNCH_SPLIT(true, 1);
       else if (ldsmode == 2) PDYN_LAUNCH_SPLIT(true, 2);
       else PDYN_LAUNCH_SPLIT(true, 0);
     } else {
-      if (ldsmode == 1) PDYN_LAUNCH_SPLIT(false, 1);
+      if (ldsmode == 3) PDYN_LAUNCH_SPLIT(false, 3);
+      else if (ldsmode == 1) PDYN_LAUNCH_SPLIT(false, 1);
       else if (ldsmode == 2) PDYN_LAUNCH_SPLIT(false, 2);
       else PDYN_LAUNCH_SPLIT(false, 0);
     }

@@ -673,9 +673,13 @@ PD_HD void split_abi_from_poses(int n, Tab table, const Scratch<T>& abi, const G
 }
 
 // Pass B1 (base to tip): V, bias acceleration, bias wrench Fhat_bias, (sin, cos).
+// fhat (if given) takes the bias wrenches in place of words 0-5 of `bias`
+// (e.g. in LDS); (sin, cos) stay in words 8-9 of `bias`.
 template <class T, class PoseSrc = FormPose<T>, bool PF = false, class Tab = const T*>
 PD_HD void split_bias_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> qd, const Boundary<T>& bd,
-                              const Scratch<T>& bias, const PoseSrc& pose = PoseSrc()) {
+                              const Scratch<T>& bias, const PoseSrc& pose = PoseSrc(),
+                              const Scratch<T>* fhat = nullptr) {
+  const Scratch<T>& fh = fhat ? *fhat : bias;
   struct In {
     T q, qd;
     Link<T> L;
@@ -701,7 +705,7 @@ PD_HD void split_bias_forward(int n, Tab table, SPtr<const T> q, SPtr<const T> q
         const Sp<T> Sqd = x.qd * L.S;
         V = XV + Sqd;
         dVb = X_twist(g, dVb) - ad_twist(Sqd, XV);
-        bias.put(i, 0, mul(L.J, dVb) - adT_wrench(V, mul(L.J, V)));
+        fh.put(i, 0, mul(L.J, dVb) - adT_wrench(V, mul(L.J, V)));
       });
 }
 
@@ -718,7 +722,8 @@ template <class T, class Need = NoHandoff, bool PF = false, bool FOLD = false, c
           class WTab = const double*>
 PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, SPtr<const T> tau_in,
                                const Boundary<T>& bd, const Scratch<T>& bias, const Scratch<T>& abi,
-                               const Need& need = Need()) {
+                               const Need& need = Need(), const Scratch<T>* fhat = nullptr) {
+  const Scratch<T>& fh = fhat ? *fhat : bias;  // where split_bias_forward left the bias wrenches
   struct In {
     Sp<T> fb, U;
     T invD, sn, cs, q, tau;
@@ -731,7 +736,7 @@ PD_HD void split_bias_backward(int n, Tab table, WTab wtable, SPtr<const T> q, S
       n, n - 1, -1,
       [&](int i) {
         In x;
-        x.fb = bias.get(i, 0);
+        x.fb = fh.get(i, 0);
         x.sn = bias.at(i, 8);
         x.cs = bias.at(i, 9);
         need(n - i);
