@@ -47,6 +47,17 @@ Operands (1-based links, n links):
        A_{n+1}, A_n, ..., A_0 from (F_{n+1}, 0, 0, 0, 1) = (tip wrench, 0, 0, 0, 1), with the padding
        X_{n+1} = I, S_{n+1} = 0, tau_{n+1} = 0 and Pi_{n,n+1} = Y_{n,n+1} = Omega_{n+1}^-1 = 0 (no
        child of link n), Fhat_0 = 0, S_0 = 0 and tau_0 = 0 (no joint 0).
+  (7) articulated-body inertia, which Sec. II-B leaves serial, in an associative form (not in the
+       paper). The step Jhat_i = J_i + X_{i+1}^T (P - P s (s^T P s)^-1 s^T P) X_{i+1}, P = Jhat_{i+1},
+       s = S_{i+1}, is a Riccati map: with P - P s (s^T P s)^-1 s^T P = lim_{r->inf} P (I + r s s^T P)^-1
+       it is E(P) = Q + A^T P (I + C P)^-1 A with (A, C, Q) = (X_{i+1}, inf s s^T, J_i). Such maps form a
+       monoid under composition: E1(E2(P)) = E(P) with W = (I + C1 Q2)^-1 and
+         A = A2 W A1,   C = C2 + A2 W C1 A2^T,   Q = Q1 + A1^T Q2 W A1
+       (eliminate the inner port variables of z = A v - C y, f = Q v + A^T y). An element carries
+       C = C_f + inf u u^T (u = 0: none) and the limits are taken in closed form: with B = I + C1_f Q2
+       and k = u1^T Q2 B^-1 u1, W = B^-1 - B^-1 u1 k^-1 u1^T Q2 B^-1 and W C1 = W C1_f + B^-1 u1 u1^T / k;
+       C keeps the inner element's infinite direction. Per link, e_i = (X_{i+1}, 0, S_{i+1}, J_i) and
+       e_n = (I, 0, 0, J_n); the prefix e_i o ... o e_n evaluated at P = 0 is Q = Jhat_i.
 """
 
 from __future__ import annotations
@@ -103,7 +114,7 @@ def prefix_blelloch(ops):
     m = 1
     while m < len(ops):
         m *= 2
-    eye = np.eye(ops[0].shape[0])
+    eye = ops[0].identity() if hasattr(ops[0], "identity") else np.eye(ops[0].shape[0])
     t = list(ops) + [eye] * (m - len(ops))
     d = 1
     while d < m:
@@ -302,6 +313,63 @@ def merged_forward_operands(ch, rt, qd, qdd, V0, dV0):
         A[21:27, 15:21], A[21:27, 27] = J @ AdV + G @ AQV, J @ (S * ud) + G @ cQ
         A[27, 27] = 1.0
         ops.append(A)
+    return ops
+
+
+class AbiElement:
+    """E(P) = Q + A^T P (I + C P)^-1 A with C = Cf + inf u u^T (u None: no infinite part); `a @ b` is
+    a o b, b applied first (the later element on the left, as the dense operands). The closed-form
+    limits need k = u1^T Q2 B^-1 u1 > 0, which holds whenever the inner element contains a link (its Q is
+    positive definite); the identity map (Q = 0) is therefore kept as a marked element."""
+
+    def __init__(self, A, Cf, u, Q, is_identity=False):
+        self.A, self.Cf, self.u, self.Q, self.is_identity = A, Cf, u, Q, is_identity
+
+    @staticmethod
+    def identity():
+        return AbiElement(np.eye(6), np.zeros((6, 6)), None, np.zeros((6, 6)), True)
+
+    def __matmul__(self, inner):
+        if inner.is_identity:
+            return self
+        if self.is_identity:
+            return inner
+        A1, C1f, u1, Q1 = self.A, self.Cf, self.u, self.Q
+        A2, C2f, u2, Q2 = inner.A, inner.Cf, inner.u, inner.Q
+        Binv = np.linalg.inv(np.eye(6) + C1f @ Q2)
+        if u1 is None:
+            W, WC1 = Binv, Binv @ C1f
+        else:
+            k = u1 @ Q2 @ Binv @ u1
+            Bu = Binv @ u1
+            W = Binv - np.outer(Bu, u1 @ Q2 @ Binv) / k
+            WC1 = W @ C1f + np.outer(Bu, u1) / k
+        return AbiElement(A2 @ W @ A1, C2f + A2 @ WC1 @ A2.T, u2, Q1 + A1.T @ Q2 @ W @ A1)
+
+    def apply(self, P):
+        """E(P) for a symmetric P (the articulated inertia beyond the element's tip end)."""
+        Bp = np.eye(6) + self.Cf @ P
+        Binv = np.linalg.inv(Bp)
+        if self.u is None:
+            G = P @ Binv
+        else:
+            u = self.u
+            G = P @ (Binv - np.outer(Binv @ u, u @ P @ Binv) / (u @ P @ Binv @ u))
+        return self.Q + self.A.T @ G @ self.A
+
+
+def abi_elements(ch, rt):
+    """The per-link elements of eq. (7) in scan order e_n, e_{n-1}, ..., e_1 (rt: an RNEA trace at the
+    same q, for the transforms f_{i-1,i})."""
+    n = len(rt["tau"]) - 1
+    ops = []
+    for i in range(n, 0, -1):
+        J = spatial_inertia(np.asarray(ch.inertia[i - 1], float))
+        if i == n:
+            ops.append(AbiElement(np.eye(6), np.zeros((6, 6)), None, J))
+        else:
+            X = Ad(*inv_pose(rt["R"][i + 1], rt["p"][i + 1]))
+            ops.append(AbiElement(X, np.zeros((6, 6)), np.asarray(ch.twist[i], float), J))
     return ops
 
 

@@ -50,6 +50,10 @@ MUTANTS = {
         "np.cross(a, s_v) + np.cross(s_w, b)", "np.cross(a, s_v) - np.cross(s_w, b)"),
     "eq. (15) operand: gyroscopic moment drops w x (I_O w)": ("scan_form.py",
         "np.cross(h, c) + wIw", "np.cross(h, c)"),
+    "associative eq. (7): outer infinite direction not absorbed": ("scan_form.py",
+        "WC1 = W @ C1f + np.outer(Bu, u1) / k", "WC1 = W @ C1f"),
+    "associative eq. (7): projector on the wrong side": ("scan_form.py",
+        "W = Binv - np.outer(Bu, u1 @ Q2 @ Binv) / k", "W = Binv - np.outer(Q2 @ Bu, u1 @ Binv) / k"),
     "gravity sign": ("__init__.py",
         "GRAVITY_ACC = np.array([0.0, 0.0, 9.81, 0.0, 0.0, 0.0])", "GRAVITY_ACC = np.array([0.0, 0.0, -9.81, 0.0, 0.0, 0.0])"),
 }

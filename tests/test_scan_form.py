@@ -221,3 +221,67 @@ def test_compact_scan_reads_off_velocity_and_acceleration(n):
         P = sf.compact_combine(ops[i], P)
         assert np.abs(P[2] - rt["dV"][i]).max() <= 1e-12 * (1 + np.abs(rt["dV"][i]).max())
         assert np.abs(P[3] - rt["V"][i]).max() <= 1e-12 * (1 + np.abs(rt["V"][i]).max())
+
+
+# ---- eq. (7) in an associative (Riccati) form -------------------------------------------
+
+def _abi_setup(n, seed):
+    ch, q, qd, _, tau, V0, dV0, Ft = _setup(n, seed)
+    return ch, oracle.rnea_trace(ch, q, qd, np.zeros(n), V0, dV0, Ft), oracle.aba_trace(ch, q, qd, tau, V0, dV0, Ft)
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_articulated_inertia_scan(n, how):
+    """Eq. (7) as a scan: e_i o ... o e_n evaluated at P = 0 is the serial Jhat_i, and S_i^T Jhat_i S_i is
+    the oracle's Omega_i."""
+    ch, rt, at = _abi_setup(n, 600 + n)
+    P = sf.prefix(sf.abi_elements(ch, rt), how, np.random.default_rng(n))
+    for k, i in enumerate(range(n, 0, -1)):
+        J = at["Jhat"][i]
+        assert np.abs(P[k].Q - J).max() <= 1e-12 * np.abs(J).max()
+        S = ch.twist[i - 1]
+        assert abs(S @ P[k].Q @ S - at["Omega"][i]) <= 1e-12 * abs(at["Omega"][i])
+
+
+@pytest.mark.parametrize("how", sf.BRACKETINGS)
+def test_articulated_inertia_scan_with_a_tip_load(how):
+    """The composite maps act on a load beyond the tip, not only on 0: with a payload inertia P rigidly
+    attached to link n, E(P) equals the recursion (7) started from Jhat_n = J_n + P (this exercises the
+    A and C parts of every prefix, which P = 0 does not see)."""
+    n = 7
+    ch, rt, _ = _abi_setup(n, 650)
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((6, 6))
+    Pload = G @ G.T + 0.1 * np.eye(6)
+    ref = {n: sf.spatial_inertia(ch.inertia[n - 1]) + Pload}
+    for i in range(n - 1, 0, -1):
+        Jn, S = ref[i + 1], ch.twist[i]
+        Ja = Jn - np.outer(Jn @ S, S @ Jn) / (S @ Jn @ S)
+        X = sf.Ad(*sf.inv_pose(rt["R"][i + 1], rt["p"][i + 1]))
+        ref[i] = sf.spatial_inertia(ch.inertia[i - 1]) + X.T @ Ja @ X
+    P = sf.prefix(sf.abi_elements(ch, rt), how, np.random.default_rng(5))
+    for k, i in enumerate(range(n, 0, -1)):
+        assert np.abs(P[k].apply(Pload) - ref[i]).max() <= 1e-11 * np.abs(ref[i]).max()
+
+
+def _random_element(rng, infinite):
+    G, H, K = (rng.standard_normal((6, 6)) for _ in range(3))
+    return sf.AbiElement(G, 0.1 * H @ H.T, rng.standard_normal(6) if infinite else None, K @ K.T + np.eye(6))
+
+
+def test_articulated_inertia_operator_is_associative_with_identity():
+    """(a o b) o c = a o (b o c) for general elements (finite and infinite C parts), as maps and as stored
+    parts; the identity element leaves an element unchanged."""
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        a, b, c = (_random_element(rng, infinite=bool((trial >> k) & 1)) for k in range(3))
+        left, right = (a @ b) @ c, a @ (b @ c)
+        for x, y in ((left.A, right.A), (left.Cf, right.Cf), (left.Q, right.Q)):
+            assert np.abs(x - y).max() <= 1e-9 * (1 + np.abs(y).max())
+        M = rng.standard_normal((6, 6))
+        P = M @ M.T + np.eye(6)
+        assert np.abs(left.apply(P) - a.apply(b.apply(c.apply(P)))).max() <= 1e-9 * np.abs(left.apply(P)).max()
+        I = sf.AbiElement.identity()
+        for e in ((I @ a), (a @ I)):
+            assert np.abs(e.apply(P) - a.apply(P)).max() <= 1e-12 * np.abs(a.apply(P)).max()
