@@ -95,8 +95,8 @@ def measured_traffic():
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=500)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-other-workloads", action="store_true", help="only the 32-link headline workload")
     p.add_argument("--profile-only", action="store_true", help="launch the timed steps only (for rocprofv3)")
@@ -455,9 +455,14 @@ def main():
         api.aba_fd(model, q, qd, tau, out=qdd_out, workspace=ws)
 
     torch.cuda.synchronize()
-    ms_fused = time_steps(fused, args.steps, args.warmup, stream)
-    print(f"fused ID+FD: {ms_fused * 1e3:.1f} us/step", file=sys.stderr, flush=True)
-    win_fused = time_windows(fused, stream)
+    # the timed step: one pdyn_id_fd launch through a plan (arguments marshalled once, as a serving loop
+    # would call it); the same step through the per-call binding is reported beside it
+    fused_plan = api.plan_id_fd(model, q, qd, qdd, tau, out=(tau_out, qdd_out), workspace=ws)
+    ms_fused = time_steps(fused_plan, args.steps, args.warmup, stream)
+    ms_fused_binding = time_steps(fused, args.steps, args.warmup, stream)
+    print(f"fused ID+FD: {ms_fused * 1e3:.1f} us/step (per-call binding {ms_fused_binding * 1e3:.1f})",
+          file=sys.stderr, flush=True)
+    win_fused = time_windows(fused_plan, stream)
     print(f"fused ID+FD, median of windows: {win_fused}", file=sys.stderr, flush=True)
     variants = {}
     for v in (1, 2):
@@ -571,7 +576,7 @@ def main():
     links = N_LINKS * N_STATES
     achieved = FLOPS_PER_LINK["id_fd"] * links / (ms_fused * 1e-3)
     per_op = {}
-    for name, ms in (("id", ms_id), ("fd", ms_fd), ("id_fd", ms_fused), ("id_vjp", ms_idv), ("fd_vjp", ms_fdv)):
+    for name, ms in (("id", ms_id), ("fd", ms_fd), ("id_fd", ms_fused_binding), ("id_vjp", ms_idv), ("fd_vjp", ms_fdv)):
         fl = FLOPS_PER_LINK[name] * links / (ms * 1e-3)
         per_op[name] = {"us": ms * 1e3, "evals_per_s": N_STATES / (ms * 1e-3), "tflops": fl / 1e12,
                         "roofline_frac": fl / PEAK_VALU_FLOPS}
@@ -612,15 +617,18 @@ def main():
                          + FLOPS_PER_LINK_FP64["id_fd"] / (peaks["fp64_fma_tflops"] * 1e12))),
                      "median_of_windows": dict(win_fused, achieved_tflops=FLOPS_PER_LINK["id_fd"] * links
                                                / (win_fused["median_ms"] * 1e-3) / 1e12)},
+        "timed_step": {"form": "pdyn_id_fd through api.plan_id_fd (arguments marshalled once)",
+                       "per_call_binding_ms_per_step": ms_fused_binding,
+                       "note": "the per-op, variant and plain comparisons below all go through the per-call binding"},
         "measured_peaks": peaks,
         "kernel_variants": {"1": dict(variants[1], form="one wavefront per 64 states, all sweeps"),
                             "2": dict(variants[2], form="role split across wavefronts with LDS hand-offs"),
                             "3": dict(per_sweep, form="plain: one launch per recursion sweep, HBM intermediates")},
         "fused_over_plain_per_sweep": {"id": per_sweep["id_us"] / (ms_id * 1e3),
                                        "fd": per_sweep["fd_us"] / (ms_fd * 1e3),
-                                       "id_fd": per_sweep["id_fd_us"] / (ms_fused * 1e3)},
+                                       "id_fd": per_sweep["id_fd_us"] / (ms_fused_binding * 1e3)},
         "plain": {"form": "separate pdyn_rnea_id + pdyn_aba_fd calls", "value": N_STATES / (ms_plain * 1e-3),
-                  "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused},
+                  "ms_per_step": ms_plain, "fused_over_plain": ms_plain / ms_fused_binding},
         "per_op_evals_per_s": {"id": N_STATES / (ms_id * 1e-3), "fd": N_STATES / (ms_fd * 1e-3),
                                "id_vjp": N_STATES / (ms_idv * 1e-3), "fd_vjp": N_STATES / (ms_fdv * 1e-3)},
         "per_op": per_op,

@@ -292,6 +292,48 @@ def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace):
     _check(st, name)
 
 
+class Plan:
+    """One library call with its arguments marshalled once. Calling the plan launches the same operation on
+    the same tensors again, on the stream that was current when the plan was made: the per-call Python
+    work of the functions below (argument checks, the C structs, the workspace query) is done here once,
+    for loops that repeat a call. The plan keeps the tensors it points to alive; changing the model's
+    launch choice or its tables afterwards needs a new plan."""
+
+    def __init__(self, name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace):
+        L = lib()
+        self.name = name
+        self._fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
+        self._m = model.c_struct()
+        self._b = _batch_struct(n_states, base_vel, base_acc, tip, op)
+        nbytes = L.pdyn_workspace_bytes(op, ctypes.byref(self._m), ctypes.byref(self._b), model.scalar_bytes)
+        if nbytes == 0:
+            raise PdynError(f"{name}: invalid model/batch for workspace query")
+        self._ws = (workspace or _workspace(model.device)).get(nbytes, model.device)
+        stream = torch.cuda.current_stream(model.device).cuda_stream
+        self._keep = (model, tip) + tuple(ptrs)
+        self._args = (ctypes.byref(self._m), ctypes.byref(self._b),
+                      *[0 if p is None else p.data_ptr() for p in ptrs], self._ws.data_ptr(), self._ws.numel(), stream)
+
+    def __call__(self):
+        st = self._fn(*self._args)
+        if st:
+            _check(st, self.name)
+
+
+def plan_id_fd(model: Model, q, qd, qdd_in, tau_in, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None,
+               workspace=None) -> Plan:
+    """A Plan of id_fd on these tensors (outputs allocated here unless `out` gives them): plan() runs
+    pdyn_id_fd again; plan.out is (tau_out, qdd_out)."""
+    n_states = _n_states(model, q)
+    _prep(model, (q, qd, qdd_in, tau_in, tip))
+    tau_out, qdd_out = (torch.empty_like(q), torch.empty_like(q)) if out is None else out
+    _prep(model, (tau_out, qdd_out))
+    plan = Plan("pdyn_id_fd", OP_ID_FD, model, n_states, (q, qd, qdd_in, tau_in, tau_out, qdd_out), base_vel,
+                base_acc, tip, workspace)
+    plan.out = (tau_out, qdd_out)
+    return plan
+
+
 def rnea_id(model: Model, q, qd, qdd, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, out=None, workspace=None):
     """tau = ID(q, qd, qdd, V0, dV0, F_tip) for every state (eq. (3))."""
     n_states = _n_states(model, q)

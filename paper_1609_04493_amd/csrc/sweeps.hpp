@@ -1471,11 +1471,27 @@ PD_HD void vjp_back_outputs(int n, Tab table, SPtr<const T> qd, SPtr<const T> qd
 // ============================================================================
 
 // Keeps qdd_i in word 7 of link i's scratch (c-hat_i, which the lambda pass has read before
-// the body of link i runs); the Euler update then runs as its own loop after the pass, so the
-// pass carries no loads that its prefetch does not cover.
+// the body of link i runs); the forward rollout's Euler update then runs as its own loop after
+// the pass, so the pass carries no loads of the caller's strided rows that its prefetch does
+// not cover.
 template <class T> struct StashQddScr {
   Scratch<T> scr;
   PD_HD void operator()(int i, T qdd) const { scr.at(i, 7) = qdd; }
+};
+
+// The Euler update inside the lambda pass's epilogue, recording qdd_t for the reverse pass: used
+// by the adjoint's segment recompute, whose working rows are lane-interleaved (coalesced).
+template <class T> struct EulerStepKeep {
+  SPtr<T> q;
+  SPtr<T> qd;
+  SPtr<T> qdd_keep;
+  T dt;
+  PD_HD void operator()(int i, T qdd) const {
+    qdd_keep[i] = qdd;
+    const T v = qd[i] + dt * qdd;
+    qd[i] = v;
+    q[i] = q[i] + dt * v;
+  }
 };
 
 // Forward rollout of one state: q, qd (length n) are advanced in place; tau(t)
@@ -1540,15 +1556,8 @@ PD_HD void rollout_vjp_one_state(int n, Tab table, WTab wtable, int steps, T dt,
       const int j = t - t0;
       for (int i = 0; i < n; ++i) { rows.seg_q(j)[i] = rows.cur_q[i]; rows.seg_qd(j)[i] = rows.cur_qd[i]; }
       JointIO<T> io{rows.cur_q, rows.cur_qd, SPtr<const T>(), tau(t), SPtr<T>(), SPtr<T>()};
-      dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr, StashQddScr<T>{scr});
-      const SPtr<T> keep = rows.seg_qdd(j);
-      for (int i = 0; i < n; ++i) {
-        const T qdd = scr.at(i, 7);
-        keep[i] = qdd;
-        const T v = rows.cur_qd[i] + dt * qdd;
-        rows.cur_qd[i] = v;
-        rows.cur_q[i] = rows.cur_q[i] + dt * v;
-      }
+      dynamics_one_state<T, kModeFD>(n, table, wtable, io, bd, scr,
+                                     EulerStepKeep<T>{rows.cur_q, rows.cur_qd, rows.seg_qdd(j), dt});
     }
     // reverse steps
     for (int t = t1 - 1; t >= t0; --t) {

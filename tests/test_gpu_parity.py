@@ -369,3 +369,21 @@ def test_role_split_lds_modes(device, n, B, dtype):
         for op in (api.OP_ABA_FD, api.OP_ID_FD):
             api.set_launch(op, 0, 0, 0)
 
+
+
+def test_plan_repeats_the_call_bit_for_bit(device):
+    """api.plan_id_fd marshals the arguments once; each call of the plan gives what id_fd gives."""
+    print("case: id_fd plan, 32 links x 1000 states", flush=True)
+    ch = synth.make_chains([32], 41)
+    st = synth.make_states((1000, 32), 41)
+    model = api.Model(ch, device, torch.float32)
+    q, qd, qdd, tau = (torch.as_tensor(a, dtype=torch.float32).to(device) for a in (st.q, st.qd, st.qdd, st.tau))
+    ref_tau, ref_qdd = api.id_fd(model, q, qd, qdd, tau)
+    plan = api.plan_id_fd(model, q, qd, qdd, tau)
+    for _ in range(3):
+        plan.out[0].zero_()
+        plan.out[1].zero_()
+        plan()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.out[0], ref_tau) and torch.equal(plan.out[1], ref_qdd)
+    assert api.read_status(device) == 0
