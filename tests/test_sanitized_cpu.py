@@ -35,10 +35,16 @@ def test_oracle_and_kernel_host_builds_under_asan_ubsan(tmp_path):
                     "-ffp-contract=off", *SAN, "-o", oracle_so, os.path.join(ROOT, "oracle", "oracle_capi.cpp")],
                    check=True)
     host_flags = " ".join(f"-Xarch_host {f}" for f in SAN) + " -g"  # host pass only: no GPU code is built
-    env = dict(os.environ, PDYN_ORACLE_LIB=oracle_so, PDYN_HOST_BUILD_FLAGS=host_flags, LD_PRELOAD=_runtime(),
+    preload = _runtime() + (":" + os.environ["LD_PRELOAD"] if os.environ.get("LD_PRELOAD") else "")
+    env = dict(os.environ, PDYN_ORACLE_LIB=oracle_so, PDYN_HOST_BUILD_FLAGS=host_flags, LD_PRELOAD=preload,
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
+    try:  # the modules build their host libraries independently: run them side by side
+        import xdist  # noqa: F401
+        par = ["-n", str(min(4, len(TESTS), os.cpu_count() or 1))]
+    except ImportError:
+        par = []
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", *par, "-m", "not gpu",
                         *TESTS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=1500)
     out = r.stdout + r.stderr
     assert "ERROR: AddressSanitizer" not in out and "runtime error:" not in out, out[-4000:]
