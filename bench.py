@@ -106,8 +106,9 @@ def parse():
                    help="with --profile-only: forward-dynamics kernel variant (0 = library default)")
     p.add_argument("--segments", type=int, default=0,
                    help="with --profile-only and --variant 4: lanes (segments) per chain")
-    p.add_argument("--profile-workload", choices=("32link", "uneven"), default="32link",
-                   help="with --profile-only: the 32-link, 16384-state batch, or the uneven 4096-chain batch")
+    p.add_argument("--profile-workload", choices=("32link", "uneven", "hessian"), default="32link",
+                   help="with --profile-only: the 32-link, 16384-state batch, the uneven 4096-chain batch, or "
+                        "the second derivatives of the 32-link chain at 1024 states")
     return p.parse_args()
 
 
@@ -442,6 +443,15 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     fused = lambda: api.id_fd(model, q, qd, qdd, tau, out=(tau_out, qdd_out), workspace=ws)
+    if args.profile_only and args.profile_workload == "hessian":
+        # all four second-derivative blocks of the 32-link chain at 1024 states, FP32
+        hq, hqd, hqdd = (x[:1024].contiguous() for x in (q, qd, qdd))
+        hout = {b: torch.empty((1024, N_LINKS, N_LINKS, N_LINKS), device=dev) for b in api.HESSIAN_BLOCKS}
+        for _ in range(args.warmup + args.steps):
+            api.rnea_id_hessian(model, hq, hqd, hqdd, out=hout, workspace=ws)
+        torch.cuda.synchronize()
+        print("profile-only run done", flush=True)
+        return 0
     if args.profile_only:
         api.set_launch(api.OP_ID_FD, 0, 0, args.variant, args.segments)
         for _ in range(args.warmup + args.steps):
