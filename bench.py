@@ -53,6 +53,7 @@ def hessian_thread_flops(n: int) -> int:
 PEAK_FP32_VECTOR = 157.3e12  # published MI355X FP32 vector rate
 PEAK_FP64_VECTOR = 78.6e12   # published MI355X FP64 vector rate (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
 PEAK_VALU_FLOPS = PEAK_FP32_VECTOR  # the denominator of the per-operation fractions
+PEAK_HBM = 8.0e12  # published MI355X HBM3E bandwidth, bytes/s
 
 
 def blended_peak(op: str) -> float:
@@ -106,9 +107,10 @@ def parse():
                    help="with --profile-only: forward-dynamics kernel variant (0 = library default)")
     p.add_argument("--segments", type=int, default=0,
                    help="with --profile-only and --variant 4: lanes (segments) per chain")
-    p.add_argument("--profile-workload", choices=("32link", "uneven", "hessian"), default="32link",
-                   help="with --profile-only: the 32-link, 16384-state batch, the uneven 4096-chain batch, or "
-                        "the second derivatives of the 32-link chain at 1024 states")
+    p.add_argument("--profile-workload", choices=("32link", "uneven", "hessian", "abi"), default="32link",
+                   help="with --profile-only: the 32-link, 16384-state batch, the uneven 4096-chain batch, "
+                        "the second derivatives of the 32-link chain at 1024 states, or the articulated-body "
+                        "inertias of a 512-link chain at 256 states (serial, then the 64-lane scan)")
     return p.parse_args()
 
 
@@ -344,6 +346,41 @@ def bench_hessian(args, dev):
     return rows
 
 
+def bench_abi_scan(args, dev):
+    """Articulated-body inertias of eq. (7) by pdyn_articulated_inertia (FP32 entry: FP32 joint angles and
+    output, double inside) at every lane count per state: P = 1 is the serial recursion, P > 1 the
+    associative scan. Long chains with few states are where the scan pays."""
+    import torch
+    from paper_1609_04493_amd import api, synth
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    for n, B in ((1024, 64), (512, 256), (128, 1024), (N_LINKS, N_STATES)):
+        ch = synth.make_chains([n], synth.config_seed(3))
+        st = synth.make_states((B, n), synth.config_seed(3))
+        model = api.Model(ch, dev, torch.float32)
+        q = torch.as_tensor(st.q, dtype=torch.float32).to(dev)
+        J = torch.empty((B, n, 6, 6), device=dev)
+        ws = api.Workspace()
+        by_p = {}
+        for P in (0, 1, 2, 4, 8, 16, 32, 64):
+            by_p[P] = time_windows(lambda: api.articulated_inertia(model, q, segments=P, out=J, workspace=ws),
+                                   stream)["median_ms"]
+        status = api.read_status(dev)
+        best = min((p for p in by_p if p), key=lambda p: by_p[p])
+        out_bytes = B * n * 36 * 4
+        rows[f"{n}_links_{B}_states"] = {
+            "us_by_lanes_per_state": {str(p): by_p[p] * 1e3 for p in by_p if p},
+            "us_default": by_p[0] * 1e3, "best_lanes": best, "serial_over_best": by_p[1] / by_p[best],
+            "link_inertias_per_s_best": B * n / (by_p[best] * 1e-3),
+            "output_bytes": out_bytes, "hbm_roof_us": out_bytes / PEAK_HBM * 1e6,
+            "frac_hbm_best": out_bytes / PEAK_HBM / (by_p[best] * 1e-3), "status_bits": status}
+        print(f"articulated inertia, {n} links x {B}: {rows[f'{n}_links_{B}_states']}", file=sys.stderr, flush=True)
+        del J
+    rows["note"] = ("us per call (median of windows); default = the library's lane count for the batch; the "
+                    "roofline figure is the output write alone (36 words per link) against 8 TB/s")
+    return rows
+
+
 def bench_fd_grad_50(args, dev):
     """50-link chain, 8192 states: FD, then the FD adjoint of L = ||qdd||^2 (inertia gradients on)."""
     import torch
@@ -449,6 +486,17 @@ def main():
         hout = {b: torch.empty((1024, N_LINKS, N_LINKS, N_LINKS), device=dev) for b in api.HESSIAN_BLOCKS}
         for _ in range(args.warmup + args.steps):
             api.rnea_id_hessian(model, hq, hqd, hqdd, out=hout, workspace=ws)
+        torch.cuda.synchronize()
+        print("profile-only run done", flush=True)
+        return 0
+    if args.profile_only and args.profile_workload == "abi":
+        ach = synth.make_chains([512], synth.config_seed(3))
+        aq = torch.as_tensor(synth.make_states((256, 512), synth.config_seed(3)).q, dtype=torch.float32).to(dev)
+        amodel = api.Model(ach, dev, torch.float32)
+        J = torch.empty((256, 512, 6, 6), device=dev)
+        for P in (1, 64):
+            for _ in range(args.warmup + args.steps):
+                api.articulated_inertia(amodel, aq, segments=P, out=J, workspace=ws)
         torch.cuda.synchronize()
         print("profile-only run done", flush=True)
         return 0
@@ -662,7 +710,7 @@ def main():
         others = {}
         for name, fn in (("uneven_4096_chains", bench_uneven), ("jsiia_vs_aba", bench_jsiia),
                          ("fd_grad_50_links", bench_fd_grad_50), ("rollout_grad_100_links", bench_rollout_100),
-                         ("id_hessian", bench_hessian)):
+                         ("id_hessian", bench_hessian), ("articulated_inertia_scan", bench_abi_scan)):
             others[name] = fn(args, dev)
             print(f"{name}: {json.dumps(others[name])}", file=sys.stderr, flush=True)
         out["other_workloads"] = others

@@ -187,7 +187,8 @@ enum {
   PDYN_OP_MASS_MATRIX = 6,
   PDYN_OP_RNEA_ID_JACOBIAN = 7,
   PDYN_OP_ABA_FD_JACOBIAN = 8,
-  PDYN_OP_RNEA_ID_HESSIAN = 9
+  PDYN_OP_RNEA_ID_HESSIAN = 9,
+  PDYN_OP_ARTICULATED_INERTIA = 10
 };
 
 /* Bytes of device workspace that operation op needs for this model and batch
@@ -374,6 +375,39 @@ int pdyn_rnea_id_hessian(const pdyn_model* model, const pdyn_batch* batch, const
 int pdyn_rnea_id_hessian_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
                              const double* qdd, double* H_qq, double* H_qqd, double* H_qdqd, double* H_qqdd,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Articulated-body inertias Jhat_1 .. Jhat_n of eq. (7) (Sec. II-B) for every
+ * state of a shared chain (model->n_chains == 1; PDYN_EUNSUPPORTED otherwise),
+ * computed by an associative scan instead of the serial tip-to-base recursion.
+ * Sec. II-B treats eq. (7) as unscannable because its step is not linear in
+ * Jhat_{i+1}; the step is, however, the limit of a Riccati (linear-fractional)
+ * map E(P) = Q + A^T P (I + C P)^-1 A with C = infinity * S_{i+1} S_{i+1}^T, and
+ * such maps compose in closed form, so the recursion becomes a prefix scan of
+ * 84-number elements.
+ *
+ * batch->segments: lanes per state P, a power of two 1 .. 64 (PDYN_EINVAL
+ * otherwise); 0 = library default (the smallest P that gives the batch 16384
+ * lanes, at most 64, keeping at least 8 links per segment). P = 1 is the
+ * serial recursion, one lane per state; with P > 1 each lane folds a
+ * consecutive segment of links into one element, the lanes combine them with
+ * log2(P) scan steps, and each lane reruns its segment from the result. Both
+ * give Jhat to rounding; the scan shortens the per-state latency of long
+ * chains (O(n / P + log P) steps instead of O(n)). The other launch fields are
+ * ignored.
+ *
+ * q: [n_states][n]. Jhat: [n_states][n][6][6] row-major, Jhat[s][i] the
+ * articulated inertia of link i+1 in its own frame, mapping a twist (v, w) to
+ * a wrench (f, n). Everything after the joint angles' (sin, cos) runs in
+ * double; the FP32 entry rounds the result. A pivot S^T Jhat S (or a pivot of
+ * the scan's combines) that is not positive sets PDYN_STATUS_PIVOT, a
+ * non-finite entry PDYN_STATUS_NONFINITE. Workspace:
+ * pdyn_workspace_bytes(PDYN_OP_ARTICULATED_INERTIA, ...).
+ */
+int pdyn_articulated_inertia(const pdyn_model* model, const pdyn_batch* batch, const float* q, float* Jhat,
+                             void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, double* Jhat,
+                                 void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * pdyn_id_fd without a workspace argument, for callers that cannot allocate

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdyn.so")
 
 OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP, OP_JSIIA_FD, OP_MASS_MATRIX = 0, 1, 2, 3, 4, 5, 6
-OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN, OP_RNEA_ID_HESSIAN = 7, 8, 9
+OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN, OP_RNEA_ID_HESSIAN, OP_ARTICULATED_INERTIA = 7, 8, 9, 10
 GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
 ZERO6 = (0.0,) * 6
 
@@ -50,6 +50,7 @@ _ENTRY_ARITY = {
     "pdyn_jsiia_fd": 4, "pdyn_mass_matrix": 2,
     "pdyn_rnea_id_jacobian": 6, "pdyn_aba_fd_jacobian": 6,
     "pdyn_rnea_id_hessian": 7,
+    "pdyn_articulated_inertia": 2,
 }
 
 
@@ -276,11 +277,13 @@ def _prep(model, arrays):
             raise PdynError("joint arrays must be contiguous, on the model's device, of the model's dtype")
 
 
-def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace):
+def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace, segments=None):
     L = lib()
     fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
     m = model.c_struct()
     b = _batch_struct(n_states, base_vel, base_acc, tip, op)
+    if segments is not None:
+        b.segments = int(segments)
     scalar = model.scalar_bytes
     nbytes = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), scalar)
     if nbytes == 0:
@@ -421,6 +424,22 @@ def rnea_id_hessian(model: Model, q, qd, qdd, blocks=HESSIAN_BLOCKS, base_vel=ZE
     _call("pdyn_rnea_id_hessian", OP_RNEA_ID_HESSIAN, model, n_states, (q, qd, qdd) + ptrs, base_vel, base_acc, tip,
           workspace)
     return {b: res[b] for b in blocks}
+
+
+def articulated_inertia(model: Model, q, segments=0, out=None, workspace=None):
+    """Articulated-body inertias Jhat_i of eq. (7) for every state of a shared chain by
+    pdyn_articulated_inertia: [B, n, 6, 6], Jhat[s, i] that of link i+1 in its own frame (twist (v, w) to
+    wrench (f, n)). segments: lanes per state of the associative scan (a power of two 1..64; 1 = the serial
+    recursion; 0 = the library's choice for this batch)."""
+    n_states = _n_states(model, q)
+    if model.n_chains != 1:
+        raise PdynError("pdyn_articulated_inertia: needs one chain shared by the batch")
+    _prep(model, (q,))
+    n = model.n_links_max
+    J = torch.empty((n_states, n, 6, 6), dtype=model.dtype, device=model.device) if out is None else out
+    _call("pdyn_articulated_inertia", OP_ARTICULATED_INERTIA, model, n_states, (q, J), ZERO6, ZERO6, None,
+          workspace, segments=segments)
+    return J
 
 
 def mass_matrix(model: Model, q, out=None, workspace=None):

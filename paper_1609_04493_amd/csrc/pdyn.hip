@@ -37,6 +37,7 @@
 #include <vector>
 
 #include "../../include/pdyn.h"
+#include "abi_scan.hpp"
 #include "hessian.hpp"
 #include "jsiia.hpp"
 #include "sweeps.hpp"
@@ -2246,6 +2247,109 @@ int run_id_hessian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T
   return PDYN_OK;
 }
 
+// Articulated-body inertias Jhat_i (eq. (7)) of a shared chain by the associative
+// scan of abi_scan.hpp: a team of P lanes per state (P a power of two, 1..64),
+// 64 / P states per 64-lane workgroup. P = 1 is the serial recursion, one lane
+// per state. With P > 1 the lanes of a team fold their segments, combine the
+// aggregates by a Kogge-Stone suffix scan through LDS ([kAbiElWords][64]
+// doubles, one slot per lane) and rerun their segments from the carry. Jhat is
+// written whole, [n_states][n][6][6].
+template <class T, bool SCAN>
+__global__ void __launch_bounds__(64) k_abi_scan(int n_states, int n, int P, const T* __restrict__ table,
+                                                 const double* __restrict__ wtable, const T* q, T* Jhat,
+                                                 unsigned* status) {
+  extern __shared__ double abi_lds[];
+  const int lane = threadIdx.x;
+  const int k = lane & (P - 1);
+  const int64_t s = (int64_t)blockIdx.x * (64 / P) + lane / P;
+  const bool active = s < n_states;
+  const T* qs = q + (active ? s : 0) * n;
+  const Seg g = active ? segment_of(n, P, k) : Seg{0, 0};
+  bool ok = true;
+  Sym6<double> carry{};
+  bool has_carry = false;
+  if (SCAN) {
+    abi_store(abi_lds, 64, lane, abi_fold_segment<T>(n, g.a, g.b, table, wtable, qs, &ok));
+    for (int d = 1; d < P; d <<= 1) {
+      __syncthreads();
+      const bool upd = k + d < P;
+      AbiEl r;
+      if (upd) r = abi_compose(AbiView{abi_lds, 64, lane}, AbiView{abi_lds, 64, lane + d}, &ok);
+      __syncthreads();
+      if (upd) abi_store(abi_lds, 64, lane, r);
+    }
+    __syncthreads();
+    has_carry = k + 1 < P && !AbiView{abi_lds, 64, lane + 1}.ident();
+    if (has_carry) carry = AbiView{abi_lds, 64, lane + 1}.Q();
+  }
+  bool finite = true;
+  T* const out = Jhat + (active ? s : 0) * n * 36;
+  abi_serial_segment<T>(n, g.a, g.b, table, wtable, qs, carry,
+                        [&](int i, const Sym6<double>& J) {
+                          const M6 m = m6_of(J);
+                          T* o = out + (int64_t)i * 36;
+#pragma unroll
+                          for (int e = 0; e < 36; ++e) {
+                            const T v = (T)m.m[e];
+                            o[e] = v;
+                            finite = finite && __builtin_isfinite(v);
+                          }
+                        },
+                        &ok);
+  const unsigned bits = (finite ? 0u : kStatusNonFinite) | (ok ? 0u : kStatusPivot);
+  if (active && bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workspace of the articulated-inertia scan: the status word, then the link tables unless prepared.
+size_t abi_scan_ws_bytes(const pdyn_model* m, size_t scalar) {
+  return kStatusBytes + (m->prepared ? 0 : tables_bytes(m, scalar, nullptr));
+}
+
+// Lanes per state of the scan: the batch's `segments`, or by default the
+// smallest power of two that gives the batch 16384 lanes (one wavefront per
+// compute unit), at most 64 and at least 8 links per segment.
+int abi_scan_lanes(const pdyn_model* m, const pdyn_batch* b) {
+  if (b->segments > 0) return b->segments;
+  int P = 1;
+  while (P < 64 && (int64_t)b->n_states * P < 16384 && m->n_links_max >= 16 * P) P *= 2;
+  return P;
+}
+
+template <class T>
+int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, void* ws, size_t ws_bytes,
+                 void* stream) {
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, Jhat, m->placement, m->twist, m->inertia}))) return st;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  if (ws_bytes < abi_scan_ws_bytes(m, sizeof(T))) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned* status = static_cast<unsigned*>(ws);
+  char* base = static_cast<char*>(ws) + kStatusBytes;
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  size_t woff;
+  tables_bytes(m, sizeof(T), &woff);
+  const int P = abi_scan_lanes(m, b);
+  const int64_t per_block = 64 / P;
+  const int64_t grid = ((int64_t)b->n_states + per_block - 1) / per_block;
+  const size_t lds = P > 1 ? (size_t)kAbiElWords * 64 * sizeof(double) : 0;
+  const T* const tab = reinterpret_cast<const T*>(tbase);
+  const double* const wtab = reinterpret_cast<const double*>(tbase + woff);
+  if (P > 1)
+    hipLaunchKernelGGL((k_abi_scan<T, true>), dim3((unsigned)grid), dim3(64), lds, s, b->n_states,
+                       (int)m->n_links_max, P, tab, wtab, q, Jhat, status);
+  else
+    hipLaunchKernelGGL((k_abi_scan<T, false>), dim3((unsigned)grid), dim3(64), 0, s, b->n_states,
+                       (int)m->n_links_max, 1, tab, wtab, q, Jhat, status);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
 size_t rollout_layout(int with_grad, const pdyn_model* m, const pdyn_batch* b, int every, size_t scalar,
                       size_t* scratch_off, size_t* rows_off, size_t* acc_off) {
   size_t woff;
@@ -2579,6 +2683,8 @@ size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* b
     return jl.total;
   }
   if (op == PDYN_OP_RNEA_ID_HESSIAN) return model->n_chains == 1 ? hessian_ws_bytes(model, (size_t)scalar_bytes) : 0;
+  if (op == PDYN_OP_ARTICULATED_INERTIA)
+    return model->n_chains == 1 ? abi_scan_ws_bytes(model, (size_t)scalar_bytes) : 0;
   if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX) return 0;
   const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
@@ -2688,6 +2794,15 @@ int pdyn_rnea_id_hessian_f64(const pdyn_model* m, const pdyn_batch* b, const dou
                              const double* qdd, double* H_qq, double* H_qqd, double* H_qdqd, double* H_qqdd,
                              void* ws, size_t ws_bytes, void* stream) {
   return run_id_hessian<double>(m, b, q, qd, qdd, H_qq, H_qqd, H_qdqd, H_qqdd, ws, ws_bytes, stream);
+}
+
+int pdyn_articulated_inertia(const pdyn_model* m, const pdyn_batch* b, const float* q, float* Jhat, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return run_abi_scan<float>(m, b, q, Jhat, ws, ws_bytes, stream);
+}
+int pdyn_articulated_inertia_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, double* Jhat, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  return run_abi_scan<double>(m, b, q, Jhat, ws, ws_bytes, stream);
 }
 int pdyn_rnea_id_jacobian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
                           const float* qdd, float* J_q, float* J_qd, float* J_qdd, void* ws, size_t ws_bytes,
