@@ -110,7 +110,8 @@ def parse():
     p.add_argument("--profile-workload", choices=("32link", "uneven", "hessian", "abi"), default="32link",
                    help="with --profile-only: the 32-link, 16384-state batch, the uneven 4096-chain batch, "
                         "the second derivatives of the 32-link chain at 1024 states, or the articulated-body "
-                        "inertias of a 512-link chain at 256 states (serial, then the 64-lane scan)")
+                        "inertias and the scanned forward dynamics of a 512-link chain at 256 states (each "
+                        "serially, then with 64 lanes per state)")
     return p.parse_args()
 
 
@@ -381,6 +382,45 @@ def bench_abi_scan(args, dev):
     return rows
 
 
+def bench_fd_scan(args, dev):
+    """Forward dynamics with every recursion scanned (pdyn_aba_fd_scan, FP32 entry: FP32 inputs and qdd,
+    double inside) at every lane count per state, against the library's default forward-dynamics kernel
+    (pdyn_aba_fd, FP32 with FP64 wrench recursions, serial per state)."""
+    import torch
+    from paper_1609_04493_amd import api, synth
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    for n, B in ((1024, 64), (512, 256), (128, 1024), (N_LINKS, N_STATES)):
+        ch = synth.make_chains([n], synth.config_seed(4))
+        st = synth.make_states((B, n), synth.config_seed(4))
+        model = api.Model(ch, dev, torch.float32)
+        q, qd, tau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (st.q, st.qd, st.tau))
+        qdd = torch.empty_like(q)
+        ws = api.Workspace()
+        by_p = {}
+        for P in (0, 1, 2, 4, 8, 16, 32, 64):
+            by_p[P] = time_windows(lambda: api.aba_fd_scan(model, q, qd, tau, segments=P, out=qdd, workspace=ws),
+                                   stream)["median_ms"]
+        status = api.read_status(dev)
+        scan_qdd = qdd.double().cpu().numpy()
+        ms_serial_kernel = time_windows(lambda: api.aba_fd(model, q, qd, tau, out=qdd, workspace=ws),
+                                        stream)["median_ms"]
+        status |= api.read_status(dev)
+        ref = qdd.double().cpu().numpy()
+        rel = np.linalg.norm(scan_qdd - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        best = min((p for p in by_p if p), key=lambda p: by_p[p])
+        rows[f"{n}_links_{B}_states"] = {
+            "us_by_lanes_per_state": {str(p): by_p[p] * 1e3 for p in by_p if p},
+            "us_default": by_p[0] * 1e3, "best_lanes": best, "serial_phases_over_best": by_p[1] / by_p[best],
+            "us_aba_fd_default_kernel": ms_serial_kernel * 1e3, "aba_fd_over_best_scan": ms_serial_kernel / by_p[best],
+            "evals_per_s_best": B / (by_p[best] * 1e-3), "status_bits": status,
+            "scan_vs_aba_fd_rel_diff": {"median": float(np.median(rel)), "max": float(rel.max())}}
+        print(f"scanned FD, {n} links x {B}: {rows[f'{n}_links_{B}_states']}", file=sys.stderr, flush=True)
+    rows["note"] = ("us per call (median of windows); default = the library's lane count for the batch "
+                    "(16384 lanes, at least 8 links per segment); aba_fd = the role-split kernel, FP32 bulk")
+    return rows
+
+
 def bench_fd_grad_50(args, dev):
     """50-link chain, 8192 states: FD, then the FD adjoint of L = ||qdd||^2 (inertia gradients on)."""
     import torch
@@ -492,11 +532,17 @@ def main():
     if args.profile_only and args.profile_workload == "abi":
         ach = synth.make_chains([512], synth.config_seed(3))
         aq = torch.as_tensor(synth.make_states((256, 512), synth.config_seed(3)).q, dtype=torch.float32).to(dev)
+        ast = synth.make_states((256, 512), synth.config_seed(3))
+        aqd, atau = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (ast.qd, ast.tau))
         amodel = api.Model(ach, dev, torch.float32)
         J = torch.empty((256, 512, 6, 6), device=dev)
+        aqdd = torch.empty_like(aq)
         for P in (1, 64):
             for _ in range(args.warmup + args.steps):
                 api.articulated_inertia(amodel, aq, segments=P, out=J, workspace=ws)
+        for P in (1, 64):
+            for _ in range(args.warmup + args.steps):
+                api.aba_fd_scan(amodel, aq, aqd, atau, segments=P, out=aqdd, workspace=ws)
         torch.cuda.synchronize()
         print("profile-only run done", flush=True)
         return 0
@@ -710,7 +756,8 @@ def main():
         others = {}
         for name, fn in (("uneven_4096_chains", bench_uneven), ("jsiia_vs_aba", bench_jsiia),
                          ("fd_grad_50_links", bench_fd_grad_50), ("rollout_grad_100_links", bench_rollout_100),
-                         ("id_hessian", bench_hessian), ("articulated_inertia_scan", bench_abi_scan)):
+                         ("id_hessian", bench_hessian), ("articulated_inertia_scan", bench_abi_scan),
+                         ("fd_scan", bench_fd_scan)):
             others[name] = fn(args, dev)
             print(f"{name}: {json.dumps(others[name])}", file=sys.stderr, flush=True)
         out["other_workloads"] = others

@@ -188,7 +188,8 @@ enum {
   PDYN_OP_RNEA_ID_JACOBIAN = 7,
   PDYN_OP_ABA_FD_JACOBIAN = 8,
   PDYN_OP_RNEA_ID_HESSIAN = 9,
-  PDYN_OP_ARTICULATED_INERTIA = 10
+  PDYN_OP_ARTICULATED_INERTIA = 10,
+  PDYN_OP_ABA_FD_SCAN = 11
 };
 
 /* Bytes of device workspace that operation op needs for this model and batch
@@ -408,6 +409,38 @@ int pdyn_articulated_inertia(const pdyn_model* model, const pdyn_batch* batch, c
                              void* workspace, size_t workspace_bytes, void* stream);
 int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, double* Jhat,
                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Forward dynamics qdd = ABA(q, qd, tau) (Sec. II-B, eqs. (5), (7), (8)) of a
+ * shared chain (model->n_chains == 1; PDYN_EUNSUPPORTED otherwise) with every
+ * recursion evaluated as a prefix scan over a team of batch->segments lanes
+ * per state (P, a power of two 1 .. 64, PDYN_EINVAL otherwise; 0 = library
+ * default: the smallest P that gives the batch 32768 lanes, at most 64,
+ * keeping at least 8 links per segment):
+ *   1. velocities and bias accelerations of tau_bias (eq. (5)), base to tip,
+ *      scan operand of eqs. (12)-(13);
+ *   2. the articulated-body inertias (eq. (7)) by the Riccati scan of
+ *      pdyn_articulated_inertia;
+ *   3. the bias wrench and z-hat / c-hat (eqs. (2), (8); operand eq. (18) with
+ *      the bias wrench carried in the same recursion), tip to base, a scan of
+ *      6x6 affine maps;
+ *   4. lambda and qdd (eq. (8), operand eq. (19)), base to tip, likewise.
+ * Each phase folds each lane's segment, combines the team's aggregates in
+ * log2(P) steps and reruns the segment from the result, so a state's latency
+ * is O(n / P + log P) steps instead of the serial recursions' O(n): this is
+ * the form for long chains with few states. P = 1 runs the same phases
+ * serially. Same arguments and results as pdyn_aba_fd (base motion and tip
+ * wrench from the batch; the other launch fields are ignored); everything
+ * after the joint angles' (sin, cos) runs in double. A pivot D_i = S_i^T
+ * Jhat_i S_i (or a pivot of the Riccati combines) that is not positive sets
+ * PDYN_STATUS_PIVOT, a non-finite qdd PDYN_STATUS_NONFINITE. Workspace:
+ * pdyn_workspace_bytes(PDYN_OP_ABA_FD_SCAN, ...), 112 bytes per link and
+ * state beyond the status word and tables.
+ */
+int pdyn_aba_fd_scan(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,
+                     const float* tau, float* qdd, void* workspace, size_t workspace_bytes, void* stream);
+int pdyn_aba_fd_scan_f64(const pdyn_model* model, const pdyn_batch* batch, const double* q, const double* qd,
+                         const double* tau, double* qdd, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * pdyn_id_fd without a workspace argument, for callers that cannot allocate

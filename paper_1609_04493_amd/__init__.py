@@ -7,10 +7,10 @@ binding; ``synth`` is the seeded input generator.
 """
 
 from .api import (GRAVITY_ACC, STATUS_NONFINITE, STATUS_PIVOT, Model, PdynError, Workspace, aba_fd, aba_fd_vjp,
-                  articulated_inertia, id_fd, lib, read_status, rnea_id, rnea_id_vjp)
+                  aba_fd_scan, articulated_inertia, id_fd, lib, read_status, rnea_id, rnea_id_vjp)
 from .autograd import forward_dynamics, inverse_dynamics
 from .jacobian import fd_jacobians, id_hessians, id_jacobians
 
 __all__ = ["GRAVITY_ACC", "STATUS_NONFINITE", "STATUS_PIVOT", "Model", "PdynError", "Workspace", "aba_fd",
-           "aba_fd_vjp", "articulated_inertia", "fd_jacobians", "forward_dynamics", "id_fd", "id_hessians", "id_jacobians", "inverse_dynamics", "lib",
+           "aba_fd_scan", "aba_fd_vjp", "articulated_inertia", "fd_jacobians", "forward_dynamics", "id_fd", "id_hessians", "id_jacobians", "inverse_dynamics", "lib",
            "read_status", "rnea_id", "rnea_id_vjp"]

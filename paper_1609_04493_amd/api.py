@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdyn.so")
 
 OP_RNEA_ID, OP_ABA_FD, OP_ID_FD, OP_RNEA_ID_VJP, OP_ABA_FD_VJP, OP_JSIIA_FD, OP_MASS_MATRIX = 0, 1, 2, 3, 4, 5, 6
-OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN, OP_RNEA_ID_HESSIAN, OP_ARTICULATED_INERTIA = 7, 8, 9, 10
+OP_RNEA_ID_JACOBIAN, OP_ABA_FD_JACOBIAN, OP_RNEA_ID_HESSIAN, OP_ARTICULATED_INERTIA, OP_ABA_FD_SCAN = 7, 8, 9, 10, 11
 GRAVITY_ACC = (0.0, 0.0, 9.81, 0.0, 0.0, 0.0)
 ZERO6 = (0.0,) * 6
 
@@ -50,7 +50,7 @@ _ENTRY_ARITY = {
     "pdyn_jsiia_fd": 4, "pdyn_mass_matrix": 2,
     "pdyn_rnea_id_jacobian": 6, "pdyn_aba_fd_jacobian": 6,
     "pdyn_rnea_id_hessian": 7,
-    "pdyn_articulated_inertia": 2,
+    "pdyn_articulated_inertia": 2, "pdyn_aba_fd_scan": 4,
 }
 
 
@@ -440,6 +440,22 @@ def articulated_inertia(model: Model, q, segments=0, out=None, workspace=None):
     _call("pdyn_articulated_inertia", OP_ARTICULATED_INERTIA, model, n_states, (q, J), ZERO6, ZERO6, None,
           workspace, segments=segments)
     return J
+
+
+def aba_fd_scan(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, segments=0, out=None,
+                workspace=None):
+    """qdd = FD(q, qd, tau) of a shared chain by pdyn_aba_fd_scan: every recursion of the articulated-body
+    algorithm as a prefix scan over `segments` lanes per state (a power of two 1..64; 0 = the library's
+    choice). [B, n]."""
+    n_states = _n_states(model, q)
+    if model.n_chains != 1:
+        raise PdynError("pdyn_aba_fd_scan: needs one chain shared by the batch")
+    _prep(model, (q, qd, tau, tip))
+    qdd = torch.empty_like(q) if out is None else out
+    _prep(model, (qdd,))
+    _call("pdyn_aba_fd_scan", OP_ABA_FD_SCAN, model, n_states, (q, qd, tau, qdd), base_vel, base_acc, tip,
+          workspace, segments=segments)
+    return qdd
 
 
 def mass_matrix(model: Model, q, out=None, workspace=None):

@@ -38,6 +38,7 @@
 
 #include "../../include/pdyn.h"
 #include "abi_scan.hpp"
+#include "fd_scan.hpp"
 #include "hessian.hpp"
 #include "jsiia.hpp"
 #include "sweeps.hpp"
@@ -2305,13 +2306,16 @@ size_t abi_scan_ws_bytes(const pdyn_model* m, size_t scalar) {
   return kStatusBytes + (m->prepared ? 0 : tables_bytes(m, scalar, nullptr));
 }
 
-// Lanes per state of the scan: the batch's `segments`, or by default the
-// smallest power of two that gives the batch 16384 lanes (one wavefront per
-// compute unit), at most 64 and at least 8 links per segment.
-int abi_scan_lanes(const pdyn_model* m, const pdyn_batch* b) {
+// Lanes per state of the scans: the batch's `segments`, or by default the
+// smallest power of two that gives the batch `target` lanes, at most 64 and
+// at least 8 links per segment. The articulated inertias alone take 16384
+// lanes (one wavefront per compute unit); the scanned forward dynamics,
+// whose serial phases hold four recursions, pays for twice as many (measured
+// best at 32 x 16384, 128 x 1024, 512 x 256 and 1024 x 64 links x states).
+int abi_scan_lanes(const pdyn_model* m, const pdyn_batch* b, int64_t target = 16384) {
   if (b->segments > 0) return b->segments;
   int P = 1;
-  while (P < 64 && (int64_t)b->n_states * P < 16384 && m->n_links_max >= 16 * P) P *= 2;
+  while (P < 64 && (int64_t)b->n_states * P < target && m->n_links_max >= 16 * P) P *= 2;
   return P;
 }
 
@@ -2346,6 +2350,156 @@ int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, 
   else
     hipLaunchKernelGGL((k_abi_scan<T, false>), dim3((unsigned)grid), dim3(64), 0, s, b->n_states,
                        (int)m->n_links_max, 1, tab, wtab, q, Jhat, status);
+  if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
+  return PDYN_OK;
+}
+
+// Forward dynamics of a shared chain with every recursion scanned (fd_scan.hpp):
+// a team of P lanes per state as in k_abi_scan, four phases of fold, Kogge-Stone
+// scan through LDS ([85 words][64 lanes] doubles, reused by every phase) and
+// apply. Per-link values (Fhat, U, 1/D, c-hat) in `scratch`, [n_states][n][14]
+// doubles; a lane touches only its own links there, so the phases need no
+// ordering beyond the workgroup barriers around the LDS exchanges.
+template <class T>
+__global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, const T* __restrict__ table,
+                                                const double* __restrict__ wtable, const T* q, const T* qd,
+                                                const T* tau, T* qdd, const T* tip, BoundaryArgs<T> ba,
+                                                double* scratch, unsigned* status) {
+  extern __shared__ double fs_lds[];
+  const int lane = threadIdx.x;
+  const int k = lane & (P - 1);
+  const int64_t s = (int64_t)blockIdx.x * (64 / P) + lane / P;
+  const bool active = s < n_states;
+  const int64_t so = active ? s : 0;
+  const T* const qs = q + so * n;
+  const T* const qds = qd + so * n;
+  const T* const taus = tau + so * n;
+  const Seg g = active ? segment_of(n, P, k) : Seg{0, 0};
+  const FdScanScr scr{scratch + so * n * kFdScanWords};
+  const Sp<double> V0 = {v3((double)ba.V0[0], (double)ba.V0[1], (double)ba.V0[2]),
+                         v3((double)ba.V0[3], (double)ba.V0[4], (double)ba.V0[5])};
+  const Sp<double> dV0 = {v3((double)ba.dV0[0], (double)ba.dV0[1], (double)ba.dV0[2]),
+                          v3((double)ba.dV0[3], (double)ba.dV0[4], (double)ba.dV0[5])};
+  Sp<double> Ftip = sp_zero<double>();
+  if (tip) {
+    const T* f = tip + 6 * so;
+    Ftip = {v3((double)f[0], (double)f[1], (double)f[2]), v3((double)f[3], (double)f[4], (double)f[5])};
+  }
+  bool ok = true;
+  // 1: velocities and bias accelerations (inclusive prefix), then Fhat
+  fwd_store(fs_lds, 64, lane, fds_bias_fold<T>(g, table, wtable, qs, qds, V0, dV0));
+  for (int d = 1; d < P; d <<= 1) {
+    __syncthreads();
+    const bool upd = k >= d;
+    FwdOp<double> r;
+    if (upd) r = fwd_combine(fwd_load(fs_lds, 64, lane), fwd_load(fs_lds, 64, lane - d));
+    __syncthreads();
+    if (upd) fwd_store(fs_lds, 64, lane, r);
+  }
+  __syncthreads();
+  Sp<double> dV = dV0, V = V0;
+  if (k > 0) {
+    const FwdOp<double> e = fwd_load(fs_lds, 64, lane - 1);
+    dV = e.x1;
+    V = e.x2;
+  }
+  __syncthreads();
+  fds_bias_apply<T>(g, table, wtable, qs, qds, dV, V, scr);
+  // 2: articulated inertias (inclusive suffix), then U and 1/D
+  abi_store(fs_lds, 64, lane, abi_fold_segment<T>(n, g.a, g.b, table, wtable, qs, &ok));
+  for (int d = 1; d < P; d <<= 1) {
+    __syncthreads();
+    const bool upd = k + d < P;
+    AbiEl r;
+    if (upd) r = abi_compose(AbiView{fs_lds, 64, lane}, AbiView{fs_lds, 64, lane + d}, &ok);
+    __syncthreads();
+    if (upd) abi_store(fs_lds, 64, lane, r);
+  }
+  __syncthreads();
+  Sym6<double> carry{};
+  if (k + 1 < P && !AbiView{fs_lds, 64, lane + 1}.ident()) carry = AbiView{fs_lds, 64, lane + 1}.Q();
+  __syncthreads();
+  fds_abi_apply<T>(n, g, table, wtable, qs, carry, scr, &ok);
+  // 3: bias wrench and z-hat (inclusive suffix), then c-hat
+  aff_store(fs_lds, 64, lane, fds_z_fold<T>(n, g, table, wtable, qs, taus, scr));
+  for (int d = 1; d < P; d <<= 1) {
+    __syncthreads();
+    const bool upd = k + d < P;
+    AffEl r;
+    if (upd) r = aff_compose(aff_load(fs_lds, 64, lane), aff_load(fs_lds, 64, lane + d));
+    __syncthreads();
+    if (upd) aff_store(fs_lds, 64, lane, r);
+  }
+  __syncthreads();
+  Sp<double> Pc = Ftip;
+  if (k + 1 < P) {
+    const AffEl e = aff_load(fs_lds, 64, lane + 1);
+    Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
+  }
+  __syncthreads();
+  fds_z_apply<T>(n, g, table, wtable, qs, taus, Pc, scr);
+  // 4: lambda (inclusive prefix), then qdd
+  aff_store(fs_lds, 64, lane, fds_l_fold<T>(g, table, wtable, qs, scr));
+  for (int d = 1; d < P; d <<= 1) {
+    __syncthreads();
+    const bool upd = k >= d;
+    AffEl r;
+    if (upd) r = aff_compose(aff_load(fs_lds, 64, lane), aff_load(fs_lds, 64, lane - d));
+    __syncthreads();
+    if (upd) aff_store(fs_lds, 64, lane, r);
+  }
+  __syncthreads();
+  const Sp<double> lam = k > 0 ? aff_load_c(fs_lds, 64, lane - 1) : sp_zero<double>();
+  bool finite = true;
+  T* const out = qdd + so * n;
+  fds_l_apply<T>(g, table, wtable, qs, lam, scr, [&](int i, double v) {
+    const T x = (T)v;
+    out[i] = x;
+    finite = finite && __builtin_isfinite(x);
+  });
+  const unsigned bits = (finite ? 0u : kStatusNonFinite) | (ok ? 0u : kStatusPivot);
+  if (active && bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workspace of the scanned forward dynamics: the status word, the link tables
+// unless prepared, then the per-link scratch, [n_states][n][kFdScanWords] doubles.
+size_t fd_scan_ws_bytes(const pdyn_model* m, const pdyn_batch* b, size_t scalar, size_t* scratch_off) {
+  const size_t t = kStatusBytes + (m->prepared ? 0 : align_up(tables_bytes(m, scalar, nullptr)));
+  if (scratch_off) *scratch_off = t;
+  return t + align_up((size_t)b->n_states * (size_t)m->n_links_max * kFdScanWords * sizeof(double));
+}
+
+template <class T>
+int run_fd_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* tau, T* qdd, void* ws,
+                size_t ws_bytes, void* stream) {
+  int st = check_model_batch(m, b);
+  if (st) return st;
+  if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
+  if (b->n_states == 0) return PDYN_OK;
+  if ((st = check_ptrs<T>({q, qd, tau, qdd, m->placement, m->twist, m->inertia}))) return st;
+  if (b->tip_wrench && !aligned(b->tip_wrench, sizeof(T))) return PDYN_EALIGN;
+  if (m->prepared && !aligned(m->prepared, kAlign)) return PDYN_EALIGN;
+  if (!ws) return PDYN_EINVAL;
+  if (!aligned(ws, kAlign)) return PDYN_EALIGN;
+  size_t scratch_off;
+  if (ws_bytes < fd_scan_ws_bytes(m, b, sizeof(T), &scratch_off)) return PDYN_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned* status = static_cast<unsigned*>(ws);
+  char* base = static_cast<char*>(ws) + kStatusBytes;
+  const char* tbase = m->prepared ? static_cast<const char*>(m->prepared) : base;
+  if (!m->prepared && (st = launch_link_table<T>(m, base, s))) return st;
+  size_t woff;
+  tables_bytes(m, sizeof(T), &woff);
+  BoundaryArgs<T> ba;
+  for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
+  const int P = abi_scan_lanes(m, b, 32768);
+  const int64_t per_block = 64 / P;
+  const int64_t grid = ((int64_t)b->n_states + per_block - 1) / per_block;
+  hipLaunchKernelGGL(k_fd_scan<T>, dim3((unsigned)grid), dim3(64), (size_t)kAbiElWords * 64 * sizeof(double), s,
+                     b->n_states, (int)m->n_links_max, P, reinterpret_cast<const T*>(tbase),
+                     reinterpret_cast<const double*>(tbase + woff), q, qd, tau, qdd,
+                     static_cast<const T*>(b->tip_wrench), ba,
+                     reinterpret_cast<double*>(static_cast<char*>(ws) + scratch_off), status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -2685,6 +2839,8 @@ size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* b
   if (op == PDYN_OP_RNEA_ID_HESSIAN) return model->n_chains == 1 ? hessian_ws_bytes(model, (size_t)scalar_bytes) : 0;
   if (op == PDYN_OP_ARTICULATED_INERTIA)
     return model->n_chains == 1 ? abi_scan_ws_bytes(model, (size_t)scalar_bytes) : 0;
+  if (op == PDYN_OP_ABA_FD_SCAN)
+    return model->n_chains == 1 ? fd_scan_ws_bytes(model, batch, (size_t)scalar_bytes, nullptr) : 0;
   if (op < PDYN_OP_RNEA_ID || op > PDYN_OP_MASS_MATRIX) return 0;
   const pdyn_batch bt = tuned_batch(op, model, batch, (size_t)scalar_bytes);  // the launch the call will take
   Layout L;
@@ -2803,6 +2959,14 @@ int pdyn_articulated_inertia(const pdyn_model* m, const pdyn_batch* b, const flo
 int pdyn_articulated_inertia_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, double* Jhat, void* ws,
                                  size_t ws_bytes, void* stream) {
   return run_abi_scan<double>(m, b, q, Jhat, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_scan(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd, const float* tau,
+                     float* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_fd_scan<float>(m, b, q, qd, tau, qdd, ws, ws_bytes, stream);
+}
+int pdyn_aba_fd_scan_f64(const pdyn_model* m, const pdyn_batch* b, const double* q, const double* qd,
+                         const double* tau, double* qdd, void* ws, size_t ws_bytes, void* stream) {
+  return run_fd_scan<double>(m, b, q, qd, tau, qdd, ws, ws_bytes, stream);
 }
 int pdyn_rnea_id_jacobian(const pdyn_model* m, const pdyn_batch* b, const float* q, const float* qd,
                           const float* qdd, float* J_q, float* J_qd, float* J_qdd, void* ws, size_t ws_bytes,

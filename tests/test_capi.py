@@ -493,3 +493,33 @@ def test_articulated_inertia_host_rules():
     assert L.pdyn_workspace_bytes(10, ctypes.byref(m2), ctypes.byref(b2), 4) == 0
     empty = api._batch_struct(0, api.ZERO6, api.GRAVITY_ACC, None)
     assert fn(ctypes.byref(m), ctypes.byref(empty), p, p, w, need, None) == 0
+
+
+def test_aba_fd_scan_host_rules():
+    """pdyn_aba_fd_scan: shared chains only; workspace = status word + tables + 14 doubles per link and state."""
+    L = api.lib()
+    fn = L.pdyn_aba_fd_scan
+    m, keep = _fake_model(n=5)
+    b = api._batch_struct(3, api.ZERO6, api.GRAVITY_ACC, None)
+    x = np.zeros(64, np.float32)
+    p = x.ctypes.data
+    need = L.pdyn_workspace_bytes(11, ctypes.byref(m), ctypes.byref(b), 4)
+    tables = L.pdyn_model_prepared_bytes(ctypes.byref(m), 4)
+    assert need == 256 + (tables + 255) // 256 * 256 + (3 * 5 * 14 * 8 + 255) // 256 * 256
+    ws = np.zeros(need + 512, np.uint8)
+    w = ws.ctypes.data + ((-ws.ctypes.data) % 256)
+    assert fn(ctypes.byref(m), ctypes.byref(b), None, p, p, p, w, need, None) == -1
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p + 1, w, need, None) == -2
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need - 1, None) == -3
+    b.segments = 3
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need, None) == -1
+    b.segments = 0
+    lp = np.array([0, 3, 6], np.int32)
+    m2, keep2 = _fake_model(n=6, n_chains=2, link_ptr=lp)
+    m2.n_links_max = 3
+    m2.link_ptr_host = lp.ctypes.data
+    b2 = api._batch_struct(2, api.ZERO6, api.GRAVITY_ACC, None)
+    assert fn(ctypes.byref(m2), ctypes.byref(b2), p, p, p, p, w, need, None) == -5
+    assert L.pdyn_workspace_bytes(11, ctypes.byref(m2), ctypes.byref(b2), 4) == 0
+    empty = api._batch_struct(0, api.ZERO6, api.GRAVITY_ACC, None)
+    assert fn(ctypes.byref(m), ctypes.byref(empty), p, p, p, p, w, need, None) == 0

@@ -1,0 +1,91 @@
+"""Forward dynamics with every recursion scanned (fd_scan.hpp) on the CPU (host build) against the FP64 oracle.
+
+Four phases, each a fold over a lane's segment, a Kogge-Stone scan across the
+team in the kernel's order and a rerun: bias velocities and accelerations
+(eqs. (12)-(13)), articulated inertias (the Riccati scan of eq. (7)), the
+bias wrench with z-hat (affine, eq. (18)) and lambda (affine, eq. (19)). Every
+segment count must reproduce the oracle's serial ABA, with base motion and a
+tip wrench.
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_04493_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kernel_cpu", "fd_scan_on_cpu.hip")
+SEGMENTS = (1, 2, 4, 8, 16, 32, 64)
+
+
+@pytest.fixture(scope="module")
+def fds_lib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("fcpu") / "libfds_cpu.so")
+    hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    extra = os.environ.get("PDYN_HOST_BUILD_FLAGS", "").split()  # set by the sanitizer run (test_sanitized_cpu)
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-host-only", *extra, "-o", out, SRC],
+                   check=True)
+    lib = ctypes.CDLL(out)
+    for f in (lib.cpu_fd_scan_f32, lib.cpu_fd_scan_f64):
+        f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 10
+        f.restype = ctypes.c_int
+    return lib
+
+
+def fd_scan(lib, P, ch, st, tip=None, V0=np.zeros(6), dV0=np.array(oracle.GRAVITY_ACC), dtype=np.float64):
+    B, n = st.q.shape
+    dt = np.dtype(dtype)
+    c = lambda a: None if a is None else np.ascontiguousarray(a, dtype=dt)
+    args = [c(ch.placement), c(ch.twist), c(ch.inertia), c(st.q), c(st.qd), c(st.tau), c(V0), c(dV0), c(tip)]
+    out = np.full((B, n), np.nan, dt)
+    fn = lib.cpu_fd_scan_f64 if dt == np.float64 else lib.cpu_fd_scan_f32
+    bad = fn(P, B, n, *[None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in args],
+             out.ctypes.data_as(ctypes.c_void_p))
+    return out.astype(np.float64), bad
+
+
+def state_rel(x, ref):
+    return (np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+
+
+@pytest.mark.parametrize("n", [1, 3, 7, 33, 100])
+def test_fp64_every_segment_count_equals_oracle(fds_lib, n):
+    ch = synth.make_chains([n], 500 + n)
+    st = synth.make_states((3, n), 500 + n)
+    rng = np.random.default_rng(n)
+    tip, V0, dV0 = rng.normal(size=(3, 6)), rng.normal(size=6), rng.normal(size=6)
+    ref = np.stack([oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s]) for s in range(3)])
+    for P in SEGMENTS:
+        qdd, bad = fd_scan(fds_lib, P, ch, st, tip, V0, dV0)
+        assert bad == 0
+        assert state_rel(qdd, ref) <= 1e-11, P
+
+
+def test_fp32_inputs(fds_lib):
+    n = 100
+    ch = synth.make_chains([n], 170)
+    chr_ = synth.Chains(*(a.astype(np.float32).astype(np.float64) for a in (ch.placement, ch.twist, ch.inertia)),
+                        ch.link_ptr)
+    st = synth.make_states((3, n), 170).rounded()
+    ref = np.stack([oracle.aba1(chr_, st.q[s], st.qd[s], st.tau[s]) for s in range(3)])
+    for P in (1, 16, 64):
+        qdd, bad = fd_scan(fds_lib, P, chr_, st, dtype=np.float32)
+        assert bad == 0 and state_rel(qdd, ref) <= 2e-6, P
+
+
+def test_long_chain(fds_lib):
+    """512 links: the 64-lane scan against the serial phases and the oracle."""
+    n = 512
+    ch = synth.make_chains([n], 582)
+    st = synth.make_states((2, n), 582)
+    q1, b1 = fd_scan(fds_lib, 1, ch, st)
+    q64, b64 = fd_scan(fds_lib, 64, ch, st)
+    assert b1 == 0 and b64 == 0
+    assert state_rel(q64, q1) <= 1e-10
+    ref = np.stack([oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s]) for s in range(2)])
+    assert state_rel(q64, ref) <= 1e-9

@@ -2,7 +2,7 @@
 
 Builds oracle/oracle_capi.cpp with clang and -fsanitize=address,undefined,
 then re-runs the CPU tests that exercise it and the host builds of
-sweeps.hpp, team.hpp, jsiia.hpp, hessian.hpp and abi_scan.hpp (compiled with the same sanitizers on the
+sweeps.hpp, team.hpp, jsiia.hpp, hessian.hpp, abi_scan.hpp and fd_scan.hpp (compiled with the same sanitizers on the
 host pass only) in a child process with the sanitizer runtime preloaded. Any
 out-of-bounds access, use after free or undefined behaviour (signed overflow,
 misaligned or null access, invalid shift, ...) aborts the child.
@@ -20,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 SAN = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined", "-shared-libasan"]
 TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_grad.py", "tests/test_kernel_math_cpu.py",
          "tests/test_team_cpu.py", "tests/test_jsiia_cpu.py", "tests/test_oracle_hessian.py",
-         "tests/test_hessian_cpu.py", "tests/test_abi_scan_cpu.py"]
+         "tests/test_hessian_cpu.py", "tests/test_abi_scan_cpu.py", "tests/test_fd_scan_cpu.py"]
 
 
 def _runtime():
