@@ -332,7 +332,7 @@ def bench_hessian(args, dev):
             out = {b: torch.empty((B, n, n, n), dtype=dt, device=dev) for b in api.HESSIAN_BLOCKS}
             ws = api.Workspace()
             ms = time_windows(lambda: api.rnea_id_hessian(model, q, qd, qdd, out=out, workspace=ws), stream)["median_ms"]
-            threads = 4 * B * n * n
+            threads = B * (n * (n + 1) + 2 * n * n)  # (q, q) and (qd, qd) symmetric: j <= k only
             tflops = threads * hessian_thread_flops(n) / (ms * 1e-3) / 1e12
             name = "f32" if dt == torch.float32 else "f64"
             rows[f"{n}_links_{B}_states_{name}"] = {
@@ -342,7 +342,8 @@ def bench_hessian(args, dev):
             del out
         print(f"hessian, {n} links: { {k: v for k, v in rows.items() if k.startswith(f'{n}_links')} }",
               file=sys.stderr, flush=True)
-    rows["note"] = ("one thread per (state, block, j, k): forward and reversed-forward hyper-dual passes, "
+    rows["note"] = ("one thread per (state, block, j, k), j <= k in the symmetric (q, q) and (qd, qd) blocks: "
+                    "forward and reversed-forward hyper-dual passes, "
                     f"{hessian_thread_flops(32)} flops per thread at 32 links; bound by vector ALU")
     return rows
 
@@ -417,7 +418,7 @@ def bench_fd_scan(args, dev):
             "scan_vs_aba_fd_rel_diff": {"median": float(np.median(rel)), "max": float(rel.max())}}
         print(f"scanned FD, {n} links x {B}: {rows[f'{n}_links_{B}_states']}", file=sys.stderr, flush=True)
     rows["note"] = ("us per call (median of windows); default = the library's lane count for the batch "
-                    "(16384 lanes, at least 8 links per segment); aba_fd = the role-split kernel, FP32 bulk")
+                    "(32768 lanes, at least 4 links per segment); aba_fd = the role-split kernel, FP32 bulk")
     return rows
 
 

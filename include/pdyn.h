@@ -366,7 +366,8 @@ int pdyn_aba_fd_jacobian_f64(const pdyn_model* model, const pdyn_batch* batch, c
  * and is then not computed; at least one must be given (PDYN_EINVAL). Base
  * motion and the tip wrench (held fixed) come from the batch. Exact up to
  * rounding: the recursions run on hyper-dual numbers, one thread per (state,
- * block, j, k). A non-finite entry sets PDYN_STATUS_NONFINITE in the
+ * block, j, k), with j <= k only in the two symmetric blocks (each such thread
+ * writes both halves). A non-finite entry sets PDYN_STATUS_NONFINITE in the
  * workspace's status word. Workspace: pdyn_workspace_bytes(PDYN_OP_RNEA_ID_HESSIAN,
  * ...); the batch's launch fields are ignored.
  */
@@ -389,7 +390,7 @@ int pdyn_rnea_id_hessian_f64(const pdyn_model* model, const pdyn_batch* batch, c
  *
  * batch->segments: lanes per state P, a power of two 1 .. 64 (PDYN_EINVAL
  * otherwise); 0 = library default (the smallest P that gives the batch 16384
- * lanes, at most 64, keeping at least 8 links per segment). P = 1 is the
+ * lanes, at most 64, keeping at least 4 links per segment). P = 1 is the
  * serial recursion, one lane per state; with P > 1 each lane folds a
  * consecutive segment of links into one element, the lanes combine them with
  * log2(P) scan steps, and each lane reruns its segment from the result. Both
@@ -416,7 +417,7 @@ int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batc
  * recursion evaluated as a prefix scan over a team of batch->segments lanes
  * per state (P, a power of two 1 .. 64, PDYN_EINVAL otherwise; 0 = library
  * default: the smallest P that gives the batch 32768 lanes, at most 64,
- * keeping at least 8 links per segment):
+ * keeping at least 4 links per segment):
  *   1. velocities and bias accelerations of tau_bias (eq. (5)), base to tip,
  *      scan operand of eqs. (12)-(13);
  *   2. the articulated-body inertias (eq. (7)) by the Riccati scan of

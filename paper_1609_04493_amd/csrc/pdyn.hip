@@ -2173,36 +2173,65 @@ int run_jacobian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* 
 }
 
 // Second derivatives of a shared chain's inverse dynamics: one thread per
-// (state, requested block, j, k); the e1e2 parts of tau_0..tau_{n-1} go to
-// H_b[s][i][j][k], so for each i the threads of a wavefront (k fastest) write
-// consecutive words.
+// (state, requested block, j, k), the e1e2 parts of tau_0..tau_{n-1} going to
+// H_b[s][i][j][k]. The (q, q) and (qd, qd) blocks are symmetric in (j, k): their
+// threads take j <= k only and write both H[i][j][k] and H[i][k][j]. Within a
+// block the threads run over rows j with k fastest, so for each i a wavefront
+// writes consecutive words.
 template <class T> struct HessOut {
   T* p[4];     // output of each requested block, in request order
   int blk[4];  // its block code (0 (q,q), 1 (q,qd), 2 (qd,qd), 3 (q,qdd))
   int nb;
 };
+PD_HD bool hess_symmetric(int block) { return block == 0 || block == 2; }
+// Threads of one state: n(n+1)/2 for a symmetric block, n^2 otherwise.
+template <class T> PD_HD int64_t hess_threads_per_state(const HessOut<T>& ho, int n) {
+  int64_t per = 0;
+  for (int b = 0; b < ho.nb; ++b) per += hess_symmetric(ho.blk[b]) ? (int64_t)n * (n + 1) / 2 : (int64_t)n * n;
+  return per;
+}
 
 template <class T>
 __global__ void __launch_bounds__(256) k_id_hessian(int64_t n_states, int n, const T* table, const T* q,
                                                     const T* qd, const T* qdd, BoundaryArgs<T> ba, const T* tip,
                                                     HessOut<T> ho, unsigned* status) {
-  const int64_t nn = (int64_t)n * n, per = (int64_t)ho.nb * nn, total = n_states * per;
+  const int64_t nn = (int64_t)n * n, per = hess_threads_per_state(ho, n), total = n_states * per;
   const Sp<T> V0 = {v3(ba.V0[0], ba.V0[1], ba.V0[2]), v3(ba.V0[3], ba.V0[4], ba.V0[5])};
   const Sp<T> dV0 = {v3(ba.dV0[0], ba.dV0[1], ba.dV0[2]), v3(ba.dV0[3], ba.dV0[4], ba.dV0[5])};
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = t / per, r = t - s * per;
-    const int bi = (int)(r / nn), jk = (int)(r - (int64_t)bi * nn);
-    const int j = jk / n, k = jk - j * n;
+    const int64_t s = t / per;
+    int64_t r = t - s * per;
+    int bi = 0;
+    for (; bi < ho.nb - 1; ++bi) {
+      const int64_t c = hess_symmetric(ho.blk[bi]) ? (int64_t)n * (n + 1) / 2 : nn;
+      if (r < c) break;
+      r -= c;
+    }
+    const bool sym = hess_symmetric(ho.blk[bi]);
+    int j, k;
+    if (sym) {  // row j holds k = j .. n-1
+      j = 0;
+      while (r >= n - j) {
+        r -= n - j;
+        ++j;
+      }
+      k = j + (int)r;
+    } else {
+      j = (int)(r / n);
+      k = (int)(r - (int64_t)j * n);
+    }
     Sp<T> F;
     if (tip) {
       const T* f = tip + 6 * s;
       F = {v3(f[0], f[1], f[2]), v3(f[3], f[4], f[5])};
     }
-    T* const H = ho.p[bi] + s * nn * n + jk;
+    T* const H = ho.p[bi] + s * nn * n;
+    const int64_t jk = (int64_t)j * n + k, kj = (int64_t)k * n + j;
     bool finite = true;
     id_hessian_one<T>(n, table, q + s * n, qd + s * n, qdd + s * n, V0, dV0, tip ? &F : nullptr, ho.blk[bi], j, k,
                       [&](int i, T v) {
-                        H[(int64_t)i * nn] = v;
+                        H[(int64_t)i * nn + jk] = v;
+                        if (sym && j != k) H[(int64_t)i * nn + kj] = v;
                         finite = finite && isfinite(v);
                       });
     if (!finite) atomicOr(status, PDYN_STATUS_NONFINITE);
@@ -2239,7 +2268,7 @@ int run_id_hessian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   const int64_t n = m->n_links_max;
-  const int64_t total = (int64_t)b->n_states * ho.nb * n * n;
+  const int64_t total = (int64_t)b->n_states * hess_threads_per_state(ho, (int)n);
   const int64_t grid = std::min<int64_t>((total + 255) / 256, int64_t(1) << 16);
   hipLaunchKernelGGL(k_id_hessian<T>, dim3((unsigned)grid), dim3(256), 0, s, (int64_t)b->n_states, (int)n,
                      reinterpret_cast<const T*>(tbase), q, qd, qdd, ba, static_cast<const T*>(b->tip_wrench), ho,
@@ -2308,14 +2337,15 @@ size_t abi_scan_ws_bytes(const pdyn_model* m, size_t scalar) {
 
 // Lanes per state of the scans: the batch's `segments`, or by default the
 // smallest power of two that gives the batch `target` lanes, at most 64 and
-// at least 8 links per segment. The articulated inertias alone take 16384
+// at least 4 links per segment. The articulated inertias alone take 16384
 // lanes (one wavefront per compute unit); the scanned forward dynamics,
 // whose serial phases hold four recursions, pays for twice as many (measured
-// best at 32 x 16384, 128 x 1024, 512 x 256 and 1024 x 64 links x states).
+// best at 32 x 16384, 128 x 1024 (4 links per segment), 512 x 256 and
+// 1024 x 64 links x states).
 int abi_scan_lanes(const pdyn_model* m, const pdyn_batch* b, int64_t target = 16384) {
   if (b->segments > 0) return b->segments;
   int P = 1;
-  while (P < 64 && (int64_t)b->n_states * P < target && m->n_links_max >= 16 * P) P *= 2;
+  while (P < 64 && (int64_t)b->n_states * P < target && m->n_links_max >= 8 * P) P *= 2;
   return P;
 }
 
