@@ -435,7 +435,7 @@ int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batc
  * after the joint angles' (sin, cos) runs in double. A pivot D_i = S_i^T
  * Jhat_i S_i (or a pivot of the Riccati combines) that is not positive sets
  * PDYN_STATUS_PIVOT, a non-finite qdd PDYN_STATUS_NONFINITE. Workspace:
- * pdyn_workspace_bytes(PDYN_OP_ABA_FD_SCAN, ...), 112 bytes per link and
+ * pdyn_workspace_bytes(PDYN_OP_ABA_FD_SCAN, ...), 208 bytes per link and
  * state beyond the status word and tables.
  */
 int pdyn_aba_fd_scan(const pdyn_model* model, const pdyn_batch* batch, const float* q, const float* qd,

@@ -424,20 +424,20 @@ PD_HD Pose<double> abi_pose(Tab table, WTab wtable, const T* q, int i) {
 }
 
 // The aggregate e_a o ... o e_{b-1} of links [a, b) of an n-link chain (identity if a == b), folded
-// from the tip end of the segment.
-template <class T, class Tab, class WTab>
-PD_HD AbiEl abi_fold_segment(int n, int a, int b, Tab table, WTab wtable, const T* q, bool* pivot_ok) {
+// from the tip end of the segment. pose(i) gives f_{i-1,i} in double.
+template <class WTab, class PoseOf>
+PD_HD AbiEl abi_fold_segment(int n, int a, int b, WTab wtable, const PoseOf& pose, bool* pivot_ok) {
   if (a >= b) return abi_identity();
   const int last = b - 1;
   Pose<double> g_next;
   Sp<double> S_next = sp_zero<double>();
   if (last < n - 1) {
-    g_next = abi_pose<T>(table, wtable, q, last + 1);
+    g_next = pose(last + 1);
     S_next = link_at(wtable, last + 1).S;
   }
   AbiEl agg = abi_link(last == n - 1, sym6_from_inertia(inertia_of(link_at(wtable, last))), g_next, S_next);
   for (int i = last - 1; i >= a; --i) {
-    g_next = abi_pose<T>(table, wtable, q, i + 1);
+    g_next = pose(i + 1);
     S_next = link_at(wtable, i + 1).S;
     agg = abi_fold_link(sym6_from_inertia(inertia_of(link_at(wtable, i))), g_next, S_next, agg, pivot_ok);
   }
@@ -446,8 +446,8 @@ PD_HD AbiEl abi_fold_segment(int n, int a, int b, Tab table, WTab wtable, const 
 
 // The serial recursion (7) over links [a, b), tip end first, from carry = Jhat_b (used when b < n):
 // out(i, Jhat_i) for i = b-1 .. a.
-template <class T, class Tab, class WTab, class Out>
-PD_HD void abi_serial_segment(int n, int a, int b, Tab table, WTab wtable, const T* q, const Sym6<double>& carry,
+template <class WTab, class PoseOf, class Out>
+PD_HD void abi_serial_segment(int n, int a, int b, WTab wtable, const PoseOf& pose, const Sym6<double>& carry,
                               const Out& out, bool* pivot_ok) {
   Sym6<double> Jh = carry;
   for (int i = b - 1; i >= a; --i) {
@@ -459,10 +459,18 @@ PD_HD void abi_serial_segment(int n, int a, int b, Tab table, WTab wtable, const
       const Sp<double> U = mul(Jh, S);
       const double D = dot(S, U);
       *pivot_ok = *pivot_ok && D > 0.0;
-      Jh = sym6_add(Ji, congruence_to_parent(abi_pose<T>(table, wtable, q, i + 1), sym6_minus_outer(Jh, U, 1.0 / D)));
+      Jh = sym6_add(Ji, congruence_to_parent(pose(i + 1), sym6_minus_outer(Jh, U, 1.0 / D)));
     }
     out(i, Jh);
   }
 }
+
+// Link transforms formed from the joint angles wherever they are asked for.
+template <class T, class Tab, class WTab> struct AbiPoses {
+  Tab table;
+  WTab wtable;
+  const T* q;
+  PD_HD Pose<double> operator()(int i) const { return abi_pose<T>(table, wtable, q, i); }
+};
 
 }  // namespace pdyn

@@ -25,16 +25,17 @@
 //     again a 6x6 matrix and an offset.
 //
 // Everything after the joint angles' (sin, cos) is double. Each lane keeps
-// its own links' Fhat_i, U_i, 1/D_i and c-hat_i in per-state scratch
-// (kFdScanWords doubles per link) and reads no other lane's; link transforms
-// are formed again wherever a phase needs them.
+// its own links' transforms f_{i-1,i} (formed once, in phase 1), Fhat_i, U_i,
+// 1/D_i and c-hat_i in per-state scratch (kFdScanWords doubles per link) and
+// reads no other lane's: the one transform a phase needs beyond the segment
+// (that of the next segment's first link) it forms itself.
 #pragma once
 
 #include "abi_scan.hpp"
 
 namespace pdyn {
 
-constexpr int kFdScanWords = 14;  // Fhat (6), U (6), 1 / D, c-hat
+constexpr int kFdScanWords = 26;  // Fhat (6), U (6), 1 / D, c-hat, then f_{i-1,i} (R row-major, p)
 
 // An affine map x -> M x + c on 6-vectors.
 struct AffEl {
@@ -127,15 +128,43 @@ struct FdScanScr {
   PD_HD double* at(int i) const { return p + (long)i * kFdScanWords; }
   PD_HD void put_sp(int i, int w, const Sp<double>& x) const { sp_to(x, at(i) + w); }
   PD_HD Sp<double> get_sp(int i, int w) const { return sp_of(at(i) + w); }
+  PD_HD void put_pose(int i, const Pose<double>& g) const {
+    double* w = at(i) + 14;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = g.R.m[k];
+    w[9] = g.p.x; w[10] = g.p.y; w[11] = g.p.z;
+  }
+  PD_HD Pose<double> get_pose(int i) const {
+    const double* w = at(i) + 14;
+    Pose<double> g;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g.R.m[k] = w[k];
+    g.p = v3(w[9], w[10], w[11]);
+    return g;
+  }
+};
+
+// f_{i-1,i} for a lane whose segment is sg: its own links' from the scratch (after phase 1), any other
+// link's formed from the joint angle.
+template <class T, class Tab, class WTab> struct FdPoses {
+  Seg sg;
+  Tab table;
+  WTab wtable;
+  const T* q;
+  FdScanScr scr;
+  PD_HD Pose<double> operator()(int i) const {
+    return (i >= sg.a && i < sg.b) ? scr.get_pose(i) : abi_pose<T>(table, wtable, q, i);
+  }
 };
 
 // ---- phase 1: velocities and bias accelerations, base to tip ----------------------
 
 // The segment's operand; the lane that owns link 0 starts from the base values, so that its x1, x2 are
-// the true values at its last link (team.hpp, pass 1).
+// the true values at its last link (team.hpp, pass 1). The segment's link transforms are formed here,
+// once, and kept in the scratch for the later phases.
 template <class T, class Tab, class WTab>
 PD_HD FwdOp<double> fds_bias_fold(Seg sg, Tab table, WTab wtable, const T* q, const T* qd, const Sp<double>& V0,
-                                  const Sp<double>& dV0) {
+                                  const Sp<double>& dV0, const FdScanScr& scr) {
   FwdOp<double> op = fwd_identity<double>();
   if (sg.a == 0 && sg.b > 0) {
     op.x1 = dV0;
@@ -143,6 +172,7 @@ PD_HD FwdOp<double> fds_bias_fold(Seg sg, Tab table, WTab wtable, const T* q, co
   }
   for (int i = sg.a; i < sg.b; ++i) {
     const Pose<double> g = abi_pose<T>(table, wtable, q, i);
+    scr.put_pose(i, g);
     const Sp<double> XV = X_twist(g, op.x2);
     const Sp<double> Sqd = (double)qd[i] * link_at(wtable, i).S;
     op.x1 = X_twist(g, op.x1) - ad_twist(Sqd, XV);
@@ -153,11 +183,10 @@ PD_HD FwdOp<double> fds_bias_fold(Seg sg, Tab table, WTab wtable, const T* q, co
 }
 
 // From (dV, V) at the link before the segment: Fhat_i of every link of the segment.
-template <class T, class Tab, class WTab>
-PD_HD void fds_bias_apply(Seg sg, Tab table, WTab wtable, const T* q, const T* qd, Sp<double> dV, Sp<double> V,
-                          const FdScanScr& scr) {
+template <class T, class WTab>
+PD_HD void fds_bias_apply(Seg sg, WTab wtable, const T* qd, Sp<double> dV, Sp<double> V, const FdScanScr& scr) {
   for (int i = sg.a; i < sg.b; ++i) {
-    const Pose<double> g = abi_pose<T>(table, wtable, q, i);
+    const Pose<double> g = scr.get_pose(i);
     const Link<double> L = link_at(wtable, i);
     const Inertia<double> J = inertia_of(L);
     const Sp<double> XV = X_twist(g, V);
@@ -170,10 +199,10 @@ PD_HD void fds_bias_apply(Seg sg, Tab table, WTab wtable, const T* q, const T* q
 
 // ---- phase 2: U_i and 1 / D_i from the articulated-body inertias -------------------
 
-template <class T, class Tab, class WTab>
-PD_HD void fds_abi_apply(int n, Seg sg, Tab table, WTab wtable, const T* q, const Sym6<double>& carry,
+template <class WTab, class PoseOf>
+PD_HD void fds_abi_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, const Sym6<double>& carry,
                          const FdScanScr& scr, bool* pivot_ok) {
-  abi_serial_segment<T>(n, sg.a, sg.b, table, wtable, q, carry,
+  abi_serial_segment(n, sg.a, sg.b, wtable, pose, carry,
                         [&](int i, const Sym6<double>& Jh) {
                           const Sp<double> U = mul(Jh, link_at(wtable, i).S);
                           const double D = dot(link_at(wtable, i).S, U);
@@ -194,8 +223,8 @@ struct ZLin {
 };
 
 // The segment's map from P at its tip end (P_{b+1}, or the tip wrench when b = n) to P_a.
-template <class T, class Tab, class WTab>
-PD_HD AffEl fds_z_fold(int n, Seg sg, Tab table, WTab wtable, const T* q, const T* tau, const FdScanScr& scr) {
+template <class T, class WTab, class PoseOf>
+PD_HD AffEl fds_z_fold(int n, Seg sg, WTab wtable, const PoseOf& pose, const T* tau, const FdScanScr& scr) {
   AffEl agg = aff_identity();
   for (int i = sg.b - 1; i >= sg.a; --i) {
     const ZLin z{scr.get_sp(i, 6), link_at(wtable, i).S, scr.at(i)[12]};
@@ -203,7 +232,7 @@ PD_HD AffEl fds_z_fold(int n, Seg sg, Tab table, WTab wtable, const T* q, const 
     if (i == n - 1) {
       agg = aff_after([&](const Sp<double>& v) { return z.K(v); }, off, agg);
     } else {
-      const Pose<double> gn = abi_pose<T>(table, wtable, q, i + 1);
+      const Pose<double> gn = pose(i + 1);
       agg = aff_after([&](const Sp<double>& v) { return z.K(XT_wrench(gn, v)); }, off, agg);
     }
   }
@@ -211,12 +240,12 @@ PD_HD AffEl fds_z_fold(int n, Seg sg, Tab table, WTab wtable, const T* q, const 
 }
 
 // From P at the segment's tip end: c-hat_i of every link of the segment.
-template <class T, class Tab, class WTab>
-PD_HD void fds_z_apply(int n, Seg sg, Tab table, WTab wtable, const T* q, const T* tau, Sp<double> P,
+template <class T, class WTab, class PoseOf>
+PD_HD void fds_z_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, const T* tau, Sp<double> P,
                        const FdScanScr& scr) {
   for (int i = sg.b - 1; i >= sg.a; --i) {
     const Sp<double> S = link_at(wtable, i).S;
-    const Sp<double> W = (i == n - 1 ? P : XT_wrench(abi_pose<T>(table, wtable, q, i + 1), P)) + scr.get_sp(i, 0);
+    const Sp<double> W = (i == n - 1 ? P : XT_wrench(pose(i + 1), P)) + scr.get_sp(i, 0);
     const double invD = scr.at(i)[12];
     const double chat = ((double)tau[i] - dot(S, W)) * invD;
     scr.at(i)[13] = chat;
@@ -227,11 +256,11 @@ PD_HD void fds_z_apply(int n, Seg sg, Tab table, WTab wtable, const T* q, const 
 // ---- phase 4: lambda and qdd, base to tip --------------------------------------------
 
 // The segment's map from lambda before its first link to lambda at its last.
-template <class T, class Tab, class WTab>
-PD_HD AffEl fds_l_fold(Seg sg, Tab table, WTab wtable, const T* q, const FdScanScr& scr) {
+template <class WTab>
+PD_HD AffEl fds_l_fold(Seg sg, WTab wtable, const FdScanScr& scr) {
   AffEl agg = aff_identity();
   for (int i = sg.a; i < sg.b; ++i) {
-    const Pose<double> g = abi_pose<T>(table, wtable, q, i);
+    const Pose<double> g = scr.get_pose(i);
     const Sp<double> S = link_at(wtable, i).S, U = scr.get_sp(i, 6);
     const double invD = scr.at(i)[12];
     agg = aff_after(
@@ -245,11 +274,10 @@ PD_HD AffEl fds_l_fold(Seg sg, Tab table, WTab wtable, const T* q, const FdScanS
 }
 
 // From lambda before the segment: qdd_i of every link, out(i, qdd_i).
-template <class T, class Tab, class WTab, class Out>
-PD_HD void fds_l_apply(Seg sg, Tab table, WTab wtable, const T* q, Sp<double> lambda, const FdScanScr& scr,
-                       const Out& out) {
+template <class WTab, class Out>
+PD_HD void fds_l_apply(Seg sg, WTab wtable, Sp<double> lambda, const FdScanScr& scr, const Out& out) {
   for (int i = sg.a; i < sg.b; ++i) {
-    const Sp<double> a = X_twist(abi_pose<T>(table, wtable, q, i), lambda);
+    const Sp<double> a = X_twist(scr.get_pose(i), lambda);
     const Sp<double> S = link_at(wtable, i).S;
     const double qdd = scr.at(i)[13] - dot(scr.get_sp(i, 6), a) * scr.at(i)[12];
     lambda = a + qdd * S;

@@ -2295,11 +2295,12 @@ __global__ void __launch_bounds__(64) k_abi_scan(int n_states, int n, int P, con
   const bool active = s < n_states;
   const T* qs = q + (active ? s : 0) * n;
   const Seg g = active ? segment_of(n, P, k) : Seg{0, 0};
+  const AbiPoses<T, const T*, const double*> poses{table, wtable, qs};
   bool ok = true;
   Sym6<double> carry{};
   bool has_carry = false;
   if (SCAN) {
-    abi_store(abi_lds, 64, lane, abi_fold_segment<T>(n, g.a, g.b, table, wtable, qs, &ok));
+    abi_store(abi_lds, 64, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
     for (int d = 1; d < P; d <<= 1) {
       __syncthreads();
       const bool upd = k + d < P;
@@ -2314,7 +2315,7 @@ __global__ void __launch_bounds__(64) k_abi_scan(int n_states, int n, int P, con
   }
   bool finite = true;
   T* const out = Jhat + (active ? s : 0) * n * 36;
-  abi_serial_segment<T>(n, g.a, g.b, table, wtable, qs, carry,
+  abi_serial_segment(n, g.a, g.b, wtable, poses, carry,
                         [&](int i, const Sym6<double>& J) {
                           const M6 m = m6_of(J);
                           T* o = out + (int64_t)i * 36;
@@ -2387,9 +2388,10 @@ int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, 
 // Forward dynamics of a shared chain with every recursion scanned (fd_scan.hpp):
 // a team of P lanes per state as in k_abi_scan, four phases of fold, Kogge-Stone
 // scan through LDS ([85 words][64 lanes] doubles, reused by every phase) and
-// apply. Per-link values (Fhat, U, 1/D, c-hat) in `scratch`, [n_states][n][14]
-// doubles; a lane touches only its own links there, so the phases need no
-// ordering beyond the workgroup barriers around the LDS exchanges.
+// apply. Per-link values (Fhat, U, 1/D, c-hat, the link transform) in `scratch`,
+// [n_states][n][kFdScanWords] doubles; a lane touches only its own links there,
+// so the phases need no ordering beyond the workgroup barriers around the LDS
+// exchanges.
 template <class T>
 __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, const T* __restrict__ table,
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
@@ -2406,6 +2408,7 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
   const T* const taus = tau + so * n;
   const Seg g = active ? segment_of(n, P, k) : Seg{0, 0};
   const FdScanScr scr{scratch + so * n * kFdScanWords};
+  const FdPoses<T, const T*, const double*> poses{g, table, wtable, qs, scr};
   const Sp<double> V0 = {v3((double)ba.V0[0], (double)ba.V0[1], (double)ba.V0[2]),
                          v3((double)ba.V0[3], (double)ba.V0[4], (double)ba.V0[5])};
   const Sp<double> dV0 = {v3((double)ba.dV0[0], (double)ba.dV0[1], (double)ba.dV0[2]),
@@ -2417,7 +2420,7 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
   }
   bool ok = true;
   // 1: velocities and bias accelerations (inclusive prefix), then Fhat
-  fwd_store(fs_lds, 64, lane, fds_bias_fold<T>(g, table, wtable, qs, qds, V0, dV0));
+  fwd_store(fs_lds, 64, lane, fds_bias_fold<T>(g, table, wtable, qs, qds, V0, dV0, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k >= d;
@@ -2434,9 +2437,9 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
     V = e.x2;
   }
   __syncthreads();
-  fds_bias_apply<T>(g, table, wtable, qs, qds, dV, V, scr);
+  fds_bias_apply<T>(g, wtable, qds, dV, V, scr);
   // 2: articulated inertias (inclusive suffix), then U and 1/D
-  abi_store(fs_lds, 64, lane, abi_fold_segment<T>(n, g.a, g.b, table, wtable, qs, &ok));
+  abi_store(fs_lds, 64, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k + d < P;
@@ -2449,9 +2452,9 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
   Sym6<double> carry{};
   if (k + 1 < P && !AbiView{fs_lds, 64, lane + 1}.ident()) carry = AbiView{fs_lds, 64, lane + 1}.Q();
   __syncthreads();
-  fds_abi_apply<T>(n, g, table, wtable, qs, carry, scr, &ok);
+  fds_abi_apply(n, g, wtable, poses, carry, scr, &ok);
   // 3: bias wrench and z-hat (inclusive suffix), then c-hat
-  aff_store(fs_lds, 64, lane, fds_z_fold<T>(n, g, table, wtable, qs, taus, scr));
+  aff_store(fs_lds, 64, lane, fds_z_fold<T>(n, g, wtable, poses, taus, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k + d < P;
@@ -2467,9 +2470,9 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
     Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
   }
   __syncthreads();
-  fds_z_apply<T>(n, g, table, wtable, qs, taus, Pc, scr);
+  fds_z_apply<T>(n, g, wtable, poses, taus, Pc, scr);
   // 4: lambda (inclusive prefix), then qdd
-  aff_store(fs_lds, 64, lane, fds_l_fold<T>(g, table, wtable, qs, scr));
+  aff_store(fs_lds, 64, lane, fds_l_fold(g, wtable, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k >= d;
@@ -2482,7 +2485,7 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
   const Sp<double> lam = k > 0 ? aff_load_c(fs_lds, 64, lane - 1) : sp_zero<double>();
   bool finite = true;
   T* const out = qdd + so * n;
-  fds_l_apply<T>(g, table, wtable, qs, lam, scr, [&](int i, double v) {
+  fds_l_apply(g, wtable, lam, scr, [&](int i, double v) {
     const T x = (T)v;
     out[i] = x;
     finite = finite && __builtin_isfinite(x);

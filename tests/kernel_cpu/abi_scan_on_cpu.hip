@@ -34,10 +34,11 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
   std::vector<AbiEl> nx(P);
   for (int s = 0; s < n_states; ++s) {
     const T* qs = q + (int64_t)s * n;
+    const AbiPoses<T, const T*, const double*> poses{table.data(), wtable.data(), qs};
     bool ok = true;
     for (int k = 0; k < P; ++k) {
       const Seg g = segment_of(n, P, k);
-      abi_store(store.data(), P, k, abi_fold_segment<T>(n, g.a, g.b, table.data(), wtable.data(), qs, &ok));
+      abi_store(store.data(), P, k, abi_fold_segment(n, g.a, g.b, wtable.data(), poses, &ok));
     }
     for (int d = 1; d < P; d <<= 1) {
       for (int k = 0; k + d < P; ++k)
@@ -49,7 +50,7 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
       Sym6<double> carry{};
       const bool has = k + 1 < P && !AbiView{store.data(), P, k + 1}.ident();
       if (has) carry = AbiView{store.data(), P, k + 1}.Q();
-      abi_serial_segment<T>(n, g.a, g.b, table.data(), wtable.data(), qs, carry,
+      abi_serial_segment(n, g.a, g.b, wtable.data(), poses, carry,
                             [&](int i, const Sym6<double>& J) {
                               const M6 m = m6_of(J);
                               for (int e = 0; e < 36; ++e) Jhat[((int64_t)s * n + i) * 36 + e] = (T)m.m[e];

@@ -38,6 +38,7 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
   for (int s = 0; s < n_states; ++s) {
     const T *qs = q + (int64_t)s * n, *qds = qd + (int64_t)s * n, *taus = tau + (int64_t)s * n;
     const FdScanScr scr{scratch.data()};
+    auto poses = [&](Seg g) { return FdPoses<T, const T*, const double*>{g, table.data(), wtable.data(), qs, scr}; };
     Sp<double> Ftip = sp_zero<double>();
     if (tip) {
       const T* f = tip + 6 * (int64_t)s;
@@ -47,7 +48,7 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
     double* st = store.data();
     // 1: velocities and bias accelerations, inclusive prefix
     for (int k = 0; k < P; ++k)
-      fwd_store(st, P, k, fds_bias_fold<T>(segment_of(n, P, k), table.data(), wtable.data(), qs, qds, v0, dv0));
+      fwd_store(st, P, k, fds_bias_fold<T>(segment_of(n, P, k), table.data(), wtable.data(), qs, qds, v0, dv0, scr));
     for (int d = 1; d < P; d <<= 1) {
       for (int k = d; k < P; ++k) nf[k] = fwd_combine(fwd_load(st, P, k), fwd_load(st, P, k - d));
       for (int k = d; k < P; ++k) fwd_store(st, P, k, nf[k]);
@@ -59,12 +60,12 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
         dV = e.x1;
         V = e.x2;
       }
-      fds_bias_apply<T>(segment_of(n, P, k), table.data(), wtable.data(), qs, qds, dV, V, scr);
+      fds_bias_apply<T>(segment_of(n, P, k), wtable.data(), qds, dV, V, scr);
     }
     // 2: articulated inertias, inclusive suffix
     for (int k = 0; k < P; ++k) {
       const Seg g = segment_of(n, P, k);
-      abi_store(st, P, k, abi_fold_segment<T>(n, g.a, g.b, table.data(), wtable.data(), qs, &ok));
+      abi_store(st, P, k, abi_fold_segment(n, g.a, g.b, wtable.data(), poses(g), &ok));
     }
     for (int d = 1; d < P; d <<= 1) {
       for (int k = 0; k + d < P; ++k) na[k] = abi_compose(AbiView{st, P, k}, AbiView{st, P, k + d}, &ok);
@@ -73,11 +74,11 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
     for (int k = 0; k < P; ++k) {
       Sym6<double> carry{};
       if (k + 1 < P && !AbiView{st, P, k + 1}.ident()) carry = AbiView{st, P, k + 1}.Q();
-      fds_abi_apply<T>(n, segment_of(n, P, k), table.data(), wtable.data(), qs, carry, scr, &ok);
+      fds_abi_apply(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), carry, scr, &ok);
     }
     // 3: bias wrench and z-hat, inclusive suffix
     for (int k = 0; k < P; ++k)
-      aff_store(st, P, k, fds_z_fold<T>(n, segment_of(n, P, k), table.data(), wtable.data(), qs, taus, scr));
+      aff_store(st, P, k, fds_z_fold<T>(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), taus, scr));
     for (int d = 1; d < P; d <<= 1) {
       for (int k = 0; k + d < P; ++k) nz[k] = aff_compose(aff_load(st, P, k), aff_load(st, P, k + d));
       for (int k = 0; k + d < P; ++k) aff_store(st, P, k, nz[k]);
@@ -88,18 +89,18 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
         const AffEl e = aff_load(st, P, k + 1);
         Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
       }
-      fds_z_apply<T>(n, segment_of(n, P, k), table.data(), wtable.data(), qs, taus, Pc, scr);
+      fds_z_apply<T>(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), taus, Pc, scr);
     }
     // 4: lambda and qdd, inclusive prefix
     for (int k = 0; k < P; ++k)
-      aff_store(st, P, k, fds_l_fold<T>(segment_of(n, P, k), table.data(), wtable.data(), qs, scr));
+      aff_store(st, P, k, fds_l_fold(segment_of(n, P, k), wtable.data(), scr));
     for (int d = 1; d < P; d <<= 1) {
       for (int k = d; k < P; ++k) nz[k] = aff_compose(aff_load(st, P, k), aff_load(st, P, k - d));
       for (int k = d; k < P; ++k) aff_store(st, P, k, nz[k]);
     }
     for (int k = 0; k < P; ++k) {
       const Sp<double> lam = k > 0 ? aff_load_c(st, P, k - 1) : sp_zero<double>();
-      fds_l_apply<T>(segment_of(n, P, k), table.data(), wtable.data(), qs, lam, scr,
+      fds_l_apply(segment_of(n, P, k), wtable.data(), lam, scr,
                      [&](int i, double v) { qdd[(int64_t)s * n + i] = (T)v; });
     }
     if (!ok) ++bad;

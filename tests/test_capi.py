@@ -496,7 +496,7 @@ def test_articulated_inertia_host_rules():
 
 
 def test_aba_fd_scan_host_rules():
-    """pdyn_aba_fd_scan: shared chains only; workspace = status word + tables + 14 doubles per link and state."""
+    """pdyn_aba_fd_scan: shared chains only; workspace = status word + tables + 26 doubles per link and state."""
     L = api.lib()
     fn = L.pdyn_aba_fd_scan
     m, keep = _fake_model(n=5)
@@ -505,7 +505,7 @@ def test_aba_fd_scan_host_rules():
     p = x.ctypes.data
     need = L.pdyn_workspace_bytes(11, ctypes.byref(m), ctypes.byref(b), 4)
     tables = L.pdyn_model_prepared_bytes(ctypes.byref(m), 4)
-    assert need == 256 + (tables + 255) // 256 * 256 + (3 * 5 * 14 * 8 + 255) // 256 * 256
+    assert need == 256 + (tables + 255) // 256 * 256 + (3 * 5 * 26 * 8 + 255) // 256 * 256
     ws = np.zeros(need + 512, np.uint8)
     w = ws.ctypes.data + ((-ws.ctypes.data) % 256)
     assert fn(ctypes.byref(m), ctypes.byref(b), None, p, p, p, w, need, None) == -1
