@@ -98,3 +98,18 @@ def test_empty_batch_and_pivot_status(device):
     for P in (1, 4):
         api.articulated_inertia(mb, dev(st.q, device, torch.float64), segments=P)
         assert api.read_status(device) & api.STATUS_PIVOT, P
+
+
+def test_unprepared_tables(device):
+    """Tables derived inside the workspace (no pdyn_model_prepare) give the same Jhat bit for bit."""
+    n, B = 100, 9
+    print(f"case: articulated inertia unprepared tables {n} links x {B}", flush=True)
+    ch = synth.make_chains([n], 8)
+    st = synth.make_states((B, n), 8)
+    for dt in (torch.float64, torch.float32):
+        q = dev(st.q, device, dt)
+        for P in (1, 16):
+            a = api.articulated_inertia(api.Model(ch, device, dt), q, segments=P).cpu().numpy()
+            b = api.articulated_inertia(api.Model(ch, device, dt, prepare=False), q, segments=P).cpu().numpy()
+            assert np.array_equal(a, b), (dt, P)
+    assert api.read_status(device) == 0

@@ -90,3 +90,20 @@ def test_empty_batch_and_pivot_status(device):
     for P in (1, 4):
         api.aba_fd_scan(mb, q, qd, tau, segments=P)
         assert api.read_status(device) & api.STATUS_PIVOT, P
+
+
+def test_unprepared_tables_and_agreement_with_aba_fd(device):
+    """Tables derived inside the workspace (no pdyn_model_prepare) give the same qdd bit for bit; the FP32
+    scan agrees with the role-split forward dynamics (pdyn_aba_fd) at the 512-link workload."""
+    n, B = 512, 64
+    print(f"case: scanned FD unprepared tables, vs pdyn_aba_fd, {n} links x {B}", flush=True)
+    ch = synth.make_chains([n], 4)
+    st = synth.make_states((B, n), 4)
+    for dt in (torch.float64, torch.float32):
+        q, qd, tau = (dev(a, device, dt) for a in (st.q, st.qd, st.tau))
+        a = api.aba_fd_scan(api.Model(ch, device, dt), q, qd, tau).cpu().numpy()
+        b = api.aba_fd_scan(api.Model(ch, device, dt, prepare=False), q, qd, tau).cpu().numpy()
+        assert api.read_status(device) == 0
+        assert np.array_equal(a, b)
+    ref = api.aba_fd(api.Model(ch, device, torch.float32), q, qd, tau).cpu().numpy().astype(np.float64)
+    assert state_rel(a.astype(np.float64), ref) <= 1e-3
