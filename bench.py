@@ -111,7 +111,7 @@ def parse():
                    help="with --profile-only: the 32-link, 16384-state batch, the uneven 4096-chain batch, "
                         "the second derivatives of the 32-link chain at 1024 states, or the articulated-body "
                         "inertias and the scanned forward dynamics of a 512-link chain at 256 states (each "
-                        "serially, then with 64 lanes per state)")
+                        "serially, then with 64 and 128 lanes per state)")
     return p.parse_args()
 
 
@@ -364,7 +364,7 @@ def bench_abi_scan(args, dev):
         J = torch.empty((B, n, 6, 6), device=dev)
         ws = api.Workspace()
         by_p = {}
-        for P in (0, 1, 2, 4, 8, 16, 32, 64):
+        for P in (0, 1, 2, 4, 8, 16, 32, 64, 128):
             by_p[P] = time_windows(lambda: api.articulated_inertia(model, q, segments=P, out=J, workspace=ws),
                                    stream)["median_ms"]
         status = api.read_status(dev)
@@ -399,7 +399,7 @@ def bench_fd_scan(args, dev):
         qdd = torch.empty_like(q)
         ws = api.Workspace()
         by_p = {}
-        for P in (0, 1, 2, 4, 8, 16, 32, 64):
+        for P in (0, 1, 2, 4, 8, 16, 32, 64, 128):
             by_p[P] = time_windows(lambda: api.aba_fd_scan(model, q, qd, tau, segments=P, out=qdd, workspace=ws),
                                    stream)["median_ms"]
         status = api.read_status(dev)
@@ -538,10 +538,10 @@ def main():
         amodel = api.Model(ach, dev, torch.float32)
         J = torch.empty((256, 512, 6, 6), device=dev)
         aqdd = torch.empty_like(aq)
-        for P in (1, 64):
+        for P in (1, 64, 128):
             for _ in range(args.warmup + args.steps):
                 api.articulated_inertia(amodel, aq, segments=P, out=J, workspace=ws)
-        for P in (1, 64):
+        for P in (1, 64, 128):
             for _ in range(args.warmup + args.steps):
                 api.aba_fd_scan(amodel, aq, aqd, atau, segments=P, out=aqdd, workspace=ws)
         torch.cuda.synchronize()

@@ -388,9 +388,10 @@ int pdyn_rnea_id_hessian_f64(const pdyn_model* model, const pdyn_batch* batch, c
  * such maps compose in closed form, so the recursion becomes a prefix scan of
  * 84-number elements.
  *
- * batch->segments: lanes per state P, a power of two 1 .. 64 (PDYN_EINVAL
- * otherwise); 0 = library default (the smallest P that gives the batch 16384
- * lanes, at most 64, keeping at least 4 links per segment). P = 1 is the
+ * batch->segments: lanes per state P, a power of two 1 .. 128 (PDYN_EINVAL
+ * otherwise; P = 128 spans two wavefronts of one workgroup); 0 = library
+ * default (the smallest P that gives the batch 16384 lanes, at most 128,
+ * keeping at least 4 links per segment). P = 1 is the
  * serial recursion, one lane per state; with P > 1 each lane folds a
  * consecutive segment of links into one element, the lanes combine them with
  * log2(P) scan steps, and each lane reruns its segment from the result. Both
@@ -415,8 +416,8 @@ int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batc
  * Forward dynamics qdd = ABA(q, qd, tau) (Sec. II-B, eqs. (5), (7), (8)) of a
  * shared chain (model->n_chains == 1; PDYN_EUNSUPPORTED otherwise) with every
  * recursion evaluated as a prefix scan over a team of batch->segments lanes
- * per state (P, a power of two 1 .. 64, PDYN_EINVAL otherwise; 0 = library
- * default: the smallest P that gives the batch 32768 lanes, at most 64,
+ * per state (P, a power of two 1 .. 128, PDYN_EINVAL otherwise; 0 = library
+ * default: the smallest P that gives the batch 32768 lanes, at most 128,
  * keeping at least 4 links per segment):
  *   1. velocities and bias accelerations of tau_bias (eq. (5)), base to tip,
  *      scan operand of eqs. (12)-(13);

@@ -429,7 +429,7 @@ def rnea_id_hessian(model: Model, q, qd, qdd, blocks=HESSIAN_BLOCKS, base_vel=ZE
 def articulated_inertia(model: Model, q, segments=0, out=None, workspace=None):
     """Articulated-body inertias Jhat_i of eq. (7) for every state of a shared chain by
     pdyn_articulated_inertia: [B, n, 6, 6], Jhat[s, i] that of link i+1 in its own frame (twist (v, w) to
-    wrench (f, n)). segments: lanes per state of the associative scan (a power of two 1..64; 1 = the serial
+    wrench (f, n)). segments: lanes per state of the associative scan (a power of two 1..128; 1 = the serial
     recursion; 0 = the library's choice for this batch)."""
     n_states = _n_states(model, q)
     if model.n_chains != 1:
@@ -445,7 +445,7 @@ def articulated_inertia(model: Model, q, segments=0, out=None, workspace=None):
 def aba_fd_scan(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, segments=0, out=None,
                 workspace=None):
     """qdd = FD(q, qd, tau) of a shared chain by pdyn_aba_fd_scan: every recursion of the articulated-body
-    algorithm as a prefix scan over `segments` lanes per state (a power of two 1..64; 0 = the library's
+    algorithm as a prefix scan over `segments` lanes per state (a power of two 1..128; 0 = the library's
     choice). [B, n]."""
     n_states = _n_states(model, q)
     if model.n_chains != 1:

@@ -48,6 +48,7 @@ namespace pdyn {
 namespace {
 
 constexpr int kMaxLinks = 1 << 16;
+constexpr int kMaxScanLanes = 128;  // lanes per state of the articulated-inertia and forward-dynamics scans
 constexpr int kMaxFdSegments = 16;  // team forward dynamics: 16 chains x 16 lanes + 2 wavefronts per workgroup
 constexpr int kBlock = 64;      // adjoint kernels, and the default workgroup
 constexpr int kMaxBlock = 256;  // largest workgroup of the tunable kernels
@@ -2278,20 +2279,21 @@ int run_id_hessian(const pdyn_model* m, const pdyn_batch* b, const T* q, const T
 }
 
 // Articulated-body inertias Jhat_i (eq. (7)) of a shared chain by the associative
-// scan of abi_scan.hpp: a team of P lanes per state (P a power of two, 1..64),
-// 64 / P states per 64-lane workgroup. P = 1 is the serial recursion, one lane
-// per state. With P > 1 the lanes of a team fold their segments, combine the
-// aggregates by a Kogge-Stone suffix scan through LDS ([kAbiElWords][64]
-// doubles, one slot per lane) and rerun their segments from the carry. Jhat is
-// written whole, [n_states][n][6][6].
-template <class T, bool SCAN>
-__global__ void __launch_bounds__(64) k_abi_scan(int n_states, int n, int P, const T* __restrict__ table,
+// scan of abi_scan.hpp: a team of P lanes per state (P a power of two, 1..128)
+// in workgroups of max(64, P) threads (64 / P states each, or one state whose
+// team spans P / 64 wavefronts). P = 1 is the serial recursion, one lane per
+// state. With P > 1 the lanes of a team fold their segments, combine the
+// aggregates by a Kogge-Stone suffix scan through LDS ([kAbiElWords][workgroup]
+// doubles, one slot per lane, workgroup barriers between the steps) and rerun
+// their segments from the carry. Jhat is written whole, [n_states][n][6][6].
+template <class T, bool SCAN, int BT>  // BT = workgroup threads, max(64, P)
+__global__ void __launch_bounds__(BT) k_abi_scan(int n_states, int n, int P, const T* __restrict__ table,
                                                  const double* __restrict__ wtable, const T* q, T* Jhat,
                                                  unsigned* status) {
   extern __shared__ double abi_lds[];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x;  // BT / P teams, or one team of P lanes over P / 64 wavefronts
   const int k = lane & (P - 1);
-  const int64_t s = (int64_t)blockIdx.x * (64 / P) + lane / P;
+  const int64_t s = (int64_t)blockIdx.x * (BT / P) + lane / P;
   const bool active = s < n_states;
   const T* qs = q + (active ? s : 0) * n;
   const Seg g = active ? segment_of(n, P, k) : Seg{0, 0};
@@ -2300,18 +2302,18 @@ __global__ void __launch_bounds__(64) k_abi_scan(int n_states, int n, int P, con
   Sym6<double> carry{};
   bool has_carry = false;
   if (SCAN) {
-    abi_store(abi_lds, 64, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
+    abi_store(abi_lds, BT, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
     for (int d = 1; d < P; d <<= 1) {
       __syncthreads();
       const bool upd = k + d < P;
       AbiEl r;
-      if (upd) r = abi_compose(AbiView{abi_lds, 64, lane}, AbiView{abi_lds, 64, lane + d}, &ok);
+      if (upd) r = abi_compose(AbiView{abi_lds, BT, lane}, AbiView{abi_lds, BT, lane + d}, &ok);
       __syncthreads();
-      if (upd) abi_store(abi_lds, 64, lane, r);
+      if (upd) abi_store(abi_lds, BT, lane, r);
     }
     __syncthreads();
-    has_carry = k + 1 < P && !AbiView{abi_lds, 64, lane + 1}.ident();
-    if (has_carry) carry = AbiView{abi_lds, 64, lane + 1}.Q();
+    has_carry = k + 1 < P && !AbiView{abi_lds, BT, lane + 1}.ident();
+    if (has_carry) carry = AbiView{abi_lds, BT, lane + 1}.Q();
   }
   bool finite = true;
   T* const out = Jhat + (active ? s : 0) * n * 36;
@@ -2346,14 +2348,30 @@ size_t abi_scan_ws_bytes(const pdyn_model* m, size_t scalar) {
 int abi_scan_lanes(const pdyn_model* m, const pdyn_batch* b, int64_t target = 16384) {
   if (b->segments > 0) return b->segments;
   int P = 1;
-  while (P < 64 && (int64_t)b->n_states * P < target && m->n_links_max >= 8 * P) P *= 2;
+  while (P < kMaxScanLanes && (int64_t)b->n_states * P < target && m->n_links_max >= 8 * P) P *= 2;
   return P;
 }
+
+// The scans take `segments` up to kMaxScanLanes (a power of two; 0 = default);
+// the rest of the batch is checked as for every call.
+int check_scan_batch(const pdyn_model* m, const pdyn_batch* b) {
+  if (!b) return PDYN_EINVAL;
+  pdyn_batch c = *b;
+  c.segments = 0;
+  const int st = check_model_batch(m, &c);
+  if (st) return st;
+  if (b->segments < 0 || b->segments > kMaxScanLanes || (b->segments & (b->segments - 1))) return PDYN_EINVAL;
+  return PDYN_OK;
+}
+
+// Workgroup threads and dynamic LDS of a scan launch with P lanes per state.
+unsigned scan_block(int P) { return P > 64 ? (unsigned)P : 64u; }
+size_t scan_lds(int P) { return (size_t)kAbiElWords * scan_block(P) * sizeof(double); }
 
 template <class T>
 int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, void* ws, size_t ws_bytes,
                  void* stream) {
-  int st = check_model_batch(m, b);
+  int st = check_scan_batch(m, b);
   if (st) return st;
   if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
   if (b->n_states == 0) return PDYN_OK;
@@ -2370,37 +2388,44 @@ int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, 
   size_t woff;
   tables_bytes(m, sizeof(T), &woff);
   const int P = abi_scan_lanes(m, b);
-  const int64_t per_block = 64 / P;
+  const unsigned block = scan_block(P);
+  const int64_t per_block = block / P;
   const int64_t grid = ((int64_t)b->n_states + per_block - 1) / per_block;
-  const size_t lds = P > 1 ? (size_t)kAbiElWords * 64 * sizeof(double) : 0;
+  const size_t lds = scan_lds(P);
   const T* const tab = reinterpret_cast<const T*>(tbase);
   const double* const wtab = reinterpret_cast<const double*>(tbase + woff);
-  if (P > 1)
-    hipLaunchKernelGGL((k_abi_scan<T, true>), dim3((unsigned)grid), dim3(64), lds, s, b->n_states,
+  if (P > 64) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_abi_scan<T, true, kMaxScanLanes>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return PDYN_ELAUNCH;
+    hipLaunchKernelGGL((k_abi_scan<T, true, kMaxScanLanes>), dim3((unsigned)grid), dim3(block), lds, s,
+                       b->n_states, (int)m->n_links_max, P, tab, wtab, q, Jhat, status);
+  } else if (P > 1)
+    hipLaunchKernelGGL((k_abi_scan<T, true, 64>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,
                        (int)m->n_links_max, P, tab, wtab, q, Jhat, status);
   else
-    hipLaunchKernelGGL((k_abi_scan<T, false>), dim3((unsigned)grid), dim3(64), 0, s, b->n_states,
+    hipLaunchKernelGGL((k_abi_scan<T, false, 64>), dim3((unsigned)grid), dim3(64), 0, s, b->n_states,
                        (int)m->n_links_max, 1, tab, wtab, q, Jhat, status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
 
 // Forward dynamics of a shared chain with every recursion scanned (fd_scan.hpp):
-// a team of P lanes per state as in k_abi_scan, four phases of fold, Kogge-Stone
-// scan through LDS ([85 words][64 lanes] doubles, reused by every phase) and
-// apply. Per-link values (Fhat, U, 1/D, c-hat, the link transform) in `scratch`,
+// a team of P lanes per state in workgroups as in k_abi_scan, four phases of
+// fold, Kogge-Stone scan through LDS ([85 words][workgroup] doubles, reused by
+// every phase) and apply. Per-link values (Fhat, U, 1/D, c-hat, the link transform) in `scratch`,
 // [n_states][n][kFdScanWords] doubles; a lane touches only its own links there,
 // so the phases need no ordering beyond the workgroup barriers around the LDS
 // exchanges.
-template <class T>
-__global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, const T* __restrict__ table,
+template <class T, int BT>  // BT = workgroup threads, max(64, P), as in k_abi_scan
+__global__ void __launch_bounds__(BT) k_fd_scan(int n_states, int n, int P, const T* __restrict__ table,
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
                                                 const T* tau, T* qdd, const T* tip, BoundaryArgs<T> ba,
                                                 double* scratch, unsigned* status) {
   extern __shared__ double fs_lds[];
   const int lane = threadIdx.x;
   const int k = lane & (P - 1);
-  const int64_t s = (int64_t)blockIdx.x * (64 / P) + lane / P;
+  const int64_t s = (int64_t)blockIdx.x * (BT / P) + lane / P;
   const bool active = s < n_states;
   const int64_t so = active ? s : 0;
   const T* const qs = q + so * n;
@@ -2420,69 +2445,69 @@ __global__ void __launch_bounds__(64) k_fd_scan(int n_states, int n, int P, cons
   }
   bool ok = true;
   // 1: velocities and bias accelerations (inclusive prefix), then Fhat
-  fwd_store(fs_lds, 64, lane, fds_bias_fold<T>(g, table, wtable, qs, qds, V0, dV0, scr));
+  fwd_store(fs_lds, BT, lane, fds_bias_fold<T>(g, table, wtable, qs, qds, V0, dV0, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k >= d;
     FwdOp<double> r;
-    if (upd) r = fwd_combine(fwd_load(fs_lds, 64, lane), fwd_load(fs_lds, 64, lane - d));
+    if (upd) r = fwd_combine(fwd_load(fs_lds, BT, lane), fwd_load(fs_lds, BT, lane - d));
     __syncthreads();
-    if (upd) fwd_store(fs_lds, 64, lane, r);
+    if (upd) fwd_store(fs_lds, BT, lane, r);
   }
   __syncthreads();
   Sp<double> dV = dV0, V = V0;
   if (k > 0) {
-    const FwdOp<double> e = fwd_load(fs_lds, 64, lane - 1);
+    const FwdOp<double> e = fwd_load(fs_lds, BT, lane - 1);
     dV = e.x1;
     V = e.x2;
   }
   __syncthreads();
   fds_bias_apply<T>(g, wtable, qds, dV, V, scr);
   // 2: articulated inertias (inclusive suffix), then U and 1/D
-  abi_store(fs_lds, 64, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
+  abi_store(fs_lds, BT, lane, abi_fold_segment(n, g.a, g.b, wtable, poses, &ok));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k + d < P;
     AbiEl r;
-    if (upd) r = abi_compose(AbiView{fs_lds, 64, lane}, AbiView{fs_lds, 64, lane + d}, &ok);
+    if (upd) r = abi_compose(AbiView{fs_lds, BT, lane}, AbiView{fs_lds, BT, lane + d}, &ok);
     __syncthreads();
-    if (upd) abi_store(fs_lds, 64, lane, r);
+    if (upd) abi_store(fs_lds, BT, lane, r);
   }
   __syncthreads();
   Sym6<double> carry{};
-  if (k + 1 < P && !AbiView{fs_lds, 64, lane + 1}.ident()) carry = AbiView{fs_lds, 64, lane + 1}.Q();
+  if (k + 1 < P && !AbiView{fs_lds, BT, lane + 1}.ident()) carry = AbiView{fs_lds, BT, lane + 1}.Q();
   __syncthreads();
   fds_abi_apply(n, g, wtable, poses, carry, scr, &ok);
   // 3: bias wrench and z-hat (inclusive suffix), then c-hat
-  aff_store(fs_lds, 64, lane, fds_z_fold<T>(n, g, wtable, poses, taus, scr));
+  aff_store(fs_lds, BT, lane, fds_z_fold<T>(n, g, wtable, poses, taus, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k + d < P;
     AffEl r;
-    if (upd) r = aff_compose(aff_load(fs_lds, 64, lane), aff_load(fs_lds, 64, lane + d));
+    if (upd) r = aff_compose(aff_load(fs_lds, BT, lane), aff_load(fs_lds, BT, lane + d));
     __syncthreads();
-    if (upd) aff_store(fs_lds, 64, lane, r);
+    if (upd) aff_store(fs_lds, BT, lane, r);
   }
   __syncthreads();
   Sp<double> Pc = Ftip;
   if (k + 1 < P) {
-    const AffEl e = aff_load(fs_lds, 64, lane + 1);
+    const AffEl e = aff_load(fs_lds, BT, lane + 1);
     Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
   }
   __syncthreads();
   fds_z_apply<T>(n, g, wtable, poses, taus, Pc, scr);
   // 4: lambda (inclusive prefix), then qdd
-  aff_store(fs_lds, 64, lane, fds_l_fold(g, wtable, scr));
+  aff_store(fs_lds, BT, lane, fds_l_fold(g, wtable, scr));
   for (int d = 1; d < P; d <<= 1) {
     __syncthreads();
     const bool upd = k >= d;
     AffEl r;
-    if (upd) r = aff_compose(aff_load(fs_lds, 64, lane), aff_load(fs_lds, 64, lane - d));
+    if (upd) r = aff_compose(aff_load(fs_lds, BT, lane), aff_load(fs_lds, BT, lane - d));
     __syncthreads();
-    if (upd) aff_store(fs_lds, 64, lane, r);
+    if (upd) aff_store(fs_lds, BT, lane, r);
   }
   __syncthreads();
-  const Sp<double> lam = k > 0 ? aff_load_c(fs_lds, 64, lane - 1) : sp_zero<double>();
+  const Sp<double> lam = k > 0 ? aff_load_c(fs_lds, BT, lane - 1) : sp_zero<double>();
   bool finite = true;
   T* const out = qdd + so * n;
   fds_l_apply(g, wtable, lam, scr, [&](int i, double v) {
@@ -2505,7 +2530,7 @@ size_t fd_scan_ws_bytes(const pdyn_model* m, const pdyn_batch* b, size_t scalar,
 template <class T>
 int run_fd_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* qd, const T* tau, T* qdd, void* ws,
                 size_t ws_bytes, void* stream) {
-  int st = check_model_batch(m, b);
+  int st = check_scan_batch(m, b);
   if (st) return st;
   if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
   if (b->n_states == 0) return PDYN_OK;
@@ -2526,13 +2551,23 @@ int run_fd_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* q
   BoundaryArgs<T> ba;
   for (int k = 0; k < 6; ++k) { ba.V0[k] = (T)b->base_vel[k]; ba.dV0[k] = (T)b->base_acc[k]; }
   const int P = abi_scan_lanes(m, b, 32768);
-  const int64_t per_block = 64 / P;
+  const unsigned block = scan_block(P);
+  const int64_t per_block = block / P;
   const int64_t grid = ((int64_t)b->n_states + per_block - 1) / per_block;
-  hipLaunchKernelGGL(k_fd_scan<T>, dim3((unsigned)grid), dim3(64), (size_t)kAbiElWords * 64 * sizeof(double), s,
-                     b->n_states, (int)m->n_links_max, P, reinterpret_cast<const T*>(tbase),
-                     reinterpret_cast<const double*>(tbase + woff), q, qd, tau, qdd,
-                     static_cast<const T*>(b->tip_wrench), ba,
-                     reinterpret_cast<double*>(static_cast<char*>(ws) + scratch_off), status);
+  const size_t lds = scan_lds(P);
+  if (P > 64 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_scan<T, kMaxScanLanes>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return PDYN_ELAUNCH;
+  const T* const tab = reinterpret_cast<const T*>(tbase);
+  const double* const wtab = reinterpret_cast<const double*>(tbase + woff);
+  const T* const tip = static_cast<const T*>(b->tip_wrench);
+  double* const scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + scratch_off);
+  if (P > 64)
+    hipLaunchKernelGGL((k_fd_scan<T, kMaxScanLanes>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,
+                       (int)m->n_links_max, P, tab, wtab, q, qd, tau, qdd, tip, ba, scratch, status);
+  else
+    hipLaunchKernelGGL((k_fd_scan<T, 64>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,
+                       (int)m->n_links_max, P, tab, wtab, q, qd, tau, qdd, tip, ba, scratch, status);
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }
@@ -2860,7 +2895,8 @@ int pdyn_read_status(void* ws, void* stream, uint32_t* bits) {
 
 size_t pdyn_workspace_bytes(int op, const pdyn_model* model, const pdyn_batch* batch, int scalar_bytes) {
   if (scalar_bytes != 4 && scalar_bytes != 8) return 0;
-  if (check_model_batch(model, batch)) return 0;
+  const bool scan_op = op == PDYN_OP_ARTICULATED_INERTIA || op == PDYN_OP_ABA_FD_SCAN;
+  if (scan_op ? check_scan_batch(model, batch) : check_model_batch(model, batch)) return 0;
   if (op == PDYN_OP_RNEA_ID_JACOBIAN || op == PDYN_OP_ABA_FD_JACOBIAN) {
     JacLayout jl;
     if (model->n_chains != 1 ||

@@ -1,7 +1,7 @@
 """The articulated-body inertia scan (abi_scan.hpp) runs on the CPU (host build) against the FP64 oracle.
 
 Eq. (7) as an associative scan of Riccati elements: every segment count from
-the serial recursion (P = 1) to 64 lanes per state, with the kernel's own
+the serial recursion (P = 1) to 128 lanes per state, with the kernel's own
 Kogge-Stone order and its word-major element store, must reproduce the
 oracle's serial Jhat_i (aba_trace) link by link. The oracle's recursion is the
 plain tip-to-base step of eq. (7), pinned through the forward dynamics it
@@ -20,7 +20,7 @@ from paper_1609_04493_amd import synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_cpu", "abi_scan_on_cpu.hip")
-SEGMENTS = (1, 2, 4, 8, 16, 32, 64)
+SEGMENTS = (1, 2, 4, 8, 16, 32, 64, 128)
 
 
 @pytest.fixture(scope="module")

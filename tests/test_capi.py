@@ -464,7 +464,7 @@ def test_hessian_host_rules():
 
 
 def test_articulated_inertia_host_rules():
-    """pdyn_articulated_inertia: shared chains only, segments a power of two up to 64, workspace = status word
+    """pdyn_articulated_inertia: shared chains only, segments a power of two up to 128, workspace = status word
     + tables; an empty batch queues nothing."""
     L = api.lib()
     fn = L.pdyn_articulated_inertia
@@ -480,9 +480,13 @@ def test_articulated_inertia_host_rules():
     assert fn(ctypes.byref(m), ctypes.byref(b), p, p + 1, w, need, None) == -2
     assert fn(ctypes.byref(m), ctypes.byref(b), p, p, w, need - 1, None) == -3
     assert fn(ctypes.byref(m), ctypes.byref(b), p, p, None, need, None) == -1
-    for bad in (3, 128, -2):
+    for bad in (3, 256, -2):
         b.segments = bad
         assert fn(ctypes.byref(m), ctypes.byref(b), p, p, w, need, None) == -1, bad
+        assert L.pdyn_workspace_bytes(10, ctypes.byref(m), ctypes.byref(b), 4) == 0
+    b.segments = 128  # the scans take up to 128 lanes per state (other operations 64)
+    assert L.pdyn_workspace_bytes(10, ctypes.byref(m), ctypes.byref(b), 4) == need
+    assert L.pdyn_workspace_bytes(0, ctypes.byref(m), ctypes.byref(b), 4) == 0
     b.segments = 0
     lp = np.array([0, 3, 6], np.int32)
     m2, keep2 = _fake_model(n=6, n_chains=2, link_ptr=lp)

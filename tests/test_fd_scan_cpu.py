@@ -20,7 +20,7 @@ from paper_1609_04493_amd import synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_cpu", "fd_scan_on_cpu.hip")
-SEGMENTS = (1, 2, 4, 8, 16, 32, 64)
+SEGMENTS = (1, 2, 4, 8, 16, 32, 64, 128)
 
 
 @pytest.fixture(scope="module")

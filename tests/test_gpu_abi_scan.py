@@ -3,7 +3,7 @@
 The kernel computes Jhat_i of eq. (7) either by the serial recursion (one lane
 per state) or by the associative scan of Riccati elements across a team of P
 lanes. FP64: every link to 1e-12 of its own largest entry, for every P from 1
-to 64, chains of 1 to 100 links and batches that leave a ragged last
+to 128, chains of 1 to 100 links and batches that leave a ragged last
 workgroup. FP32 inputs (the oracle given the same rounded inputs): 2e-6 (the
 joint angles' (sin, cos) are FP32, the rest double). At the 512-link, 256-state
 workload the scan and the serial recursion agree at every state to 1e-12,
@@ -19,7 +19,7 @@ from paper_1609_04493_amd import api, synth
 
 pytestmark = pytest.mark.gpu
 
-SEGMENTS = (1, 2, 4, 8, 16, 32, 64)
+SEGMENTS = (1, 2, 4, 8, 16, 32, 64, 128)
 
 
 def dev(a, device, dtype):

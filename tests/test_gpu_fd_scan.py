@@ -1,7 +1,7 @@
 """GPU forward dynamics with every recursion scanned (pdyn_aba_fd_scan) against the FP64 oracle.
 
 FP64: every state to 1e-11 (per-state relative norm) for every segment count
-from the serial phases (P = 1) to 64 lanes per state, with base motion and a
+from the serial phases (P = 1) to 128 lanes per state, with base motion and a
 tip wrench, on chains of 1 to 100 links and batches that leave a ragged last
 workgroup. FP32 inputs (the oracle given the same rounded inputs): 2e-6. At
 the 512-link, 256-state workload the 64-lane scan and the serial phases
@@ -17,7 +17,7 @@ from paper_1609_04493_amd import api, synth
 
 pytestmark = pytest.mark.gpu
 
-SEGMENTS = (1, 2, 4, 8, 16, 32, 64)
+SEGMENTS = (1, 2, 4, 8, 16, 32, 64, 128)
 
 
 def dev(a, device, dtype):
