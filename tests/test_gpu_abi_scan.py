@@ -59,7 +59,7 @@ def test_fp32_inputs(device):
     ref = oracle_jhat(chr_, st.q)
     model = api.Model(ch, device, torch.float32)
     q = dev(st.q, device, torch.float32)
-    for P in (1, 8, 64):
+    for P in (1, 8, 64, 128):
         J = api.articulated_inertia(model, q, segments=P).cpu().numpy().astype(np.float64)
         assert link_rel(J, ref) <= 2e-6, P
 
@@ -108,7 +108,7 @@ def test_unprepared_tables(device):
     st = synth.make_states((B, n), 8)
     for dt in (torch.float64, torch.float32):
         q = dev(st.q, device, dt)
-        for P in (1, 16):
+        for P in (1, 16, 128):
             a = api.articulated_inertia(api.Model(ch, device, dt), q, segments=P).cpu().numpy()
             b = api.articulated_inertia(api.Model(ch, device, dt, prepare=False), q, segments=P).cpu().numpy()
             assert np.array_equal(a, b), (dt, P)

@@ -54,7 +54,7 @@ def test_fp32_inputs(device):
     ref = np.stack([oracle.aba1(chr_, st.q[s], st.qd[s], st.tau[s]) for s in range(B)])
     model = api.Model(ch, device, torch.float32)
     q, qd, tau = (dev(a, device, torch.float32) for a in (st.q, st.qd, st.tau))
-    for P in (1, 16, 64):
+    for P in (1, 16, 64, 128):
         qdd = api.aba_fd_scan(model, q, qd, tau, segments=P).cpu().numpy().astype(np.float64)
         assert state_rel(qdd, ref) <= 2e-6, P
 
