@@ -410,8 +410,12 @@ def bench_fd_scan(args, dev):
         ref = qdd.double().cpu().numpy()
         rel = np.linalg.norm(scan_qdd - ref, axis=1) / np.linalg.norm(ref, axis=1)
         best = min((p for p in by_p if p), key=lambda p: by_p[p])
+        # the bias wrench and z-hat as two scans (split) against the one merged scan, at the best lane count
+        ms_split = time_windows(lambda: api.aba_fd_scan(model, q, qd, tau, segments=best, out=qdd, workspace=ws,
+                                                        split=True), stream)["median_ms"]
         rows[f"{n}_links_{B}_states"] = {
             "us_by_lanes_per_state": {str(p): by_p[p] * 1e3 for p in by_p if p},
+            "us_split_at_best_lanes": ms_split * 1e3, "split_over_merged": ms_split / by_p[best],
             "us_default": by_p[0] * 1e3, "best_lanes": best, "serial_phases_over_best": by_p[1] / by_p[best],
             "us_aba_fd_default_kernel": ms_serial_kernel * 1e3, "aba_fd_over_best_scan": ms_serial_kernel / by_p[best],
             "evals_per_s_best": B / (by_p[best] * 1e-3), "status_bits": status,

@@ -431,8 +431,12 @@ int pdyn_articulated_inertia_f64(const pdyn_model* model, const pdyn_batch* batc
  * log2(P) steps and reruns the segment from the result, so a state's latency
  * is O(n / P + log P) steps instead of the serial recursions' O(n): this is
  * the form for long chains with few states. P = 1 runs the same phases
- * serially. Same arguments and results as pdyn_aba_fd (base motion and tip
- * wrench from the batch; the other launch fields are ignored); everything
+ * serially. batch->variant: 0 or 1 (default) runs phase 3 as one scan of
+ * the merged recursion; 2 runs it as two scans, the bias wrench (eq. (2),
+ * giving tau-hat of eq. (5)) and then z-hat (operand eq. (18)), the split
+ * form the merged one is measured against; other values PDYN_EINVAL. Same
+ * arguments and results as pdyn_aba_fd (base motion and tip wrench from the
+ * batch; the other launch fields are ignored); everything
  * after the joint angles' (sin, cos) runs in double. A pivot D_i = S_i^T
  * Jhat_i S_i (or a pivot of the Riccati combines) that is not positive sets
  * PDYN_STATUS_PIVOT, a non-finite qdd PDYN_STATUS_NONFINITE. Workspace:

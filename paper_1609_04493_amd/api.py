@@ -277,13 +277,15 @@ def _prep(model, arrays):
             raise PdynError("joint arrays must be contiguous, on the model's device, of the model's dtype")
 
 
-def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace, segments=None):
+def _call(name, op, model, n_states, ptrs, base_vel, base_acc, tip, workspace, segments=None, variant=None):
     L = lib()
     fn = getattr(L, name + ("_f64" if model.dtype == torch.float64 else ""))
     m = model.c_struct()
     b = _batch_struct(n_states, base_vel, base_acc, tip, op)
     if segments is not None:
         b.segments = int(segments)
+    if variant is not None:
+        b.variant = int(variant)
     scalar = model.scalar_bytes
     nbytes = L.pdyn_workspace_bytes(op, ctypes.byref(m), ctypes.byref(b), scalar)
     if nbytes == 0:
@@ -443,10 +445,10 @@ def articulated_inertia(model: Model, q, segments=0, out=None, workspace=None):
 
 
 def aba_fd_scan(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, tip=None, segments=0, out=None,
-                workspace=None):
+                workspace=None, split=False):
     """qdd = FD(q, qd, tau) of a shared chain by pdyn_aba_fd_scan: every recursion of the articulated-body
     algorithm as a prefix scan over `segments` lanes per state (a power of two 1..128; 0 = the library's
-    choice). [B, n]."""
+    choice). split: the bias wrench and z-hat as two scans instead of one merged scan. [B, n]."""
     n_states = _n_states(model, q)
     if model.n_chains != 1:
         raise PdynError("pdyn_aba_fd_scan: needs one chain shared by the batch")
@@ -454,7 +456,7 @@ def aba_fd_scan(model: Model, q, qd, tau, base_vel=ZERO6, base_acc=GRAVITY_ACC, 
     qdd = torch.empty_like(q) if out is None else out
     _prep(model, (qdd,))
     _call("pdyn_aba_fd_scan", OP_ABA_FD_SCAN, model, n_states, (q, qd, tau, qdd), base_vel, base_acc, tip,
-          workspace, segments=segments)
+          workspace, segments=segments, variant=2 if split else 0)
     return qdd
 
 

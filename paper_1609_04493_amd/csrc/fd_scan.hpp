@@ -253,6 +253,66 @@ PD_HD void fds_z_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, const T* 
   }
 }
 
+// ---- phase 3, split form: the bias wrench alone, then z-hat --------------------------
+//
+// The same values by two scans instead of one (for measuring the merged form
+// against them). With Z_i = P_i - F_i (F_i the bias wrench of eq. (2),
+// F_{n+1} the tip wrench; Z_{n+1} = 0):
+//   3a. F_i = X_{i+1}^T F_{i+1} + Fhat_i, then tau-hat_i = tau_i - S_i^T F_i (eq. (5));
+//   3b. Z_i = K_i X_{i+1}^T Z_{i+1} + U_i tau-hat_i / D_i, with
+//       c-hat_i = (tau-hat_i - S_i^T X_{i+1}^T Z_{i+1}) / D_i (eq. (8), operand eq. (18)).
+// tau-hat_i is kept in the c-hat word between the two scans.
+
+template <class WTab, class PoseOf>
+PD_HD AffEl fds_f_fold(int n, Seg sg, WTab wtable, const PoseOf& pose, const FdScanScr& scr) {
+  AffEl agg = aff_identity();
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const Sp<double> off = scr.get_sp(i, 0);
+    if (i == n - 1) {
+      agg = aff_after([&](const Sp<double>& v) { return v; }, off, agg);
+    } else {
+      const Pose<double> gn = pose(i + 1);
+      agg = aff_after([&](const Sp<double>& v) { return XT_wrench(gn, v); }, off, agg);
+    }
+  }
+  return agg;
+}
+
+template <class T, class WTab, class PoseOf>
+PD_HD void fds_f_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, const T* tau, Sp<double> F,
+                       const FdScanScr& scr) {
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    F = (i == n - 1 ? F : XT_wrench(pose(i + 1), F)) + scr.get_sp(i, 0);
+    scr.at(i)[13] = (double)tau[i] - dot(link_at(wtable, i).S, F);
+  }
+}
+
+template <class WTab, class PoseOf>
+PD_HD AffEl fds_zs_fold(int n, Seg sg, WTab wtable, const PoseOf& pose, const FdScanScr& scr) {
+  AffEl agg = aff_identity();
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const ZLin z{scr.get_sp(i, 6), link_at(wtable, i).S, scr.at(i)[12]};
+    const Sp<double> off = (scr.at(i)[13] * z.invD) * z.U;
+    if (i == n - 1) {
+      agg = aff_after([&](const Sp<double>& v) { return z.K(v); }, off, agg);
+    } else {
+      const Pose<double> gn = pose(i + 1);
+      agg = aff_after([&](const Sp<double>& v) { return z.K(XT_wrench(gn, v)); }, off, agg);
+    }
+  }
+  return agg;
+}
+
+template <class WTab, class PoseOf>
+PD_HD void fds_zs_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, Sp<double> Z, const FdScanScr& scr) {
+  for (int i = sg.b - 1; i >= sg.a; --i) {
+    const Sp<double> XZ = i == n - 1 ? Z : XT_wrench(pose(i + 1), Z);
+    const double chat = (scr.at(i)[13] - dot(link_at(wtable, i).S, XZ)) * scr.at(i)[12];
+    scr.at(i)[13] = chat;
+    Z = XZ + chat * scr.get_sp(i, 6);
+  }
+}
+
 // ---- phase 4: lambda and qdd, base to tip --------------------------------------------
 
 // The segment's map from lambda before its first link to lambda at its last.

@@ -2413,11 +2413,28 @@ int run_abi_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, T* Jhat, 
 // Forward dynamics of a shared chain with every recursion scanned (fd_scan.hpp):
 // a team of P lanes per state in workgroups as in k_abi_scan, four phases of
 // fold, Kogge-Stone scan through LDS ([85 words][workgroup] doubles, reused by
-// every phase) and apply. Per-link values (Fhat, U, 1/D, c-hat, the link transform) in `scratch`,
+// every phase) and apply; SPLIT runs the third phase as two scans (the bias
+// wrench, then z-hat) instead of one scan of the merged recursion. Per-link values (Fhat, U, 1/D, c-hat, the link transform) in `scratch`,
 // [n_states][n][kFdScanWords] doubles; a lane touches only its own links there,
 // so the phases need no ordering beyond the workgroup barriers around the LDS
 // exchanges.
-template <class T, int BT>  // BT = workgroup threads, max(64, P), as in k_abi_scan
+// Kogge-Stone inclusive scan of the affine elements that every lane of the
+// workgroup has stored in LDS ([word][BT]): suffix (lane k takes x_k o x_{k+d})
+// or prefix (x_k o x_{k-d}) within each team of P lanes; ends with a barrier.
+template <int BT, bool SUFFIX>
+__device__ __forceinline__ void lds_aff_scan(double* lds, int lane, int k, int P) {
+  for (int d = 1; d < P; d <<= 1) {
+    __syncthreads();
+    const bool upd = SUFFIX ? k + d < P : k >= d;
+    AffEl r;
+    if (upd) r = aff_compose(aff_load(lds, BT, lane), aff_load(lds, BT, SUFFIX ? lane + d : lane - d));
+    __syncthreads();
+    if (upd) aff_store(lds, BT, lane, r);
+  }
+  __syncthreads();
+}
+
+template <class T, int BT, bool SPLIT>  // BT = workgroup threads, max(64, P), as in k_abi_scan; SPLIT: phase 3
 __global__ void __launch_bounds__(BT) k_fd_scan(int n_states, int n, int P, const T* __restrict__ table,
                                                 const double* __restrict__ wtable, const T* q, const T* qd,
                                                 const T* tau, T* qdd, const T* tip, BoundaryArgs<T> ba,
@@ -2478,35 +2495,37 @@ __global__ void __launch_bounds__(BT) k_fd_scan(int n_states, int n, int P, cons
   if (k + 1 < P && !AbiView{fs_lds, BT, lane + 1}.ident()) carry = AbiView{fs_lds, BT, lane + 1}.Q();
   __syncthreads();
   fds_abi_apply(n, g, wtable, poses, carry, scr, &ok);
-  // 3: bias wrench and z-hat (inclusive suffix), then c-hat
-  aff_store(fs_lds, BT, lane, fds_z_fold<T>(n, g, wtable, poses, taus, scr));
-  for (int d = 1; d < P; d <<= 1) {
+  // 3: bias wrench and z-hat (inclusive suffix), then c-hat: one scan of the merged recursion, or
+  // (SPLIT) the bias wrench and then z-hat as two scans
+  if (SPLIT) {
+    aff_store(fs_lds, BT, lane, fds_f_fold(n, g, wtable, poses, scr));
+    lds_aff_scan<BT, true>(fs_lds, lane, k, P);
+    Sp<double> Fc = Ftip;
+    if (k + 1 < P) {
+      const AffEl e = aff_load(fs_lds, BT, lane + 1);
+      Fc = m6_apply(e.M, Ftip) + sp_of(e.c);
+    }
     __syncthreads();
-    const bool upd = k + d < P;
-    AffEl r;
-    if (upd) r = aff_compose(aff_load(fs_lds, BT, lane), aff_load(fs_lds, BT, lane + d));
+    fds_f_apply<T>(n, g, wtable, poses, taus, Fc, scr);
+    aff_store(fs_lds, BT, lane, fds_zs_fold(n, g, wtable, poses, scr));
+    lds_aff_scan<BT, true>(fs_lds, lane, k, P);
+    const Sp<double> Zc = k + 1 < P ? aff_load_c(fs_lds, BT, lane + 1) : sp_zero<double>();
     __syncthreads();
-    if (upd) aff_store(fs_lds, BT, lane, r);
+    fds_zs_apply(n, g, wtable, poses, Zc, scr);
+  } else {
+    aff_store(fs_lds, BT, lane, fds_z_fold<T>(n, g, wtable, poses, taus, scr));
+    lds_aff_scan<BT, true>(fs_lds, lane, k, P);
+    Sp<double> Pc = Ftip;
+    if (k + 1 < P) {
+      const AffEl e = aff_load(fs_lds, BT, lane + 1);
+      Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
+    }
+    __syncthreads();
+    fds_z_apply<T>(n, g, wtable, poses, taus, Pc, scr);
   }
-  __syncthreads();
-  Sp<double> Pc = Ftip;
-  if (k + 1 < P) {
-    const AffEl e = aff_load(fs_lds, BT, lane + 1);
-    Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
-  }
-  __syncthreads();
-  fds_z_apply<T>(n, g, wtable, poses, taus, Pc, scr);
   // 4: lambda (inclusive prefix), then qdd
   aff_store(fs_lds, BT, lane, fds_l_fold(g, wtable, scr));
-  for (int d = 1; d < P; d <<= 1) {
-    __syncthreads();
-    const bool upd = k >= d;
-    AffEl r;
-    if (upd) r = aff_compose(aff_load(fs_lds, BT, lane), aff_load(fs_lds, BT, lane - d));
-    __syncthreads();
-    if (upd) aff_store(fs_lds, BT, lane, r);
-  }
-  __syncthreads();
+  lds_aff_scan<BT, false>(fs_lds, lane, k, P);
   const Sp<double> lam = k > 0 ? aff_load_c(fs_lds, BT, lane - 1) : sp_zero<double>();
   bool finite = true;
   T* const out = qdd + so * n;
@@ -2532,6 +2551,7 @@ int run_fd_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* q
                 size_t ws_bytes, void* stream) {
   int st = check_scan_batch(m, b);
   if (st) return st;
+  if (b->variant != 0 && b->variant != 1 && b->variant != 2) return PDYN_EINVAL;
   if (m->n_chains != 1) return PDYN_EUNSUPPORTED;
   if (b->n_states == 0) return PDYN_OK;
   if ((st = check_ptrs<T>({q, qd, tau, qdd, m->placement, m->twist, m->inertia}))) return st;
@@ -2555,19 +2575,24 @@ int run_fd_scan(const pdyn_model* m, const pdyn_batch* b, const T* q, const T* q
   const int64_t per_block = block / P;
   const int64_t grid = ((int64_t)b->n_states + per_block - 1) / per_block;
   const size_t lds = scan_lds(P);
-  if (P > 64 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_scan<T, kMaxScanLanes>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+  const bool split = b->variant == 2;
+  if (P > 64 &&
+      hipFuncSetAttribute(split ? reinterpret_cast<const void*>(&k_fd_scan<T, kMaxScanLanes, true>)
+                                : reinterpret_cast<const void*>(&k_fd_scan<T, kMaxScanLanes, false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return PDYN_ELAUNCH;
   const T* const tab = reinterpret_cast<const T*>(tbase);
   const double* const wtab = reinterpret_cast<const double*>(tbase + woff);
   const T* const tip = static_cast<const T*>(b->tip_wrench);
   double* const scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + scratch_off);
-  if (P > 64)
-    hipLaunchKernelGGL((k_fd_scan<T, kMaxScanLanes>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,
-                       (int)m->n_links_max, P, tab, wtab, q, qd, tau, qdd, tip, ba, scratch, status);
-  else
-    hipLaunchKernelGGL((k_fd_scan<T, 64>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,
-                       (int)m->n_links_max, P, tab, wtab, q, qd, tau, qdd, tip, ba, scratch, status);
+#define PDYN_LAUNCH_FD_SCAN(BT, SPLIT)                                                                          \
+  hipLaunchKernelGGL((k_fd_scan<T, BT, SPLIT>), dim3((unsigned)grid), dim3(block), lds, s, b->n_states,          \
+                     (int)m->n_links_max, P, tab, wtab, q, qd, tau, qdd, tip, ba, scratch, status)
+  if (P > 64 && split) PDYN_LAUNCH_FD_SCAN(kMaxScanLanes, true);
+  else if (P > 64) PDYN_LAUNCH_FD_SCAN(kMaxScanLanes, false);
+  else if (split) PDYN_LAUNCH_FD_SCAN(64, true);
+  else PDYN_LAUNCH_FD_SCAN(64, false);
+#undef PDYN_LAUNCH_FD_SCAN
   if (hipGetLastError() != hipSuccess) return PDYN_ELAUNCH;
   return PDYN_OK;
 }

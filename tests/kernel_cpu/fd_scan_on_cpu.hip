@@ -2,7 +2,8 @@
 // for each state of one shared chain, the P lanes of a team run the four
 // phases (bias velocities, articulated inertias, bias wrench with z-hat,
 // lambda) in the kernel's order, each phase's Kogge-Stone scan reading the
-// elements back from a word-major store as the kernel does from LDS. Writes
+// elements back from a word-major store as the kernel does from LDS; with
+// `split` the third phase runs as two scans (bias wrench, then z-hat). Writes
 // qdd [state][link]. CPU tests compare it with the oracle's ABA.
 #include <cstdint>
 #include <vector>
@@ -12,7 +13,7 @@
 using namespace pdyn;
 
 template <class T>
-static int run(int P, int n_states, int n, const T* placement, const T* twist, const T* inertia, const T* q,
+static int run(int P, int split, int n_states, int n, const T* placement, const T* twist, const T* inertia, const T* q,
                const T* qd, const T* tau, const T* V0, const T* dV0, const T* tip, T* qdd) {
   std::vector<T> table((size_t)n * kLinkWords);
   std::vector<double> wtable((size_t)n * kLinkWords);
@@ -76,20 +77,31 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
       if (k + 1 < P && !AbiView{st, P, k + 1}.ident()) carry = AbiView{st, P, k + 1}.Q();
       fds_abi_apply(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), carry, scr, &ok);
     }
-    // 3: bias wrench and z-hat, inclusive suffix
-    for (int k = 0; k < P; ++k)
-      aff_store(st, P, k, fds_z_fold<T>(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), taus, scr));
-    for (int d = 1; d < P; d <<= 1) {
-      for (int k = 0; k + d < P; ++k) nz[k] = aff_compose(aff_load(st, P, k), aff_load(st, P, k + d));
-      for (int k = 0; k + d < P; ++k) aff_store(st, P, k, nz[k]);
-    }
-    for (int k = 0; k < P; ++k) {
-      Sp<double> Pc = Ftip;
-      if (k + 1 < P) {
-        const AffEl e = aff_load(st, P, k + 1);
-        Pc = m6_apply(e.M, Ftip) + sp_of(e.c);
+    // 3: bias wrench and z-hat, inclusive suffix: one scan of the merged recursion, or (split) the bias
+    // wrench and z-hat as two scans
+    auto suffix = [&](auto fold_of, const Sp<double>& beyond, auto apply_from) {
+      for (int k = 0; k < P; ++k) aff_store(st, P, k, fold_of(segment_of(n, P, k)));
+      for (int d = 1; d < P; d <<= 1) {
+        for (int k = 0; k + d < P; ++k) nz[k] = aff_compose(aff_load(st, P, k), aff_load(st, P, k + d));
+        for (int k = 0; k + d < P; ++k) aff_store(st, P, k, nz[k]);
       }
-      fds_z_apply<T>(n, segment_of(n, P, k), wtable.data(), poses(segment_of(n, P, k)), taus, Pc, scr);
+      for (int k = 0; k < P; ++k) {
+        Sp<double> c = beyond;
+        if (k + 1 < P) {
+          const AffEl e = aff_load(st, P, k + 1);
+          c = m6_apply(e.M, beyond) + sp_of(e.c);
+        }
+        apply_from(segment_of(n, P, k), c);
+      }
+    };
+    if (!split) {
+      suffix([&](Seg g) { return fds_z_fold<T>(n, g, wtable.data(), poses(g), taus, scr); }, Ftip,
+             [&](Seg g, const Sp<double>& c) { fds_z_apply<T>(n, g, wtable.data(), poses(g), taus, c, scr); });
+    } else {
+      suffix([&](Seg g) { return fds_f_fold(n, g, wtable.data(), poses(g), scr); }, Ftip,
+             [&](Seg g, const Sp<double>& c) { fds_f_apply<T>(n, g, wtable.data(), poses(g), taus, c, scr); });
+      suffix([&](Seg g) { return fds_zs_fold(n, g, wtable.data(), poses(g), scr); }, sp_zero<double>(),
+             [&](Seg g, const Sp<double>& c) { fds_zs_apply(n, g, wtable.data(), poses(g), c, scr); });
     }
     // 4: lambda and qdd, inclusive prefix
     for (int k = 0; k < P; ++k)
@@ -108,13 +120,13 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
   return bad;
 }
 
-extern "C" int cpu_fd_scan_f32(int P, int n_states, int n, const float* pl, const float* tw, const float* in,
+extern "C" int cpu_fd_scan_f32(int P, int split, int n_states, int n, const float* pl, const float* tw, const float* in,
                                const float* q, const float* qd, const float* tau, const float* V0, const float* dV0,
                                const float* tip, float* qdd) {
-  return run<float>(P, n_states, n, pl, tw, in, q, qd, tau, V0, dV0, tip, qdd);
+  return run<float>(P, split, n_states, n, pl, tw, in, q, qd, tau, V0, dV0, tip, qdd);
 }
-extern "C" int cpu_fd_scan_f64(int P, int n_states, int n, const double* pl, const double* tw, const double* in,
+extern "C" int cpu_fd_scan_f64(int P, int split, int n_states, int n, const double* pl, const double* tw, const double* in,
                                const double* q, const double* qd, const double* tau, const double* V0,
                                const double* dV0, const double* tip, double* qdd) {
-  return run<double>(P, n_states, n, pl, tw, in, q, qd, tau, V0, dV0, tip, qdd);
+  return run<double>(P, split, n_states, n, pl, tw, in, q, qd, tau, V0, dV0, tip, qdd);
 }

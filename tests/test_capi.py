@@ -517,7 +517,9 @@ def test_aba_fd_scan_host_rules():
     assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need - 1, None) == -3
     b.segments = 3
     assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need, None) == -1
-    b.segments = 0
+    b.segments, b.variant = 0, 3  # 0 / 1: the merged scan, 2: split; nothing else
+    assert fn(ctypes.byref(m), ctypes.byref(b), p, p, p, p, w, need, None) == -1
+    b.variant = 0
     lp = np.array([0, 3, 6], np.int32)
     m2, keep2 = _fake_model(n=6, n_chains=2, link_ptr=lp)
     m2.n_links_max = 3

@@ -3,9 +3,10 @@
 Four phases, each a fold over a lane's segment, a Kogge-Stone scan across the
 team in the kernel's order and a rerun: bias velocities and accelerations
 (eqs. (12)-(13)), articulated inertias (the Riccati scan of eq. (7)), the
-bias wrench with z-hat (affine, eq. (18)) and lambda (affine, eq. (19)). Every
-segment count must reproduce the oracle's serial ABA, with base motion and a
-tip wrench.
+bias wrench with z-hat (affine, eq. (18); one merged scan, or split into the
+bias-wrench scan and the z-hat scan) and lambda (affine, eq. (19)). Every
+segment count, in both forms, must reproduce the oracle's serial ABA, with
+base motion and a tip wrench.
 """
 
 import ctypes
@@ -32,19 +33,19 @@ def fds_lib(tmp_path_factory):
                    check=True)
     lib = ctypes.CDLL(out)
     for f in (lib.cpu_fd_scan_f32, lib.cpu_fd_scan_f64):
-        f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 10
+        f.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 10
         f.restype = ctypes.c_int
     return lib
 
 
-def fd_scan(lib, P, ch, st, tip=None, V0=np.zeros(6), dV0=np.array(oracle.GRAVITY_ACC), dtype=np.float64):
+def fd_scan(lib, P, ch, st, tip=None, V0=np.zeros(6), dV0=np.array(oracle.GRAVITY_ACC), dtype=np.float64, split=0):
     B, n = st.q.shape
     dt = np.dtype(dtype)
     c = lambda a: None if a is None else np.ascontiguousarray(a, dtype=dt)
     args = [c(ch.placement), c(ch.twist), c(ch.inertia), c(st.q), c(st.qd), c(st.tau), c(V0), c(dV0), c(tip)]
     out = np.full((B, n), np.nan, dt)
     fn = lib.cpu_fd_scan_f64 if dt == np.float64 else lib.cpu_fd_scan_f32
-    bad = fn(P, B, n, *[None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in args],
+    bad = fn(P, split, B, n, *[None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in args],
              out.ctypes.data_as(ctypes.c_void_p))
     return out.astype(np.float64), bad
 
@@ -61,9 +62,10 @@ def test_fp64_every_segment_count_equals_oracle(fds_lib, n):
     tip, V0, dV0 = rng.normal(size=(3, 6)), rng.normal(size=6), rng.normal(size=6)
     ref = np.stack([oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s], V0, dV0, tip[s]) for s in range(3)])
     for P in SEGMENTS:
-        qdd, bad = fd_scan(fds_lib, P, ch, st, tip, V0, dV0)
-        assert bad == 0
-        assert state_rel(qdd, ref) <= 1e-11, P
+        for split in (0, 1):
+            qdd, bad = fd_scan(fds_lib, P, ch, st, tip, V0, dV0, split=split)
+            assert bad == 0
+            assert state_rel(qdd, ref) <= 1e-11, (P, split)
 
 
 def test_fp32_inputs(fds_lib):

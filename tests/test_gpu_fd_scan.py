@@ -1,11 +1,13 @@
 """GPU forward dynamics with every recursion scanned (pdyn_aba_fd_scan) against the FP64 oracle.
 
 FP64: every state to 1e-11 (per-state relative norm) for every segment count
-from the serial phases (P = 1) to 128 lanes per state, with base motion and a
+from the serial phases (P = 1) to 128 lanes per state, with the bias wrench and
+z-hat as one merged scan and as two (split), with base motion and a
 tip wrench, on chains of 1 to 100 links and batches that leave a ragged last
 workgroup. FP32 inputs (the oracle given the same rounded inputs): 2e-6. At
-the 512-link, 256-state workload the 64-lane scan and the serial phases
-agree at every state to 1e-10 and sampled states match the oracle to 1e-9.
+the 512-link, 256-state workload the default scan and the serial phases agree
+at every state to 1e-10, the split form (another rounding order) to 1e-9, and
+sampled states match the oracle to 1e-9.
 """
 
 import numpy as np
@@ -39,9 +41,11 @@ def test_fp64_every_segment_count(device, n, B):
     model = api.Model(ch, device, torch.float64)
     q, qd, tau, tipd = (dev(a, device, torch.float64) for a in (st.q, st.qd, st.tau, tip))
     for P in SEGMENTS:
-        qdd = api.aba_fd_scan(model, q, qd, tau, base_vel=V0, base_acc=dV0, tip=tipd, segments=P).cpu().numpy()
-        assert api.read_status(device) == 0, P
-        assert state_rel(qdd, ref) <= 1e-11, P
+        for split in (False, True):
+            qdd = api.aba_fd_scan(model, q, qd, tau, base_vel=V0, base_acc=dV0, tip=tipd, segments=P,
+                                  split=split).cpu().numpy()
+            assert api.read_status(device) == 0, (P, split)
+            assert state_rel(qdd, ref) <= 1e-11, (P, split)
 
 
 def test_fp32_inputs(device):
@@ -55,8 +59,9 @@ def test_fp32_inputs(device):
     model = api.Model(ch, device, torch.float32)
     q, qd, tau = (dev(a, device, torch.float32) for a in (st.q, st.qd, st.tau))
     for P in (1, 16, 64, 128):
-        qdd = api.aba_fd_scan(model, q, qd, tau, segments=P).cpu().numpy().astype(np.float64)
-        assert state_rel(qdd, ref) <= 2e-6, P
+        for split in (False, True):
+            qdd = api.aba_fd_scan(model, q, qd, tau, segments=P, split=split).cpu().numpy().astype(np.float64)
+            assert state_rel(qdd, ref) <= 2e-6, (P, split)
 
 
 def test_long_chain_batch(device):
@@ -68,8 +73,10 @@ def test_long_chain_batch(device):
     q, qd, tau = (dev(a, device, torch.float64) for a in (st.q, st.qd, st.tau))
     qs = api.aba_fd_scan(model, q, qd, tau).cpu().numpy()
     q1 = api.aba_fd_scan(model, q, qd, tau, segments=1).cpu().numpy()
+    qsp = api.aba_fd_scan(model, q, qd, tau, split=True).cpu().numpy()
     assert api.read_status(device) == 0
     assert state_rel(qs, q1) <= 1e-10
+    assert state_rel(qsp, qs) <= 1e-9  # another rounding order; the same bound as against the oracle below
     for s in (0, B - 1):
         ref = oracle.aba1(ch, st.q[s], st.qd[s], st.tau[s])
         assert state_rel(qs[s:s + 1], ref[None]) <= 1e-9, s
