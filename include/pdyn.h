@@ -152,10 +152,12 @@ typedef struct pdyn_batch {
    * two recursions of eq. (8) behind it. block_threads and max_blocks apply to
    * variants 1 and 3. Every variant gives the same results to rounding. */
   int32_t variant;
-  /* Variant 4 only: segments (lanes) per chain, a power of two 1 .. 64 for
-   * inverse dynamics, 1 .. 16 for forward dynamics and ID+FD (PDYN_EUNSUPPORTED
-   * above); 0 = library default (the largest power of two within that bound
-   * that leaves at least 8 links per segment). */
+  /* Lanes per chain, a power of two; 0 = library default. Variant 4 of the
+   * inverse dynamics: 1 .. 64; of forward dynamics and ID+FD: 1 .. 16 (32 and
+   * 64 give PDYN_EUNSUPPORTED); default the largest power of two within that
+   * bound that leaves at least 8 links per segment. pdyn_articulated_inertia
+   * and pdyn_aba_fd_scan: lanes per state 1 .. 128, default described there.
+   * Other values: PDYN_EINVAL. Ignored by the other operations and variants. */
   int32_t segments;
 } pdyn_batch;
 
