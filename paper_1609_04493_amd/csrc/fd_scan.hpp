@@ -203,14 +203,14 @@ template <class WTab, class PoseOf>
 PD_HD void fds_abi_apply(int n, Seg sg, WTab wtable, const PoseOf& pose, const Sym6<double>& carry,
                          const FdScanScr& scr, bool* pivot_ok) {
   abi_serial_segment(n, sg.a, sg.b, wtable, pose, carry,
-                        [&](int i, const Sym6<double>& Jh) {
-                          const Sp<double> U = mul(Jh, link_at(wtable, i).S);
-                          const double D = dot(link_at(wtable, i).S, U);
-                          *pivot_ok = *pivot_ok && D > 0.0;
-                          scr.put_sp(i, 6, U);
-                          scr.at(i)[12] = 1.0 / D;
-                        },
-                        pivot_ok);
+                     [&](int i, const Sym6<double>& Jh) {
+                       const Sp<double> U = mul(Jh, link_at(wtable, i).S);
+                       const double D = dot(link_at(wtable, i).S, U);
+                       *pivot_ok = *pivot_ok && D > 0.0;
+                       scr.put_sp(i, 6, U);
+                       scr.at(i)[12] = 1.0 / D;
+                     },
+                     pivot_ok);
 }
 
 // ---- phase 3: bias wrench and z-hat / c-hat, tip to base ----------------------------
@@ -222,7 +222,8 @@ struct ZLin {
   PD_HD Sp<double> K(const Sp<double>& w) const { return w - (dot(S, w) * invD) * U; }
 };
 
-// The segment's map from P at its tip end (P_{b+1}, or the tip wrench when b = n) to P_a.
+// The segment's map from P beyond its last link (that of the next link, or the tip wrench when the
+// segment ends at the tip) to P of its first link.
 template <class T, class WTab, class PoseOf>
 PD_HD AffEl fds_z_fold(int n, Seg sg, WTab wtable, const PoseOf& pose, const T* tau, const FdScanScr& scr) {
   AffEl agg = aff_identity();

@@ -2318,17 +2318,17 @@ __global__ void __launch_bounds__(BT) k_abi_scan(int n_states, int n, int P, con
   bool finite = true;
   T* const out = Jhat + (active ? s : 0) * n * 36;
   abi_serial_segment(n, g.a, g.b, wtable, poses, carry,
-                        [&](int i, const Sym6<double>& J) {
-                          const M6 m = m6_of(J);
-                          T* o = out + (int64_t)i * 36;
+                     [&](int i, const Sym6<double>& J) {
+                       const M6 m = m6_of(J);
+                       T* o = out + (int64_t)i * 36;
 #pragma unroll
-                          for (int e = 0; e < 36; ++e) {
-                            const T v = (T)m.m[e];
-                            o[e] = v;
-                            finite = finite && __builtin_isfinite(v);
-                          }
-                        },
-                        &ok);
+                       for (int e = 0; e < 36; ++e) {
+                         const T v = (T)m.m[e];
+                         o[e] = v;
+                         finite = finite && __builtin_isfinite(v);
+                       }
+                     },
+                     &ok);
   const unsigned bits = (finite ? 0u : kStatusNonFinite) | (ok ? 0u : kStatusPivot);
   if (active && bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -51,11 +51,11 @@ static int run(int P, int n_states, int n, const T* placement, const T* twist, c
       const bool has = k + 1 < P && !AbiView{store.data(), P, k + 1}.ident();
       if (has) carry = AbiView{store.data(), P, k + 1}.Q();
       abi_serial_segment(n, g.a, g.b, wtable.data(), poses, carry,
-                            [&](int i, const Sym6<double>& J) {
-                              const M6 m = m6_of(J);
-                              for (int e = 0; e < 36; ++e) Jhat[((int64_t)s * n + i) * 36 + e] = (T)m.m[e];
-                            },
-                            &ok);
+                         [&](int i, const Sym6<double>& J) {
+                           const M6 m = m6_of(J);
+                           for (int e = 0; e < 36; ++e) Jhat[((int64_t)s * n + i) * 36 + e] = (T)m.m[e];
+                         },
+                         &ok);
     }
     if (!ok) ++bad;
   }

@@ -113,7 +113,7 @@ static int run(int P, int split, int n_states, int n, const T* placement, const 
     for (int k = 0; k < P; ++k) {
       const Sp<double> lam = k > 0 ? aff_load_c(st, P, k - 1) : sp_zero<double>();
       fds_l_apply(segment_of(n, P, k), wtable.data(), lam, scr,
-                     [&](int i, double v) { qdd[(int64_t)s * n + i] = (T)v; });
+                  [&](int i, double v) { qdd[(int64_t)s * n + i] = (T)v; });
     }
     if (!ok) ++bad;
   }
